@@ -1,0 +1,859 @@
+/*
+ * oracle.c -- plain, slow FP64 CPU oracle for the GPU-resident roll-out path.
+ *
+ * TEST INFRASTRUCTURE. Only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark may load this library. The product path never calls it.
+ * It shares no code, header, table or constant with the HIP kernels: both
+ * sides follow the same written specification (the readings listed in the
+ * design notes), nothing more.
+ *
+ * What the paper fixes (arXiv 2408.00930):
+ *   - Sec. 2 and App. B: many environment replicas run independently and
+ *     concurrently; each agent samples actions from a policy model and gets a
+ *     reward; roll-out data are stored in place for training.
+ *   - Sec. 3 (Environments Agnostic): actor-critic training for discrete and
+ *     continuous actions, which consumes returns and advantages (GAE).
+ *   - App. C: the workloads are classic control (CartPole, Acrobot), a
+ *     multi-agent economic simulation and a noisy high-dimensional
+ *     potential-energy walk for reaction paths.
+ * Everything below that the paper leaves open is a reading of this project
+ * (random-number layout, dynamics constants, market rules, potential,
+ * quantisation points); each reading is named where it is used.
+ *
+ * Parity unpinned: the classic-control constants are not checked against gym
+ * (its source is not available); the dynamics themselves are pinned to
+ * Euler-Lagrange equations generated from the bodies' energies.
+ *
+ * Style: obvious loops, no blocking, no fusion, no reordering, FP64 unless a
+ * quantisation point of the policy is being emulated. OpenMP parallelises
+ * only the loop over independent environments.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------------ */
+/* Counter-based RNG: Philox-4x32-10                                         */
+/* Salmon, Moraes, Dror, Shaw, "Parallel Random Numbers: As Easy as 1, 2, 3" */
+/* (SC'11), Sec. 3: the Philox S-box with two 32x32->64 multiplications per  */
+/* round, a Weyl-sequence key schedule, ten rounds.                          */
+/* ------------------------------------------------------------------------ */
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const uint32_t mult0 = 0xD2511F53u, mult1 = 0xCD9E8D57u;  /* round multipliers */
+    const uint32_t weyl0 = 0x9E3779B9u, weyl1 = 0xBB67AE85u;  /* key increments */
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t prod0 = (uint64_t)mult0 * (uint64_t)x0;
+        uint64_t prod1 = (uint64_t)mult1 * (uint64_t)x2;
+        uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+        uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+        uint32_t y0 = hi1 ^ x1 ^ k0;
+        uint32_t y1 = lo1;
+        uint32_t y2 = hi0 ^ x3 ^ k1;
+        uint32_t y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+        k0 += weyl0;
+        k1 += weyl1;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Reading (counter layout): key = (seed low 32 bits, seed high 32 bits);
+ * counter = (step t, row, purpose | sub-block << 8, epoch).                 */
+enum { ORC_ACTION = 0, ORC_RESET = 1, ORC_ENV_NOISE = 2 };
+
+void orc_draw(uint64_t seed, uint32_t t, uint32_t row, uint32_t purpose,
+              uint32_t sub, uint32_t epoch, uint32_t out[4])
+{
+    uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    uint32_t ctr[4] = {t, row, (purpose & 0xffu) | (sub << 8), epoch};
+    orc_philox4x32_10(ctr, key, out);
+}
+
+/* Reading: uniform in (0,1) from the top 23 bits, u = (2*(x>>9)+1) * 2^-24.
+ * It is an odd multiple of 2^-24, hence never 0 or 1 and exact in FP32.     */
+double orc_u01(uint32_t x)
+{
+    return (double)(2u * (x >> 9) + 1u) * 0x1p-24;
+}
+
+/* Box-Muller (Box and Muller 1958): one pair of uniforms -> two normals.   */
+void orc_box_muller(double u1, double u2, double* z_cos, double* z_sin)
+{
+    double radius = sqrt(-2.0 * log(u1));
+    *z_cos = radius * cos(2.0 * ORC_PI * u2);
+    *z_sin = radius * sin(2.0 * ORC_PI * u2);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Rounding to the policy's narrow formats (quantisation points).            */
+/* ------------------------------------------------------------------------ */
+
+/* Round a double to the nearest value with `mant` explicit mantissa bits and
+ * minimum normal exponent `emin`, ties to even. Values below 2^emin use the
+ * subnormal spacing 2^(emin-mant). Overflow is handled by the callers.       */
+static double round_to_format(double x, int mant, int emin)
+{
+    if (x == 0.0 || isnan(x) || isinf(x)) return x;
+    int e2;
+    frexp(x, &e2);                  /* |x| in [2^(e2-1), 2^e2) */
+    int e = e2 - 1;
+    if (e < emin) e = emin;
+    double quantum = ldexp(1.0, e - mant);
+    double k = nearbyint(x / quantum);   /* default rounding: ties to even */
+    return k * quantum;
+}
+
+/* bfloat16: 8 exponent bits, 7 mantissa bits, IEEE-like; overflow -> inf.   */
+double orc_round_bf16(double x)
+{
+    double r = round_to_format(x, 7, -126);
+    if (fabs(r) >= 0x1p128) r = copysign(INFINITY, x);
+    return r;
+}
+
+/* OCP FP8 E4M3FN: 4 exponent bits (bias 7), 3 mantissa bits, largest finite
+ * 448, no infinities. Reading: saturating conversion.                        */
+double orc_round_fp8e4m3(double x)
+{
+    if (isnan(x)) return x;
+    double r = round_to_format(x, 3, -6);
+    if (r > 448.0) r = 448.0;
+    if (r < -448.0) r = -448.0;
+    return r;
+}
+
+/* Reading: per-row activation scale for FP8 is the power of two
+ * s = 2^k with the smallest k such that amax <= 448 * 2^k (s = 1 if amax is
+ * zero). Dividing by a power of two is exact, so the quantised code depends
+ * only on the activation value, not on the precision the scale is taken in. */
+double orc_fp8_pow2_scale(double amax)
+{
+    if (!(amax > 0.0)) return 1.0;
+    int k;
+    frexp(amax / 448.0, &k);        /* first guess */
+    while (amax > ldexp(448.0, k)) ++k;
+    while (amax <= ldexp(448.0, k - 1)) --k;
+    return ldexp(1.0, k);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Policy MLP (App. B: agents sample actions from deep policy models held    */
+/* in global memory; Sec. 3: actor-critic, so a value estimate is needed).   */
+/* Reading: two tanh hidden layers and one linear head whose last row is the */
+/* value V(s); the first rows are logits (discrete) or means (continuous).   */
+/* ------------------------------------------------------------------------ */
+
+enum { ORC_F32 = 0, ORC_BF16 = 1, ORC_FP8 = 2 };
+
+typedef struct {
+    int32_t dtype;     /* quantisation of layer inputs: F32 none, BF16, FP8   */
+    int32_t d_in, h1, h2, n_head;   /* n_head = number of outputs + 1 (value) */
+    const double* W1;  /* [h1][d_in]   exact (dequantised) weight values      */
+    const double* b1;  /* [h1]                                                */
+    const double* W2;  /* [h2][h1]                                            */
+    const double* b2;  /* [h2]                                                */
+    const double* W3;  /* [n_head][h2]                                        */
+    const double* b3;  /* [n_head]                                            */
+} orc_mlp;
+
+/* Quantisation point before every product. F32: none (exact FP64 reference).
+ * BF16: round each element. FP8: power-of-two row scale, round x/s, times s. */
+static void quantize_inputs(int dtype, const double* x, int n, double* xq)
+{
+    if (dtype == ORC_BF16) {
+        for (int k = 0; k < n; ++k) xq[k] = orc_round_bf16(x[k]);
+    } else if (dtype == ORC_FP8) {
+        double amax = 0.0;
+        for (int k = 0; k < n; ++k) if (fabs(x[k]) > amax) amax = fabs(x[k]);
+        double s = orc_fp8_pow2_scale(amax);
+        for (int k = 0; k < n; ++k) xq[k] = s * orc_round_fp8e4m3(x[k] / s);
+    } else {
+        for (int k = 0; k < n; ++k) xq[k] = x[k];
+    }
+}
+
+static void dense(const double* W, const double* b, int n_out, int n_in,
+                  const double* xq, double* y)
+{
+    for (int j = 0; j < n_out; ++j) {
+        double acc = 0.0;
+        for (int k = 0; k < n_in; ++k) acc += W[(size_t)j * n_in + k] * xq[k];
+        y[j] = acc + b[j];
+    }
+}
+
+/* head_out[n_head]: logits or means, then the value in the last slot.       */
+void orc_mlp_forward(const orc_mlp* p, const double* obs, double* head_out)
+{
+    int widest = p->d_in;
+    if (p->h1 > widest) widest = p->h1;
+    if (p->h2 > widest) widest = p->h2;
+    double* xq = (double*)malloc(sizeof(double) * widest);
+    double* h1 = (double*)malloc(sizeof(double) * p->h1);
+    double* h2 = (double*)malloc(sizeof(double) * p->h2);
+
+    quantize_inputs(p->dtype, obs, p->d_in, xq);
+    dense(p->W1, p->b1, p->h1, p->d_in, xq, h1);
+    for (int j = 0; j < p->h1; ++j) h1[j] = tanh(h1[j]);
+
+    quantize_inputs(p->dtype, h1, p->h1, xq);
+    dense(p->W2, p->b2, p->h2, p->h1, xq, h2);
+    for (int j = 0; j < p->h2; ++j) h2[j] = tanh(h2[j]);
+
+    quantize_inputs(p->dtype, h2, p->h2, xq);
+    dense(p->W3, p->b3, p->n_head, p->h2, xq, head_out);
+
+    free(xq); free(h1); free(h2);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Action sampling (App. B: every agent samples its own action).             */
+/* ------------------------------------------------------------------------ */
+
+/* Categorical by inverse CDF. Reading: p = softmax(logits) with the maximum
+ * subtracted, C_k = p_0 + ... + p_k, a = min{k : u < C_k} (strict), and
+ * a = K-1 if no C_k exceeds u. *margin = min over k < K-1 of |u - C_k|: the
+ * distance of the draw to the nearest decision boundary.                    */
+int orc_sample_categorical(const double* logits, int K, double u,
+                           double* logp, double* margin)
+{
+    double mx = logits[0];
+    for (int k = 1; k < K; ++k) if (logits[k] > mx) mx = logits[k];
+    double z = 0.0;
+    for (int k = 0; k < K; ++k) z += exp(logits[k] - mx);
+    int a = K - 1;
+    double cdf = 0.0, best = INFINITY;
+    int found = 0;
+    for (int k = 0; k < K; ++k) {
+        cdf += exp(logits[k] - mx) / z;
+        if (k < K - 1 && fabs(u - cdf) < best) best = fabs(u - cdf);
+        if (!found && u < cdf) { a = k; found = 1; }
+    }
+    *logp = (logits[a] - mx) - log(z);
+    *margin = best;
+    return a;
+}
+
+/* Diagonal Gaussian: a_j = mu_j + exp(log_std_j) * z_j and
+ * log p(a) = sum_j ( -z_j^2/2 - log_std_j - log(2 pi)/2 ).                  */
+void orc_sample_gaussian(const double* mu, const double* log_std, const double* z,
+                         int d, double* a, double* logp)
+{
+    double lp = 0.0;
+    for (int j = 0; j < d; ++j) {
+        a[j] = mu[j] + exp(log_std[j]) * z[j];
+        lp += -0.5 * z[j] * z[j] - log_std[j] - 0.5 * log(2.0 * ORC_PI);
+    }
+    *logp = lp;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Environments. App. C names CartPole and Acrobot from gym classic control, */
+/* a multi-agent economic simulation and a noisy >20-D potential energy walk.*/
+/* The gym source is not available here, so the classic-control equations    */
+/* are derived from Lagrangian mechanics and the constants are this          */
+/* project's (faithfulness to gym is not checked).                           */
+/* ------------------------------------------------------------------------ */
+
+enum { ORC_CARTPOLE = 1, ORC_PENDULUM = 2, ORC_ACROBOT = 3, ORC_MARKET = 4, ORC_REACTION = 5 };
+
+int orc_state_dim(int kind)
+{
+    switch (kind) {
+    case ORC_CARTPOLE: return 4;   /* x, x_dot, theta, theta_dot           */
+    case ORC_PENDULUM: return 2;   /* theta, theta_dot                     */
+    case ORC_ACROBOT:  return 4;   /* theta1, theta2, omega1, omega2       */
+    case ORC_MARKET:   return 32;  /* per-agent state                      */
+    case ORC_REACTION: return 21;  /* x[20], cached noisy energy           */
+    }
+    return -1;
+}
+
+int orc_obs_dim(int kind)
+{
+    switch (kind) {
+    case ORC_CARTPOLE: return 4;
+    case ORC_PENDULUM: return 3;   /* cos, sin, theta_dot                  */
+    case ORC_ACROBOT:  return 6;   /* cos1, sin1, cos2, sin2, w1, w2       */
+    case ORC_MARKET:   return 32;
+    case ORC_REACTION: return 20;
+    }
+    return -1;
+}
+
+/* Number of discrete actions, or 0 for a continuous (Gaussian) action.      */
+int orc_n_actions(int kind)
+{
+    switch (kind) {
+    case ORC_CARTPOLE: return 2;
+    case ORC_MARKET:   return 50;
+    case ORC_REACTION: return 40;
+    }
+    return 0;
+}
+
+/* --- CartPole: cart of mass M on a frictionless track, uniform pole of mass
+ * m and half-length l hinged on it, horizontal force F. theta = 0 is upright
+ * and positive when the pole leans towards +x. From the Lagrangian
+ * L = (M+m) xd^2/2 + m l cos(th) xd thd + (2/3) m l^2 thd^2 - m g l cos(th):
+ *   (M+m) xdd + m l cos(th) thdd - m l sin(th) thd^2 = F
+ *   cos(th) xdd + (4/3) l thdd = g sin(th)
+ * Constants (reading): the classic cart-pole benchmark values.             */
+#define CP_G 9.8
+#define CP_MCART 1.0
+#define CP_MPOLE 0.1
+#define CP_HALFLEN 0.5
+#define CP_FORCE 10.0
+#define CP_DT 0.02
+#define CP_X_LIMIT 2.4
+#define CP_TH_LIMIT (12.0 * 2.0 * ORC_PI / 360.0)
+
+void orc_cartpole_accel(const double* s, double force, double* xdd, double* thdd)
+{
+    double th = s[2], thd = s[3];
+    double total = CP_MCART + CP_MPOLE;
+    double c = cos(th), sn = sin(th);
+    double tmp = (force + CP_MPOLE * CP_HALFLEN * thd * thd * sn) / total;
+    double th_acc = (CP_G * sn - c * tmp) /
+                    (CP_HALFLEN * (4.0 / 3.0 - CP_MPOLE * c * c / total));
+    *thdd = th_acc;
+    *xdd = tmp - CP_MPOLE * CP_HALFLEN * th_acc * c / total;
+}
+
+/* Explicit Euler; the transition terminates when the new state leaves the
+ * track or the pole passes 12 degrees; reward 1 for every step taken.       */
+static void cartpole_step(const double* s, int action, double* s_next,
+                          double* reward, int* done, double* done_margin)
+{
+    double force = action == 1 ? CP_FORCE : -CP_FORCE;
+    double xdd, thdd;
+    orc_cartpole_accel(s, force, &xdd, &thdd);
+    s_next[0] = s[0] + CP_DT * s[1];
+    s_next[1] = s[1] + CP_DT * xdd;
+    s_next[2] = s[2] + CP_DT * s[3];
+    s_next[3] = s[3] + CP_DT * thdd;
+    *done = (fabs(s_next[0]) > CP_X_LIMIT) || (fabs(s_next[2]) > CP_TH_LIMIT);
+    double m1 = fabs(fabs(s_next[0]) - CP_X_LIMIT);
+    double m2 = fabs(fabs(s_next[2]) - CP_TH_LIMIT);
+    *done_margin = m1 < m2 ? m1 : m2;
+    *reward = 1.0;
+}
+
+/* --- Pendulum: uniform rod of mass m, length l, pivoted at one end, torque u
+ * at the pivot, theta = 0 upright: I thdd = m g (l/2) sin(th) + u with
+ * I = m l^2 / 3. Semi-implicit Euler, speed clipped, torque clipped.
+ * Cost (reading): wrap(th)^2 + 0.1 thd^2 + 0.001 u^2 on the pre-step state.  */
+#define PD_G 10.0
+#define PD_M 1.0
+#define PD_L 1.0
+#define PD_DT 0.05
+#define PD_MAX_SPEED 8.0
+#define PD_MAX_TORQUE 2.0
+
+static double clip(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+/* Angle wrapped to [-pi, pi).                                               */
+double orc_wrap_angle(double th)
+{
+    return th - 2.0 * ORC_PI * floor((th + ORC_PI) / (2.0 * ORC_PI));
+}
+
+double orc_pendulum_accel(double th, double u)
+{
+    return 3.0 * PD_G / (2.0 * PD_L) * sin(th) + 3.0 / (PD_M * PD_L * PD_L) * u;
+}
+
+static void pendulum_step(const double* s, double u_raw, double* s_next,
+                          double* reward, int* done, double* done_margin)
+{
+    double u = clip(u_raw, -PD_MAX_TORQUE, PD_MAX_TORQUE);
+    double th = s[0], thd = s[1];
+    double wth = orc_wrap_angle(th);
+    double cost = wth * wth + 0.1 * thd * thd + 0.001 * u * u;
+    double thd_new = clip(thd + orc_pendulum_accel(th, u) * PD_DT, -PD_MAX_SPEED, PD_MAX_SPEED);
+    s_next[0] = th + thd_new * PD_DT;
+    s_next[1] = thd_new;
+    *reward = -cost;
+    *done = 0;
+    *done_margin = INFINITY;
+}
+
+/* --- Acrobot: two rigid links in a vertical plane, the first pinned at a
+ * fixed base, torque tau at the elbow only; theta1 from hanging down,
+ * theta2 relative to link 1. Manipulator equations from the Lagrangian
+ * (Spong, "The swing up control problem for the Acrobot", 1995):
+ *   d11 w1' + d12 w2' + h1 + phi1 = 0,   d12 w1' + d22 w2' + h2 + phi2 = tau.
+ * RK4 over one step with tau held, then angles wrapped and rates clipped.
+ * Terminal when the tip rises above the base by more than one link length.
+ * Continuous torque in [-1, 1] (reading of the continuous-action config).   */
+#define AC_L1 1.0
+#define AC_LC1 0.5
+#define AC_LC2 0.5
+#define AC_M1 1.0
+#define AC_M2 1.0
+#define AC_I1 1.0
+#define AC_I2 1.0
+#define AC_G 9.8
+#define AC_DT 0.2
+#define AC_MAX_W1 (4.0 * ORC_PI)
+#define AC_MAX_W2 (9.0 * ORC_PI)
+#define AC_MAX_TORQUE 1.0
+
+void orc_acrobot_deriv(const double* s, double tau, double* ds)
+{
+    double th1 = s[0], th2 = s[1], w1 = s[2], w2 = s[3];
+    double d11 = AC_M1 * AC_LC1 * AC_LC1
+               + AC_M2 * (AC_L1 * AC_L1 + AC_LC2 * AC_LC2 + 2.0 * AC_L1 * AC_LC2 * cos(th2))
+               + AC_I1 + AC_I2;
+    double d12 = AC_M2 * (AC_LC2 * AC_LC2 + AC_L1 * AC_LC2 * cos(th2)) + AC_I2;
+    double d22 = AC_M2 * AC_LC2 * AC_LC2 + AC_I2;
+    double h1 = -AC_M2 * AC_L1 * AC_LC2 * sin(th2) * (w2 * w2 + 2.0 * w1 * w2);
+    double h2 = AC_M2 * AC_L1 * AC_LC2 * sin(th2) * w1 * w1;
+    double phi2 = AC_M2 * AC_LC2 * AC_G * sin(th1 + th2);
+    double phi1 = (AC_M1 * AC_LC1 + AC_M2 * AC_L1) * AC_G * sin(th1) + phi2;
+    double w2dot = (tau + d12 / d11 * (h1 + phi1) - h2 - phi2) / (d22 - d12 * d12 / d11);
+    double w1dot = -(d12 * w2dot + h1 + phi1) / d11;
+    ds[0] = w1;
+    ds[1] = w2;
+    ds[2] = w1dot;
+    ds[3] = w2dot;
+}
+
+/* Classical fourth-order Runge-Kutta over one interval with tau held.       */
+static void rk4_acrobot(const double* s, double tau, double dt, double* out)
+{
+    double k1[4], k2[4], k3[4], k4[4], tmp[4];
+    orc_acrobot_deriv(s, tau, k1);
+    for (int i = 0; i < 4; ++i) tmp[i] = s[i] + 0.5 * dt * k1[i];
+    orc_acrobot_deriv(tmp, tau, k2);
+    for (int i = 0; i < 4; ++i) tmp[i] = s[i] + 0.5 * dt * k2[i];
+    orc_acrobot_deriv(tmp, tau, k3);
+    for (int i = 0; i < 4; ++i) tmp[i] = s[i] + dt * k3[i];
+    orc_acrobot_deriv(tmp, tau, k4);
+    for (int i = 0; i < 4; ++i)
+        out[i] = s[i] + dt / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+}
+
+static void acrobot_step(const double* s, double tau_raw, double* s_next,
+                         double* reward, int* done, double* done_margin)
+{
+    double tau = clip(tau_raw, -AC_MAX_TORQUE, AC_MAX_TORQUE);
+    double ns[4];
+    rk4_acrobot(s, tau, AC_DT, ns);
+    s_next[0] = orc_wrap_angle(ns[0]);
+    s_next[1] = orc_wrap_angle(ns[1]);
+    s_next[2] = clip(ns[2], -AC_MAX_W1, AC_MAX_W1);
+    s_next[3] = clip(ns[3], -AC_MAX_W2, AC_MAX_W2);
+    double height = -cos(s_next[0]) - cos(s_next[0] + s_next[1]);
+    *done = height > 1.0;
+    *done_margin = fabs(height - 1.0);
+    *reward = *done ? 0.0 : -1.0;
+}
+
+/* --- Market (multi-agent economics stand-in). Reading of the config text:
+ * action a in [0,50) decodes to labour l = (a mod 10)/9 and trade
+ * tau = (floor(a/10) - 2)/2 in {-1,-1/2,0,1/2,1}; demand D = sum max(tau,0),
+ * supply S = sum (l + max(-tau,0)) over the environment's agents; price
+ * p = (D + eps)/(S + eps); consumption c = max(0, l - max(-tau,0) + max(tau,0)/p);
+ * reward log(1+c) - 0.1 l^2. Agent state update below. Never terminates.    */
+#define MK_EPS 1e-3
+
+void orc_market_decode(int a, double* labour, double* trade)
+{
+    *labour = (double)(a % 10) / 9.0;
+    *trade = ((double)(a / 10) - 2.0) / 2.0;
+}
+
+/* One environment of n agents: states [n][32], actions [n] -> next states,
+ * rewards. Also returns the price.                                          */
+double orc_market_step(int n, const double* states, const int* actions,
+                       double* next_states, double* rewards)
+{
+    double demand = 0.0, supply = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double l, tr;
+        orc_market_decode(actions[i], &l, &tr);
+        demand += tr > 0.0 ? tr : 0.0;
+        supply += l + (tr < 0.0 ? -tr : 0.0);
+    }
+    double price = (demand + MK_EPS) / (supply + MK_EPS);
+    for (int i = 0; i < n; ++i) {
+        double l, tr;
+        orc_market_decode(actions[i], &l, &tr);
+        double sold = tr < 0.0 ? -tr : 0.0;
+        double bought = tr > 0.0 ? tr : 0.0;
+        double cons = l - sold + bought / price;
+        if (cons < 0.0) cons = 0.0;
+        rewards[i] = log(1.0 + cons) - 0.1 * l * l;
+        const double* s = states + (size_t)i * 32;
+        double* o = next_states + (size_t)i * 32;
+        o[0] = 0.9 * s[0] + 0.1 * (cons - 0.5);
+        o[1] = log(price);
+        o[2] = l;
+        o[3] = tr;
+        o[4] = cons;
+        for (int k = 5; k < 32; ++k) o[k] = 0.99 * s[k];
+    }
+    return price;
+}
+
+/* --- Reaction-path walk on a noisy 20-D potential (stand-in for the
+ * catalytic study). E(x) = x^T A x / 2 + sum_k a_k exp(-|x - c_k|^2 / (2 w_k^2)).
+ * Parameter block (read as data, shared by every replica, App. B):
+ * A [20][20], centres [64][20], widths [64], amplitudes [64].               */
+#define RX_DIM 20
+#define RX_NG 64
+#define RX_STEP 0.05
+#define RX_NOISE 0.05
+
+double orc_reaction_energy(const double* params, const double* x)
+{
+    const double* A = params;
+    const double* cen = params + RX_DIM * RX_DIM;
+    const double* wid = cen + RX_NG * RX_DIM;
+    const double* amp = wid + RX_NG;
+    double quad = 0.0;
+    for (int i = 0; i < RX_DIM; ++i)
+        for (int j = 0; j < RX_DIM; ++j)
+            quad += x[i] * A[i * RX_DIM + j] * x[j];
+    double e = 0.5 * quad;
+    for (int k = 0; k < RX_NG; ++k) {
+        double d2 = 0.0;
+        for (int i = 0; i < RX_DIM; ++i) {
+            double d = x[i] - cen[k * RX_DIM + i];
+            d2 += d * d;
+        }
+        e += amp[k] * exp(-d2 / (2.0 * wid[k] * wid[k]));
+    }
+    return e;
+}
+
+/* Noisy energy of the state reached at step t: E(x) + 0.05 * xi with xi the
+ * cos-branch normal of the ENV_NOISE block (t, row).                        */
+static double reaction_noisy_energy(const double* params, const double* x, uint64_t seed,
+                                    uint32_t t, uint32_t row, uint32_t epoch)
+{
+    uint32_t w[4];
+    orc_draw(seed, t, row, ORC_ENV_NOISE, 0, epoch, w);
+    double z0, z1;
+    orc_box_muller(orc_u01(w[0]), orc_u01(w[1]), &z0, &z1);
+    return orc_reaction_energy(params, x) + RX_NOISE * z0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Reset (App. B: reset runs on the device). Reading: the state of row r    */
+/* reset at step t draws from the RESET stream at (t, r, sub, epoch).        */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t kind;
+    int32_t n_envs;
+    const int32_t* agent_offsets;  /* market: [n_envs+1] CSR offsets, else NULL */
+    const double* params;          /* reaction: potential block, else NULL      */
+} orc_env;
+
+int64_t orc_n_rows(const orc_env* env)
+{
+    return env->kind == ORC_MARKET ? env->agent_offsets[env->n_envs] : env->n_envs;
+}
+
+void orc_reset_row(const orc_env* env, uint64_t seed, uint32_t epoch, uint32_t t,
+                   uint32_t row, double* s)
+{
+    uint32_t w[4];
+    switch (env->kind) {
+    case ORC_CARTPOLE:
+        orc_draw(seed, t, row, ORC_RESET, 0, epoch, w);
+        for (int i = 0; i < 4; ++i) s[i] = -0.05 + 0.1 * orc_u01(w[i]);
+        break;
+    case ORC_PENDULUM:
+        orc_draw(seed, t, row, ORC_RESET, 0, epoch, w);
+        s[0] = -ORC_PI + 2.0 * ORC_PI * orc_u01(w[0]);
+        s[1] = -1.0 + 2.0 * orc_u01(w[1]);
+        break;
+    case ORC_ACROBOT:
+        orc_draw(seed, t, row, ORC_RESET, 0, epoch, w);
+        for (int i = 0; i < 4; ++i) s[i] = -0.1 + 0.2 * orc_u01(w[i]);
+        break;
+    case ORC_MARKET:
+        for (uint32_t sub = 0; sub < 8; ++sub) {
+            orc_draw(seed, t, row, ORC_RESET, sub, epoch, w);
+            orc_box_muller(orc_u01(w[0]), orc_u01(w[1]), &s[4 * sub + 0], &s[4 * sub + 1]);
+            orc_box_muller(orc_u01(w[2]), orc_u01(w[3]), &s[4 * sub + 2], &s[4 * sub + 3]);
+        }
+        break;
+    case ORC_REACTION:
+        for (uint32_t sub = 0; sub < 5; ++sub) {
+            orc_draw(seed, t, row, ORC_RESET, sub, epoch, w);
+            for (int i = 0; i < 4; ++i) s[4 * sub + i] = -3.0 + 6.0 * orc_u01(w[i]);
+        }
+        s[20] = reaction_noisy_energy(env->params, s, seed, t, row, epoch);
+        break;
+    }
+}
+
+void orc_env_reset(const orc_env* env, uint64_t seed, uint32_t epoch, uint32_t t,
+                   double* states /* [rows][state_dim] */)
+{
+    int64_t rows = orc_n_rows(env);
+    int sd = orc_state_dim(env->kind);
+    #pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < rows; ++r)
+        orc_reset_row(env, seed, epoch, t, (uint32_t)r, states + r * sd);
+}
+
+void orc_observe(int kind, const double* s, double* obs)
+{
+    switch (kind) {
+    case ORC_CARTPOLE:
+        for (int i = 0; i < 4; ++i) obs[i] = s[i];
+        break;
+    case ORC_PENDULUM:
+        obs[0] = cos(s[0]); obs[1] = sin(s[0]); obs[2] = s[1];
+        break;
+    case ORC_ACROBOT:
+        obs[0] = cos(s[0]); obs[1] = sin(s[0]);
+        obs[2] = cos(s[1]); obs[3] = sin(s[1]);
+        obs[4] = s[2]; obs[5] = s[3];
+        break;
+    case ORC_MARKET:
+        for (int i = 0; i < 32; ++i) obs[i] = s[i];
+        break;
+    case ORC_REACTION:
+        for (int i = 0; i < 20; ++i) obs[i] = s[i];
+        break;
+    }
+}
+
+/* One transition of a single-agent row (CartPole, Pendulum, Acrobot,
+ * Reaction) taken at step t, without the auto-reset: next state, reward,
+ * done flag and distance to the termination threshold. Returns -1 for the
+ * market, whose transition couples all agents of an environment.           */
+int orc_env_step_row(const orc_env* env, uint64_t seed, uint32_t epoch, uint32_t t,
+                     uint32_t row, const double* s, double action, double* s_next,
+                     double* reward, int* done, double* done_margin)
+{
+    *done = 0;
+    *done_margin = INFINITY;
+    switch (env->kind) {
+    case ORC_CARTPOLE:
+        cartpole_step(s, (int)action, s_next, reward, done, done_margin);
+        return 0;
+    case ORC_PENDULUM:
+        pendulum_step(s, action, s_next, reward, done, done_margin);
+        return 0;
+    case ORC_ACROBOT:
+        acrobot_step(s, action, s_next, reward, done, done_margin);
+        return 0;
+    case ORC_REACTION: {
+        /* action a moves coordinate a/2 by +0.05 (a even) or -0.05 (a odd);
+         * reward = -(noisy energy after - cached noisy energy before).     */
+        int a = (int)action;
+        int coord = a / 2;
+        double sign = (a % 2 == 0) ? 1.0 : -1.0;
+        for (int i = 0; i < RX_DIM; ++i) s_next[i] = s[i];
+        s_next[coord] += sign * RX_STEP;
+        s_next[RX_DIM] = reaction_noisy_energy(env->params, s_next, seed, t + 1, row, epoch);
+        *reward = -(s_next[RX_DIM] - s[RX_DIM]);
+        return 0;
+    }
+    }
+    return -1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Free-running roll-out (App. B: every replica steps in place, samples its  */
+/* actions and stores its roll-out data for training).                       */
+/* Per step t of row r: record obs_t and V(s_t); draw the action from the    */
+/* ACTION block (t, r); record a_t, log p(a_t); step the env; record r_t and */
+/* done_t; if done_t the row restarts from the RESET draw at t+1 (auto-      */
+/* reset). After the last step record V(s_T). done_t marks the transition.  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double* obs;          /* [T][rows][obs_dim]                              */
+    double* action;       /* [T][rows]  (index for discrete, value otherwise)*/
+    double* reward;       /* [T][rows]                                       */
+    uint8_t* done;        /* [T][rows]                                       */
+    double* value;        /* [T][rows]                                       */
+    double* logp;         /* [T][rows]                                       */
+    double* last_value;   /* [rows]                                          */
+    double* margin_action;/* [T][rows] distance to a CDF boundary, or NULL   */
+    double* margin_done;  /* [T][rows] distance to a termination threshold   */
+} orc_traj;
+
+int orc_rollout(const orc_env* env, const orc_mlp* pol, const double* log_std,
+                uint64_t seed, uint32_t epoch, uint32_t t0, int32_t T,
+                double* states /* [rows][state_dim], in/out */, const orc_traj* tr)
+{
+    const int kind = env->kind;
+    const int sd = orc_state_dim(kind), od = orc_obs_dim(kind);
+    const int n_act = orc_n_actions(kind);
+    const int64_t rows = orc_n_rows(env);
+    if (pol->d_in != od) return -1;
+    if (pol->n_head != (n_act ? n_act : 1) + 1) return -2;
+
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t e = 0; e < env->n_envs; ++e) {
+        int64_t r0 = kind == ORC_MARKET ? env->agent_offsets[e] : e;
+        int64_t r1 = kind == ORC_MARKET ? env->agent_offsets[e + 1] : e + 1;
+        int64_t n = r1 - r0;
+        double* obs = (double*)malloc(sizeof(double) * od);
+        double* head = (double*)malloc(sizeof(double) * pol->n_head);
+        double* next = (double*)malloc(sizeof(double) * sd * n);
+        double* rew = (double*)malloc(sizeof(double) * n);
+        int* acts = (int*)malloc(sizeof(int) * n);
+        double* cont = (double*)malloc(sizeof(double) * n);
+
+        for (int32_t step = 0; step < T; ++step) {
+            uint32_t t = t0 + (uint32_t)step;
+            size_t base = (size_t)step * rows;
+            /* observe, evaluate the policy, sample */
+            for (int64_t r = r0; r < r1; ++r) {
+                double* s = states + r * sd;
+                orc_observe(kind, s, obs);
+                if (tr->obs)
+                    for (int i = 0; i < od; ++i) tr->obs[(base + r) * od + i] = obs[i];
+                orc_mlp_forward(pol, obs, head);
+                tr->value[base + r] = head[pol->n_head - 1];
+                uint32_t w[4];
+                orc_draw(seed, t, (uint32_t)r, ORC_ACTION, 0, epoch, w);
+                if (n_act) {
+                    double lp, mg;
+                    int a = orc_sample_categorical(head, n_act, orc_u01(w[0]), &lp, &mg);
+                    acts[r - r0] = a;
+                    tr->action[base + r] = a;
+                    tr->logp[base + r] = lp;
+                    if (tr->margin_action) tr->margin_action[base + r] = mg;
+                } else {
+                    double z0, z1, a, lp;
+                    orc_box_muller(orc_u01(w[0]), orc_u01(w[1]), &z0, &z1);
+                    orc_sample_gaussian(head, log_std, &z0, 1, &a, &lp);
+                    cont[r - r0] = a;
+                    tr->action[base + r] = a;
+                    tr->logp[base + r] = lp;
+                    if (tr->margin_action) tr->margin_action[base + r] = INFINITY;
+                }
+            }
+            /* step the environment */
+            if (kind == ORC_MARKET) {
+                orc_market_step((int)n, states + r0 * sd, acts, next, rew);
+                for (int64_t r = r0; r < r1; ++r) {
+                    for (int i = 0; i < sd; ++i) states[r * sd + i] = next[(r - r0) * sd + i];
+                    tr->reward[base + r] = rew[r - r0];
+                    tr->done[base + r] = 0;
+                    if (tr->margin_done) tr->margin_done[base + r] = INFINITY;
+                }
+            } else {
+                int64_t r = r0;
+                double* s = states + r * sd;
+                double reward = 0.0, dmargin = INFINITY;
+                int done = 0;
+                double a = n_act ? (double)acts[0] : cont[0];
+                orc_env_step_row(env, seed, epoch, t, (uint32_t)r, s, a, next, &reward,
+                                 &done, &dmargin);
+                tr->reward[base + r] = reward;
+                tr->done[base + r] = (uint8_t)done;
+                if (tr->margin_done) tr->margin_done[base + r] = dmargin;
+                if (done) orc_reset_row(env, seed, epoch, t + 1, (uint32_t)r, s);
+                else for (int i = 0; i < sd; ++i) s[i] = next[i];
+            }
+        }
+        /* bootstrap value of the state reached after the last step */
+        for (int64_t r = r0; r < r1; ++r) {
+            orc_observe(kind, states + r * sd, obs);
+            orc_mlp_forward(pol, obs, head);
+            tr->last_value[r] = head[pol->n_head - 1];
+        }
+        free(obs); free(head); free(next); free(rew); free(acts); free(cont);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Discounted returns and GAE (Sec. 3: actor-critic; generalized advantage   */
+/* estimation, Schulman et al. 2016). done_t cuts the tail at t. With        */
+/* bootstrapping the value after the last step is last_value, else 0.        */
+/*   delta_t = r_t + g (1-d_t) V_{t+1} - V_t                                 */
+/*   A_t = delta_t + g l (1-d_t) A_{t+1},   G_t = r_t + g (1-d_t) G_{t+1}    */
+/* ------------------------------------------------------------------------ */
+
+void orc_returns_gae(int32_t T, int64_t rows, const double* reward, const double* value,
+                     const uint8_t* done, const double* last_value, double gamma,
+                     double lambda, int32_t bootstrap, double* ret, double* adv)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < rows; ++r) {
+        double v_next = bootstrap ? last_value[r] : 0.0;
+        double g_next = v_next;
+        double a_next = 0.0;
+        for (int32_t t = T - 1; t >= 0; --t) {
+            size_t i = (size_t)t * rows + r;
+            double keep = done[i] ? 0.0 : 1.0;
+            double delta = reward[i] + gamma * keep * v_next - value[i];
+            double a = delta + gamma * lambda * keep * a_next;
+            double g = reward[i] + gamma * keep * g_next;
+            adv[i] = a;
+            ret[i] = g;
+            a_next = a;
+            g_next = g;
+            v_next = value[i];
+        }
+    }
+}
+
+/* The same quantities as explicit finite sums over the future (O(T^2)), for
+ * pinning the recursion on tiny horizons:
+ *   A_t = sum_{l>=0} [prod_{j<l} g l (1-d_{t+j})] delta_{t+l}
+ *   G_t = sum_{l>=0} [prod_{j<l} g (1-d_{t+j})] r_{t+l} + [prod_{j<T-t} g (1-d_{t+j})] V_T */
+void orc_gae_bruteforce(int32_t T, int64_t rows, const double* reward, const double* value,
+                        const uint8_t* done, const double* last_value, double gamma,
+                        double lambda, int32_t bootstrap, double* ret, double* adv)
+{
+    for (int64_t r = 0; r < rows; ++r) {
+        double vT = bootstrap ? last_value[r] : 0.0;
+        for (int32_t t = 0; t < T; ++t) {
+            double a = 0.0, g = 0.0;
+            for (int32_t l = 0; t + l < T; ++l) {
+                double wa = 1.0, wg = 1.0;
+                for (int32_t j = 0; j < l; ++j) {
+                    double keep = done[(size_t)(t + j) * rows + r] ? 0.0 : 1.0;
+                    wa *= gamma * lambda * keep;
+                    wg *= gamma * keep;
+                }
+                size_t i = (size_t)(t + l) * rows + r;
+                double keep_l = done[i] ? 0.0 : 1.0;
+                double v_next = (t + l + 1 < T) ? value[(size_t)(t + l + 1) * rows + r] : vT;
+                double delta = reward[i] + gamma * keep_l * v_next - value[i];
+                a += wa * delta;
+                g += wg * reward[i];
+            }
+            double wtail = 1.0;
+            for (int32_t j = 0; t + j < T; ++j)
+                wtail *= gamma * (done[(size_t)(t + j) * rows + r] ? 0.0 : 1.0);
+            g += wtail * vT;
+            adv[(size_t)t * rows + r] = a;
+            ret[(size_t)t * rows + r] = g;
+        }
+    }
+}
+
+/* Threads the OpenMP loops over environments use (1 without OpenMP).        */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
