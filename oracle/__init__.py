@@ -57,7 +57,8 @@ class _Mlp(C.Structure):
     _fields_ = [("dtype", C.c_int32), ("d_in", C.c_int32), ("h1", C.c_int32),
                 ("h2", C.c_int32), ("n_head", C.c_int32),
                 ("W1", C.c_void_p), ("b1", C.c_void_p), ("W2", C.c_void_p),
-                ("b2", C.c_void_p), ("W3", C.c_void_p), ("b3", C.c_void_p)]
+                ("b2", C.c_void_p), ("W3", C.c_void_p), ("b3", C.c_void_p),
+                ("act_scale", C.c_double * 3)]
 
 
 class _Env(C.Structure):
@@ -81,8 +82,7 @@ def _declare(L):
     L.orc_u01.argtypes = [C.c_uint32]
     L.orc_u01.restype = C.c_double
     L.orc_box_muller.argtypes = [C.c_double, C.c_double, dp, dp]
-    for name in ("orc_round_bf16", "orc_round_fp8e4m3", "orc_fp8_pow2_scale",
-                 "orc_wrap_angle"):
+    for name in ("orc_round_bf16", "orc_round_fp8e4m3", "orc_wrap_angle"):
         getattr(L, name).argtypes = [C.c_double]
         getattr(L, name).restype = C.c_double
     L.orc_mlp_forward.argtypes = [C.POINTER(_Mlp), dp, dp]
@@ -166,10 +166,6 @@ def round_fp8(x):
     return np.array([f(float(v)) for v in np.ravel(x)]).reshape(np.shape(x))
 
 
-def fp8_scale(amax):
-    return lib().orc_fp8_pow2_scale(float(amax))
-
-
 def wrap_angle(th):
     return lib().orc_wrap_angle(float(th))
 
@@ -179,19 +175,20 @@ def wrap_angle(th):
 class _MlpHold:
     """Keeps the numpy buffers alive while the C struct points at them."""
 
-    def __init__(self, dtype, W1, b1, W2, b2, W3, b3):
+    def __init__(self, dtype, W1, b1, W2, b2, W3, b3, act_scale=(1.0, 1.0, 1.0)):
         self.arrs = [_f64(a) for a in (W1, b1, W2, b2, W3, b3)]
         W1, b1, W2, b2, W3, b3 = self.arrs
         self.s = _Mlp(DTYPE_CODE[dtype] if isinstance(dtype, str) else dtype,
                       W1.shape[1], W1.shape[0], W2.shape[0], W3.shape[0],
-                      *[a.ctypes.data for a in self.arrs])
+                      *[a.ctypes.data for a in self.arrs],
+                      (C.c_double * 3)(*[float(v) for v in act_scale]))
 
 
 def mlp_hold(policy):
     """Build the C view of a policy from its exact (dequantised) weights."""
     return _MlpHold(policy.dtype, policy.exact("w1"), policy.exact("b1"),
                     policy.exact("w2"), policy.exact("b2"), policy.exact("w3"),
-                    policy.exact("b3"))
+                    policy.exact("b3"), policy.act_scale)
 
 
 def mlp_forward(policy, obs):

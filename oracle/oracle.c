@@ -132,20 +132,6 @@ double orc_round_fp8e4m3(double x)
     return r;
 }
 
-/* Reading: per-row activation scale for FP8 is the power of two
- * s = 2^k with the smallest k such that amax <= 448 * 2^k (s = 1 if amax is
- * zero). Dividing by a power of two is exact, so the quantised code depends
- * only on the activation value, not on the precision the scale is taken in. */
-double orc_fp8_pow2_scale(double amax)
-{
-    if (!(amax > 0.0)) return 1.0;
-    int k;
-    frexp(amax / 448.0, &k);        /* first guess */
-    while (amax > ldexp(448.0, k)) ++k;
-    while (amax <= ldexp(448.0, k - 1)) --k;
-    return ldexp(1.0, k);
-}
-
 /* ------------------------------------------------------------------------ */
 /* Policy MLP (App. B: agents sample actions from deep policy models held    */
 /* in global memory; Sec. 3: actor-critic, so a value estimate is needed).   */
@@ -164,19 +150,19 @@ typedef struct {
     const double* b2;  /* [h2]                                                */
     const double* W3;  /* [n_head][h2]                                        */
     const double* b3;  /* [n_head]                                            */
+    double act_scale[3];  /* FP8: power-of-two scale of each layer's input    */
 } orc_mlp;
 
 /* Quantisation point before every product. F32: none (exact FP64 reference).
- * BF16: round each element. FP8: power-of-two row scale, round x/s, times s. */
-static void quantize_inputs(int dtype, const double* x, int n, double* xq)
+ * BF16: round each element. FP8 (reading): the layer's input x is divided by
+ * the layer's power-of-two scale s (exact), rounded to E4M3 with saturation
+ * and multiplied back, x_q = s * fp8(x / s).                                 */
+static void quantize_inputs(int dtype, double scale, const double* x, int n, double* xq)
 {
     if (dtype == ORC_BF16) {
         for (int k = 0; k < n; ++k) xq[k] = orc_round_bf16(x[k]);
     } else if (dtype == ORC_FP8) {
-        double amax = 0.0;
-        for (int k = 0; k < n; ++k) if (fabs(x[k]) > amax) amax = fabs(x[k]);
-        double s = orc_fp8_pow2_scale(amax);
-        for (int k = 0; k < n; ++k) xq[k] = s * orc_round_fp8e4m3(x[k] / s);
+        for (int k = 0; k < n; ++k) xq[k] = scale * orc_round_fp8e4m3(x[k] / scale);
     } else {
         for (int k = 0; k < n; ++k) xq[k] = x[k];
     }
@@ -202,15 +188,15 @@ void orc_mlp_forward(const orc_mlp* p, const double* obs, double* head_out)
     double* h1 = (double*)malloc(sizeof(double) * p->h1);
     double* h2 = (double*)malloc(sizeof(double) * p->h2);
 
-    quantize_inputs(p->dtype, obs, p->d_in, xq);
+    quantize_inputs(p->dtype, p->act_scale[0], obs, p->d_in, xq);
     dense(p->W1, p->b1, p->h1, p->d_in, xq, h1);
     for (int j = 0; j < p->h1; ++j) h1[j] = tanh(h1[j]);
 
-    quantize_inputs(p->dtype, h1, p->h1, xq);
+    quantize_inputs(p->dtype, p->act_scale[1], h1, p->h1, xq);
     dense(p->W2, p->b2, p->h2, p->h1, xq, h2);
     for (int j = 0; j < p->h2; ++j) h2[j] = tanh(h2[j]);
 
-    quantize_inputs(p->dtype, h2, p->h2, xq);
+    quantize_inputs(p->dtype, p->act_scale[2], h2, p->h2, xq);
     dense(p->W3, p->b3, p->n_head, p->h2, xq, head_out);
 
     free(xq); free(h1); free(h2);

@@ -39,7 +39,8 @@ class Policy:
     n_out + 1 rows; the last row is the value head.
     dtype 'f32': w* float32. 'bf16': w* uint16 bit patterns.
     'fp8': w* uint8 OCP E4M3FN codes with per-output-row float32 scales s*
-    (powers of two), real weight = s[j] * fp8(code[j][k]).
+    (powers of two), real weight = s[j] * fp8(code[j][k]); act_scale holds
+    the power-of-two scale of each layer's input (observation, h1, h2).
     """
 
     dtype: str
@@ -57,6 +58,7 @@ class Policy:
     s2: np.ndarray
     s3: np.ndarray
     log_std: np.ndarray = field(default_factory=lambda: np.zeros(1, np.float32))
+    act_scale: tuple = (1.0, 1.0, 1.0)
 
     def exact(self, name: str) -> np.ndarray:
         """Exact real values (float64) of a weight, bias or scale array."""
@@ -103,8 +105,11 @@ def make_policy(d_in: int, h1: int, h2: int, n_out: int, dtype: str, seed: int =
     q1, s1 = _to_storage(w1, dtype)
     q2, s2 = _to_storage(w2, dtype)
     q3, s3 = _to_storage(w3, dtype)
+    # FP8 activation scales: observations up to 28 in magnitude, tanh outputs
+    # (|h| < 1) mapped below 256; BF16 and FP32 inputs are not scaled.
+    act_scale = (2.0 ** -4, 2.0 ** -8, 2.0 ** -8) if dtype == "fp8" else (1.0, 1.0, 1.0)
     return Policy(dtype, d_in, h1, h2, n_head, q1, q2, q3, b1, b2, b3, s1, s2, s3,
-                  np.full(max(n_out, 1), log_std_init, np.float32))
+                  np.full(max(n_out, 1), log_std_init, np.float32), act_scale)
 
 
 def policy_for(kind: int, dtype: str, h: int, seed: int = 0) -> Policy:

@@ -27,10 +27,13 @@ def _q_bf16(x):
     return x.to(torch.float32).to(torch.bfloat16).to(torch.float64)
 
 
-def _q_fp8(x):
-    amax = x.abs().amax(dim=1, keepdim=True).numpy()
-    s = torch.from_numpy(np.array([[O.fp8_scale(a)] for a in amax[:, 0]]))
-    return (x / s).to(torch.float32).to(torch.float8_e4m3fn).to(torch.float64) * s
+def _q_fp8(scales):
+    it = iter(scales)
+
+    def q(x):
+        s = next(it)
+        return (x / s).to(torch.float32).to(torch.float8_e4m3fn).to(torch.float64) * s
+    return q
 
 
 def test_mlp_f32_matches_torch_linear_chain():
@@ -59,7 +62,8 @@ def test_mlp_fp8_quantisation_points():
     obs = np.random.default_rng(2).uniform(-3, 3, size=(30, 20))
     obs = obs.astype(np.float32).astype(np.float64)
     got = O.mlp_forward(pol, obs)
-    want = _torch_forward(pol, obs, _q_fp8)
+    assert pol.act_scale == (2.0 ** -4, 2.0 ** -8, 2.0 ** -8)
+    want = _torch_forward(pol, obs, _q_fp8(pol.act_scale))
     assert np.allclose(got, want, rtol=0, atol=1e-12)
 
 
