@@ -1,0 +1,243 @@
+#!/usr/bin/env python3
+"""Roll-out throughput on one MI355X: fused vs per-step-launch forms.
+
+One step = the whole hot path over one batch: env_reset, rollout(horizon)
+and compute_returns for every environment set of the workload. The default
+workload is 10,000 Pendulum + 10,000 Acrobot replicas, horizon 200, BF16
+policies obs-256-256-(1+1), the two sets on two streams. Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "env-steps/s fused vs per-step-launch at tolerance; p50/p99 rollout latency"
+PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
+
+# name -> list of (config key in inputs.CONFIGS)
+WORKLOADS = {
+    "pendulum_acrobot_10k": ["pendulum_10k", "acrobot_10k"],
+    "cartpole_1k": ["cartpole_1k"],
+    "market_2k": ["market_2k"],
+    "reaction_4k": ["reaction_4k"],
+}
+
+
+def policy_flops(pol):
+    return 2 * (pol.d_in * pol.h1 + pol.h1 * pol.h2 + pol.h2 * pol.n_head)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2408_00930_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+class EnvSet:
+    def __init__(self, key, seed, tile_rows, wsx, inputs, torch):
+        cfg = inputs.CONFIGS[key]
+        self.key = key
+        self.kind = cfg["kind"]
+        self.T = cfg["horizon"]
+        self.n_envs = cfg["n_envs"]
+        self.policy = inputs.policy_for(self.kind, cfg["dtype"], cfg["hidden"], seed=seed)
+        self.dp = wsx.DevicePolicy(self.policy)
+        offsets = inputs.agent_offsets(self.n_envs, seed=seed) if self.kind == wsx.MARKET else None
+        params = inputs.reaction_params(seed) if self.kind == wsx.REACTION else None
+        self.env = wsx.Env(self.kind, self.n_envs, seed=seed, agent_offsets=offsets,
+                           params=params, tile_rows=tile_rows)
+        self.rows = self.env.rows
+        self.traj = wsx.Trajectory(self.kind, self.T, self.rows)
+        self.ret = torch.empty((self.T, self.rows), dtype=torch.float32, device="cuda")
+        self.adv = torch.empty_like(self.ret)
+        self.stream = torch.cuda.Stream()
+        self.flop_per_launch = policy_flops(self.policy) * self.rows * (self.T + 1)
+        self.k_start, self.k_end = [], []
+
+    def step(self, i, mode, wsx, torch, timed):
+        with torch.cuda.stream(self.stream):
+            wsx.env_reset(self.env, epoch=i)
+            if timed:
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(self.stream)
+            wsx.rollout(self.env, self.dp, self.T, self.traj, mode)
+            if timed:
+                b.record(self.stream)
+                self.k_start.append(a)
+                self.k_end.append(b)
+            wsx.compute_returns(self.traj, self.T, 0.99, 0.95, True, torch.float32,
+                                self.ret, self.adv)
+
+
+def run_form(sets, mode, steps, warmup, wsx, torch, first_epoch):
+    main = torch.cuda.current_stream()
+    for i in range(warmup):
+        for s in sets:
+            s.stream.wait_stream(main)
+            s.step(first_epoch + i, mode, wsx, torch, timed=False)
+        for s in sets:
+            main.wait_stream(s.stream)
+    for s in sets:
+        s.k_start, s.k_end = [], []
+    torch.cuda.synchronize()
+    step_ev = []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        a = torch.cuda.Event(enable_timing=True)
+        a.record(main)
+        for s in sets:
+            s.stream.wait_stream(main)
+            s.step(first_epoch + warmup + i, mode, wsx, torch, timed=True)
+        for s in sets:
+            main.wait_stream(s.stream)
+        b = torch.cuda.Event(enable_timing=True)
+        b.record(main)
+        step_ev.append((a, b))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    lat = sorted(a.elapsed_time(b) for a, b in step_ev)
+    kern = {s.key: [a.elapsed_time(b) for a, b in zip(s.k_start, s.k_end)] for s in sets}
+    return elapsed, lat, kern
+
+
+def percentile(sorted_vals, q):
+    if not sorted_vals:
+        return None
+    k = min(len(sorted_vals) - 1, max(0, int(round(q / 100.0 * (len(sorted_vals) - 1)))))
+    return sorted_vals[k]
+
+
+def cpu_baseline(sets, sample_envs):
+    """The FP64 oracle on a bounded sample of the same workload."""
+    import numpy as np
+
+    import oracle as O
+    from paper_2408_00930_amd import inputs
+    total_env_steps = 0
+    t0 = time.perf_counter()
+    for s in sets:
+        n = min(sample_envs, s.n_envs)
+        offsets = inputs.agent_offsets(s.n_envs, seed=0)[:n + 1] if s.kind == O.MARKET else None
+        params = inputs.reaction_params(0).astype(np.float64) if s.kind == O.REACTION else None
+        oenv = O.env_hold(s.kind, n, offsets, params)
+        st = O.env_reset(oenv, 0, 0)
+        out = O.rollout(oenv, O.mlp_hold(s.policy), 0, 0, 0, s.T, st,
+                        s.policy.exact("log_std"), margins=False)
+        O.returns_gae(out["reward"], out["value"], out["done"], out["last_value"], 0.99, 0.95)
+        total_env_steps += n * s.T
+    el = time.perf_counter() - t0
+    return {"value": total_env_steps / el, "unit": "env-steps/s", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"first {sample_envs} envs of each set over the full horizon "
+                      f"({total_env_steps} env-steps, {el:.1f} s), FP64 C oracle with "
+                      f"OpenMP over envs, returns/GAE included"}
+
+
+def traffic_for(kernel_name, launches_bytes_key):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    ent = data.get(kernel_name)
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent.get(launches_bytes_key)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--workload", default="pendulum_acrobot_10k", choices=sorted(WORKLOADS))
+    ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--cpu-sample-envs", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="fused,plain,graph")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(replicas shard by contiguous env ranges with no exchange; see the design "
+              "notes). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2408_00930_amd import inputs, wsx
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    wsx.lib()
+    sets = [EnvSet(k, 0, args.tile_rows, wsx, inputs, torch) for k in WORKLOADS[args.workload]]
+    env_steps = sum(s.n_envs * s.T for s in sets)
+    forms = args.forms.split(",")
+
+    result = {}
+    el, lat, kern = run_form(sets, wsx.MODE_FUSED, args.steps, args.warmup, wsx, torch, 0)
+    result["fused"] = (el, lat, kern)
+    print(f"[bench] fused: {args.steps} steps in {el:.3f} s", file=sys.stderr, flush=True)
+    for name, mode in (("plain", wsx.MODE_PLAIN), ("graph", wsx.MODE_GRAPH)):
+        if name in forms and args.plain_steps > 0:
+            r = run_form(sets, mode, args.plain_steps, 1, wsx, torch, 1000)
+            result[name] = r
+            print(f"[bench] {name}: {args.plain_steps} steps in {r[0]:.3f} s", file=sys.stderr,
+                  flush=True)
+
+    el, lat, kern = result["fused"]
+    value = env_steps * args.steps / el
+    # dominant kernel: the fused roll-out launch with the most total time
+    dom = max(sets, key=lambda s: sum(kern[s.key]))
+    avg_ms = sum(kern[dom.key]) / len(kern[dom.key])
+    dtype = dom.policy.dtype
+    achieved = dom.flop_per_launch / (avg_ms * 1e-3) / 1e12
+    kname = f"k_fused/{dom.key}"
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_TFLOPS[dtype],
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[dtype], 4),
+                "traffic": traffic_for(kname, "hbm_bytes_per_launch"),
+                "kernel": kname, "avg_launch_ms": round(avg_ms, 4),
+                "flop_per_launch": dom.flop_per_launch}
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "env-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(el / args.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16" if any(s.policy.dtype == "bf16" for s in sets) else dtype,
+        "data": "synthetic (seeded inputs; random-init policies)",
+        "config": {"workload": args.workload, "envs": sum(s.n_envs for s in sets),
+                   "rows": sum(s.rows for s in sets),
+                   "horizon": max(s.T for s in sets), "sets": [s.key for s in sets],
+                   "policy": {s.key: f"{s.policy.dtype} {s.policy.d_in}-{s.policy.h1}-"
+                                     f"{s.policy.h2}-{s.policy.n_head}" for s in sets},
+                   "returns": "FP64 scan, FP32 outputs", "streams": len(sets)},
+        "latency_ms": {"p50": round(percentile(lat, 50), 4), "p99": round(percentile(lat, 99), 4)},
+        "roofline": roofline,
+    }
+    for name in ("plain", "graph"):
+        if name in result:
+            pel, plat, _ = result[name]
+            pv = env_steps * args.plain_steps / pel
+            out[name] = {"value": round(pv, 1), "ms_per_step": round(pel / args.plain_steps * 1e3, 3),
+                         "latency_ms": {"p50": round(percentile(plat, 50), 3),
+                                        "p99": round(percentile(plat, 99), 3)}}
+            out[f"fused_speedup_vs_{name}"] = round(value / pv, 2)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sets, args.cpu_sample_envs)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,181 @@
+/*
+ * wsx.h -- C ABI of the GPU-resident roll-out library (libwsx.so, gfx950).
+ *
+ * The library runs the data-parallel hot path of a GPU-resident RL
+ * workflow (arXiv 2408.00930, Sec. 2 and App. B): every environment replica
+ * steps in place on the GPU, its agents sample actions from a policy model in
+ * device memory, and the roll-out data are written to device memory for
+ * training; discounted returns and GAE advantages (Sec. 3, actor-critic)
+ * follow on the device. No call on the hot path copies data between host and
+ * device.
+ *
+ * Conventions for every entry point:
+ *  - Device buffers are owned by the caller (e.g. torch tensors) and passed as
+ *    raw device pointers; the library never allocates device memory except
+ *    where an entry point says so. Host pointers are read during the call only.
+ *  - `stream` is a hipStream_t (NULL = the null stream). Work is enqueued
+ *    asynchronously on it; no entry point synchronises the device unless it
+ *    says so.
+ *  - Return value: WSX_OK (0) or a negative error code. All arguments are
+ *    validated on the host before anything is enqueued; on error nothing is
+ *    enqueued and wsx_last_error() describes the failure (thread-local string,
+ *    valid until the next call on that thread). No C++ exception crosses the
+ *    ABI.
+ *  - Layouts are row-major. "rows" are agents: one per environment for the
+ *    single-agent kinds, the sum of agent counts for the market.
+ */
+#ifndef WSX_H
+#define WSX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WSX_OK 0
+#define WSX_EINVAL (-1)        /* invalid argument                                */
+#define WSX_EUNSUPPORTED (-2)  /* valid but not supported (shape, dtype, kind)     */
+#define WSX_EHIP (-3)          /* the HIP runtime reported an error                */
+#define WSX_ESTATE (-4)        /* object used in a state that does not allow it    */
+
+/* Environment kinds (App. C example families; dynamics are the project's
+ * readings, see the design notes). */
+#define WSX_CARTPOLE 1   /* state 4, obs 4, 2 discrete actions                   */
+#define WSX_PENDULUM 2   /* state 2, obs 3, 1 continuous action (torque)         */
+#define WSX_ACROBOT 3    /* state 4, obs 6, 1 continuous action (elbow torque)   */
+#define WSX_MARKET 4     /* per agent: state 32, obs 32, 50 discrete actions      */
+#define WSX_REACTION 5   /* state 21 (x[20], cached noisy energy), obs 20, 40 actions */
+
+/* Element types. */
+#define WSX_F32 0
+#define WSX_BF16 1
+#define WSX_FP8_E4M3 2   /* OCP E4M3FN                                           */
+#define WSX_F64 3
+
+/* Roll-out execution modes. */
+#define WSX_MODE_FUSED 0   /* one persistent kernel for the whole horizon          */
+#define WSX_MODE_PLAIN 1   /* per step: policy, sample and step kernels           */
+#define WSX_MODE_GRAPH 2   /* the PLAIN launches captured once in a hipGraph and   */
+                           /* replayed                                            */
+
+typedef struct wsx_env wsx_env;   /* opaque host handle */
+
+/* Policy model (App. B: deep policy models held in device memory, referenced
+ * by every replica, never copied). Two tanh hidden layers and a linear head of
+ * n_head = n_out + 1 rows whose last row is the value V(s).
+ * Weights are [out][in] row-major in `dtype`: float for WSX_F32, bfloat16 bit
+ * patterns for WSX_BF16, E4M3FN codes for WSX_FP8_E4M3 with real weight
+ * s[out] * code. Biases are float. Products accumulate in FP32. */
+typedef struct {
+    int32_t dtype;           /* WSX_F32, WSX_BF16 or WSX_FP8_E4M3                 */
+    int32_t d_in, h1, h2;    /* d_in = obs dim of the env kind; h1 == h2          */
+    int32_t n_head;          /* outputs + 1 (value)                               */
+    const void* w1;          /* device [h1][d_in]                                 */
+    const void* w2;          /* device [h2][h1]                                   */
+    const void* w3;          /* device [n_head][h2]                               */
+    const float* b1;         /* device [h1]                                       */
+    const float* b2;         /* device [h2]                                       */
+    const float* b3;         /* device [n_head]                                   */
+    const float* s1;         /* FP8: device [h1] power-of-two row scales, else NULL */
+    const float* s2;         /* FP8: device [h2]                                  */
+    const float* s3;         /* FP8: device [n_head]                              */
+    float act_scale[3];      /* FP8: power-of-two scale of the obs, h1, h2 inputs */
+    const float* log_std;    /* continuous kinds: device [n_head - 1], else NULL  */
+} wsx_policy;
+
+/* Trajectory buffers (App. B: roll-out data stored in place for training).
+ * Slots [0, horizon) are written by wsx_rollout. Layout [T][rows] with
+ * consecutive rows adjacent (obs: [T][rows][obs_dim]). */
+typedef struct {
+    int32_t capacity;        /* number of T slots allocated                       */
+    float* obs;              /* observation before the step                       */
+    void* action;            /* uint8 [T][rows] (discrete) or float (continuous)  */
+    float* reward;
+    uint8_t* done;           /* 1 if the transition terminated (auto-reset next)  */
+    float* value;            /* V(s_t)                                            */
+    float* logp;             /* log-probability of the action taken               */
+    float* last_value;       /* [rows] V(s_T) of the state after the last step    */
+} wsx_traj;
+
+/* Size in bytes of the device state block an environment set needs
+ * (state, per-step scratch for the PLAIN mode, and for the market the CSR
+ * offsets and the tile table). n_rows: agents (market) or n_envs. */
+int wsx_env_state_bytes(int32_t kind, int64_t n_envs, int64_t n_rows, size_t* bytes);
+
+typedef struct {
+    int32_t kind;            /* WSX_CARTPOLE ... WSX_REACTION                     */
+    int32_t tile_rows;       /* rows per workgroup tile, 0 = the tuned default    */
+    int64_t n_envs;
+    uint64_t seed;           /* Philox key                                        */
+    void* state;             /* device, wsx_env_state_bytes bytes, caller-owned,  */
+                             /* must stay valid until wsx_env_destroy             */
+    const int32_t* agent_offsets; /* market: HOST [n_envs + 1] CSR offsets of the */
+                             /* agents (copied into `state` at create), else NULL */
+    const float* params;     /* reaction: DEVICE potential block (A[20][20],      */
+                             /* centres[64][20], widths[64], amplitudes[64]),     */
+                             /* referenced, not copied; else NULL                 */
+} wsx_env_desc;
+
+/* Creates the host handle of an environment set (App. B: each replica runs
+ * independently; the market's agents interact within their environment).
+ * For the market, uploads the offsets and the tile table synchronously on the
+ * null stream (the only host-to-device copy the library makes). The state is
+ * undefined until wsx_env_reset. */
+int wsx_env_create(const wsx_env_desc* desc, wsx_env** out);
+
+/* Resets every row (App. B: reset runs on the device): draws the initial
+ * state from the Philox RESET stream at step 0 of `epoch` and sets the step
+ * counter to 0. */
+int wsx_env_reset(wsx_env* env, uint32_t epoch, void* stream);
+
+/* Rolls every replica forward `horizon` steps (App. B; Sec. 2: no CPU-GPU
+ * transfer): per step observe, policy forward, sample, store the record,
+ * step the dynamics, auto-reset terminated rows; then V(s_T). The step
+ * counter advances by `horizon`, so consecutive calls continue the same
+ * random streams (rollout(a) then rollout(b) equals rollout(a + b)).
+ * traj->capacity must be >= horizon. */
+int wsx_rollout(wsx_env* env, const wsx_policy* policy, int32_t horizon,
+                const wsx_traj* traj, int32_t mode, void* stream);
+
+/* Number of rows, current step counter and epoch of an environment set. */
+int wsx_env_info(const wsx_env* env, int64_t* n_rows, uint32_t* step, uint32_t* epoch);
+
+/* Sets the step counter (resuming from a saved state block). */
+int wsx_env_set_step(wsx_env* env, uint32_t step);
+
+/* Releases the host handle (and cached graphs); the state block is the
+ * caller's. */
+int wsx_env_destroy(wsx_env* env);
+
+/* Discounted returns and GAE advantages (Sec. 3, actor-critic), FP64:
+ *   delta_t = r_t + gamma (1 - d_t) V_{t+1} - V_t
+ *   A_t = delta_t + gamma lambda (1 - d_t) A_{t+1}
+ *   G_t = r_t + gamma (1 - d_t) G_{t+1}
+ * with V_T = G_T = last_value[row] if bootstrap, else 0. Inputs are the
+ * trajectory fields ([T][rows]); outputs [T][rows] in WSX_F32 or WSX_F64. */
+int wsx_compute_returns(const float* reward, const float* value, const uint8_t* done,
+                        const float* last_value, int32_t horizon, int64_t rows,
+                        double gamma, double lambda, int32_t bootstrap,
+                        void* returns, void* advantages, int32_t out_dtype, void* stream);
+
+/* Policy forward alone (the inference step of App. B) for `rows`
+ * observations [rows][d_in] float: head outputs [rows][n_head] float. Uses
+ * the same device code and accumulation order as the roll-out kernels. */
+int wsx_policy_forward(const wsx_policy* policy, const float* obs, int64_t rows,
+                       float* head, void* stream);
+
+/* Rounds n floats to `dtype` (WSX_BF16: RNE; WSX_FP8_E4M3: s * fp8(x / s),
+ * RNE, saturating) with the device conversion the kernels use and returns
+ * the real values as float. */
+int wsx_quantize(int32_t dtype, float scale, const float* x, float* y, int64_t n, void* stream);
+
+/* Human-readable description of the last error on the calling thread. */
+const char* wsx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WSX_H */

@@ -1,0 +1,445 @@
+// abi.cpp -- the C ABI declared in include/wsx.h: argument validation, the
+// environment handle (state-block layout, market tile table, step counter),
+// variant selection and the launch of the roll-out, reset and returns
+// kernels. No C++ exception leaves this file.
+#include "../../include/wsx.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace wsx;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(WSX_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+struct KindInfo {
+    int sd, od, nact, dtype, hidden, tile_rows, waves;
+};
+
+// Shapes of each kind and the default tile (rows, waves) of its fused kernel.
+bool kind_info(int kind, KindInfo& k) {
+    switch (kind) {
+    case WSX_CARTPOLE: k = {4, 4, 2, WSX_F32, 64, 16, 4}; return true;
+    case WSX_PENDULUM: k = {2, 3, 0, WSX_BF16, 256, 80, 4}; return true;
+    case WSX_ACROBOT: k = {4, 6, 0, WSX_BF16, 256, 80, 4}; return true;
+    case WSX_MARKET: k = {32, 32, 50, WSX_BF16, 256, 128, 4}; return true;
+    case WSX_REACTION: k = {21, 20, 40, WSX_FP8_E4M3, 512, 16, 8}; return true;
+    }
+    return false;
+}
+
+int n_head_of(const KindInfo& k) { return (k.nact ? k.nact : 1) + 1; }
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Byte offsets of the parts of an environment set's device state block.
+struct Layout {
+    size_t state, obs, head, offsets, tiles, step, total;
+};
+
+Layout layout_of(const KindInfo& k, int64_t n_envs, int64_t n_rows, bool market) {
+    Layout L{};
+    size_t at = 0;
+    L.state = at;
+    at = align256(at + (size_t)k.sd * n_rows * 4);
+    L.obs = at;
+    at = align256(at + (size_t)k.od * n_rows * 4);
+    L.head = at;
+    at = align256(at + (size_t)n_head_of(k) * n_rows * 4);
+    L.offsets = at;
+    if (market) at = align256(at + (size_t)(n_envs + 1) * 4);
+    L.tiles = at;
+    if (market) at = align256(at + (size_t)n_envs * sizeof(Tile));
+    L.step = at;
+    at = align256(at + 4);
+    L.total = at;
+    return L;
+}
+
+bool find_variant(int kind, int dtype, int hidden, int waves, int tile_rows, Variant& out) {
+    for (int i = 0; i < n_variants(); ++i) {
+        const Variant& v = variant(i);
+        if (v.kind == kind && v.dtype == dtype && v.hidden == hidden && v.tile_rows == tile_rows &&
+            (waves == 0 || v.waves == waves)) {
+            out = v;
+            return true;
+        }
+    }
+    return false;
+}
+
+}  // namespace
+
+struct wsx_env {
+    int kind;
+    KindInfo info;
+    int64_t n_envs, n_rows;
+    uint64_t seed;
+    uint32_t step, epoch;
+    char* block;
+    const float* params;
+    Layout lay;
+    int n_tiles;
+    int tile_rows;
+    int device;
+    int cus;
+    // graph cache (PLAIN launches of one horizon)
+    hipGraphExec_t graph;
+    hipStream_t capture_stream;
+    std::vector<char> graph_key;
+};
+
+extern "C" {
+
+const char* wsx_last_error(void) { return g_last_error.c_str(); }
+
+int wsx_env_state_bytes(int32_t kind, int64_t n_envs, int64_t n_rows, size_t* bytes) {
+    KindInfo k;
+    if (!kind_info(kind, k)) return fail(WSX_EINVAL, "unknown environment kind %d", kind);
+    if (n_envs <= 0 || n_rows < n_envs) return fail(WSX_EINVAL, "need 0 < n_envs <= n_rows");
+    if (kind != WSX_MARKET && n_rows != n_envs)
+        return fail(WSX_EINVAL, "single-agent kinds have n_rows == n_envs");
+    if (n_rows > 0x7FFFFFFF) return fail(WSX_EUNSUPPORTED, "at most 2^31-1 rows");
+    if (!bytes) return fail(WSX_EINVAL, "bytes is NULL");
+    *bytes = layout_of(k, n_envs, n_rows, kind == WSX_MARKET).total;
+    return WSX_OK;
+}
+
+int wsx_env_create(const wsx_env_desc* d, wsx_env** out) {
+    if (!d || !out) return fail(WSX_EINVAL, "desc and out must not be NULL");
+    *out = nullptr;
+    KindInfo k;
+    if (!kind_info(d->kind, k)) return fail(WSX_EINVAL, "unknown environment kind %d", d->kind);
+    if (d->n_envs <= 0 || d->n_envs > 0x7FFFFFFF) return fail(WSX_EINVAL, "n_envs out of range");
+    if (!d->state) return fail(WSX_EINVAL, "state block is NULL");
+    const bool market = d->kind == WSX_MARKET;
+    if (market != (d->agent_offsets != nullptr))
+        return fail(WSX_EINVAL, "agent_offsets is required for the market and only for it");
+    if ((d->kind == WSX_REACTION) != (d->params != nullptr))
+        return fail(WSX_EINVAL, "params is required for the reaction walk and only for it");
+    const int tile_rows = d->tile_rows ? d->tile_rows : k.tile_rows;
+    Variant probe;
+    if (!find_variant(d->kind, k.dtype, k.hidden, 0, tile_rows, probe))
+        return fail(WSX_EUNSUPPORTED, "no compiled kernel with %d rows per tile for kind %d",
+                    tile_rows, d->kind);
+
+    int64_t n_rows = d->n_envs;
+    std::vector<Tile> tiles;
+    if (market) {
+        const int32_t* off = d->agent_offsets;
+        if (off[0] != 0) return fail(WSX_EINVAL, "agent_offsets[0] must be 0");
+        for (int64_t e = 0; e < d->n_envs; ++e) {
+            const int64_t c = (int64_t)off[e + 1] - off[e];
+            if (c < 1 || c > tile_rows)
+                return fail(WSX_EINVAL, "env %lld has %lld agents (allowed 1..%d)", (long long)e,
+                            (long long)c, tile_rows);
+        }
+        n_rows = off[d->n_envs];
+        // contiguous greedy packing of whole envs into tiles of <= tile_rows agents
+        Tile cur{0, 0, 0, 0};
+        for (int32_t e = 0; e < (int32_t)d->n_envs; ++e) {
+            if (off[e + 1] - cur.row0 > tile_rows) {
+                tiles.push_back(cur);
+                cur = Tile{off[e], off[e], e, e};
+            }
+            cur.row1 = off[e + 1];
+            cur.env1 = e + 1;
+        }
+        tiles.push_back(cur);
+    }
+    wsx_env* env = new (std::nothrow) wsx_env();
+    if (!env) return fail(WSX_EINVAL, "out of host memory");
+    env->kind = d->kind;
+    env->info = k;
+    env->n_envs = d->n_envs;
+    env->n_rows = n_rows;
+    env->seed = d->seed;
+    env->step = 0;
+    env->epoch = 0;
+    env->block = static_cast<char*>(d->state);
+    env->params = d->params;
+    env->lay = layout_of(k, d->n_envs, n_rows, market);
+    env->tile_rows = tile_rows;
+    env->n_tiles = market ? (int)tiles.size() : (int)((n_rows + tile_rows - 1) / tile_rows);
+    env->graph = nullptr;
+    env->capture_stream = nullptr;
+    hipError_t e = hipGetDevice(&env->device);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&env->cus, hipDeviceAttributeMultiprocessorCount, env->device);
+    if (e == hipSuccess && market) {
+        e = hipMemcpy(env->block + env->lay.offsets, d->agent_offsets,
+                      (size_t)(d->n_envs + 1) * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(env->block + env->lay.tiles, tiles.data(), tiles.size() * sizeof(Tile),
+                          hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        delete env;
+        return hip_fail(e, "wsx_env_create");
+    }
+    *out = env;
+    return WSX_OK;
+}
+
+int wsx_env_destroy(wsx_env* env) {
+    if (!env) return fail(WSX_EINVAL, "env is NULL");
+    if (env->graph) hipGraphExecDestroy(env->graph);
+    if (env->capture_stream) hipStreamDestroy(env->capture_stream);
+    delete env;
+    return WSX_OK;
+}
+
+int wsx_env_info(const wsx_env* env, int64_t* n_rows, uint32_t* step, uint32_t* epoch) {
+    if (!env) return fail(WSX_EINVAL, "env is NULL");
+    if (n_rows) *n_rows = env->n_rows;
+    if (step) *step = env->step;
+    if (epoch) *epoch = env->epoch;
+    return WSX_OK;
+}
+
+int wsx_env_set_step(wsx_env* env, uint32_t step) {
+    if (!env) return fail(WSX_EINVAL, "env is NULL");
+    env->step = step;
+    return WSX_OK;
+}
+
+static EnvArgs env_args(const wsx_env* env) {
+    EnvArgs a{};
+    a.state = reinterpret_cast<float*>(env->block + env->lay.state);
+    a.obs_scratch = reinterpret_cast<float*>(env->block + env->lay.obs);
+    a.head_scratch = reinterpret_cast<float*>(env->block + env->lay.head);
+    a.params = env->params;
+    a.offsets = env->kind == WSX_MARKET ? reinterpret_cast<const int32_t*>(env->block + env->lay.offsets)
+                                        : nullptr;
+    a.tiles = env->kind == WSX_MARKET ? reinterpret_cast<const Tile*>(env->block + env->lay.tiles)
+                                      : nullptr;
+    a.step_ptr = nullptr;
+    a.n_rows = env->n_rows;
+    a.n_envs = (int32_t)env->n_envs;
+    a.n_tiles = env->n_tiles;
+    a.k0 = (uint32_t)(env->seed & 0xFFFFFFFFu);
+    a.k1 = (uint32_t)(env->seed >> 32);
+    a.epoch = env->epoch;
+    a.t0 = env->step;
+    return a;
+}
+
+int wsx_env_reset(wsx_env* env, uint32_t epoch, void* stream) {
+    if (!env) return fail(WSX_EINVAL, "env is NULL");
+    env->epoch = epoch;
+    env->step = 0;
+    const hipError_t e = launch_reset(env->kind, env_args(env), static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "wsx_env_reset");
+    return WSX_OK;
+}
+
+static int check_policy(const wsx_policy* p, const KindInfo& k, int kind) {
+    if (!p) return fail(WSX_EINVAL, "policy is NULL");
+    if (p->dtype != k.dtype)
+        return fail(WSX_EUNSUPPORTED, "kind %d runs dtype %d policies (got %d)", kind, k.dtype, p->dtype);
+    if (p->d_in != k.od) return fail(WSX_EINVAL, "policy d_in %d != observation size %d", p->d_in, k.od);
+    if (p->h1 != k.hidden || p->h2 != k.hidden)
+        return fail(WSX_EUNSUPPORTED, "kind %d runs %d-unit hidden layers (got %d, %d)", kind,
+                    k.hidden, p->h1, p->h2);
+    if (p->n_head != n_head_of(k))
+        return fail(WSX_EINVAL, "policy n_head %d != %d", p->n_head, n_head_of(k));
+    if (!p->w1 || !p->w2 || !p->w3 || !p->b1 || !p->b2 || !p->b3)
+        return fail(WSX_EINVAL, "policy weight or bias pointer is NULL");
+    if (p->dtype == WSX_FP8_E4M3) {
+        if (!p->s1 || !p->s2 || !p->s3) return fail(WSX_EINVAL, "FP8 policy needs row scales");
+        for (int i = 0; i < 3; ++i) {
+            int ex;
+            const float m = frexpf(p->act_scale[i], &ex);
+            if (!(p->act_scale[i] > 0.0f) || m != 0.5f)
+                return fail(WSX_EINVAL, "act_scale[%d] must be a positive power of two", i);
+        }
+    }
+    if (k.nact == 0 && !p->log_std) return fail(WSX_EINVAL, "continuous policy needs log_std");
+    return WSX_OK;
+}
+
+static PolicyArgs policy_args(const wsx_policy* p) {
+    PolicyArgs a{};
+    a.w1 = p->w1;
+    a.w2 = p->w2;
+    a.w3 = p->w3;
+    a.b1 = p->b1;
+    a.b2 = p->b2;
+    a.b3 = p->b3;
+    a.s1 = p->s1;
+    a.s2 = p->s2;
+    a.s3 = p->s3;
+    a.log_std = p->log_std;
+    for (int i = 0; i < 3; ++i) a.act_scale[i] = p->act_scale[i];
+    a.d_in = p->d_in;
+    a.hidden = p->h1;
+    a.n_head = p->n_head;
+    return a;
+}
+
+int wsx_rollout(wsx_env* env, const wsx_policy* policy, int32_t horizon, const wsx_traj* traj,
+                int32_t mode, void* stream) {
+    if (!env) return fail(WSX_EINVAL, "env is NULL");
+    int rc = check_policy(policy, env->info, env->kind);
+    if (rc) return rc;
+    if (horizon < 0) return fail(WSX_EINVAL, "horizon must be >= 0");
+    if (!traj) return fail(WSX_EINVAL, "traj is NULL");
+    if (traj->capacity < horizon) return fail(WSX_EINVAL, "traj capacity %d < horizon %d", traj->capacity, horizon);
+    if (!traj->last_value || (horizon > 0 && (!traj->obs || !traj->action || !traj->reward ||
+                                              !traj->done || !traj->value || !traj->logp)))
+        return fail(WSX_EINVAL, "trajectory pointer is NULL");
+    if ((uint64_t)env->step + (uint64_t)horizon > 0xFFFFFFFFull)
+        return fail(WSX_EINVAL, "step counter would wrap");
+    Variant v;
+    if (!find_variant(env->kind, policy->dtype, policy->h1, env->info.waves, env->tile_rows, v) &&
+        !find_variant(env->kind, policy->dtype, policy->h1, 0, env->tile_rows, v))
+        return fail(WSX_EUNSUPPORTED, "no compiled kernel for this policy and tile");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const EnvArgs ea = env_args(env);
+    const PolicyArgs pa = policy_args(policy);
+    TrajArgs ta{};
+    ta.obs = traj->obs;
+    ta.action = traj->action;
+    ta.reward = traj->reward;
+    ta.done = traj->done;
+    ta.value = traj->value;
+    ta.logp = traj->logp;
+    ta.last_value = traj->last_value;
+    hipError_t e = hipSuccess;
+    if (mode == WSX_MODE_FUSED) {
+        const int per_cu = fused_blocks_per_cu(v);
+        const int grid = std::max(1, std::min(env->n_tiles, env->cus * per_cu));
+        e = launch_fused(v, ea, pa, ta, horizon, grid, s);
+    } else if (mode == WSX_MODE_PLAIN) {
+        e = launch_plain(v, ea, pa, ta, horizon, false, s);
+    } else if (mode == WSX_MODE_GRAPH) {
+        // the launches read the step counter from the state block, so one
+        // captured graph serves every call with the same buffers and horizon
+        EnvArgs ga = ea;
+        ga.step_ptr = reinterpret_cast<const uint32_t*>(env->block + env->lay.step);
+        std::vector<char> key(sizeof(PolicyArgs) + sizeof(TrajArgs) + sizeof(int) + sizeof(Variant));
+        std::memcpy(key.data(), &pa, sizeof pa);
+        std::memcpy(key.data() + sizeof pa, &ta, sizeof ta);
+        std::memcpy(key.data() + sizeof pa + sizeof ta, &horizon, sizeof horizon);
+        std::memcpy(key.data() + sizeof pa + sizeof ta + sizeof horizon, &v, sizeof v);
+        if (!env->graph || env->graph_key != key) {
+            if (env->graph) {
+                hipGraphExecDestroy(env->graph);
+                env->graph = nullptr;
+            }
+            if (!env->capture_stream) {
+                e = hipStreamCreateWithFlags(&env->capture_stream, hipStreamNonBlocking);
+                if (e != hipSuccess) return hip_fail(e, "wsx_rollout (capture stream)");
+            }
+            e = hipStreamBeginCapture(env->capture_stream, hipStreamCaptureModeRelaxed);
+            if (e != hipSuccess) return hip_fail(e, "wsx_rollout (begin capture)");
+            hipError_t le = launch_plain(v, ga, pa, ta, horizon, true, env->capture_stream);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(env->capture_stream, &g);
+            if (le != hipSuccess) e = le;
+            if (e == hipSuccess) e = hipGraphInstantiate(&env->graph, g, nullptr, nullptr, 0);
+            if (g) hipGraphDestroy(g);
+            if (e != hipSuccess) return hip_fail(e, "wsx_rollout (capture)");
+            env->graph_key = key;
+        }
+        e = launch_set_step(const_cast<uint32_t*>(ga.step_ptr), (int)env->step, s);
+        if (e == hipSuccess) e = hipGraphLaunch(env->graph, s);
+    } else {
+        return fail(WSX_EINVAL, "unknown mode %d", mode);
+    }
+    if (e != hipSuccess) return hip_fail(e, "wsx_rollout");
+    env->step += (uint32_t)horizon;
+    return WSX_OK;
+}
+
+int wsx_compute_returns(const float* reward, const float* value, const uint8_t* done,
+                        const float* last_value, int32_t horizon, int64_t rows, double gamma,
+                        double lambda, int32_t bootstrap, void* returns, void* advantages,
+                        int32_t out_dtype, void* stream) {
+    if (horizon < 0 || rows < 0) return fail(WSX_EINVAL, "negative horizon or rows");
+    if (out_dtype != WSX_F32 && out_dtype != WSX_F64)
+        return fail(WSX_EUNSUPPORTED, "returns are written as WSX_F32 or WSX_F64");
+    if (!(gamma >= 0.0 && gamma <= 1.0) || !(lambda >= 0.0 && lambda <= 1.0))
+        return fail(WSX_EINVAL, "gamma and lambda must lie in [0, 1]");
+    if (horizon == 0 || rows == 0) return WSX_OK;
+    if (!reward || !value || !done || !last_value || !returns || !advantages)
+        return fail(WSX_EINVAL, "a buffer pointer is NULL");
+    const hipError_t e = launch_returns(reward, value, done, last_value, horizon, rows, gamma, lambda,
+                                        bootstrap ? 1 : 0, returns, advantages,
+                                        out_dtype == WSX_F64 ? 1 : 0, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "wsx_compute_returns");
+    return WSX_OK;
+}
+
+int wsx_policy_forward(const wsx_policy* policy, const float* obs, int64_t rows, float* head,
+                       void* stream) {
+    if (!policy) return fail(WSX_EINVAL, "policy is NULL");
+    if (rows < 0 || rows > 0x7FFFFFFF) return fail(WSX_EINVAL, "rows out of range");
+    // the kind whose policy shape this is
+    int kind = 0;
+    KindInfo k{};
+    for (int c = WSX_CARTPOLE; c <= WSX_REACTION; ++c) {
+        KindInfo ki;
+        kind_info(c, ki);
+        if (ki.dtype == policy->dtype && ki.od == policy->d_in && ki.hidden == policy->h1 &&
+            n_head_of(ki) == policy->n_head) {
+            kind = c;
+            k = ki;
+            break;
+        }
+    }
+    if (!kind) return fail(WSX_EUNSUPPORTED, "no compiled kernel for this policy shape");
+    int rc = check_policy(policy, k, kind);
+    if (rc) return rc;
+    if (rows == 0) return WSX_OK;
+    if (!obs || !head) return fail(WSX_EINVAL, "obs or head is NULL");
+    Variant v;
+    if (!find_variant(kind, k.dtype, k.hidden, k.waves, k.tile_rows, v))
+        return fail(WSX_EUNSUPPORTED, "no compiled kernel for this policy shape");
+    const hipError_t e = launch_policy_forward(v, policy_args(policy), obs, rows, head,
+                                               static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "wsx_policy_forward");
+    return WSX_OK;
+}
+
+int wsx_quantize(int32_t dtype, float scale, const float* x, float* y, int64_t n, void* stream) {
+    if (dtype != WSX_F32 && dtype != WSX_BF16 && dtype != WSX_FP8_E4M3)
+        return fail(WSX_EINVAL, "unknown dtype %d", dtype);
+    int ex;
+    if (!(scale > 0.0f) || frexpf(scale, &ex) != 0.5f)
+        return fail(WSX_EINVAL, "scale must be a positive power of two");
+    if (n < 0) return fail(WSX_EINVAL, "n < 0");
+    if (n == 0) return WSX_OK;
+    if (!x || !y) return fail(WSX_EINVAL, "x or y is NULL");
+    const hipError_t e = launch_quantize(dtype, scale, x, y, n, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "wsx_quantize");
+    return WSX_OK;
+}
+
+}  // extern "C"

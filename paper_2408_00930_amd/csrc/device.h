@@ -1,0 +1,166 @@
+// device.h -- device building blocks of the roll-out kernels (gfx950).
+//
+// Counter-based random numbers (Philox-4x32-10), the uniform and normal
+// mappings, narrow-format conversions and the MFMA operand traits. Written
+// from the published definitions; nothing here is shared with the oracle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wsx {
+
+// ------------------------------------------------------------------ RNG --
+// Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11, Sec. 3): each round
+// multiplies words 0 and 2 by the two Philox constants, mixes the high halves
+// with words 1 and 3 and the key, and the key advances by the Weyl
+// increments; ten rounds.
+struct Words {
+    uint32_t w[4];
+};
+
+__device__ __forceinline__ Words philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                          uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo_a = 0xD2511F53u * c0;
+        const uint32_t hi_a = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo_b = 0xCD9E8D57u * c2;
+        const uint32_t hi_b = __umulhi(0xCD9E8D57u, c2);
+        c0 = hi_b ^ c1 ^ k0;
+        c2 = hi_a ^ c3 ^ k1;
+        c1 = lo_b;
+        c3 = lo_a;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    Words out;
+    out.w[0] = c0;
+    out.w[1] = c1;
+    out.w[2] = c2;
+    out.w[3] = c3;
+    return out;
+}
+
+// Streams of the roll-out: the counter is (step, row, purpose | sub << 8,
+// epoch) under the key (seed low, seed high).
+enum : uint32_t { PURPOSE_ACTION = 0, PURPOSE_RESET = 1, PURPOSE_NOISE = 2 };
+
+struct RngKey {
+    uint32_t k0, k1, epoch;
+};
+
+__device__ __forceinline__ Words draw(const RngKey& key, uint32_t t, uint32_t row,
+                                      uint32_t purpose, uint32_t sub) {
+    return philox10(t, row, purpose | (sub << 8), key.epoch, key.k0, key.k1);
+}
+
+// Uniform in (0,1): the top 23 bits as an odd multiple of 2^-24 (exact in
+// FP32, never 0 or 1).
+__device__ __forceinline__ float unit_uniform(uint32_t x) {
+    return (float)((x >> 9) * 2u + 1u) * 5.9604644775390625e-08f;
+}
+
+// Box-Muller: z_cos = sqrt(-2 ln u1) cos(2 pi u2), z_sin with sin.
+__device__ __forceinline__ void gauss_pair(float u1, float u2, float& z_cos, float& z_sin) {
+    const float radius = sqrtf(-2.0f * logf(u1));
+    float s, c;
+    sincospif(2.0f * u2, &s, &c);
+    z_cos = radius * c;
+    z_sin = radius * s;
+}
+
+// ------------------------------------------------------ element formats --
+enum : int { DT_F32 = 0, DT_BF16 = 1, DT_FP8 = 2 };
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// f32 -> bf16 bits, round to nearest even (v_cvt_pk_bf16_f32 on gfx950).
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+    __bf16 a = (__bf16)lo, b = (__bf16)hi;
+    return (uint32_t)__builtin_bit_cast(uint16_t, a) |
+           ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+}
+
+// Four floats -> four OCP E4M3FN codes (little-endian in a word). Inputs are
+// clamped to +-448 first so the conversion saturates.
+__device__ __forceinline__ uint32_t pack_fp8x4(float a, float b, float c, float d) {
+    a = fminf(fmaxf(a, -448.0f), 448.0f);
+    b = fminf(fmaxf(b, -448.0f), 448.0f);
+    c = fminf(fmaxf(c, -448.0f), 448.0f);
+    d = fminf(fmaxf(d, -448.0f), 448.0f);
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
+    return (uint32_t)w;
+}
+
+__device__ __forceinline__ float bf16_bits_to_f32(uint32_t bits16) {
+    return __uint_as_float(bits16 << 16);
+}
+
+// Real value of an E4M3FN code (bias 7, 3 mantissa bits, no infinities).
+__device__ __forceinline__ float fp8_code_to_f32(uint32_t code) {
+    const uint32_t sign = code & 0x80u, e = (code >> 3) & 0xFu, m = code & 0x7u;
+    float mag;
+    if (e == 0)
+        mag = (float)m * 0.001953125f;  // subnormal: m * 2^-9
+    else
+        mag = __uint_as_float(((e + 120u) << 23) | (m << 20));
+    return sign ? -mag : mag;
+}
+
+// MFMA operand traits for the 16x16 output tile: A is [16 x K], B is
+// [K x 16]; lane l holds row/column (l mod 16) and the K-chunk (l / 16) of
+// KC consecutive elements; the accumulator holds rows 4*(l/16)+i, i < 4, of
+// column (l mod 16).
+template <int DT>
+struct Mma;
+
+template <>
+struct Mma<DT_F32> {
+    static constexpr int K = 4, KC = 1, EB = 4;
+    typedef float frag;
+    __device__ static __forceinline__ f32x4 mma(frag a, frag b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ frag lds(const char* p) {
+        return *reinterpret_cast<const float*>(p);
+    }
+};
+
+template <>
+struct Mma<DT_BF16> {
+    static constexpr int K = 32, KC = 8, EB = 2;
+    typedef bf16x8 frag;
+    __device__ static __forceinline__ f32x4 mma(frag a, frag b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ frag lds(const char* p) {
+        return __builtin_bit_cast(frag, *reinterpret_cast<const uint4*>(p));
+    }
+};
+
+template <>
+struct Mma<DT_FP8> {
+    static constexpr int K = 32, KC = 8, EB = 1;
+    typedef long frag;
+    __device__ static __forceinline__ f32x4 mma(frag a, frag b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ frag lds(const char* p) {
+        return __builtin_bit_cast(frag, *reinterpret_cast<const uint2*>(p));
+    }
+};
+
+// tanh(x) = 1 - 2 / (1 + 2^(2 x log2 e)); `k2` carries 2 log2(e) times the
+// accumulator's scale so the FP8 dequantisation folds into the exponent.
+// Saturates to +-1 for large |x| (2^inf = inf, rcp(inf) = 0).
+__device__ __forceinline__ float tanh_scaled(float acc, float k2) {
+    const float e = __builtin_amdgcn_exp2f(acc * k2);
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + e);
+}
+
+constexpr float kTwoLog2e = 2.8853900817779268f;  // 2 / ln 2
+
+}  // namespace wsx

@@ -1,0 +1,274 @@
+// envs.h -- FP32 environment dynamics on the device.
+//
+// The example families of arXiv 2408.00930, App. C (classic control, a
+// multi-agent economy, a noisy potential-energy walk). The paper gives no
+// equations; these follow the project's specification: Lagrangian mechanics
+// for the classic-control bodies, the market and reaction rules read from the
+// workload descriptions. Every function works on one row (agent) held in
+// registers; the market's cross-agent sums are done by the kernels.
+#pragma once
+
+#include "device.h"
+
+namespace wsx {
+
+struct EnvCtx {
+    const float* lds_params;  // reaction: potential block staged in LDS
+};
+
+// ------------------------------------------------------------ CartPole --
+// Cart (mass 1) with a hinged uniform pole (mass 0.1, half-length 0.5), force
+// +-10, explicit Euler dt 0.02; ends when |x| > 2.4 or |theta| > 12 degrees.
+struct CartPole {
+    static constexpr int KIND = 1, SD = 4, OD = 4, NACT = 2;
+    __device__ static void reset(float* s, const RngKey& key, uint32_t t, uint32_t row,
+                                 const EnvCtx&) {
+        const Words w = draw(key, t, row, PURPOSE_RESET, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s[i] = -0.05f + 0.1f * unit_uniform(w.w[i]);
+    }
+    __device__ static void observe(const float* s, float* o) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) o[i] = s[i];
+    }
+    __device__ static void step(float* s, int action, float, uint32_t, uint32_t, const RngKey&,
+                                const EnvCtx&, float& reward, bool& done) {
+        const float gravity = 9.8f, m_pole = 0.1f, m_total = 1.1f, half_len = 0.5f;
+        const float dt = 0.02f;
+        const float force = action == 1 ? 10.0f : -10.0f;
+        const float x = s[0], xd = s[1], th = s[2], thd = s[3];
+        float sn, cs;
+        sincosf(th, &sn, &cs);
+        const float push = (force + m_pole * half_len * thd * thd * sn) / m_total;
+        const float thdd =
+            (gravity * sn - cs * push) / (half_len * (4.0f / 3.0f - m_pole * cs * cs / m_total));
+        const float xdd = push - m_pole * half_len * thdd * cs / m_total;
+        s[0] = x + dt * xd;
+        s[1] = xd + dt * xdd;
+        s[2] = th + dt * thd;
+        s[3] = thd + dt * thdd;
+        const float th_limit = 0.20943951023931953f;  // 12 degrees
+        done = fabsf(s[0]) > 2.4f || fabsf(s[2]) > th_limit;
+        reward = 1.0f;
+    }
+};
+
+__device__ __forceinline__ float wrap_pi(float a) {
+    // a - 2 pi floor((a + pi) / (2 pi)), in [-pi, pi)
+    const float two_pi = 6.283185307179586f;
+    return a - two_pi * floorf((a + 3.141592653589793f) * 0.15915494309189535f);
+}
+
+// ------------------------------------------------------------ Pendulum --
+// Rod (m 1, l 1) under gravity 10 about its end, theta 0 upright, torque
+// clipped to 2; semi-implicit Euler dt 0.05, rate clipped to 8.
+struct Pendulum {
+    static constexpr int KIND = 2, SD = 2, OD = 3, NACT = 0;
+    __device__ static void reset(float* s, const RngKey& key, uint32_t t, uint32_t row,
+                                 const EnvCtx&) {
+        const Words w = draw(key, t, row, PURPOSE_RESET, 0);
+        s[0] = -3.141592653589793f + 6.283185307179586f * unit_uniform(w.w[0]);
+        s[1] = -1.0f + 2.0f * unit_uniform(w.w[1]);
+    }
+    __device__ static void observe(const float* s, float* o) {
+        sincosf(s[0], &o[1], &o[0]);
+        o[2] = s[1];
+    }
+    __device__ static void step(float* s, int, float torque, uint32_t, uint32_t, const RngKey&,
+                                const EnvCtx&, float& reward, bool& done) {
+        const float u = fminf(fmaxf(torque, -2.0f), 2.0f);
+        const float th = s[0], thd = s[1];
+        const float a = wrap_pi(th);
+        reward = -(a * a + 0.1f * thd * thd + 0.001f * u * u);
+        // theta'' = 3 g / (2 l) sin(theta) + 3 u / (m l^2)
+        const float acc = 15.0f * sinf(th) + 3.0f * u;
+        const float w = fminf(fmaxf(thd + acc * 0.05f, -8.0f), 8.0f);
+        s[0] = th + w * 0.05f;
+        s[1] = w;
+        done = false;
+    }
+};
+
+// ------------------------------------------------------------- Acrobot --
+// Two links (length 1, centre of mass 0.5, mass 1, inertia 1), elbow torque
+// in [-1, 1], RK4 over dt 0.2; ends when the tip is more than one link length
+// above the base.
+struct Acrobot {
+    static constexpr int KIND = 3, SD = 4, OD = 6, NACT = 0;
+    __device__ static void reset(float* s, const RngKey& key, uint32_t t, uint32_t row,
+                                 const EnvCtx&) {
+        const Words w = draw(key, t, row, PURPOSE_RESET, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s[i] = -0.1f + 0.2f * unit_uniform(w.w[i]);
+    }
+    __device__ static void observe(const float* s, float* o) {
+        sincosf(s[0], &o[1], &o[0]);
+        sincosf(s[1], &o[3], &o[2]);
+        o[4] = s[2];
+        o[5] = s[3];
+    }
+    // Manipulator equations M(q) q'' + C(q, q') + G(q) = (0, tau) solved for
+    // q'' with the 2x2 inertia matrix of the two links.
+    __device__ static void deriv(const float* q, float tau, float* dq) {
+        const float g = 9.8f;
+        float s2, c2;
+        sincosf(q[1], &s2, &c2);
+        const float m11 = 0.25f + (1.0f + 0.25f + c2) + 2.0f;  // lc1^2 + (l1^2+lc2^2+2 l1 lc2 c2) + I1 + I2
+        const float m12 = (0.25f + 0.5f * c2) + 1.0f;
+        const float m22 = 0.25f + 1.0f;
+        const float w1 = q[2], w2 = q[3];
+        const float cor1 = -0.5f * s2 * (w2 * w2 + 2.0f * w1 * w2);
+        const float cor2 = 0.5f * s2 * w1 * w1;
+        const float grav2 = 0.5f * g * sinf(q[0] + q[1]);
+        const float grav1 = 1.5f * g * sinf(q[0]) + grav2;
+        const float rhs1 = -(cor1 + grav1);
+        const float rhs2 = tau - cor2 - grav2;
+        const float det = m11 * m22 - m12 * m12;
+        dq[0] = w1;
+        dq[1] = w2;
+        dq[2] = (m22 * rhs1 - m12 * rhs2) / det;
+        dq[3] = (m11 * rhs2 - m12 * rhs1) / det;
+    }
+    __device__ static void step(float* s, int, float torque, uint32_t, uint32_t, const RngKey&,
+                                const EnvCtx&, float& reward, bool& done) {
+        const float tau = fminf(fmaxf(torque, -1.0f), 1.0f);
+        const float h = 0.2f;
+        float k1[4], k2[4], k3[4], k4[4], y[4];
+        deriv(s, tau, k1);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) y[i] = s[i] + 0.5f * h * k1[i];
+        deriv(y, tau, k2);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) y[i] = s[i] + 0.5f * h * k2[i];
+        deriv(y, tau, k3);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) y[i] = s[i] + h * k3[i];
+        deriv(y, tau, k4);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) y[i] = s[i] + (h / 6.0f) * (k1[i] + 2.0f * k2[i] + 2.0f * k3[i] + k4[i]);
+        s[0] = wrap_pi(y[0]);
+        s[1] = wrap_pi(y[1]);
+        s[2] = fminf(fmaxf(y[2], -12.566370614359172f), 12.566370614359172f);
+        s[3] = fminf(fmaxf(y[3], -28.274333882308138f), 28.274333882308138f);
+        const float tip = -cosf(s[0]) - cosf(s[0] + s[1]);
+        done = tip > 1.0f;
+        reward = done ? 0.0f : -1.0f;
+    }
+};
+
+// -------------------------------------------------------------- Market --
+// Per agent: 32-d state; the env-wide demand and supply sums are formed by
+// the kernels (exactly, in integer units) between decide() and settle().
+struct Market {
+    static constexpr int KIND = 4, SD = 32, OD = 32, NACT = 50;
+    __device__ static void reset(float* s, const RngKey& key, uint32_t t, uint32_t row,
+                                 const EnvCtx&) {
+#pragma unroll
+        for (int sub = 0; sub < 8; ++sub) {
+            const Words w = draw(key, t, row, PURPOSE_RESET, (uint32_t)sub);
+            gauss_pair(unit_uniform(w.w[0]), unit_uniform(w.w[1]), s[4 * sub], s[4 * sub + 1]);
+            gauss_pair(unit_uniform(w.w[2]), unit_uniform(w.w[3]), s[4 * sub + 2], s[4 * sub + 3]);
+        }
+    }
+    __device__ static void observe(const float* s, float* o) {
+#pragma unroll
+        for (int i = 0; i < 32; ++i) o[i] = s[i];
+    }
+    // Action a -> labour level k in 0..9 (labour k/9) and trade level j in
+    // 0..4 (trade (j-2)/2). Demand in half units: max(j-2, 0). Supply in
+    // 1/18 units: 2k + 9 max(2-j, 0).
+    __device__ static void decide(int a, int& demand_half, int& supply_18th) {
+        const int k = a % 10, j = a / 10;
+        demand_half = j > 2 ? j - 2 : 0;
+        supply_18th = 2 * k + 9 * (j < 2 ? 2 - j : 0);
+    }
+    __device__ static void settle(float* s, int a, int demand_half_sum, int supply_18th_sum,
+                                  float& reward) {
+        const int k = a % 10, j = a / 10;
+        const float labour = (float)k / 9.0f;
+        const float trade = (float)(j - 2) * 0.5f;
+        const float eps = 1e-3f;
+        const float demand = (float)demand_half_sum * 0.5f;
+        const float supply = (float)supply_18th_sum / 18.0f;
+        const float price = (demand + eps) / (supply + eps);
+        const float sold = trade < 0.0f ? -trade : 0.0f;
+        const float bought = trade > 0.0f ? trade : 0.0f;
+        const float cons = fmaxf(0.0f, labour - sold + bought / price);
+        reward = log1pf(cons) - 0.1f * labour * labour;
+        s[0] = 0.9f * s[0] + 0.1f * (cons - 0.5f);
+        s[1] = logf(price);
+        s[2] = labour;
+        s[3] = trade;
+        s[4] = cons;
+#pragma unroll
+        for (int i = 5; i < 32; ++i) s[i] = 0.99f * s[i];
+    }
+};
+
+// ------------------------------------------------------------ Reaction --
+// 20-D walk on E(x) = x^T A x / 2 + sum_k a_k exp(-|x - c_k|^2 / (2 w_k^2))
+// plus 0.05 N(0,1) noise per evaluation. The LDS parameter block is A (400),
+// centres (64 x 20), -1/(2 w^2) (64), amplitudes (64).
+struct Reaction {
+    static constexpr int KIND = 5, SD = 21, OD = 20, NACT = 40, NDIM = 20, NG = 64;
+    static constexpr int PARAM_FLOATS = NDIM * NDIM + NG * NDIM + NG + NG;
+    __device__ static float energy(const float* x, const float* p) {
+        const float* A = p;
+        const float* cen = p + NDIM * NDIM;
+        const float* nhw = cen + NG * NDIM;
+        const float* amp = nhw + NG;
+        float quad = 0.0f;
+        for (int i = 0; i < NDIM; ++i) {
+            float row = 0.0f;
+#pragma unroll
+            for (int j = 0; j < NDIM; ++j) row += A[i * NDIM + j] * x[j];
+            quad += x[i] * row;
+        }
+        float e = 0.5f * quad;
+        for (int k = 0; k < NG; ++k) {
+            float d2 = 0.0f;
+#pragma unroll
+            for (int i = 0; i < NDIM; ++i) {
+                const float d = x[i] - cen[k * NDIM + i];
+                d2 += d * d;
+            }
+            e += amp[k] * expf(d2 * nhw[k]);
+        }
+        return e;
+    }
+    __device__ static float noisy_energy(const float* x, const RngKey& key, uint32_t t, uint32_t row,
+                                         const EnvCtx& c) {
+        const Words w = draw(key, t, row, PURPOSE_NOISE, 0);
+        float zc, zs;
+        gauss_pair(unit_uniform(w.w[0]), unit_uniform(w.w[1]), zc, zs);
+        return energy(x, c.lds_params) + 0.05f * zc;
+    }
+    __device__ static void reset(float* s, const RngKey& key, uint32_t t, uint32_t row,
+                                 const EnvCtx& c) {
+#pragma unroll
+        for (int sub = 0; sub < 5; ++sub) {
+            const Words w = draw(key, t, row, PURPOSE_RESET, (uint32_t)sub);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) s[4 * sub + i] = -3.0f + 6.0f * unit_uniform(w.w[i]);
+        }
+        s[20] = noisy_energy(s, key, t, row, c);
+    }
+    __device__ static void observe(const float* s, float* o) {
+#pragma unroll
+        for (int i = 0; i < 20; ++i) o[i] = s[i];
+    }
+    __device__ static void step(float* s, int a, float, uint32_t t, uint32_t row, const RngKey& key,
+                                const EnvCtx& c, float& reward, bool& done) {
+        const int coord = a >> 1;
+        const float delta = (a & 1) ? -0.05f : 0.05f;
+#pragma unroll
+        for (int i = 0; i < 20; ++i)
+            if (i == coord) s[i] += delta;
+        const float e_new = noisy_energy(s, key, t + 1, row, c);
+        reward = -(e_new - s[20]);
+        s[20] = e_new;
+        done = false;
+    }
+};
+
+}  // namespace wsx

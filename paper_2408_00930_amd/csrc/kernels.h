@@ -1,0 +1,83 @@
+// kernels.h -- kernel argument blocks and host-side launcher declarations
+// shared by the roll-out kernels (rollout.hip, returns.hip) and the C-ABI
+// layer (abi.cpp). Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wsx {
+
+struct PolicyArgs {
+    const void* w1;
+    const void* w2;
+    const void* w3;
+    const float* b1;
+    const float* b2;
+    const float* b3;
+    const float* s1;  // FP8 row scales (NULL otherwise)
+    const float* s2;
+    const float* s3;
+    const float* log_std;
+    float act_scale[3];
+    int32_t d_in, hidden, n_head;
+};
+
+struct TrajArgs {
+    float* obs;
+    void* action;
+    float* reward;
+    uint8_t* done;
+    float* value;
+    float* logp;
+    float* last_value;
+};
+
+// Tile of a workgroup: rows [row0, row1) of envs [env0, env1).
+struct Tile {
+    int32_t row0, row1, env0, env1;
+};
+
+struct EnvArgs {
+    float* state;             // SoA [state_dim][n_rows]
+    float* obs_scratch;       // [n_rows][obs_dim]    (plain mode)
+    float* head_scratch;      // [n_rows][n_head]     (plain mode)
+    const float* params;      // reaction potential block (global)
+    const int32_t* offsets;   // market CSR offsets [n_envs + 1]
+    const Tile* tiles;        // tile table [n_tiles]
+    const uint32_t* step_ptr; // graph mode: device copy of the step counter
+    int64_t n_rows;
+    int32_t n_envs;
+    int32_t n_tiles;
+    uint32_t k0, k1, epoch;
+    uint32_t t0;              // step counter at the start of the launch
+};
+
+// One compiled variant of the fused / plain kernels for an environment kind.
+struct Variant {
+    int32_t kind, dtype, hidden, waves, tile_rows;
+};
+
+// Launchers (return hipError_t of the launch).
+hipError_t launch_reset(int kind, const EnvArgs& env, hipStream_t s);
+hipError_t launch_fused(const Variant& v, const EnvArgs& env, const PolicyArgs& pol,
+                        const TrajArgs& tr, int horizon, int grid, hipStream_t s);
+hipError_t launch_plain(const Variant& v, const EnvArgs& env, const PolicyArgs& pol,
+                        const TrajArgs& tr, int horizon, bool counter_from_device,
+                        hipStream_t s);
+hipError_t launch_set_step(uint32_t* step_ptr, int value, hipStream_t s);
+hipError_t launch_policy_forward(const Variant& v, const PolicyArgs& pol, const float* obs,
+                                 int64_t rows, float* head, hipStream_t s);
+hipError_t launch_quantize(int dtype, float scale, const float* x, float* y, int64_t n,
+                           hipStream_t s);
+hipError_t launch_returns(const float* reward, const float* value, const uint8_t* done,
+                          const float* last_value, int horizon, int64_t rows, double gamma,
+                          double lambda, int bootstrap, void* ret, void* adv, int out_f64,
+                          hipStream_t s);
+
+// The compiled variants and the workgroups of a fused launch a CU can hold.
+int n_variants();
+const Variant& variant(int i);
+int fused_blocks_per_cu(const Variant& v);
+
+}  // namespace wsx

@@ -1,0 +1,128 @@
+// returns.hip -- discounted returns and GAE advantages on the device, FP64
+// (arXiv 2408.00930, Sec. 3: actor-critic training consumes them; GAE of
+// Schulman et al. 2016).
+//
+// Both recursions are affine maps run backwards in time,
+//   A_t = delta_t + gamma lambda (1 - d_t) A_{t+1},  G_t = r_t + gamma (1 - d_t) G_{t+1},
+// so a block of consecutive steps composes into one map x -> b + c x with
+// (c1, b1) o (c2, b2) = (c1 c2, b1 + c1 b2). A workgroup owns 32 rows and
+// walks the horizon backwards in tiles of 64 steps: the tile is loaded
+// coalesced (consecutive rows adjacent) into LDS; each wave then takes a row
+// with one step per lane and forms the suffix compositions of the tile with a
+// Hillis-Steele scan over wavefront shuffles (6 rounds of 64-bit shuffles),
+// applies them to the carry from the later tile, and leaves the carry of the
+// tile's first step for the next (earlier) tile.
+#include "device.h"
+#include "kernels.h"
+
+namespace wsx {
+
+constexpr int kRetRows = 32;   // rows per workgroup (128-byte rows of float)
+constexpr int kRetSteps = 64;  // steps per tile = lanes of a wave
+
+__global__ void __launch_bounds__(256)
+k_returns(const float* __restrict__ reward, const float* __restrict__ value,
+          const uint8_t* __restrict__ done, const float* __restrict__ last_value, int T,
+          int64_t rows, double gamma, double lambda, int bootstrap, void* ret, void* adv,
+          int out_f64) {
+    __shared__ float s_r[kRetSteps][kRetRows + 1];
+    __shared__ float s_v[kRetSteps][kRetRows + 1];
+    __shared__ uint8_t s_d[kRetSteps][kRetRows + 4];
+    __shared__ double s_g[kRetSteps][kRetRows + 1];
+    __shared__ double s_a[kRetSteps][kRetRows + 1];
+    __shared__ double carry_g[kRetRows], carry_a[kRetRows], carry_v[kRetRows];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t row0 = (int64_t)blockIdx.x * kRetRows;
+    if (tid < kRetRows) {
+        const int64_t r = row0 + tid;
+        const double vT = (bootstrap && r < rows) ? (double)last_value[r] : 0.0;
+        carry_g[tid] = vT;   // G_T
+        carry_a[tid] = 0.0;  // A_T
+        carry_v[tid] = vT;   // V_T
+    }
+    const double gl = gamma * lambda;
+    const int n_tiles = (T + kRetSteps - 1) / kRetSteps;
+    for (int tt = n_tiles - 1; tt >= 0; --tt) {
+        const int tbase = tt * kRetSteps;
+        const int tlen = min(kRetSteps, T - tbase);
+        __syncthreads();   // previous tile's outputs have been stored
+        for (int i = tid; i < kRetSteps * kRetRows; i += 256) {
+            const int t = i / kRetRows, j = i % kRetRows;
+            const int64_t r = row0 + j;
+            if (t < tlen && r < rows) {
+                const size_t g = (size_t)(tbase + t) * rows + r;
+                s_r[t][j] = reward[g];
+                s_v[t][j] = value[g];
+                s_d[t][j] = done[g];
+            } else {
+                s_r[t][j] = 0.0f;
+                s_v[t][j] = 0.0f;
+                s_d[t][j] = 0;
+            }
+        }
+        __syncthreads();
+        for (int j = wave; j < kRetRows; j += 4) {
+            const int t = lane;
+            const bool live = t < tlen;
+            const double r = s_r[t][j];
+            const double v = s_v[t][j];
+            const double keep = s_d[t][j] ? 0.0 : 1.0;
+            double v_next = __shfl_down(v, 1);
+            const double ca_in = carry_a[j], cg_in = carry_g[j], cv_in = carry_v[j];
+            if (t == tlen - 1) v_next = cv_in;
+            // this step's maps; steps past the horizon are the identity
+            double ca = live ? gl * keep : 1.0;
+            double ba = live ? r + gamma * keep * v_next - v : 0.0;
+            double cg = live ? gamma * keep : 1.0;
+            double bg = live ? r : 0.0;
+#pragma unroll
+            for (int off = 1; off < kRetSteps; off <<= 1) {
+                const double ca2 = __shfl_down(ca, off), ba2 = __shfl_down(ba, off);
+                const double cg2 = __shfl_down(cg, off), bg2 = __shfl_down(bg, off);
+                if (lane + off < kRetSteps) {
+                    ba = ba + ca * ba2;
+                    ca = ca * ca2;
+                    bg = bg + cg * bg2;
+                    cg = cg * cg2;
+                }
+            }
+            const double a = ba + ca * ca_in;
+            const double g = bg + cg * cg_in;
+            s_a[t][j] = a;
+            s_g[t][j] = g;
+            if (lane == 0) {
+                carry_a[j] = a;
+                carry_g[j] = g;
+                carry_v[j] = v;
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < kRetSteps * kRetRows; i += 256) {
+            const int t = i / kRetRows, j = i % kRetRows;
+            const int64_t r = row0 + j;
+            if (t < tlen && r < rows) {
+                const size_t g = (size_t)(tbase + t) * rows + r;
+                if (out_f64) {
+                    static_cast<double*>(ret)[g] = s_g[t][j];
+                    static_cast<double*>(adv)[g] = s_a[t][j];
+                } else {
+                    static_cast<float*>(ret)[g] = (float)s_g[t][j];
+                    static_cast<float*>(adv)[g] = (float)s_a[t][j];
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_returns(const float* reward, const float* value, const uint8_t* done,
+                          const float* last_value, int horizon, int64_t rows, double gamma,
+                          double lambda, int bootstrap, void* ret, void* adv, int out_f64,
+                          hipStream_t s) {
+    const unsigned blocks = (unsigned)((rows + kRetRows - 1) / kRetRows);
+    hipLaunchKernelGGL(k_returns, dim3(blocks), dim3(256), 0, s, reward, value, done, last_value,
+                       horizon, rows, gamma, lambda, bootstrap, ret, adv, out_f64);
+    return hipGetLastError();
+}
+
+}  // namespace wsx

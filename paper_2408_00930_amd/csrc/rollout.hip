@@ -1,0 +1,900 @@
+// rollout.hip -- the roll-out kernels (arXiv 2408.00930, Sec. 2 and App. B:
+// replicas step in place on the GPU, agents sample actions from a policy in
+// device memory, roll-out data are stored in place; no host round trips).
+//
+// Fused form: one persistent kernel runs the whole horizon. A workgroup owns a
+// tile of R rows (env replicas, or the agents of whole market envs) and keeps
+// their state in registers for all steps. The policy weights stay resident in
+// VGPRs as MFMA A-operands (weight-stationary: wave w owns output features
+// [w*H/NW, (w+1)*H/NW) of both hidden layers and a K-slice of the head);
+// activations go through LDS as B-operands. Per step:
+//   A  layer 1 (all waves)            -> h1 tile in LDS        | barrier
+//   B  layer 2 (all waves)            -> own h2 slice in LDS   | wave-local
+//   C  head partial over own K-slice  -> partials in LDS       | barrier
+//   D  one thread per row: head = bias + sum of partials, sample, store the
+//      record, step the dynamics, auto-reset, next observation -> LDS | barrier
+// Plain form: per step a policy kernel, a sample kernel and a step kernel
+// with HBM round trips for the intermediates (the comparison baseline).
+#include "device.h"
+#include "envs.h"
+#include "kernels.h"
+
+namespace wsx {
+
+// ------------------------------------------------------ per-kind shapes --
+template <class E>
+struct HeadOf {
+    static constexpr int NOUT = E::NACT ? E::NACT : 1;   // logits or one mean
+    static constexpr int NH = NOUT + 1;                   // + value
+    static constexpr int NHP = (NH + 15) / 16 * 16;
+};
+
+template <class E, int DT>
+constexpr int kin_of() {
+    return (E::OD + Mma<DT>::K - 1) / Mma<DT>::K * Mma<DT>::K;
+}
+
+// ------------------------------------------------------------ MLP tile --
+template <class T>
+__device__ __forceinline__ T zero_frag() {
+    T t;
+    __builtin_memset(&t, 0, sizeof(T));
+    return t;
+}
+
+// KC consecutive weights W[m][k0 .. k0+KC) as an A fragment; zero outside
+// rows [0, m_valid) and columns [0, k_valid).
+__device__ __forceinline__ void load_a(float& f, const void* W, int ld, int m, int m_valid, int k0,
+                                       int k_valid) {
+    const float* w = static_cast<const float*>(W);
+    f = (m < m_valid && k0 < k_valid) ? w[(size_t)m * ld + k0] : 0.0f;
+}
+
+__device__ __forceinline__ void load_a(bf16x8& f, const void* W, int ld, int m, int m_valid, int k0,
+                                       int k_valid) {
+    const uint16_t* w = static_cast<const uint16_t*>(W);
+    uint16_t v[8];
+    if (m < m_valid && k0 + 8 <= k_valid && (ld % 8) == 0) {
+        const uint4 q = *reinterpret_cast<const uint4*>(w + (size_t)m * ld + k0);
+        __builtin_memcpy(v, &q, 16);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            v[i] = (m < m_valid && k0 + i < k_valid) ? w[(size_t)m * ld + k0 + i] : (uint16_t)0;
+    }
+    __builtin_memcpy(&f, v, 16);
+}
+
+__device__ __forceinline__ void load_a(long& f, const void* W, int ld, int m, int m_valid, int k0,
+                                       int k_valid) {
+    const uint8_t* w = static_cast<const uint8_t*>(W);
+    uint8_t v[8];
+    if (m < m_valid && k0 + 8 <= k_valid && (ld % 8) == 0) {
+        const uint2 q = *reinterpret_cast<const uint2*>(w + (size_t)m * ld + k0);
+        __builtin_memcpy(v, &q, 8);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            v[i] = (m < m_valid && k0 + i < k_valid) ? w[(size_t)m * ld + k0 + i] : (uint8_t)0;
+    }
+    __builtin_memcpy(&f, v, 8);
+}
+
+// Store four consecutive features of one row (quantised for the next layer).
+template <int DT>
+__device__ __forceinline__ void store4(char* p, float a, float b, float c, float d, float inv_s);
+
+template <>
+__device__ __forceinline__ void store4<DT_F32>(char* p, float a, float b, float c, float d, float) {
+    *reinterpret_cast<float4*>(p) = make_float4(a, b, c, d);
+}
+template <>
+__device__ __forceinline__ void store4<DT_BF16>(char* p, float a, float b, float c, float d, float) {
+    *reinterpret_cast<uint2*>(p) = make_uint2(pack_bf16x2(a, b), pack_bf16x2(c, d));
+}
+template <>
+__device__ __forceinline__ void store4<DT_FP8>(char* p, float a, float b, float c, float d,
+                                               float inv_s) {
+    *reinterpret_cast<uint32_t*>(p) = pack_fp8x4(a * inv_s, b * inv_s, c * inv_s, d * inv_s);
+}
+
+// Store one quantised element (observations).
+template <int DT>
+__device__ __forceinline__ void store1(char* p, float v, float inv_s) {
+    if constexpr (DT == DT_F32) {
+        *reinterpret_cast<float*>(p) = v;
+    } else if constexpr (DT == DT_BF16) {
+        *reinterpret_cast<__bf16*>(p) = (__bf16)v;
+    } else {
+        *reinterpret_cast<uint8_t*>(p) = (uint8_t)(pack_fp8x4(v * inv_s, 0.f, 0.f, 0.f) & 0xFFu);
+    }
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+    // LDS writes of this wave complete before its later LDS reads of them.
+    __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
+// HS selects how the head is spread over the waves. HS = 0 (split-K): wave w
+// multiplies its own h2 features by its K-slice of the head for every head
+// row, leaving NW partial sums per row (no extra barrier). HS = 1 (split-M):
+// after a barrier, wave w computes head row tiles w, w + NW, ... over the whole
+// K (one result per row; for wide heads whose partials would not fit in LDS).
+template <int DT, int H, int NW, int NT, int KIN, int NHP, int HS>
+struct Mlp {
+    using M = Mma<DT>;
+    using Frag = typename M::frag;
+    static constexpr int K = M::K, KC = M::KC, EB = M::EB;
+    static constexpr int FPW = H / NW;   // hidden features owned by a wave
+    static constexpr int MT = FPW / 16;
+    static constexpr int K1S = KIN / K, K2S = H / K, K3S = FPW / K, NHT = NHP / 16;
+    static constexpr int NHW = HS ? (NHT + NW - 1) / NW : NHT;   // head tiles held by a wave
+    static constexpr int KHS = HS ? K2S : K3S;                   // head K-steps of a wave
+    static constexpr int NPART = HS ? 1 : NW;                    // head results per row
+    static constexpr int R = 16 * NT;
+    static constexpr int P_IN = KIN * EB + 16;   // LDS row pitches (bytes)
+    static constexpr int P_H = H * EB + 16;
+    static constexpr int P_PART = NHP + 4;       // floats
+    static constexpr int OFF_IN = 0;
+    static constexpr int OFF_H1 = OFF_IN + R * P_IN;
+    static constexpr int OFF_H2 = OFF_H1 + R * P_H;
+    // split-M writes the head after a barrier that follows the last read of
+    // h1, so its results reuse the h1 tile
+    static constexpr int OFF_PART = HS ? OFF_H1 : OFF_H2 + R * P_H;
+    static constexpr int BYTES = HS ? OFF_H2 + R * P_H : OFF_PART + NPART * R * P_PART * 4;
+    static_assert(!HS || P_PART * 4 <= P_H, "head results fit in the h1 tile");
+    static_assert(FPW % 16 == 0 && FPW % K == 0 && KIN % K == 0 && H % K == 0, "tile shape");
+    static_assert(BYTES <= 160 * 1024, "LDS budget");
+
+    Frag w1[MT][K1S];
+    Frag w2[MT][K2S];
+    Frag w3[NHW][KHS];
+    float init1[MT][4], init2[MT][4];  // bias / output scale: accumulator start
+    float kx1[MT][4], kx2[MT][4];      // 2 log2(e) * output scale (tanh argument)
+    float o3[NHW][4];                  // head output scale
+    float inv_q1, inv_q2;              // 1 / scale of the h1 and h2 quantisation
+
+    __device__ static float row_scale(const float* s, int m, int m_valid) {
+        return (s != nullptr && m < m_valid) ? s[m] : 1.0f;
+    }
+
+    __device__ void load(const PolicyArgs& p, int wave, int lane) {
+        const int lr = lane & 15, kq = (lane >> 4) * KC;
+        const float a0 = DT == DT_FP8 ? p.act_scale[0] : 1.0f;
+        const float a1 = DT == DT_FP8 ? p.act_scale[1] : 1.0f;
+        const float a2 = DT == DT_FP8 ? p.act_scale[2] : 1.0f;
+        inv_q1 = 1.0f / a1;
+        inv_q2 = 1.0f / a2;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const int m = wave * FPW + mt * 16 + lr;
+#pragma unroll
+            for (int ks = 0; ks < K1S; ++ks) load_a(w1[mt][ks], p.w1, p.d_in, m, H, ks * K + kq, p.d_in);
+#pragma unroll
+            for (int ks = 0; ks < K2S; ++ks) load_a(w2[mt][ks], p.w2, H, m, H, ks * K + kq, H);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int mc = wave * FPW + mt * 16 + 4 * (lane >> 4) + i;   // C row
+                const float sc1 = row_scale(p.s1, mc, H) * a0;
+                const float sc2 = row_scale(p.s2, mc, H) * a1;
+                init1[mt][i] = p.b1[mc] / sc1;
+                init2[mt][i] = p.b2[mc] / sc2;
+                kx1[mt][i] = kTwoLog2e * sc1;
+                kx2[mt][i] = kTwoLog2e * sc2;
+            }
+        }
+#pragma unroll
+        for (int hw = 0; hw < NHW; ++hw) {
+            const int ht = HS ? wave + hw * NW : hw;   // head row tile
+            const int m = ht * 16 + lr;
+            const int kbase = HS ? 0 : wave * FPW;
+#pragma unroll
+            for (int ks = 0; ks < KHS; ++ks)
+                load_a(w3[hw][ks], p.w3, H, m, p.n_head, kbase + ks * K + kq, H);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) o3[hw][i] = row_scale(p.s3, ht * 16 + 4 * (lane >> 4) + i, p.n_head) * a2;
+        }
+    }
+
+    // Dense layer of this wave's MT output tiles for all NT row tiles,
+    // then tanh and quantisation into `out` (row-major [R][H]).
+    template <int KS>
+    __device__ __forceinline__ void dense_tanh(const Frag (&w)[MT][KS], const float (&init)[MT][4],
+                                               const float (&kx)[MT][4], const char* in, int p_in,
+                                               char* out, float inv_q, int wave, int lane) {
+        const int lr = lane & 15, kq = (lane >> 4) * KC;
+        f32x4 acc[MT][NT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                acc[mt][nt] = f32x4{init[mt][0], init[mt][1], init[mt][2], init[mt][3]};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            Frag b[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                b[nt] = M::lds(in + (nt * 16 + lr) * p_in + (ks * K + kq) * EB);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = M::mma(w[mt][ks], b[nt], acc[mt][nt]);
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const int feat = wave * FPW + mt * 16 + 4 * (lane >> 4);
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const f32x4 a = acc[mt][nt];
+                store4<DT>(out + (nt * 16 + lr) * P_H + feat * EB, tanh_scaled(a[0], kx[mt][0]),
+                           tanh_scaled(a[1], kx[mt][1]), tanh_scaled(a[2], kx[mt][2]),
+                           tanh_scaled(a[3], kx[mt][3]), inv_q);
+            }
+        }
+    }
+
+    // Phases A-C. The caller synchronises the workgroup afterwards.
+    __device__ void forward(char* smem, int wave, int lane) {
+        dense_tanh<K1S>(w1, init1, kx1, smem + OFF_IN, P_IN, smem + OFF_H1, inv_q1, wave, lane);
+        __syncthreads();
+        dense_tanh<K2S>(w2, init2, kx2, smem + OFF_H1, P_H, smem + OFF_H2, inv_q2, wave, lane);
+        if constexpr (HS)
+            __syncthreads();   // every wave reads all of h2
+        else
+            wave_lds_sync();   // each wave reads only its own h2 features
+        const int lr = lane & 15, kq = (lane >> 4) * KC;
+        const int kbase = HS ? 0 : wave * FPW;
+        f32x4 acc[NHW][NT];
+#pragma unroll
+        for (int hw = 0; hw < NHW; ++hw)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[hw][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const char* h2 = smem + OFF_H2;
+#pragma unroll
+        for (int ks = 0; ks < KHS; ++ks) {
+            Frag b[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                b[nt] = M::lds(h2 + (nt * 16 + lr) * P_H + (kbase + ks * K + kq) * EB);
+#pragma unroll
+            for (int hw = 0; hw < NHW; ++hw) {
+                if (HS && wave + hw * NW >= NHT) break;
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) acc[hw][nt] = M::mma(w3[hw][ks], b[nt], acc[hw][nt]);
+            }
+        }
+        float* part = reinterpret_cast<float*>(smem + OFF_PART) + (HS ? 0 : wave * R * P_PART);
+#pragma unroll
+        for (int hw = 0; hw < NHW; ++hw) {
+            const int ht = HS ? wave + hw * NW : hw;
+            if (HS && ht >= NHT) break;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const f32x4 a = acc[hw][nt];
+                const int j = ht * 16 + 4 * (lane >> 4);
+                *reinterpret_cast<float4*>(part + (nt * 16 + lr) * P_PART + j) =
+                    make_float4(a[0] * o3[hw][0], a[1] * o3[hw][1], a[2] * o3[hw][2], a[3] * o3[hw][3]);
+            }
+        }
+    }
+
+    // Head outputs of tile row r: bias + partials summed in wave order (split-K)
+    // or bias + the one result (split-M).
+    template <int NH>
+    __device__ static void head_row(const char* smem, const float* b3, int r, float (&h)[NH]) {
+        const float* part = reinterpret_cast<const float*>(smem + OFF_PART);
+#pragma unroll
+        for (int j = 0; j < NH; ++j) h[j] = 0.0f;
+#pragma unroll
+        for (int w = 0; w < NPART; ++w) {
+            const float* pr = part + (w * R + r) * P_PART;
+#pragma unroll
+            for (int j4 = 0; j4 < NHP / 4; ++j4) {
+                if (j4 * 4 >= NH) break;
+                const float4 v = *reinterpret_cast<const float4*>(pr + j4 * 4);
+                if (j4 * 4 + 0 < NH) h[j4 * 4 + 0] += v.x;
+                if (j4 * 4 + 1 < NH) h[j4 * 4 + 1] += v.y;
+                if (j4 * 4 + 2 < NH) h[j4 * 4 + 2] += v.z;
+                if (j4 * 4 + 3 < NH) h[j4 * 4 + 3] += v.w;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NH; ++j) h[j] += b3[j];
+    }
+
+    // Quantised observation row into the input tile.
+    template <int OD>
+    __device__ static void put_obs(char* smem, int r, const float (&o)[OD], float inv_q0) {
+        char* p = smem + OFF_IN + r * P_IN;
+#pragma unroll
+        for (int k = 0; k < OD; ++k) store1<DT>(p + k * EB, o[k], inv_q0);
+    }
+};
+
+// ------------------------------------------------------------- sampling --
+// Categorical: softmax (max subtracted), CDF, a = min{k : u < C_k} else K-1.
+template <int K>
+__device__ __forceinline__ int sample_categorical(const float* logits, float u, float& logp) {
+    float mx = logits[0];
+#pragma unroll
+    for (int k = 1; k < K; ++k) mx = fmaxf(mx, logits[k]);
+    float e[K];
+    float z = 0.0f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        e[k] = expf(logits[k] - mx);
+        z += e[k];
+    }
+    const float inv_z = 1.0f / z;
+    int a = K - 1;
+    bool found = false;
+    float cdf = 0.0f, la = logits[K - 1];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        cdf += e[k] * inv_z;
+        if (!found && u < cdf) {
+            a = k;
+            la = logits[k];
+            found = true;
+        }
+    }
+    logp = (la - mx) - logf(z);
+    return a;
+}
+
+template <class E>
+struct Act {
+    int index;
+    float value;
+};
+
+// Draw the action of row `row` at step t from its head outputs.
+template <class E, int NH>
+__device__ __forceinline__ Act<E> choose(const float (&h)[NH], const RngKey& key, uint32_t t,
+                                         uint32_t row, float log_std, float& logp) {
+    const Words w = draw(key, t, row, PURPOSE_ACTION, 0);
+    Act<E> act{0, 0.0f};
+    if constexpr (E::NACT > 0) {
+        act.index = sample_categorical<E::NACT>(h, unit_uniform(w.w[0]), logp);
+        act.value = (float)act.index;
+    } else {
+        float zc, zs;
+        gauss_pair(unit_uniform(w.w[0]), unit_uniform(w.w[1]), zc, zs);
+        act.value = h[0] + expf(log_std) * zc;
+        logp = -0.5f * zc * zc - log_std - 0.91893853320467274f;   // log(2 pi) / 2
+    }
+    return act;
+}
+
+template <class E>
+__device__ __forceinline__ void store_action(const TrajArgs& tr, size_t idx, const Act<E>& a) {
+    if constexpr (E::NACT > 0)
+        static_cast<uint8_t*>(tr.action)[idx] = (uint8_t)a.index;
+    else
+        static_cast<float*>(tr.action)[idx] = a.value;
+}
+
+template <class E>
+__device__ __forceinline__ Act<E> load_action(const TrajArgs& tr, size_t idx) {
+    Act<E> a{0, 0.0f};
+    if constexpr (E::NACT > 0)
+        a.index = static_cast<const uint8_t*>(tr.action)[idx];
+    else
+        a.value = static_cast<const float*>(tr.action)[idx];
+    return a;
+}
+
+// ------------------------------------------------------------- env glue --
+template <class E>
+__device__ __forceinline__ void load_state(const EnvArgs& env, int64_t row, float (&s)[E::SD]) {
+#pragma unroll
+    for (int i = 0; i < E::SD; ++i) s[i] = env.state[(size_t)i * env.n_rows + row];
+}
+
+template <class E>
+__device__ __forceinline__ void save_state(const EnvArgs& env, int64_t row, const float (&s)[E::SD]) {
+#pragma unroll
+    for (int i = 0; i < E::SD; ++i) env.state[(size_t)i * env.n_rows + row] = s[i];
+}
+
+// Stage the reaction potential in LDS: A, centres, -1/(2 w^2), amplitudes.
+__device__ void stage_params(float* dst, const float* src, int tid, int nthreads) {
+    constexpr int NA = Reaction::NDIM * Reaction::NDIM + Reaction::NG * Reaction::NDIM;
+    for (int i = tid; i < Reaction::PARAM_FLOATS; i += nthreads) {
+        float v = src[i];
+        if (i >= NA && i < NA + Reaction::NG) v = -0.5f / (v * v);
+        dst[i] = v;
+    }
+}
+
+template <class E>
+constexpr int extra_lds_bytes(int R) {
+    if constexpr (E::KIND == Reaction::KIND) return Reaction::PARAM_FLOATS * 4;
+    if constexpr (E::KIND == Market::KIND) return 2 * R * 2 * 4;   // [parity][slot][D, S]
+    return 0;
+}
+
+__device__ __forceinline__ uint32_t step_base(const EnvArgs& env) {
+    return env.step_ptr ? *env.step_ptr : env.t0;
+}
+
+__device__ __forceinline__ Tile tile_of(const EnvArgs& env, int tile, int R) {
+    if (env.tiles) return env.tiles[tile];
+    Tile t;
+    t.row0 = tile * R;
+    t.row1 = (int)min((int64_t)(tile + 1) * R, env.n_rows);
+    t.env0 = t.row0;
+    t.env1 = t.row1;
+    return t;
+}
+
+// Market: slot of row r (global) among the tile's envs (binary search).
+__device__ __forceinline__ int env_slot(const EnvArgs& env, const Tile& tl, int r) {
+    int lo = tl.env0, hi = tl.env1 - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (env.offsets[mid] <= r) lo = mid; else hi = mid - 1;
+    }
+    return lo - tl.env0;
+}
+
+// ---------------------------------------------------------- fused form --
+template <class E, int DT, int H, int NW, int NT, int HS>
+__global__ void __launch_bounds__(NW * 64, 1)
+k_fused(EnvArgs env, PolicyArgs pol, TrajArgs tr, int horizon) {
+    using HO = HeadOf<E>;
+    using L = Mlp<DT, H, NW, NT, kin_of<E, DT>(), HO::NHP, HS>;
+    constexpr int R = L::R;
+    constexpr int NTHR = NW * 64;
+    static_assert(R <= NTHR, "one thread per tile row");
+    __shared__ __attribute__((aligned(16))) char smem[L::BYTES + extra_lds_bytes<E>(R)];
+    char* extra = smem + L::BYTES;
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    L mlp;
+    mlp.load(pol, wave, lane);
+    const float inv_q0 = DT == DT_FP8 ? 1.0f / pol.act_scale[0] : 1.0f;
+    const float log_std = (E::NACT == 0 && pol.log_std) ? pol.log_std[0] : 0.0f;
+    float b3[HO::NH];
+#pragma unroll
+    for (int j = 0; j < HO::NH; ++j) b3[j] = pol.b3[j];
+
+    EnvCtx ctx{nullptr};
+    if constexpr (E::KIND == Reaction::KIND) {
+        stage_params(reinterpret_cast<float*>(extra), env.params, tid, NTHR);
+        ctx.lds_params = reinterpret_cast<const float*>(extra);
+    }
+    // zero the input tile once: its padding columns stay zero
+    for (int i = tid; i < R * L::P_IN / 4; i += NTHR)
+        reinterpret_cast<uint32_t*>(smem + L::OFF_IN)[i] = 0u;
+    __syncthreads();
+
+    const RngKey key{env.k0, env.k1, env.epoch};
+    const uint32_t t0 = step_base(env);
+    int* sums = reinterpret_cast<int*>(extra);   // market: [2][R][2]
+
+    for (int tile = blockIdx.x; tile < env.n_tiles; tile += gridDim.x) {
+        const Tile tl = tile_of(env, tile, R);
+        const int row = tl.row0 + tid;
+        const bool mine = tid < R;
+        const bool valid = mine && row < tl.row1;
+        float s[E::SD];
+#pragma unroll
+        for (int i = 0; i < E::SD; ++i) s[i] = 0.0f;
+        if (valid) load_state<E>(env, row, s);
+        int slot = 0;
+        if constexpr (E::KIND == Market::KIND) {
+            if (valid) slot = env_slot(env, tl, row);
+            for (int i = tid; i < 4 * R; i += NTHR) sums[i] = 0;
+        }
+        if (mine) {
+            float o[E::OD];
+            E::observe(s, o);
+            L::template put_obs<E::OD>(smem, tid, o, inv_q0);
+            if (valid && horizon > 0)
+#pragma unroll
+                for (int k = 0; k < E::OD; ++k) tr.obs[(size_t)row * E::OD + k] = o[k];
+        }
+        __syncthreads();
+
+        for (int step = 0; step <= horizon; ++step) {
+            mlp.forward(smem, wave, lane);
+            __syncthreads();
+            const uint32_t t = t0 + (uint32_t)step;
+            const size_t idx = (size_t)step * env.n_rows + row;
+            Act<E> act{0, 0.0f};
+            if (mine) {
+                float h[HO::NH];
+                L::template head_row<HO::NH>(smem, b3, tid, h);
+                if (step == horizon) {
+                    if (valid) tr.last_value[row] = h[HO::NOUT];
+                } else if (valid) {
+                    float logp;
+                    act = choose<E, HO::NH>(h, key, t, (uint32_t)row, log_std, logp);
+                    tr.value[idx] = h[HO::NOUT];
+                    tr.logp[idx] = logp;
+                    store_action<E>(tr, idx, act);
+                    if constexpr (E::KIND == Market::KIND) {
+                        int dh, s18;
+                        Market::decide(act.index, dh, s18);
+                        int* sl = sums + ((step & 1) * R + slot) * 2;
+                        atomicAdd(sl, dh);
+                        atomicAdd(sl + 1, s18);
+                    }
+                }
+            }
+            if constexpr (E::KIND == Market::KIND) {
+                __syncthreads();
+                if (step < horizon) {
+                    if (valid) {
+                        const int* sl = sums + ((step & 1) * R + slot) * 2;
+                        float reward;
+                        Market::settle(s, act.index, sl[0], sl[1], reward);
+                        tr.reward[idx] = reward;
+                        tr.done[idx] = 0;
+                    }
+                    // the other parity's sums were last read in the previous step
+                    for (int i = tid; i < 2 * R; i += NTHR) sums[((step + 1) & 1) * 2 * R + i] = 0;
+                }
+            } else {
+                if (valid && step < horizon) {
+                    float reward;
+                    bool done;
+                    E::step(s, act.index, act.value, t, (uint32_t)row, key, ctx, reward, done);
+                    if (done) E::reset(s, key, t + 1, (uint32_t)row, ctx);
+                    tr.reward[idx] = reward;
+                    tr.done[idx] = done ? 1 : 0;
+                }
+            }
+            if (valid && step < horizon) {
+                float o[E::OD];
+                E::observe(s, o);
+                L::template put_obs<E::OD>(smem, tid, o, inv_q0);
+                if (step + 1 < horizon) {
+                    const size_t nidx = (size_t)(step + 1) * env.n_rows + row;
+#pragma unroll
+                    for (int k = 0; k < E::OD; ++k) tr.obs[nidx * E::OD + k] = o[k];
+                }
+            }
+            __syncthreads();
+        }
+        if (valid) save_state<E>(env, row, s);
+    }
+}
+
+// ---------------------------------------------------------- plain form --
+template <class E>
+__global__ void k_plain_observe(EnvArgs env, TrajArgs tr, int horizon) {
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= env.n_rows) return;
+    float s[E::SD];
+    load_state<E>(env, row, s);
+    float o[E::OD];
+    E::observe(s, o);
+#pragma unroll
+    for (int k = 0; k < E::OD; ++k) {
+        env.obs_scratch[row * E::OD + k] = o[k];
+        if (horizon > 0) tr.obs[row * E::OD + k] = o[k];
+    }
+}
+
+// Policy over one tile of rows per workgroup: obs_scratch -> head_scratch.
+template <class E, int DT, int H, int NW, int NT, int HS>
+__global__ void __launch_bounds__(NW * 64, 1) k_plain_policy(EnvArgs env, PolicyArgs pol) {
+    using HO = HeadOf<E>;
+    using L = Mlp<DT, H, NW, NT, kin_of<E, DT>(), HO::NHP, HS>;
+    constexpr int R = L::R;
+    __shared__ __attribute__((aligned(16))) char smem[L::BYTES];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    L mlp;
+    mlp.load(pol, wave, lane);
+    const float inv_q0 = DT == DT_FP8 ? 1.0f / pol.act_scale[0] : 1.0f;
+    for (int i = tid; i < R * L::P_IN / 4; i += NW * 64)
+        reinterpret_cast<uint32_t*>(smem + L::OFF_IN)[i] = 0u;
+    __syncthreads();
+    const Tile tl = tile_of(env, blockIdx.x, R);
+    const int row = tl.row0 + tid;
+    const bool valid = tid < R && row < tl.row1;
+    if (valid) {
+        float o[E::OD];
+#pragma unroll
+        for (int k = 0; k < E::OD; ++k) o[k] = env.obs_scratch[(size_t)row * E::OD + k];
+        L::template put_obs<E::OD>(smem, tid, o, inv_q0);
+    }
+    __syncthreads();
+    mlp.forward(smem, wave, lane);
+    __syncthreads();
+    if (valid) {
+        float b3[HO::NH];
+#pragma unroll
+        for (int j = 0; j < HO::NH; ++j) b3[j] = pol.b3[j];
+        float h[HO::NH];
+        L::template head_row<HO::NH>(smem, b3, tid, h);
+#pragma unroll
+        for (int j = 0; j < HO::NH; ++j) env.head_scratch[(size_t)row * HO::NH + j] = h[j];
+    }
+}
+
+template <class E>
+__global__ void k_plain_sample(EnvArgs env, PolicyArgs pol, TrajArgs tr, int step) {
+    using HO = HeadOf<E>;
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= env.n_rows) return;
+    float h[HO::NH];
+#pragma unroll
+    for (int j = 0; j < HO::NH; ++j) h[j] = env.head_scratch[row * HO::NH + j];
+    const RngKey key{env.k0, env.k1, env.epoch};
+    const uint32_t t = step_base(env) + (uint32_t)step;
+    const float log_std = (E::NACT == 0 && pol.log_std) ? pol.log_std[0] : 0.0f;
+    float logp;
+    const Act<E> a = choose<E, HO::NH>(h, key, t, (uint32_t)row, log_std, logp);
+    const size_t idx = (size_t)step * env.n_rows + row;
+    tr.value[idx] = h[HO::NOUT];
+    tr.logp[idx] = logp;
+    store_action<E>(tr, idx, a);
+}
+
+template <class E>
+__device__ __forceinline__ void finish_row(const EnvArgs& env, const TrajArgs& tr, int64_t row,
+                                           const float (&s)[E::SD], int step, int horizon) {
+    save_state<E>(env, row, s);
+    float o[E::OD];
+    E::observe(s, o);
+    const size_t nidx = (size_t)(step + 1) * env.n_rows + row;
+#pragma unroll
+    for (int k = 0; k < E::OD; ++k) {
+        env.obs_scratch[row * E::OD + k] = o[k];
+        if (step + 1 < horizon) tr.obs[nidx * E::OD + k] = o[k];
+    }
+}
+
+template <class E>
+__global__ void k_plain_step(EnvArgs env, TrajArgs tr, int step, int horizon) {
+    __shared__ float params[E::KIND == Reaction::KIND ? Reaction::PARAM_FLOATS : 1];
+    EnvCtx ctx{nullptr};
+    if constexpr (E::KIND == Reaction::KIND) {
+        // every block stages the potential (the plain form re-reads it per launch)
+        stage_params(params, env.params, threadIdx.x, blockDim.x);
+        ctx.lds_params = params;
+    }
+    __syncthreads();
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= env.n_rows) return;
+    const RngKey key{env.k0, env.k1, env.epoch};
+    const uint32_t t = step_base(env) + (uint32_t)step;
+    float s[E::SD];
+    load_state<E>(env, row, s);
+    const size_t idx = (size_t)step * env.n_rows + row;
+    const Act<E> a = load_action<E>(tr, idx);
+    float reward;
+    bool done;
+    E::step(s, a.index, a.value, t, (uint32_t)row, key, ctx, reward, done);
+    if (done) E::reset(s, key, t + 1, (uint32_t)row, ctx);
+    tr.reward[idx] = reward;
+    tr.done[idx] = done ? 1 : 0;
+    finish_row<E>(env, tr, row, s, step, horizon);
+}
+
+// Market step: one workgroup per tile of whole envs, exact integer sums.
+__global__ void __launch_bounds__(256) k_plain_step_market(EnvArgs env, TrajArgs tr, int step,
+                                                           int horizon) {
+    __shared__ int sums[256 * 2];
+    const Tile tl = env.tiles[blockIdx.x];
+    const int n = tl.row1 - tl.row0;
+    for (int i = threadIdx.x; i < 2 * (tl.env1 - tl.env0); i += blockDim.x) sums[i] = 0;
+    __syncthreads();
+    int slot[2], act[2];
+    for (int r = threadIdx.x, q = 0; q < 2; r += blockDim.x, ++q) {
+        slot[q] = -1;
+        if (r < n) {
+            const int row = tl.row0 + r;
+            slot[q] = env_slot(env, tl, row);
+            act[q] = static_cast<const uint8_t*>(tr.action)[(size_t)step * env.n_rows + row];
+            int dh, s18;
+            Market::decide(act[q], dh, s18);
+            atomicAdd(&sums[slot[q] * 2], dh);
+            atomicAdd(&sums[slot[q] * 2 + 1], s18);
+        }
+    }
+    __syncthreads();
+    for (int r = threadIdx.x, q = 0; q < 2; r += blockDim.x, ++q) {
+        if (slot[q] < 0) continue;
+        const int64_t row = tl.row0 + r;
+        float s[Market::SD];
+        load_state<Market>(env, row, s);
+        float reward;
+        Market::settle(s, act[q], sums[slot[q] * 2], sums[slot[q] * 2 + 1], reward);
+        const size_t idx = (size_t)step * env.n_rows + row;
+        tr.reward[idx] = reward;
+        tr.done[idx] = 0;
+        finish_row<Market>(env, tr, row, s, step, horizon);
+    }
+}
+
+template <class E>
+__global__ void k_plain_last(EnvArgs env, TrajArgs tr) {
+    using HO = HeadOf<E>;
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= env.n_rows) return;
+    tr.last_value[row] = env.head_scratch[row * HO::NH + HO::NOUT];
+}
+
+__global__ void k_set_step(uint32_t* p, uint32_t v) { *p = v; }
+
+// -------------------------------------------------------------- reset --
+template <class E>
+__global__ void k_reset(EnvArgs env) {
+    __shared__ float params[E::KIND == Reaction::KIND ? Reaction::PARAM_FLOATS : 1];
+    EnvCtx ctx{nullptr};
+    if constexpr (E::KIND == Reaction::KIND) {
+        stage_params(params, env.params, threadIdx.x, blockDim.x);
+        ctx.lds_params = params;
+    }
+    __syncthreads();
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= env.n_rows) return;
+    const RngKey key{env.k0, env.k1, env.epoch};
+    float s[E::SD];
+    E::reset(s, key, 0u, (uint32_t)row, ctx);
+    save_state<E>(env, row, s);
+}
+
+// -------------------------------------------------------- small kernels --
+__global__ void k_quantize(int dtype, float scale, const float* x, float* y, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float v = x[i];
+    if (dtype == DT_BF16) {
+        y[i] = bf16_bits_to_f32(pack_bf16x2(v, 0.0f) & 0xFFFFu);
+    } else if (dtype == DT_FP8) {
+        y[i] = fp8_code_to_f32(pack_fp8x4(v / scale, 0.f, 0.f, 0.f) & 0xFFu) * scale;
+    } else {
+        y[i] = v;
+    }
+}
+
+// ---------------------------------------------------------- dispatching --
+#define WSX_VARIANTS(X)                      \
+    X(CartPole, DT_F32, 64, 4, 1, 0)         \
+    X(CartPole, DT_F32, 64, 4, 2, 0)         \
+    X(CartPole, DT_F32, 64, 4, 4, 0)         \
+    X(Pendulum, DT_BF16, 256, 4, 2, 0)       \
+    X(Pendulum, DT_BF16, 256, 4, 4, 0)       \
+    X(Pendulum, DT_BF16, 256, 4, 5, 0)       \
+    X(Pendulum, DT_BF16, 256, 8, 4, 0)       \
+    X(Pendulum, DT_BF16, 256, 8, 5, 0)       \
+    X(Acrobot, DT_BF16, 256, 4, 2, 0)        \
+    X(Acrobot, DT_BF16, 256, 4, 4, 0)        \
+    X(Acrobot, DT_BF16, 256, 4, 5, 0)        \
+    X(Acrobot, DT_BF16, 256, 8, 4, 0)        \
+    X(Acrobot, DT_BF16, 256, 8, 5, 0)        \
+    X(Market, DT_BF16, 256, 4, 8, 1)         \
+    X(Market, DT_BF16, 256, 8, 8, 1)         \
+    X(Reaction, DT_FP8, 512, 8, 1, 0)        \
+    X(Reaction, DT_FP8, 512, 8, 2, 0)        \
+    X(Reaction, DT_FP8, 512, 8, 4, 1)
+
+struct VariantEntry {
+    Variant v;
+    const void* fused;
+    const void* policy;
+};
+
+#define WSX_ENTRY(E, DT, H, NW, NT, HS)                                               \
+    {{E::KIND, DT, H, NW, 16 * NT},                                                   \
+     reinterpret_cast<const void*>(&k_fused<E, DT, H, NW, NT, HS>),                   \
+     reinterpret_cast<const void*>(&k_plain_policy<E, DT, H, NW, NT, HS>)},
+
+static const VariantEntry kVariants[] = {WSX_VARIANTS(WSX_ENTRY)};
+static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+int n_variants() { return kNumVariants; }
+const Variant& variant(int i) { return kVariants[i].v; }
+
+static const VariantEntry* find_entry(const Variant& v) {
+    for (int i = 0; i < kNumVariants; ++i) {
+        const Variant& w = kVariants[i].v;
+        if (w.kind == v.kind && w.dtype == v.dtype && w.hidden == v.hidden && w.waves == v.waves &&
+            w.tile_rows == v.tile_rows)
+            return &kVariants[i];
+    }
+    return nullptr;
+}
+
+int fused_blocks_per_cu(const Variant& v) {
+    const VariantEntry* e = find_entry(v);
+    if (!e) return 0;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, e->fused, v.waves * 64, 0) != hipSuccess)
+        return 1;
+    return n > 0 ? n : 1;
+}
+
+hipError_t launch_fused(const Variant& v, const EnvArgs& env, const PolicyArgs& pol,
+                        const TrajArgs& tr, int horizon, int grid, hipStream_t s) {
+    const VariantEntry* e = find_entry(v);
+    if (!e) return hipErrorInvalidValue;
+    void* args[] = {(void*)&env, (void*)&pol, (void*)&tr, (void*)&horizon};
+    return hipLaunchKernel(e->fused, dim3(grid), dim3(v.waves * 64), args, 0, s);
+}
+
+template <class E>
+static hipError_t plain_sequence(const VariantEntry* e, const EnvArgs& env, const PolicyArgs& pol,
+                                 const TrajArgs& tr, int horizon, hipStream_t s) {
+    const int threads = 256;
+    const int blocks = (int)((env.n_rows + threads - 1) / threads);
+    hipLaunchKernelGGL(k_plain_observe<E>, dim3(blocks), dim3(threads), 0, s, env, tr, horizon);
+    void* pargs[] = {(void*)&env, (void*)&pol};
+    for (int step = 0; step <= horizon; ++step) {
+        hipError_t err = hipLaunchKernel(e->policy, dim3(env.n_tiles), dim3(e->v.waves * 64),
+                                         pargs, 0, s);
+        if (err != hipSuccess) return err;
+        if (step == horizon) break;
+        hipLaunchKernelGGL(k_plain_sample<E>, dim3(blocks), dim3(threads), 0, s, env, pol, tr,
+                           step);
+        if constexpr (E::KIND == Market::KIND)
+            hipLaunchKernelGGL(k_plain_step_market, dim3(env.n_tiles), dim3(256), 0, s, env, tr,
+                               step, horizon);
+        else
+            hipLaunchKernelGGL(k_plain_step<E>, dim3(blocks), dim3(threads), 0, s, env, tr, step,
+                               horizon);
+    }
+    hipLaunchKernelGGL(k_plain_last<E>, dim3(blocks), dim3(threads), 0, s, env, tr);
+    return hipGetLastError();
+}
+
+hipError_t launch_plain(const Variant& v, const EnvArgs& env, const PolicyArgs& pol,
+                        const TrajArgs& tr, int horizon, bool, hipStream_t s) {
+    const VariantEntry* e = find_entry(v);
+    if (!e) return hipErrorInvalidValue;
+    switch (v.kind) {
+    case CartPole::KIND: return plain_sequence<CartPole>(e, env, pol, tr, horizon, s);
+    case Pendulum::KIND: return plain_sequence<Pendulum>(e, env, pol, tr, horizon, s);
+    case Acrobot::KIND: return plain_sequence<Acrobot>(e, env, pol, tr, horizon, s);
+    case Market::KIND: return plain_sequence<Market>(e, env, pol, tr, horizon, s);
+    case Reaction::KIND: return plain_sequence<Reaction>(e, env, pol, tr, horizon, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_set_step(uint32_t* step_ptr, int value, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, s, step_ptr, (uint32_t)value);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset(int kind, const EnvArgs& env, hipStream_t s) {
+    const int threads = 256;
+    const int blocks = (int)((env.n_rows + threads - 1) / threads);
+    switch (kind) {
+    case CartPole::KIND: hipLaunchKernelGGL(k_reset<CartPole>, dim3(blocks), dim3(threads), 0, s, env); break;
+    case Pendulum::KIND: hipLaunchKernelGGL(k_reset<Pendulum>, dim3(blocks), dim3(threads), 0, s, env); break;
+    case Acrobot::KIND: hipLaunchKernelGGL(k_reset<Acrobot>, dim3(blocks), dim3(threads), 0, s, env); break;
+    case Market::KIND: hipLaunchKernelGGL(k_reset<Market>, dim3(blocks), dim3(threads), 0, s, env); break;
+    case Reaction::KIND: hipLaunchKernelGGL(k_reset<Reaction>, dim3(blocks), dim3(threads), 0, s, env); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_policy_forward(const Variant& v, const PolicyArgs& pol, const float* obs,
+                                 int64_t rows, float* head, hipStream_t s) {
+    const VariantEntry* e = find_entry(v);
+    if (!e) return hipErrorInvalidValue;
+    EnvArgs env{};
+    env.obs_scratch = const_cast<float*>(obs);
+    env.head_scratch = head;
+    env.n_rows = rows;
+    env.n_tiles = (int)((rows + v.tile_rows - 1) / v.tile_rows);
+    void* args[] = {(void*)&env, (void*)&pol};
+    return hipLaunchKernel(e->policy, dim3(env.n_tiles), dim3(v.waves * 64), args, 0, s);
+}
+
+hipError_t launch_quantize(int dtype, float scale, const float* x, float* y, int64_t n,
+                           hipStream_t s) {
+    const int threads = 256;
+    hipLaunchKernelGGL(k_quantize, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0,
+                       s, dtype, scale, x, y, n);
+    return hipGetLastError();
+}
+
+}  // namespace wsx

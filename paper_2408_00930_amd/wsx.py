@@ -1,0 +1,248 @@
+"""Thin ctypes binding of libwsx.so (include/wsx.h), argument marshalling only.
+
+torch provides the device memory (tensors) and the stream (torch's current
+stream); every step of the roll-out runs in the library's HIP kernels. torch
+is imported before the library is loaded so that the library binds to the HIP
+runtime torch has already loaded. There is no fallback: if the library is
+missing or fails to load, every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwsx.so")
+
+CARTPOLE, PENDULUM, ACROBOT, MARKET, REACTION = 1, 2, 3, 4, 5
+F32, BF16, FP8_E4M3, F64 = 0, 1, 2, 3
+MODE_FUSED, MODE_PLAIN, MODE_GRAPH = 0, 1, 2
+DTYPE_CODE = {"f32": F32, "bf16": BF16, "fp8": FP8_E4M3}
+
+OBS_DIM = {CARTPOLE: 4, PENDULUM: 3, ACROBOT: 6, MARKET: 32, REACTION: 20}
+STATE_DIM = {CARTPOLE: 4, PENDULUM: 2, ACROBOT: 4, MARKET: 32, REACTION: 21}
+N_ACTIONS = {CARTPOLE: 2, PENDULUM: 0, ACROBOT: 0, MARKET: 50, REACTION: 40}
+
+
+class WsxError(RuntimeError):
+    pass
+
+
+class _Policy(C.Structure):
+    _fields_ = [("dtype", C.c_int32), ("d_in", C.c_int32), ("h1", C.c_int32),
+                ("h2", C.c_int32), ("n_head", C.c_int32),
+                ("w1", C.c_void_p), ("w2", C.c_void_p), ("w3", C.c_void_p),
+                ("b1", C.c_void_p), ("b2", C.c_void_p), ("b3", C.c_void_p),
+                ("s1", C.c_void_p), ("s2", C.c_void_p), ("s3", C.c_void_p),
+                ("act_scale", C.c_float * 3), ("log_std", C.c_void_p)]
+
+
+class _Traj(C.Structure):
+    _fields_ = [("capacity", C.c_int32), ("obs", C.c_void_p), ("action", C.c_void_p),
+                ("reward", C.c_void_p), ("done", C.c_void_p), ("value", C.c_void_p),
+                ("logp", C.c_void_p), ("last_value", C.c_void_p)]
+
+
+class _EnvDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("tile_rows", C.c_int32), ("n_envs", C.c_int64),
+                ("seed", C.c_uint64), ("state", C.c_void_p), ("agent_offsets", C.c_void_p),
+                ("params", C.c_void_p)]
+
+
+EXPORTS = ["wsx_env_state_bytes", "wsx_env_create", "wsx_env_reset", "wsx_rollout",
+           "wsx_env_info", "wsx_env_set_step", "wsx_env_destroy", "wsx_compute_returns",
+           "wsx_policy_forward", "wsx_quantize", "wsx_last_error"]
+
+_lib = None
+
+
+def lib():
+    """Load libwsx.so (raises if it is missing: there is no other path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise WsxError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2408_00930_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, u32, u64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_double
+        L.wsx_env_state_bytes.argtypes = [i32, i64, i64, C.POINTER(C.c_size_t)]
+        L.wsx_env_create.argtypes = [C.POINTER(_EnvDesc), C.POINTER(vp)]
+        L.wsx_env_reset.argtypes = [vp, u32, vp]
+        L.wsx_rollout.argtypes = [vp, C.POINTER(_Policy), i32, C.POINTER(_Traj), i32, vp]
+        L.wsx_env_info.argtypes = [vp, C.POINTER(i64), C.POINTER(u32), C.POINTER(u32)]
+        L.wsx_env_set_step.argtypes = [vp, u32]
+        L.wsx_env_destroy.argtypes = [vp]
+        L.wsx_compute_returns.argtypes = [vp, vp, vp, vp, i32, i64, f64, f64, i32, vp, vp, i32, vp]
+        L.wsx_policy_forward.argtypes = [C.POINTER(_Policy), vp, i64, vp, vp]
+        L.wsx_quantize.argtypes = [i32, C.c_float, vp, vp, i64, vp]
+        L.wsx_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise WsxError(f"wsx error {rc}: {lib().wsx_last_error().decode()}")
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------- policies ----
+
+class DevicePolicy:
+    """A policy's weights as device tensors plus the wsx_policy view of them."""
+
+    def __init__(self, policy, device="cuda"):
+        self.host = policy
+        dev = torch.device(device)
+
+        def t(a):
+            return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        self.tensors = {n: t(getattr(policy, n)) for n in
+                        ("w1", "w2", "w3", "b1", "b2", "b3", "s1", "s2", "s3", "log_std")}
+        fp8 = policy.dtype == "fp8"
+        g = self.tensors
+        self.c = _Policy(DTYPE_CODE[policy.dtype], policy.d_in, policy.h1, policy.h2,
+                         policy.n_head, g["w1"].data_ptr(), g["w2"].data_ptr(),
+                         g["w3"].data_ptr(), g["b1"].data_ptr(), g["b2"].data_ptr(),
+                         g["b3"].data_ptr(),
+                         g["s1"].data_ptr() if fp8 else None,
+                         g["s2"].data_ptr() if fp8 else None,
+                         g["s3"].data_ptr() if fp8 else None,
+                         (C.c_float * 3)(*policy.act_scale), g["log_std"].data_ptr())
+
+
+# ----------------------------------------------------------- trajectory ----
+
+class Trajectory:
+    """Device trajectory buffers, [T][rows] (obs [T][rows][obs_dim])."""
+
+    def __init__(self, kind, horizon, rows, device="cuda"):
+        dev = torch.device(device)
+        self.capacity = horizon
+        self.obs = torch.empty((horizon, rows, OBS_DIM[kind]), dtype=torch.float32, device=dev)
+        adt = torch.uint8 if N_ACTIONS[kind] else torch.float32
+        self.action = torch.empty((horizon, rows), dtype=adt, device=dev)
+        self.reward = torch.empty((horizon, rows), dtype=torch.float32, device=dev)
+        self.done = torch.empty((horizon, rows), dtype=torch.uint8, device=dev)
+        self.value = torch.empty((horizon, rows), dtype=torch.float32, device=dev)
+        self.logp = torch.empty((horizon, rows), dtype=torch.float32, device=dev)
+        self.last_value = torch.empty((rows,), dtype=torch.float32, device=dev)
+        self.c = _Traj(horizon, *[_ptr(x) for x in (self.obs, self.action, self.reward,
+                                                     self.done, self.value, self.logp,
+                                                     self.last_value)])
+
+    def host(self):
+        return {k: getattr(self, k).cpu().numpy() for k in
+                ("obs", "action", "reward", "done", "value", "logp", "last_value")}
+
+
+# ----------------------------------------------------------------- envs ----
+
+def env_state_bytes(kind, n_envs, n_rows):
+    out = C.c_size_t()
+    _check(lib().wsx_env_state_bytes(kind, n_envs, n_rows, C.byref(out)))
+    return out.value
+
+
+class Env:
+    """An environment set: its device state block and the library handle."""
+
+    def __init__(self, kind, n_envs, seed=0, agent_offsets=None, params=None, tile_rows=0,
+                 device="cuda"):
+        self.kind = kind
+        self.n_envs = n_envs
+        dev = torch.device(device)
+        self.offsets = None if agent_offsets is None else np.ascontiguousarray(agent_offsets, np.int32)
+        rows = int(self.offsets[-1]) if self.offsets is not None else n_envs
+        self.rows = rows
+        nbytes = env_state_bytes(kind, n_envs, rows)
+        self.block = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
+        self.params = None if params is None else torch.from_numpy(
+            np.ascontiguousarray(params, np.float32)).to(dev)
+        desc = _EnvDesc(kind, tile_rows, n_envs, seed, self.block.data_ptr(),
+                        None if self.offsets is None else self.offsets.ctypes.data,
+                        None if self.params is None else self.params.data_ptr())
+        h = C.c_void_p()
+        _check(lib().wsx_env_create(C.byref(desc), C.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.wsx_env_destroy(self.handle)
+            self.handle = None
+
+    @property
+    def state(self):
+        """The state as a [state_dim, rows] float32 view (structure of arrays)."""
+        sd = STATE_DIM[self.kind]
+        return self.block[: sd * self.rows * 4].view(torch.float32).view(sd, self.rows)
+
+    def info(self):
+        rows, step, epoch = C.c_int64(), C.c_uint32(), C.c_uint32()
+        _check(lib().wsx_env_info(self.handle, C.byref(rows), C.byref(step), C.byref(epoch)))
+        return rows.value, step.value, epoch.value
+
+    def set_step(self, step):
+        _check(lib().wsx_env_set_step(self.handle, step))
+
+
+def env_reset(env, epoch=0, stream=None):
+    _check(lib().wsx_env_reset(env.handle, epoch, _stream(stream)))
+
+
+def rollout(env, policy, horizon, traj, mode=MODE_FUSED, stream=None):
+    _check(lib().wsx_rollout(env.handle, C.byref(policy.c), horizon, C.byref(traj.c), mode,
+                             _stream(stream)))
+
+
+def compute_returns(traj, horizon, gamma, lam, bootstrap=True, out_dtype=torch.float64,
+                    returns=None, advantages=None, stream=None):
+    rows = traj.reward.shape[1]
+    if returns is None:
+        returns = torch.empty((horizon, rows), dtype=out_dtype, device=traj.reward.device)
+    if advantages is None:
+        advantages = torch.empty((horizon, rows), dtype=out_dtype, device=traj.reward.device)
+    code = F64 if out_dtype == torch.float64 else F32
+    _check(lib().wsx_compute_returns(_ptr(traj.reward), _ptr(traj.value), _ptr(traj.done),
+                                     _ptr(traj.last_value), horizon, rows, gamma, lam,
+                                     int(bootstrap), _ptr(returns), _ptr(advantages), code,
+                                     _stream(stream)))
+    return returns, advantages
+
+
+def compute_returns_raw(reward, value, done, last_value, gamma, lam, bootstrap=True,
+                        out_dtype=torch.float64, stream=None):
+    """Returns/GAE of raw [T][rows] device tensors."""
+    T, rows = reward.shape
+    ret = torch.empty((T, rows), dtype=out_dtype, device=reward.device)
+    adv = torch.empty((T, rows), dtype=out_dtype, device=reward.device)
+    code = F64 if out_dtype == torch.float64 else F32
+    _check(lib().wsx_compute_returns(_ptr(reward), _ptr(value), _ptr(done), _ptr(last_value),
+                                     T, rows, gamma, lam, int(bootstrap), _ptr(ret), _ptr(adv),
+                                     code, _stream(stream)))
+    return ret, adv
+
+
+def policy_forward(policy, obs, stream=None):
+    rows = obs.shape[0]
+    head = torch.empty((rows, policy.host.n_head), dtype=torch.float32, device=obs.device)
+    _check(lib().wsx_policy_forward(C.byref(policy.c), _ptr(obs), rows, _ptr(head),
+                                    _stream(stream)))
+    return head
+
+
+def quantize(dtype, x, scale=1.0, stream=None):
+    y = torch.empty_like(x)
+    _check(lib().wsx_quantize(dtype, scale, _ptr(x), _ptr(y), x.numel(), _stream(stream)))
+    return y

@@ -1,0 +1,78 @@
+"""The C-ABI library loads, exports every declared entry point, and rejects
+bad arguments on the host before touching a GPU (no compute calls here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wsx.h")
+
+
+def _lib():
+    from paper_2408_00930_amd import wsx
+    if not os.path.exists(wsx.LIB_PATH):
+        pytest.skip("libwsx.so not built (run __graft_entry__.build())")
+    return wsx, wsx.lib()
+
+
+def declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(wsx_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared()
+    for n in ("wsx_env_create", "wsx_env_reset", "wsx_rollout", "wsx_compute_returns",
+              "wsx_env_state_bytes", "wsx_env_destroy", "wsx_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    wsx, L = _lib()
+    for n in declared():
+        assert hasattr(L, n), n
+    assert sorted(wsx.EXPORTS) == declared()
+
+
+def test_state_bytes_validation():
+    wsx, L = _lib()
+    out = C.c_size_t()
+    assert L.wsx_env_state_bytes(99, 10, 10, C.byref(out)) == -1
+    assert b"unknown environment kind" in L.wsx_last_error()
+    assert L.wsx_env_state_bytes(wsx.PENDULUM, 0, 0, C.byref(out)) == -1
+    assert L.wsx_env_state_bytes(wsx.PENDULUM, 10, 12, C.byref(out)) == -1
+    assert L.wsx_env_state_bytes(wsx.PENDULUM, 10, 10, C.byref(out)) == 0
+    # state SoA + obs scratch + head scratch + step counter, 256-byte aligned
+    assert out.value == 256 + 256 + 256 + 256
+    assert L.wsx_env_state_bytes(wsx.MARKET, 3, 300, C.byref(out)) == 0
+    assert out.value >= 300 * (32 + 32 + 51) * 4
+
+
+def test_create_validation_without_gpu():
+    wsx, L = _lib()
+    h = C.c_void_p()
+    assert L.wsx_env_create(None, C.byref(h)) == -1
+    d = wsx._EnvDesc(wsx.MARKET, 0, 3, 0, 1234, None, None)
+    assert L.wsx_env_create(C.byref(d), C.byref(h)) == -1           # market needs offsets
+    assert b"agent_offsets" in L.wsx_last_error()
+    d = wsx._EnvDesc(wsx.REACTION, 0, 3, 0, 1234, None, None)
+    assert L.wsx_env_create(C.byref(d), C.byref(h)) == -1           # reaction needs params
+    d = wsx._EnvDesc(wsx.PENDULUM, 48, 3, 0, 1234, None, None)
+    assert L.wsx_env_create(C.byref(d), C.byref(h)) == -2           # no 48-row tile kernel
+    d = wsx._EnvDesc(wsx.PENDULUM, 0, 3, 0, None, None, None)
+    assert L.wsx_env_create(C.byref(d), C.byref(h)) == -1           # no state block
+
+
+def test_rollout_and_returns_validation_without_gpu():
+    wsx, L = _lib()
+    assert L.wsx_rollout(None, None, 1, None, 0, None) == -1
+    assert L.wsx_compute_returns(None, None, None, None, 10, 10, 1.5, 0.9, 1, None, None,
+                                 wsx.F64, None) == -1
+    assert L.wsx_compute_returns(None, None, None, None, 10, 10, 0.9, 0.9, 1, None, None,
+                                 wsx.BF16, None) == -2
+    assert L.wsx_compute_returns(None, None, None, None, 0, 10, 0.9, 0.9, 1, None, None,
+                                 wsx.F64, None) == 0                 # empty: nothing to do
+    assert L.wsx_quantize(wsx.FP8_E4M3, 0.3, None, None, 4, None) == -1
+    assert b"power of two" in L.wsx_last_error()
