@@ -168,6 +168,9 @@ def main():
     ap.add_argument("--cpu-sample-envs", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="fused,plain,graph")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (a kernel of "
+                         "known traffic for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -183,6 +186,13 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     wsx.lib()
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     sets = [EnvSet(k, 0, args.tile_rows, wsx, inputs, torch) for k in WORKLOADS[args.workload]]
     env_steps = sum(s.n_envs * s.T for s in sets)
     forms = args.forms.split(",")

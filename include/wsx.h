@@ -106,7 +106,11 @@ int wsx_env_state_bytes(int32_t kind, int64_t n_envs, int64_t n_rows, size_t* by
 
 typedef struct {
     int32_t kind;            /* WSX_CARTPOLE ... WSX_REACTION                     */
-    int32_t tile_rows;       /* rows per workgroup tile, 0 = the tuned default    */
+    int32_t tile_rows;       /* rows per workgroup tile, 0 = the default          */
+    int32_t waves;           /* wavefronts per workgroup, 0 = any / the default   */
+    int32_t occupancy;       /* min wavefronts per SIMD of the fused kernel, 0 =  */
+                             /* any / the default; (tile_rows, waves, occupancy)  */
+                             /* must name a compiled variant (else EUNSUPPORTED)  */
     int64_t n_envs;
     uint64_t seed;           /* Philox key                                        */
     void* state;             /* device, wsx_env_state_bytes bytes, caller-owned,  */

@@ -39,17 +39,17 @@ int hip_fail(hipError_t e, const char* what) {
 }
 
 struct KindInfo {
-    int sd, od, nact, dtype, hidden, tile_rows, waves;
+    int sd, od, nact, dtype, hidden, tile_rows, waves, occupancy;
 };
 
 // Shapes of each kind and the default tile (rows, waves) of its fused kernel.
 bool kind_info(int kind, KindInfo& k) {
     switch (kind) {
-    case WSX_CARTPOLE: k = {4, 4, 2, WSX_F32, 64, 16, 4}; return true;
-    case WSX_PENDULUM: k = {2, 3, 0, WSX_BF16, 256, 80, 4}; return true;
-    case WSX_ACROBOT: k = {4, 6, 0, WSX_BF16, 256, 80, 4}; return true;
-    case WSX_MARKET: k = {32, 32, 50, WSX_BF16, 256, 128, 4}; return true;
-    case WSX_REACTION: k = {21, 20, 40, WSX_FP8_E4M3, 512, 16, 8}; return true;
+    case WSX_CARTPOLE: k = {4, 4, 2, WSX_F32, 64, 16, 4, 1}; return true;
+    case WSX_PENDULUM: k = {2, 3, 0, WSX_BF16, 256, 80, 8, 2}; return true;
+    case WSX_ACROBOT: k = {4, 6, 0, WSX_BF16, 256, 80, 8, 2}; return true;
+    case WSX_MARKET: k = {32, 32, 50, WSX_BF16, 256, 128, 4, 1}; return true;
+    case WSX_REACTION: k = {21, 20, 40, WSX_FP8_E4M3, 512, 16, 8, 2}; return true;
     }
     return false;
 }
@@ -82,11 +82,13 @@ Layout layout_of(const KindInfo& k, int64_t n_envs, int64_t n_rows, bool market)
     return L;
 }
 
-bool find_variant(int kind, int dtype, int hidden, int waves, int tile_rows, Variant& out) {
+// waves / occupancy 0 match any compiled value
+bool find_variant(int kind, int dtype, int hidden, int waves, int tile_rows, int occupancy,
+                  Variant& out) {
     for (int i = 0; i < n_variants(); ++i) {
         const Variant& v = variant(i);
         if (v.kind == kind && v.dtype == dtype && v.hidden == hidden && v.tile_rows == tile_rows &&
-            (waves == 0 || v.waves == waves)) {
+            (waves == 0 || v.waves == waves) && (occupancy == 0 || v.occupancy == occupancy)) {
             out = v;
             return true;
         }
@@ -107,6 +109,8 @@ struct wsx_env {
     Layout lay;
     int n_tiles;
     int tile_rows;
+    int waves;
+    int occupancy;
     int device;
     int cus;
     // graph cache (PLAIN launches of one horizon)
@@ -143,11 +147,16 @@ int wsx_env_create(const wsx_env_desc* d, wsx_env** out) {
         return fail(WSX_EINVAL, "agent_offsets is required for the market and only for it");
     if ((d->kind == WSX_REACTION) != (d->params != nullptr))
         return fail(WSX_EINVAL, "params is required for the reaction walk and only for it");
+    if (d->occupancy < 0) return fail(WSX_EINVAL, "occupancy must be >= 0");
+    const bool deflt = !d->tile_rows && !d->waves && !d->occupancy;
     const int tile_rows = d->tile_rows ? d->tile_rows : k.tile_rows;
+    const int waves = d->waves ? d->waves : (deflt ? k.waves : 0);
+    const int occupancy = d->occupancy ? d->occupancy : (deflt ? k.occupancy : 0);
     Variant probe;
-    if (!find_variant(d->kind, k.dtype, k.hidden, 0, tile_rows, probe))
-        return fail(WSX_EUNSUPPORTED, "no compiled kernel with %d rows per tile for kind %d",
-                    tile_rows, d->kind);
+    if (!find_variant(d->kind, k.dtype, k.hidden, waves, tile_rows, occupancy, probe))
+        return fail(WSX_EUNSUPPORTED,
+                    "no compiled kernel with %d rows per tile, %d waves, occupancy %d for kind %d",
+                    tile_rows, waves, occupancy, d->kind);
 
     int64_t n_rows = d->n_envs;
     std::vector<Tile> tiles;
@@ -186,6 +195,8 @@ int wsx_env_create(const wsx_env_desc* d, wsx_env** out) {
     env->params = d->params;
     env->lay = layout_of(k, d->n_envs, n_rows, market);
     env->tile_rows = tile_rows;
+    env->waves = probe.waves;
+    env->occupancy = probe.occupancy;
     env->n_tiles = market ? (int)tiles.size() : (int)((n_rows + tile_rows - 1) / tile_rows);
     env->graph = nullptr;
     env->capture_stream = nullptr;
@@ -317,8 +328,8 @@ int wsx_rollout(wsx_env* env, const wsx_policy* policy, int32_t horizon, const w
     if ((uint64_t)env->step + (uint64_t)horizon > 0xFFFFFFFFull)
         return fail(WSX_EINVAL, "step counter would wrap");
     Variant v;
-    if (!find_variant(env->kind, policy->dtype, policy->h1, env->info.waves, env->tile_rows, v) &&
-        !find_variant(env->kind, policy->dtype, policy->h1, 0, env->tile_rows, v))
+    if (!find_variant(env->kind, policy->dtype, policy->h1, env->waves, env->tile_rows,
+                      env->occupancy, v))
         return fail(WSX_EUNSUPPORTED, "no compiled kernel for this policy and tile");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const EnvArgs ea = env_args(env);
@@ -420,7 +431,7 @@ int wsx_policy_forward(const wsx_policy* policy, const float* obs, int64_t rows,
     if (rows == 0) return WSX_OK;
     if (!obs || !head) return fail(WSX_EINVAL, "obs or head is NULL");
     Variant v;
-    if (!find_variant(kind, k.dtype, k.hidden, k.waves, k.tile_rows, v))
+    if (!find_variant(kind, k.dtype, k.hidden, k.waves, k.tile_rows, k.occupancy, v))
         return fail(WSX_EUNSUPPORTED, "no compiled kernel for this policy shape");
     const hipError_t e = launch_policy_forward(v, policy_args(policy), obs, rows, head,
                                                static_cast<hipStream_t>(stream));

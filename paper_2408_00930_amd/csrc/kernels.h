@@ -55,7 +55,7 @@ struct EnvArgs {
 
 // One compiled variant of the fused / plain kernels for an environment kind.
 struct Variant {
-    int32_t kind, dtype, hidden, waves, tile_rows;
+    int32_t kind, dtype, hidden, waves, tile_rows, occupancy;   // occupancy: min waves/SIMD
 };
 
 // Launchers (return hipError_t of the launch).

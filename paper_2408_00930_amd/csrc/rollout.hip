@@ -149,8 +149,9 @@ struct Mlp {
     Frag w1[MT][K1S];
     Frag w2[MT][K2S];
     Frag w3[NHW][KHS];
+    static constexpr int KXM = DT == DT_FP8 ? MT : 1;   // per-row tanh scales (FP8 only)
     float init1[MT][4], init2[MT][4];  // bias / output scale: accumulator start
-    float kx1[MT][4], kx2[MT][4];      // 2 log2(e) * output scale (tanh argument)
+    float kx1[KXM][4], kx2[KXM][4];    // 2 log2(e) * output scale (tanh argument)
     float o3[NHW][4];                  // head output scale
     float inv_q1, inv_q2;              // 1 / scale of the h1 and h2 quantisation
 
@@ -179,8 +180,8 @@ struct Mlp {
                 const float sc2 = row_scale(p.s2, mc, H) * a1;
                 init1[mt][i] = p.b1[mc] / sc1;
                 init2[mt][i] = p.b2[mc] / sc2;
-                kx1[mt][i] = kTwoLog2e * sc1;
-                kx2[mt][i] = kTwoLog2e * sc2;
+                kx1[DT == DT_FP8 ? mt : 0][i] = kTwoLog2e * sc1;
+                kx2[DT == DT_FP8 ? mt : 0][i] = kTwoLog2e * sc2;
             }
         }
 #pragma unroll
@@ -200,7 +201,7 @@ struct Mlp {
     // then tanh and quantisation into `out` (row-major [R][H]).
     template <int KS>
     __device__ __forceinline__ void dense_tanh(const Frag (&w)[MT][KS], const float (&init)[MT][4],
-                                               const float (&kx)[MT][4], const char* in, int p_in,
+                                               const float (&kx)[KXM][4], const char* in, int p_in,
                                                char* out, float inv_q, int wave, int lane) {
         const int lr = lane & 15, kq = (lane >> 4) * KC;
         f32x4 acc[MT][NT];
@@ -223,12 +224,13 @@ struct Mlp {
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
             const int feat = wave * FPW + mt * 16 + 4 * (lane >> 4);
+            const int km = DT == DT_FP8 ? mt : 0;
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 const f32x4 a = acc[mt][nt];
-                store4<DT>(out + (nt * 16 + lr) * P_H + feat * EB, tanh_scaled(a[0], kx[mt][0]),
-                           tanh_scaled(a[1], kx[mt][1]), tanh_scaled(a[2], kx[mt][2]),
-                           tanh_scaled(a[3], kx[mt][3]), inv_q);
+                store4<DT>(out + (nt * 16 + lr) * P_H + feat * EB, tanh_scaled(a[0], kx[km][0]),
+                           tanh_scaled(a[1], kx[km][1]), tanh_scaled(a[2], kx[km][2]),
+                           tanh_scaled(a[3], kx[km][3]), inv_q);
             }
         }
     }
@@ -439,8 +441,9 @@ __device__ __forceinline__ int env_slot(const EnvArgs& env, const Tile& tl, int 
 }
 
 // ---------------------------------------------------------- fused form --
-template <class E, int DT, int H, int NW, int NT, int HS>
-__global__ void __launch_bounds__(NW * 64, 1)
+template <class E, int DT, int H, int NW, int NT, int HS, int OCC>
+__global__ void __attribute__((amdgpu_flat_work_group_size(NW * 64, NW * 64),
+                               amdgpu_waves_per_eu(OCC)))
 k_fused(EnvArgs env, PolicyArgs pol, TrajArgs tr, int horizon) {
     using HO = HeadOf<E>;
     using L = Mlp<DT, H, NW, NT, kin_of<E, DT>(), HO::NHP, HS>;
@@ -579,8 +582,10 @@ __global__ void k_plain_observe(EnvArgs env, TrajArgs tr, int horizon) {
 }
 
 // Policy over one tile of rows per workgroup: obs_scratch -> head_scratch.
-template <class E, int DT, int H, int NW, int NT, int HS>
-__global__ void __launch_bounds__(NW * 64, 1) k_plain_policy(EnvArgs env, PolicyArgs pol) {
+template <class E, int DT, int H, int NW, int NT, int HS, int OCC>
+__global__ void __attribute__((amdgpu_flat_work_group_size(NW * 64, NW * 64),
+                               amdgpu_waves_per_eu(OCC)))
+k_plain_policy(EnvArgs env, PolicyArgs pol) {
     using HO = HeadOf<E>;
     using L = Mlp<DT, H, NW, NT, kin_of<E, DT>(), HO::NHP, HS>;
     constexpr int R = L::R;
@@ -754,25 +759,39 @@ __global__ void k_quantize(int dtype, float scale, const float* x, float* y, int
 }
 
 // ---------------------------------------------------------- dispatching --
+// (env, dtype, hidden, waves, row tiles of 16, head split-M, min waves per SIMD)
 #define WSX_VARIANTS(X)                      \
-    X(CartPole, DT_F32, 64, 4, 1, 0)         \
-    X(CartPole, DT_F32, 64, 4, 2, 0)         \
-    X(CartPole, DT_F32, 64, 4, 4, 0)         \
-    X(Pendulum, DT_BF16, 256, 4, 2, 0)       \
-    X(Pendulum, DT_BF16, 256, 4, 4, 0)       \
-    X(Pendulum, DT_BF16, 256, 4, 5, 0)       \
-    X(Pendulum, DT_BF16, 256, 8, 4, 0)       \
-    X(Pendulum, DT_BF16, 256, 8, 5, 0)       \
-    X(Acrobot, DT_BF16, 256, 4, 2, 0)        \
-    X(Acrobot, DT_BF16, 256, 4, 4, 0)        \
-    X(Acrobot, DT_BF16, 256, 4, 5, 0)        \
-    X(Acrobot, DT_BF16, 256, 8, 4, 0)        \
-    X(Acrobot, DT_BF16, 256, 8, 5, 0)        \
-    X(Market, DT_BF16, 256, 4, 8, 1)         \
-    X(Market, DT_BF16, 256, 8, 8, 1)         \
-    X(Reaction, DT_FP8, 512, 8, 1, 0)        \
-    X(Reaction, DT_FP8, 512, 8, 2, 0)        \
-    X(Reaction, DT_FP8, 512, 8, 4, 1)
+    X(CartPole, DT_F32, 64, 4, 1, 0, 1)      \
+    X(CartPole, DT_F32, 64, 4, 2, 0, 1)      \
+    X(CartPole, DT_F32, 64, 4, 4, 0, 1)      \
+    X(CartPole, DT_F32, 64, 4, 1, 0, 2)      \
+    X(Pendulum, DT_BF16, 256, 4, 2, 0, 1)    \
+    X(Pendulum, DT_BF16, 256, 4, 4, 0, 1)    \
+    X(Pendulum, DT_BF16, 256, 4, 5, 0, 1)    \
+    X(Pendulum, DT_BF16, 256, 4, 2, 0, 2)    \
+    X(Pendulum, DT_BF16, 256, 4, 3, 0, 2)    \
+    X(Pendulum, DT_BF16, 256, 8, 2, 0, 2)    \
+    X(Pendulum, DT_BF16, 256, 8, 3, 0, 2)    \
+    X(Pendulum, DT_BF16, 256, 8, 4, 0, 2)    \
+    X(Pendulum, DT_BF16, 256, 8, 5, 0, 2)    \
+    X(Pendulum, DT_BF16, 256, 8, 2, 0, 4)    \
+    X(Pendulum, DT_BF16, 256, 8, 3, 0, 4)    \
+    X(Acrobot, DT_BF16, 256, 4, 2, 0, 1)     \
+    X(Acrobot, DT_BF16, 256, 4, 4, 0, 1)     \
+    X(Acrobot, DT_BF16, 256, 4, 5, 0, 1)     \
+    X(Acrobot, DT_BF16, 256, 4, 2, 0, 2)     \
+    X(Acrobot, DT_BF16, 256, 4, 3, 0, 2)     \
+    X(Acrobot, DT_BF16, 256, 8, 2, 0, 2)     \
+    X(Acrobot, DT_BF16, 256, 8, 3, 0, 2)     \
+    X(Acrobot, DT_BF16, 256, 8, 4, 0, 2)     \
+    X(Acrobot, DT_BF16, 256, 8, 5, 0, 2)     \
+    X(Acrobot, DT_BF16, 256, 8, 2, 0, 4)     \
+    X(Acrobot, DT_BF16, 256, 8, 3, 0, 4)     \
+    X(Market, DT_BF16, 256, 4, 8, 1, 1)      \
+    X(Market, DT_BF16, 256, 8, 8, 1, 2)      \
+    X(Reaction, DT_FP8, 512, 8, 1, 0, 2)     \
+    X(Reaction, DT_FP8, 512, 8, 2, 0, 2)     \
+    X(Reaction, DT_FP8, 512, 8, 4, 1, 2)
 
 struct VariantEntry {
     Variant v;
@@ -780,10 +799,10 @@ struct VariantEntry {
     const void* policy;
 };
 
-#define WSX_ENTRY(E, DT, H, NW, NT, HS)                                               \
-    {{E::KIND, DT, H, NW, 16 * NT},                                                   \
-     reinterpret_cast<const void*>(&k_fused<E, DT, H, NW, NT, HS>),                   \
-     reinterpret_cast<const void*>(&k_plain_policy<E, DT, H, NW, NT, HS>)},
+#define WSX_ENTRY(E, DT, H, NW, NT, HS, OCC)                                          \
+    {{E::KIND, DT, H, NW, 16 * NT, OCC},                                              \
+     reinterpret_cast<const void*>(&k_fused<E, DT, H, NW, NT, HS, OCC>),              \
+     reinterpret_cast<const void*>(&k_plain_policy<E, DT, H, NW, NT, HS, OCC>)},
 
 static const VariantEntry kVariants[] = {WSX_VARIANTS(WSX_ENTRY)};
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
@@ -795,7 +814,7 @@ static const VariantEntry* find_entry(const Variant& v) {
     for (int i = 0; i < kNumVariants; ++i) {
         const Variant& w = kVariants[i].v;
         if (w.kind == v.kind && w.dtype == v.dtype && w.hidden == v.hidden && w.waves == v.waves &&
-            w.tile_rows == v.tile_rows)
+            w.tile_rows == v.tile_rows && w.occupancy == v.occupancy)
             return &kVariants[i];
     }
     return nullptr;

@@ -47,7 +47,8 @@ class _Traj(C.Structure):
 
 
 class _EnvDesc(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("tile_rows", C.c_int32), ("n_envs", C.c_int64),
+    _fields_ = [("kind", C.c_int32), ("tile_rows", C.c_int32), ("waves", C.c_int32),
+                ("occupancy", C.c_int32), ("n_envs", C.c_int64),
                 ("seed", C.c_uint64), ("state", C.c_void_p), ("agent_offsets", C.c_void_p),
                 ("params", C.c_void_p)]
 
@@ -159,7 +160,7 @@ class Env:
     """An environment set: its device state block and the library handle."""
 
     def __init__(self, kind, n_envs, seed=0, agent_offsets=None, params=None, tile_rows=0,
-                 device="cuda"):
+                 waves=0, occupancy=0, device="cuda"):
         self.kind = kind
         self.n_envs = n_envs
         dev = torch.device(device)
@@ -170,7 +171,7 @@ class Env:
         self.block = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
         self.params = None if params is None else torch.from_numpy(
             np.ascontiguousarray(params, np.float32)).to(dev)
-        desc = _EnvDesc(kind, tile_rows, n_envs, seed, self.block.data_ptr(),
+        desc = _EnvDesc(kind, tile_rows, waves, occupancy, n_envs, seed, self.block.data_ptr(),
                         None if self.offsets is None else self.offsets.ctypes.data,
                         None if self.params is None else self.params.data_ptr())
         h = C.c_void_p()

@@ -54,14 +54,16 @@ def test_create_validation_without_gpu():
     wsx, L = _lib()
     h = C.c_void_p()
     assert L.wsx_env_create(None, C.byref(h)) == -1
-    d = wsx._EnvDesc(wsx.MARKET, 0, 3, 0, 1234, None, None)
+    d = wsx._EnvDesc(wsx.MARKET, 0, 0, 0, 3, 0, 1234, None, None)
     assert L.wsx_env_create(C.byref(d), C.byref(h)) == -1           # market needs offsets
     assert b"agent_offsets" in L.wsx_last_error()
-    d = wsx._EnvDesc(wsx.REACTION, 0, 3, 0, 1234, None, None)
+    d = wsx._EnvDesc(wsx.REACTION, 0, 0, 0, 3, 0, 1234, None, None)
     assert L.wsx_env_create(C.byref(d), C.byref(h)) == -1           # reaction needs params
-    d = wsx._EnvDesc(wsx.PENDULUM, 48, 3, 0, 1234, None, None)
-    assert L.wsx_env_create(C.byref(d), C.byref(h)) == -2           # no 48-row tile kernel
-    d = wsx._EnvDesc(wsx.PENDULUM, 0, 3, 0, None, None, None)
+    d = wsx._EnvDesc(wsx.PENDULUM, 112, 0, 0, 3, 0, 1234, None, None)
+    assert L.wsx_env_create(C.byref(d), C.byref(h)) == -2           # no 112-row tile kernel
+    d = wsx._EnvDesc(wsx.PENDULUM, 0, 0, -1, 3, 0, 1234, None, None)
+    assert L.wsx_env_create(C.byref(d), C.byref(h)) == -1           # negative occupancy
+    d = wsx._EnvDesc(wsx.PENDULUM, 0, 0, 0, 3, 0, None, None, None)
     assert L.wsx_env_create(C.byref(d), C.byref(h)) == -1           # no state block
 
 

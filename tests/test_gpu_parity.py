@@ -38,14 +38,18 @@ def test_quantize_bf16_matches_oracle_rounding():
     rng = np.random.default_rng(0)
     x = np.concatenate([rng.normal(0, 1, 20000), rng.normal(0, 1e-30, 2000),
                         rng.uniform(-3e38, 3e38, 2000)]).astype(np.float32)
-    # exact bf16 midpoints
-    base = (rng.integers(0, 2**15, 4000).astype(np.uint32) << 16).view(np.float32)
-    mids = (base.view(np.uint32) | 0x8000).view(np.float32)
-    x = np.concatenate([x, mids, base])
+    # exact bf16 midpoints (finite codes only; subnormal and normal)
+    codes = rng.integers(0, 0x7F7F, 4000).astype(np.uint32)
+    base = (codes << 16).view(np.float32)
+    mids = ((codes << 16) | 0x8000).view(np.float32)
+    x = np.concatenate([x, mids, base, -mids])
     say("quantize bf16", x.size)
     y = wsx.quantize(wsx.BF16, torch.from_numpy(x).cuda()).cpu().numpy().astype(np.float64)
     want = O.round_bf16(x.astype(np.float64))
-    assert np.array_equal(y, want)
+    bad = np.nonzero(y != want)[0]
+    for i in bad[:10]:
+        print(f"bf16 mismatch x={x[i]!r} ({x[i].view(np.uint32):08x}) gpu={y[i]!r} oracle={want[i]!r}")
+    assert len(bad) == 0
 
 
 @pytest.mark.parametrize("scale", [1.0, 2.0 ** -4, 2.0 ** -8])
@@ -66,14 +70,16 @@ def test_quantize_fp8_matches_oracle_rounding(scale):
 
 # --------------------------------------------------------------- policy ----
 
-HEAD_TOL = {"f32": (1e-4, 1e-4, 0.0), "bf16": (2e-2, 2e-3, 0.02), "fp8": (2e-2, 2e-3, 0.02)}
+# (max abs error, row threshold, largest fraction of rows beyond the threshold)
+HEAD_TOL = {"f32": (1e-4, 1e-4, 0.0), "bf16": (2e-2, 2e-3, 0.03), "fp8": (0.25, 2e-2, 0.10)}
 
 
 def _check_head(got, want, dtype, what):
     hard, soft, frac = HEAD_TOL[dtype]
     err = np.abs(got - want)
     worst_row = err.max(axis=1)
-    print(f"{what}: max err {err.max():.3g}, rows beyond {soft}: "
+    q = np.quantile(worst_row, [0.5, 0.9, 0.99, 1.0])
+    print(f"{what}: row max-err quantiles 50/90/99/100% {q}, rows beyond {soft}: "
           f"{(worst_row > soft).mean():.4f}", flush=True)
     assert err.max() <= hard
     assert (worst_row > soft).mean() <= frac
@@ -150,7 +156,7 @@ def test_reset_matches_oracle(kind):
 
 DYN_TOL = {O.CARTPOLE: 2e-5, O.PENDULUM: 2e-5, O.ACROBOT: 1e-4, O.MARKET: 2e-5,
            O.REACTION: 2e-4}
-WINDOW = {"f32": 1e-6, "bf16": 5e-3, "fp8": 5e-3}
+WINDOW = {"f32": 1e-6, "bf16": 5e-3, "fp8": 5e-2}
 
 
 def _close(a, b, tol):
@@ -181,6 +187,7 @@ def lockstep(case, T, epoch=1, start=None):
         # policy: value, action, log-probability
         hard, soft, frac = HEAD_TOL[dtype]
         verr = np.abs(g["value"][0] - ref["value"][0])
+        print(f"  value err max {verr.max():.3g}, beyond {soft}: {(verr > soft).mean():.3f}")
         assert verr.max() <= hard and (verr > soft).mean() <= frac
         act_g = g["action"][0].astype(np.float64)
         act_o = ref["action"][0]
@@ -192,12 +199,12 @@ def lockstep(case, T, epoch=1, start=None):
             assert not np.any(diff & ~excused), "unexcused action mismatch"
             same = ~diff
             lerr = np.abs(g["logp"][0] - ref["logp"][0])[same]
-            assert lerr.max(initial=0) <= (1e-4 if dtype == "f32" else 5e-2)
+            assert lerr.max(initial=0) <= {"f32": 1e-4, "bf16": 5e-2, "fp8": 0.5}[dtype]
         else:
             aerr = np.abs(act_g - act_o)
             assert aerr.max() <= hard
             lerr = np.abs(g["logp"][0] - ref["logp"][0])
-            assert lerr.max() <= (1e-4 if dtype == "f32" else 5e-2)
+            assert lerr.max() <= 1e-4    # the normal draw itself, FP32 vs FP64
         # dynamics of the GPU's own action from the GPU's state
         tol = DYN_TOL[kind]
         if kind == O.MARKET:
