@@ -143,6 +143,76 @@ def cpu_baseline(sets, sample_envs):
                       f"OpenMP over envs, returns/GAE included"}
 
 
+def serving(args, wsx, inputs, torch):
+    """Poisson arrivals of roll-out requests into the continuous-batching
+    server: kind uniform over Pendulum, Acrobot, market, reaction; replicas
+    log-uniform in [64, 8192]; horizon uniform in [10, 500]."""
+    import math
+    import threading
+
+    import numpy as np
+    kinds = [wsx.PENDULUM, wsx.ACROBOT, wsx.MARKET, wsx.REACTION]
+    cfg = {wsx.PENDULUM: ("bf16", 256), wsx.ACROBOT: ("bf16", 256), wsx.MARKET: ("bf16", 256),
+           wsx.REACTION: ("fp8", 512)}
+    pols = {k: wsx.DevicePolicy(inputs.policy_for(k, cfg[k][0], cfg[k][1], seed=k)) for k in kinds}
+    params = torch.from_numpy(inputs.reaction_params(0)).cuda()
+    rng = np.random.default_rng(args.serve_seed)
+    n_total = args.serve_warmup + args.serve_requests
+    specs = []
+    for i in range(n_total):
+        k = kinds[int(rng.integers(0, 4))]
+        n = int(round(math.exp(rng.uniform(math.log(64), math.log(8192)))))
+        T = int(rng.integers(10, 501))
+        gap = rng.exponential(1.0 / args.serve_rate)
+        specs.append((k, n, T, gap))
+    srv = wsx.Server(int(args.serve_arena_gb * (1 << 30)), chunk_steps=args.serve_chunk,
+                     max_batch=64)
+    ids = [None] * n_total
+    t_sub = [0.0] * n_total
+
+    def submitter():
+        t_next = time.perf_counter()
+        for i, (k, n, T, gap) in enumerate(specs):
+            t_next += gap
+            delay = t_next - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            kw = {}
+            if k == wsx.MARKET:
+                kw["agent_offsets"] = inputs.agent_offsets(n, seed=i)
+            if k == wsx.REACTION:
+                kw["params"] = params
+            t_sub[i] = time.perf_counter()
+            ids[i] = srv.submit(k, pols[k], T, n_envs=n, seed=i, **kw)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    lat, steps, t_done = [], 0, []
+    for i in range(n_total):
+        while ids[i] is None:
+            time.sleep(1e-4)
+        r = srv.wait(ids[i], -1)
+        t_done.append(time.perf_counter())
+        if i >= args.serve_warmup:
+            lat.append(r.latency_ms)
+            steps += specs[i][1] * specs[i][2]
+        srv.release(ids[i])
+        if (i + 1) % 200 == 0:
+            print(f"[bench] serving: {i + 1}/{n_total} requests done", file=sys.stderr, flush=True)
+    th.join()
+    st = srv.stats()
+    srv.close()
+    span = t_done[-1] - t_sub[args.serve_warmup]
+    lat.sort()
+    return {"requests": args.serve_requests, "warmup_requests": args.serve_warmup,
+            "rate_per_s": args.serve_rate, "arena_gb": args.serve_arena_gb,
+            "chunk_steps": args.serve_chunk,
+            "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3),
+                           "max": round(lat[-1], 3)},
+            "env_steps_per_s": round(steps / span, 1), "makespan_s": round(span, 3),
+            "launches": st["launches"], "arena_peak_gb": round(st["arena_peak"] / 2**30, 2)}
+
+
 def traffic_for(kernel_name, launches_bytes_key):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel sources."""
@@ -168,6 +238,13 @@ def main():
     ap.add_argument("--cpu-sample-envs", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="fused,plain,graph")
+    ap.add_argument("--serve-requests", type=int, default=400,
+                    help="measured requests of the serving load (0: skip serving)")
+    ap.add_argument("--serve-warmup", type=int, default=50)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-arena-gb", type=float, default=200.0)
+    ap.add_argument("--serve-chunk", type=int, default=25)
+    ap.add_argument("--serve-seed", type=int, default=0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a kernel of "
                          "known traffic for scaling HBM byte counters)")
@@ -244,6 +321,8 @@ def main():
                          "latency_ms": {"p50": round(percentile(plat, 50), 3),
                                         "p99": round(percentile(plat, 99), 3)}}
             out[f"fused_speedup_vs_{name}"] = round(value / pv, 2)
+    if args.serve_requests > 0:
+        out["serving"] = serving(args, wsx, inputs, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sets, args.cpu_sample_envs)
     print(json.dumps(out), flush=True)

@@ -39,6 +39,7 @@ extern "C" {
 #define WSX_EUNSUPPORTED (-2)  /* valid but not supported (shape, dtype, kind)     */
 #define WSX_EHIP (-3)          /* the HIP runtime reported an error                */
 #define WSX_ESTATE (-4)        /* object used in a state that does not allow it    */
+#define WSX_ETIMEOUT (-5)      /* a wait ended before the request completed        */
 
 /* Environment kinds (App. C example families; dynamics are the project's
  * readings, see the design notes). */
@@ -174,6 +175,93 @@ int wsx_policy_forward(const wsx_policy* policy, const float* obs, int64_t rows,
  * RNE, saturating) with the device conversion the kernels use and returns
  * the real values as float. */
 int wsx_quantize(int32_t dtype, float scale, const float* x, float* y, int64_t n, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Roll-out server: continuous batching of roll-out requests.                */
+/*                                                                          */
+/* Requests (an environment kind, a number of replicas, a horizon, a policy) */
+/* are submitted from any thread and run by a scheduler thread inside the    */
+/* library. Memory for a request (its environment state block, trajectory    */
+/* and returns) is sub-allocated from a caller-owned device arena, which is   */
+/* the HBM admission budget: a request waits until its memory fits. The      */
+/* scheduler advances every admitted request in rounds of at most            */
+/* chunk_steps steps; each round issues, per (kind, policy), ONE fused       */
+/* launch covering the tiles of all admitted requests of that kind, so a     */
+/* request that arrives while others run joins the next round and shares    */
+/* launches with them, and kinds run concurrently on separate streams. A     */
+/* finished request gets its returns/GAE and its latency recorded.           */
+/* Environment state is device-resident in sessions: a request may continue  */
+/* a session left by an earlier request. Results do not depend on the mix:   */
+/* a request's numbers equal those of the same roll-out run alone.           */
+/* ------------------------------------------------------------------------ */
+
+typedef struct wsx_server wsx_server;   /* opaque */
+
+typedef struct {
+    void* arena;             /* caller-owned device memory sub-allocated by the   */
+    size_t arena_bytes;      /* server; its size is the admission budget          */
+    int32_t chunk_steps;     /* steps per scheduling round (> 0)                   */
+    int32_t max_batch;       /* most requests in one batched launch (> 0)          */
+} wsx_server_desc;
+
+typedef struct {
+    int32_t kind;            /* WSX_PENDULUM ... (any kind)                        */
+    int32_t horizon;         /* steps (> 0)                                        */
+    int64_t n_envs;          /* replicas of a new session (ignored when continuing) */
+    uint64_t seed;           /* Philox key of a new session                        */
+    uint32_t epoch;          /* reset epoch of a new session                       */
+    int32_t keep_session;    /* 1: keep the state resident after the request       */
+    int64_t session;         /* 0: new session; else continue this session id      */
+    const wsx_policy* policy;/* copied at submit; its device buffers must stay     */
+                             /* valid until the request completes                  */
+    const int32_t* agent_offsets; /* market, new session: HOST [n_envs + 1], copied */
+    const float* params;     /* reaction, new session: DEVICE potential block      */
+    double gamma, lambda;    /* returns / GAE parameters                           */
+} wsx_request;
+
+typedef struct {
+    int32_t status;          /* 0 queued, 1 admitted, 2 done, < 0 failed (code)    */
+    int32_t reserved;
+    int64_t session;         /* the session the request ran in                     */
+    int64_t n_rows;
+    wsx_traj traj;           /* device pointers in the arena, valid until release  */
+    float* returns;          /* device [horizon][rows] FP32 (FP64 arithmetic)      */
+    float* advantages;
+    double queue_ms;         /* submit -> admission                                */
+    double latency_ms;       /* submit -> results complete on the device           */
+} wsx_result;
+
+typedef struct {
+    int64_t submitted, admitted, completed, launches;
+    int64_t env_steps;       /* completed replica-steps                            */
+    size_t arena_in_use, arena_peak;
+    int32_t queued, running;
+} wsx_server_stats;
+
+/* Creates the server and starts its scheduler thread (streams at default
+ * priority are created on the current device). */
+int wsx_server_create(const wsx_server_desc* desc, wsx_server** out);
+
+/* Queues a request; returns its id. Fails with WSX_EINVAL if its memory can
+ * never fit the arena or the arguments are invalid. */
+int wsx_server_submit(wsx_server* srv, const wsx_request* req, int64_t* id);
+
+/* Waits up to timeout_ms (< 0: forever) for request `id`; fills *out.
+ * WSX_ETIMEOUT if it has not completed in time (then *out holds its state). */
+int wsx_server_wait(wsx_server* srv, int64_t id, int32_t timeout_ms, wsx_result* out);
+
+/* Frees a completed request's trajectory and returns (and its session unless
+ * it was kept). */
+int wsx_server_release(wsx_server* srv, int64_t id);
+
+/* Frees a kept session that no request is using. */
+int wsx_server_close_session(wsx_server* srv, int64_t session);
+
+int wsx_server_get_stats(wsx_server* srv, wsx_server_stats* out);
+
+/* Stops the scheduler after the device work in flight ends and frees the
+ * server (the arena is the caller's). */
+int wsx_server_destroy(wsx_server* srv);
 
 /* Human-readable description of the last error on the calling thread. */
 const char* wsx_last_error(void);

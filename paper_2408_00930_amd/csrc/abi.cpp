@@ -15,15 +15,15 @@
 #include <string>
 #include <vector>
 
+#include "internal.h"
 #include "kernels.h"
 
 using namespace wsx;
 
-namespace {
+namespace wsx {
 
 thread_local std::string g_last_error;
 
-int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 int fail(int code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
@@ -37,10 +37,6 @@ int fail(int code, const char* fmt, ...) {
 int hip_fail(hipError_t e, const char* what) {
     return fail(WSX_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
-
-struct KindInfo {
-    int sd, od, nact, dtype, hidden, tile_rows, waves, occupancy;
-};
 
 // Shapes of each kind and the default tile (rows, waves) of its fused kernel.
 bool kind_info(int kind, KindInfo& k) {
@@ -57,11 +53,6 @@ bool kind_info(int kind, KindInfo& k) {
 int n_head_of(const KindInfo& k) { return (k.nact ? k.nact : 1) + 1; }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-// Byte offsets of the parts of an environment set's device state block.
-struct Layout {
-    size_t state, obs, head, offsets, tiles, step, total;
-};
 
 Layout layout_of(const KindInfo& k, int64_t n_envs, int64_t n_rows, bool market) {
     Layout L{};
@@ -96,28 +87,72 @@ bool find_variant(int kind, int dtype, int hidden, int waves, int tile_rows, int
     return false;
 }
 
-}  // namespace
+}  // namespace wsx
 
-struct wsx_env {
-    int kind;
-    KindInfo info;
-    int64_t n_envs, n_rows;
-    uint64_t seed;
-    uint32_t step, epoch;
-    char* block;
-    const float* params;
-    Layout lay;
-    int n_tiles;
-    int tile_rows;
-    int waves;
-    int occupancy;
-    int device;
-    int cus;
-    // graph cache (PLAIN launches of one horizon)
-    hipGraphExec_t graph;
-    hipStream_t capture_stream;
-    std::vector<char> graph_key;
-};
+EnvArgs wsx::env_args(const wsx_env* env) {
+    EnvArgs a{};
+    a.state = reinterpret_cast<float*>(env->block + env->lay.state);
+    a.obs_scratch = reinterpret_cast<float*>(env->block + env->lay.obs);
+    a.head_scratch = reinterpret_cast<float*>(env->block + env->lay.head);
+    a.params = env->params;
+    a.offsets = env->kind == WSX_MARKET ? reinterpret_cast<const int32_t*>(env->block + env->lay.offsets)
+                                        : nullptr;
+    a.tiles = env->kind == WSX_MARKET ? reinterpret_cast<const Tile*>(env->block + env->lay.tiles)
+                                      : nullptr;
+    a.step_ptr = nullptr;
+    a.n_rows = env->n_rows;
+    a.n_envs = (int32_t)env->n_envs;
+    a.n_tiles = env->n_tiles;
+    a.k0 = (uint32_t)(env->seed & 0xFFFFFFFFu);
+    a.k1 = (uint32_t)(env->seed >> 32);
+    a.epoch = env->epoch;
+    a.t0 = env->step;
+    return a;
+}
+
+int wsx::check_policy(const wsx_policy* p, const KindInfo& k, int kind) {
+    if (!p) return fail(WSX_EINVAL, "policy is NULL");
+    if (p->dtype != k.dtype)
+        return fail(WSX_EUNSUPPORTED, "kind %d runs dtype %d policies (got %d)", kind, k.dtype, p->dtype);
+    if (p->d_in != k.od) return fail(WSX_EINVAL, "policy d_in %d != observation size %d", p->d_in, k.od);
+    if (p->h1 != k.hidden || p->h2 != k.hidden)
+        return fail(WSX_EUNSUPPORTED, "kind %d runs %d-unit hidden layers (got %d, %d)", kind,
+                    k.hidden, p->h1, p->h2);
+    if (p->n_head != n_head_of(k))
+        return fail(WSX_EINVAL, "policy n_head %d != %d", p->n_head, n_head_of(k));
+    if (!p->w1 || !p->w2 || !p->w3 || !p->b1 || !p->b2 || !p->b3)
+        return fail(WSX_EINVAL, "policy weight or bias pointer is NULL");
+    if (p->dtype == WSX_FP8_E4M3) {
+        if (!p->s1 || !p->s2 || !p->s3) return fail(WSX_EINVAL, "FP8 policy needs row scales");
+        for (int i = 0; i < 3; ++i) {
+            int ex;
+            const float m = frexpf(p->act_scale[i], &ex);
+            if (!(p->act_scale[i] > 0.0f) || m != 0.5f)
+                return fail(WSX_EINVAL, "act_scale[%d] must be a positive power of two", i);
+        }
+    }
+    if (k.nact == 0 && !p->log_std) return fail(WSX_EINVAL, "continuous policy needs log_std");
+    return WSX_OK;
+}
+
+PolicyArgs wsx::policy_args(const wsx_policy* p) {
+    PolicyArgs a{};
+    a.w1 = p->w1;
+    a.w2 = p->w2;
+    a.w3 = p->w3;
+    a.b1 = p->b1;
+    a.b2 = p->b2;
+    a.b3 = p->b3;
+    a.s1 = p->s1;
+    a.s2 = p->s2;
+    a.s3 = p->s3;
+    a.log_std = p->log_std;
+    for (int i = 0; i < 3; ++i) a.act_scale[i] = p->act_scale[i];
+    a.d_in = p->d_in;
+    a.hidden = p->h1;
+    a.n_head = p->n_head;
+    return a;
+}
 
 extern "C" {
 
@@ -220,8 +255,8 @@ int wsx_env_create(const wsx_env_desc* d, wsx_env** out) {
 
 int wsx_env_destroy(wsx_env* env) {
     if (!env) return fail(WSX_EINVAL, "env is NULL");
-    if (env->graph) hipGraphExecDestroy(env->graph);
-    if (env->capture_stream) hipStreamDestroy(env->capture_stream);
+    if (env->graph) (void)hipGraphExecDestroy(env->graph);
+    if (env->capture_stream) (void)hipStreamDestroy(env->capture_stream);
     delete env;
     return WSX_OK;
 }
@@ -240,26 +275,6 @@ int wsx_env_set_step(wsx_env* env, uint32_t step) {
     return WSX_OK;
 }
 
-static EnvArgs env_args(const wsx_env* env) {
-    EnvArgs a{};
-    a.state = reinterpret_cast<float*>(env->block + env->lay.state);
-    a.obs_scratch = reinterpret_cast<float*>(env->block + env->lay.obs);
-    a.head_scratch = reinterpret_cast<float*>(env->block + env->lay.head);
-    a.params = env->params;
-    a.offsets = env->kind == WSX_MARKET ? reinterpret_cast<const int32_t*>(env->block + env->lay.offsets)
-                                        : nullptr;
-    a.tiles = env->kind == WSX_MARKET ? reinterpret_cast<const Tile*>(env->block + env->lay.tiles)
-                                      : nullptr;
-    a.step_ptr = nullptr;
-    a.n_rows = env->n_rows;
-    a.n_envs = (int32_t)env->n_envs;
-    a.n_tiles = env->n_tiles;
-    a.k0 = (uint32_t)(env->seed & 0xFFFFFFFFu);
-    a.k1 = (uint32_t)(env->seed >> 32);
-    a.epoch = env->epoch;
-    a.t0 = env->step;
-    return a;
-}
 
 int wsx_env_reset(wsx_env* env, uint32_t epoch, void* stream) {
     if (!env) return fail(WSX_EINVAL, "env is NULL");
@@ -270,49 +285,7 @@ int wsx_env_reset(wsx_env* env, uint32_t epoch, void* stream) {
     return WSX_OK;
 }
 
-static int check_policy(const wsx_policy* p, const KindInfo& k, int kind) {
-    if (!p) return fail(WSX_EINVAL, "policy is NULL");
-    if (p->dtype != k.dtype)
-        return fail(WSX_EUNSUPPORTED, "kind %d runs dtype %d policies (got %d)", kind, k.dtype, p->dtype);
-    if (p->d_in != k.od) return fail(WSX_EINVAL, "policy d_in %d != observation size %d", p->d_in, k.od);
-    if (p->h1 != k.hidden || p->h2 != k.hidden)
-        return fail(WSX_EUNSUPPORTED, "kind %d runs %d-unit hidden layers (got %d, %d)", kind,
-                    k.hidden, p->h1, p->h2);
-    if (p->n_head != n_head_of(k))
-        return fail(WSX_EINVAL, "policy n_head %d != %d", p->n_head, n_head_of(k));
-    if (!p->w1 || !p->w2 || !p->w3 || !p->b1 || !p->b2 || !p->b3)
-        return fail(WSX_EINVAL, "policy weight or bias pointer is NULL");
-    if (p->dtype == WSX_FP8_E4M3) {
-        if (!p->s1 || !p->s2 || !p->s3) return fail(WSX_EINVAL, "FP8 policy needs row scales");
-        for (int i = 0; i < 3; ++i) {
-            int ex;
-            const float m = frexpf(p->act_scale[i], &ex);
-            if (!(p->act_scale[i] > 0.0f) || m != 0.5f)
-                return fail(WSX_EINVAL, "act_scale[%d] must be a positive power of two", i);
-        }
-    }
-    if (k.nact == 0 && !p->log_std) return fail(WSX_EINVAL, "continuous policy needs log_std");
-    return WSX_OK;
-}
 
-static PolicyArgs policy_args(const wsx_policy* p) {
-    PolicyArgs a{};
-    a.w1 = p->w1;
-    a.w2 = p->w2;
-    a.w3 = p->w3;
-    a.b1 = p->b1;
-    a.b2 = p->b2;
-    a.b3 = p->b3;
-    a.s1 = p->s1;
-    a.s2 = p->s2;
-    a.s3 = p->s3;
-    a.log_std = p->log_std;
-    for (int i = 0; i < 3; ++i) a.act_scale[i] = p->act_scale[i];
-    a.d_in = p->d_in;
-    a.hidden = p->h1;
-    a.n_head = p->n_head;
-    return a;
-}
 
 int wsx_rollout(wsx_env* env, const wsx_policy* policy, int32_t horizon, const wsx_traj* traj,
                 int32_t mode, void* stream) {
@@ -346,7 +319,15 @@ int wsx_rollout(wsx_env* env, const wsx_policy* policy, int32_t horizon, const w
     if (mode == WSX_MODE_FUSED) {
         const int per_cu = fused_blocks_per_cu(v);
         const int grid = std::max(1, std::min(env->n_tiles, env->cus * per_cu));
-        e = launch_fused(v, ea, pa, ta, horizon, grid, s);
+        Batch b{};
+        b.table = nullptr;
+        b.one.env = ea;
+        b.one.tr = ta;
+        b.one.steps = horizon;
+        b.one.tile_begin = 0;
+        b.n_segs = 1;
+        b.n_tiles = env->n_tiles;
+        e = launch_fused(v, b, pa, grid, s);
     } else if (mode == WSX_MODE_PLAIN) {
         e = launch_plain(v, ea, pa, ta, horizon, false, s);
     } else if (mode == WSX_MODE_GRAPH) {
@@ -361,7 +342,7 @@ int wsx_rollout(wsx_env* env, const wsx_policy* policy, int32_t horizon, const w
         std::memcpy(key.data() + sizeof pa + sizeof ta + sizeof horizon, &v, sizeof v);
         if (!env->graph || env->graph_key != key) {
             if (env->graph) {
-                hipGraphExecDestroy(env->graph);
+                (void)hipGraphExecDestroy(env->graph);
                 env->graph = nullptr;
             }
             if (!env->capture_stream) {
@@ -375,7 +356,7 @@ int wsx_rollout(wsx_env* env, const wsx_policy* policy, int32_t horizon, const w
             e = hipStreamEndCapture(env->capture_stream, &g);
             if (le != hipSuccess) e = le;
             if (e == hipSuccess) e = hipGraphInstantiate(&env->graph, g, nullptr, nullptr, 0);
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
             if (e != hipSuccess) return hip_fail(e, "wsx_rollout (capture)");
             env->graph_key = key;
         }

@@ -53,6 +53,24 @@ struct EnvArgs {
     uint32_t t0;              // step counter at the start of the launch
 };
 
+// One roll-out request inside a fused launch: its environment set, its
+// trajectory pointers (offset to the launch's first slot) and its steps.
+struct Segment {
+    EnvArgs env;
+    TrajArgs tr;
+    int32_t steps;
+    int32_t tile_begin;   // first tile of this segment in the launch
+};
+
+// The tiles of a fused launch: one inline segment, or a device table of them
+// sorted by tile_begin.
+struct Batch {
+    const Segment* table;
+    Segment one;
+    int32_t n_segs;
+    int32_t n_tiles;
+};
+
 // One compiled variant of the fused / plain kernels for an environment kind.
 struct Variant {
     int32_t kind, dtype, hidden, waves, tile_rows, occupancy;   // occupancy: min waves/SIMD
@@ -60,8 +78,8 @@ struct Variant {
 
 // Launchers (return hipError_t of the launch).
 hipError_t launch_reset(int kind, const EnvArgs& env, hipStream_t s);
-hipError_t launch_fused(const Variant& v, const EnvArgs& env, const PolicyArgs& pol,
-                        const TrajArgs& tr, int horizon, int grid, hipStream_t s);
+hipError_t launch_fused(const Variant& v, const Batch& batch, const PolicyArgs& pol, int grid,
+                        hipStream_t s);
 hipError_t launch_plain(const Variant& v, const EnvArgs& env, const PolicyArgs& pol,
                         const TrajArgs& tr, int horizon, bool counter_from_device,
                         hipStream_t s);

@@ -441,10 +441,23 @@ __device__ __forceinline__ int env_slot(const EnvArgs& env, const Tile& tl, int 
 }
 
 // ---------------------------------------------------------- fused form --
+// The launch covers the tiles of one or more segments (roll-out requests that
+// share the policy): tile b of the launch belongs to the segment whose
+// tile_begin is the largest one <= b.
+__device__ __forceinline__ Segment segment_of(const Batch& b, int tile) {
+    if (!b.table) return b.one;
+    int lo = 0, hi = b.n_segs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (b.table[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
+    }
+    return b.table[lo];
+}
+
 template <class E, int DT, int H, int NW, int NT, int HS, int OCC>
 __global__ void __attribute__((amdgpu_flat_work_group_size(NW * 64, NW * 64),
                                amdgpu_waves_per_eu(OCC)))
-k_fused(EnvArgs env, PolicyArgs pol, TrajArgs tr, int horizon) {
+k_fused(Batch batch, PolicyArgs pol) {
     using HO = HeadOf<E>;
     using L = Mlp<DT, H, NW, NT, kin_of<E, DT>(), HO::NHP, HS>;
     constexpr int R = L::R;
@@ -462,22 +475,30 @@ k_fused(EnvArgs env, PolicyArgs pol, TrajArgs tr, int horizon) {
 #pragma unroll
     for (int j = 0; j < HO::NH; ++j) b3[j] = pol.b3[j];
 
-    EnvCtx ctx{nullptr};
-    if constexpr (E::KIND == Reaction::KIND) {
-        stage_params(reinterpret_cast<float*>(extra), env.params, tid, NTHR);
-        ctx.lds_params = reinterpret_cast<const float*>(extra);
-    }
+    EnvCtx ctx{reinterpret_cast<const float*>(extra)};
+    const float* staged = nullptr;   // reaction: potential block now in LDS
     // zero the input tile once: its padding columns stay zero
     for (int i = tid; i < R * L::P_IN / 4; i += NTHR)
         reinterpret_cast<uint32_t*>(smem + L::OFF_IN)[i] = 0u;
     __syncthreads();
 
-    const RngKey key{env.k0, env.k1, env.epoch};
-    const uint32_t t0 = step_base(env);
     int* sums = reinterpret_cast<int*>(extra);   // market: [2][R][2]
 
-    for (int tile = blockIdx.x; tile < env.n_tiles; tile += gridDim.x) {
-        const Tile tl = tile_of(env, tile, R);
+    for (int tile = blockIdx.x; tile < batch.n_tiles; tile += gridDim.x) {
+        const Segment sg = segment_of(batch, tile);
+        const EnvArgs& env = sg.env;
+        const TrajArgs& tr = sg.tr;
+        const int horizon = sg.steps;
+        const RngKey key{env.k0, env.k1, env.epoch};
+        const uint32_t t0 = step_base(env);
+        if constexpr (E::KIND == Reaction::KIND) {
+            if (env.params != staged) {   // uniform over the workgroup
+                stage_params(reinterpret_cast<float*>(extra), env.params, tid, NTHR);
+                staged = env.params;
+                __syncthreads();
+            }
+        }
+        const Tile tl = tile_of(env, tile - sg.tile_begin, R);
         const int row = tl.row0 + tid;
         const bool mine = tid < R;
         const bool valid = mine && row < tl.row1;
@@ -829,11 +850,11 @@ int fused_blocks_per_cu(const Variant& v) {
     return n > 0 ? n : 1;
 }
 
-hipError_t launch_fused(const Variant& v, const EnvArgs& env, const PolicyArgs& pol,
-                        const TrajArgs& tr, int horizon, int grid, hipStream_t s) {
+hipError_t launch_fused(const Variant& v, const Batch& batch, const PolicyArgs& pol, int grid,
+                        hipStream_t s) {
     const VariantEntry* e = find_entry(v);
     if (!e) return hipErrorInvalidValue;
-    void* args[] = {(void*)&env, (void*)&pol, (void*)&tr, (void*)&horizon};
+    void* args[] = {(void*)&batch, (void*)&pol};
     return hipLaunchKernel(e->fused, dim3(grid), dim3(v.waves * 64), args, 0, s);
 }
 

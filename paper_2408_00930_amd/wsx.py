@@ -247,3 +247,126 @@ def quantize(dtype, x, scale=1.0, stream=None):
     y = torch.empty_like(x)
     _check(lib().wsx_quantize(dtype, scale, _ptr(x), _ptr(y), x.numel(), _stream(stream)))
     return y
+
+
+# ---------------------------------------------------------------- server ----
+
+class _ServerDesc(C.Structure):
+    _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("chunk_steps", C.c_int32),
+                ("max_batch", C.c_int32)]
+
+
+class _Request(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("horizon", C.c_int32), ("n_envs", C.c_int64),
+                ("seed", C.c_uint64), ("epoch", C.c_uint32), ("keep_session", C.c_int32),
+                ("session", C.c_int64), ("policy", C.POINTER(_Policy)),
+                ("agent_offsets", C.c_void_p), ("params", C.c_void_p),
+                ("gamma", C.c_double), ("lam", C.c_double)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("reserved", C.c_int32), ("session", C.c_int64),
+                ("n_rows", C.c_int64), ("traj", _Traj), ("returns", C.c_void_p),
+                ("advantages", C.c_void_p), ("queue_ms", C.c_double), ("latency_ms", C.c_double)]
+
+
+class _ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
+                ("launches", C.c_int64), ("env_steps", C.c_int64), ("arena_in_use", C.c_size_t),
+                ("arena_peak", C.c_size_t), ("queued", C.c_int32), ("running", C.c_int32)]
+
+
+EXPORTS += ["wsx_server_create", "wsx_server_submit", "wsx_server_wait", "wsx_server_release",
+            "wsx_server_close_session", "wsx_server_get_stats", "wsx_server_destroy"]
+
+
+def _server_sigs(L):
+    if getattr(L, "_server_sigs", False):
+        return
+    vp = C.c_void_p
+    L.wsx_server_create.argtypes = [C.POINTER(_ServerDesc), C.POINTER(vp)]
+    L.wsx_server_submit.argtypes = [vp, C.POINTER(_Request), C.POINTER(C.c_int64)]
+    L.wsx_server_wait.argtypes = [vp, C.c_int64, C.c_int32, C.POINTER(_Result)]
+    L.wsx_server_release.argtypes = [vp, C.c_int64]
+    L.wsx_server_close_session.argtypes = [vp, C.c_int64]
+    L.wsx_server_get_stats.argtypes = [vp, C.POINTER(_ServerStats)]
+    L.wsx_server_destroy.argtypes = [vp]
+    L._server_sigs = True
+
+
+class Server:
+    """Continuous-batching roll-out server over a device arena (a uint8 tensor)."""
+
+    def __init__(self, arena_bytes, chunk_steps=25, max_batch=64, device="cuda"):
+        L = lib()
+        _server_sigs(L)
+        self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=torch.device(device))
+        d = _ServerDesc(self.arena.data_ptr(), arena_bytes, chunk_steps, max_batch)
+        h = C.c_void_p()
+        _check(L.wsx_server_create(C.byref(d), C.byref(h)))
+        self.handle = h
+        self._keep = {}   # request id -> host objects the request points at
+
+    def submit(self, kind, policy, horizon, n_envs=0, seed=0, epoch=0, session=0, keep=False,
+               agent_offsets=None, params=None, gamma=0.99, lam=0.95):
+        offs = None if agent_offsets is None else np.ascontiguousarray(agent_offsets, np.int32)
+        q = _Request(kind, horizon, n_envs, seed, epoch, int(keep), session, C.pointer(policy.c),
+                     None if offs is None else offs.ctypes.data,
+                     None if params is None else params.data_ptr(), gamma, lam)
+        rid = C.c_int64()
+        _check(lib().wsx_server_submit(self.handle, C.byref(q), C.byref(rid)))
+        self._keep[rid.value] = (offs, params, policy)
+        return rid.value
+
+    def wait(self, rid, timeout_ms=-1):
+        r = _Result()
+        rc = lib().wsx_server_wait(self.handle, rid, timeout_ms, C.byref(r))
+        if rc != 0:
+            raise WsxError(f"wsx error {rc}: {lib().wsx_last_error().decode()}")
+        return r
+
+    def view(self, result, kind):
+        """torch views (inside the arena) of a completed request's outputs."""
+        base = self.arena.data_ptr()
+        rows = result.n_rows
+        T = result.traj.capacity
+
+        def v(ptr, dtype, shape):
+            itemsize = torch.empty((), dtype=dtype).element_size()
+            n = int(np.prod(shape))
+            off = ptr - base
+            return self.arena[off:off + n * itemsize].view(dtype).view(*shape)
+        adt = torch.uint8 if N_ACTIONS[kind] else torch.float32
+        t = result.traj
+        return {"obs": v(t.obs, torch.float32, (T, rows, OBS_DIM[kind])),
+                "action": v(t.action, adt, (T, rows)),
+                "reward": v(t.reward, torch.float32, (T, rows)),
+                "done": v(t.done, torch.uint8, (T, rows)),
+                "value": v(t.value, torch.float32, (T, rows)),
+                "logp": v(t.logp, torch.float32, (T, rows)),
+                "last_value": v(t.last_value, torch.float32, (rows,)),
+                "returns": v(result.returns, torch.float32, (T, rows)),
+                "advantages": v(result.advantages, torch.float32, (T, rows))}
+
+    def release(self, rid):
+        _check(lib().wsx_server_release(self.handle, rid))
+        self._keep.pop(rid, None)
+
+    def close_session(self, sid):
+        _check(lib().wsx_server_close_session(self.handle, sid))
+
+    def stats(self):
+        s = _ServerStats()
+        _check(lib().wsx_server_get_stats(self.handle, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in _ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(lib().wsx_server_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

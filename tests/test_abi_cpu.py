@@ -78,3 +78,16 @@ def test_rollout_and_returns_validation_without_gpu():
                                  wsx.F64, None) == 0                 # empty: nothing to do
     assert L.wsx_quantize(wsx.FP8_E4M3, 0.3, None, None, 4, None) == -1
     assert b"power of two" in L.wsx_last_error()
+
+
+def test_server_validation_without_gpu():
+    wsx, L = _lib()
+    wsx._server_sigs(L)
+    h = C.c_void_p()
+    d = wsx._ServerDesc(None, 0, 25, 64)
+    assert L.wsx_server_create(C.byref(d), C.byref(h)) == -1
+    d = wsx._ServerDesc(1234, 1 << 30, 0, 64)
+    assert L.wsx_server_create(C.byref(d), C.byref(h)) == -1      # chunk_steps must be > 0
+    d = wsx._ServerDesc(1234, 1024, 25, 64)
+    assert L.wsx_server_create(C.byref(d), C.byref(h)) == -1      # smaller than launch tables
+    assert L.wsx_server_submit(None, None, None) == -1

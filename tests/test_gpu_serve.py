@@ -1,0 +1,166 @@
+"""The roll-out server: continuous batching, admission by the arena budget,
+resident sessions, and results that are the same alone and in a mix."""
+import time
+
+import numpy as np
+import pytest
+
+from gpu_cases import DTYPE, HIDDEN, say
+from paper_2408_00930_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+KINDS = (2, 3, 4, 5)   # pendulum, acrobot, market, reaction
+
+
+def _wsx():
+    from paper_2408_00930_amd import wsx
+    return wsx
+
+
+class Fixture:
+    def __init__(self):
+        import torch
+        wsx = _wsx()
+        self.pol = {k: wsx.DevicePolicy(inputs.policy_for(k, DTYPE[k], HIDDEN[k], seed=k))
+                    for k in KINDS}
+        self.params = torch.from_numpy(inputs.reaction_params(1)).cuda()
+
+    def spec(self, kind, n_envs, horizon, seed, epoch=0):
+        d = dict(kind=kind, policy=self.pol[kind], horizon=horizon, n_envs=n_envs, seed=seed,
+                 epoch=epoch)
+        if kind == 4:
+            d["agent_offsets"] = inputs.agent_offsets(n_envs, seed=seed)
+        if kind == 5:
+            d["params"] = self.params
+        return d
+
+
+def _host(view):
+    return {k: v.cpu().numpy() for k, v in view.items()}
+
+
+def _direct(fx, spec):
+    """The same roll-out through wsx_rollout and wsx_compute_returns."""
+    import torch
+    wsx = _wsx()
+    kind = spec["kind"]
+    env = wsx.Env(kind, spec["n_envs"], seed=spec["seed"], agent_offsets=spec.get("agent_offsets"),
+                  params=None if kind != 5 else inputs.reaction_params(1))
+    traj = wsx.Trajectory(kind, spec["horizon"], env.rows)
+    wsx.env_reset(env, spec["epoch"])
+    wsx.rollout(env, spec["policy"], spec["horizon"], traj)
+    ret, adv = wsx.compute_returns(traj, spec["horizon"], 0.99, 0.95, True, torch.float32)
+    out = traj.host()
+    out["returns"] = ret.cpu().numpy()
+    out["advantages"] = adv.cpu().numpy()
+    return out
+
+
+def _equal(a, b):
+    for k in ("obs", "action", "reward", "done", "value", "logp", "last_value", "returns",
+              "advantages"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_result_same_alone_in_mix_and_direct(kind):
+    wsx = _wsx()
+    fx = Fixture()
+    say("serve alone vs mix", kind)
+    x = fx.spec(kind, 150 if kind != 4 else 9, 70, seed=5, epoch=2)
+    srv = wsx.Server(2 << 30, chunk_steps=16, max_batch=32)
+    rid = srv.submit(**x)
+    r = srv.wait(rid, 60000)
+    alone = _host(srv.view(r, kind))
+    srv.release(rid)
+    # a mix of every kind and size, with the request of interest in the middle
+    rng = np.random.default_rng(kind)
+    others = []
+    for i in range(8):
+        k = KINDS[i % 4]
+        n = int(rng.integers(20, 400)) if k != 4 else int(rng.integers(2, 12))
+        others.append(srv.submit(**fx.spec(k, n, int(rng.integers(10, 90)), seed=100 + i)))
+        if i == 4:
+            time.sleep(0.002)
+            xid = srv.submit(**x)
+    r = srv.wait(xid, 60000)
+    mixed = _host(srv.view(r, kind))
+    for o in others:
+        srv.wait(o, 60000)
+        srv.release(o)
+    srv.release(xid)
+    st = srv.stats()
+    srv.close()
+    _equal(alone, mixed)
+    _equal(alone, _direct(fx, x))
+    print(f"kind {kind}: {st['launches']} launches for {st['completed']} requests, "
+          f"arena peak {st['arena_peak'] / 2**20:.1f} MiB", flush=True)
+
+
+def test_requests_share_launches():
+    """Requests that overlap in time run in the same batched launches."""
+    wsx = _wsx()
+    fx = Fixture()
+    say("serve batching")
+    srv = wsx.Server(1 << 30, chunk_steps=10, max_batch=64)
+    ids = [srv.submit(**fx.spec(2, 64, 100, seed=s)) for s in range(12)]
+    for i in ids:
+        srv.wait(i, 60000)
+        srv.release(i)
+    st = srv.stats()
+    srv.close()
+    chunks = 12 * 10
+    print(f"{st['launches']} launches for {chunks} request-chunks", flush=True)
+    assert st["completed"] == 12 and st["launches"] < chunks
+
+
+def test_session_continuation_equals_one_rollout():
+    wsx = _wsx()
+    fx = Fixture()
+    say("serve session continuation")
+    srv = wsx.Server(1 << 30, chunk_steps=16)
+    x = fx.spec(3, 90, 40, seed=7, epoch=1)
+    a = srv.submit(keep=True, **x)
+    ra = srv.wait(a, 60000)
+    first = _host(srv.view(ra, 3))
+    sid = ra.session
+    srv.release(a)
+    b = srv.submit(kind=3, policy=fx.pol[3], horizon=30, session=sid, keep=False)
+    rb = srv.wait(b, 60000)
+    second = _host(srv.view(rb, 3))
+    srv.release(b)
+    srv.close()
+    full = _direct(fx, dict(x, horizon=70))
+    for k in ("obs", "action", "reward", "done", "value", "logp"):
+        assert np.array_equal(np.concatenate([first[k], second[k]]), full[k]), k
+    assert np.array_equal(second["last_value"], full["last_value"])
+
+
+def test_admission_waits_for_memory():
+    """An arena that holds two requests at a time still completes all six."""
+    wsx = _wsx()
+    fx = Fixture()
+    say("serve admission")
+    one = 3 * 1024 * 1024
+    srv = wsx.Server(2 * one + (1 << 21), chunk_steps=20)
+    ids = [srv.submit(**fx.spec(2, 1500, 60, seed=s)) for s in range(6)]
+    results = []
+    for i in ids:
+        r = srv.wait(i, 120000)
+        results.append(r.queue_ms)
+        srv.release(i)
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == 6 and st["arena_peak"] <= 2 * one + (1 << 21)
+    assert max(results) > 0.0
+
+
+def test_request_larger_than_arena_is_rejected():
+    wsx = _wsx()
+    fx = Fixture()
+    say("serve too large")
+    srv = wsx.Server(1 << 22, chunk_steps=20)
+    with pytest.raises(wsx.WsxError):
+        srv.submit(**fx.spec(2, 100000, 500, seed=1))
+    srv.close()
