@@ -163,4 +163,74 @@ __device__ __forceinline__ float tanh_scaled(float acc, float k2) {
 
 constexpr float kTwoLog2e = 2.8853900817779268f;  // 2 / ln 2
 
+// ------------------------------------------------------- lane groups --
+// A row of a tile is served by G consecutive lanes (G a power of two <= 16,
+// groups aligned within a 16-lane row of the wave). The reductions use DPP
+// lane permutations (quad swaps, half-row and row mirrors), which pair the
+// same partial results on every lane, so every lane of a group ends with the
+// same value.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __builtin_bit_cast(float, dpp_i<CTRL>(__builtin_bit_cast(int, v)));
+}
+constexpr int kDppSwap1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppSwap2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;  // lane i <-> 7 - i within 8 lanes
+constexpr int kDppMirror = 0x140;      // lane i <-> 15 - i within 16 lanes
+constexpr int kDppShr1 = 0x111;        // row_shr:n = 0x110 + n
+
+template <int G>
+__device__ __forceinline__ float group_sum(float v) {
+    static_assert(G <= 16, "groups of at most 16 lanes");
+    if constexpr (G >= 2) v += dpp_f<kDppSwap1>(v);
+    if constexpr (G >= 4) v += dpp_f<kDppSwap2>(v);
+    if constexpr (G >= 8) v += dpp_f<kDppHalfMirror>(v);
+    if constexpr (G >= 16) v += dpp_f<kDppMirror>(v);
+    return v;
+}
+
+template <int G>
+__device__ __forceinline__ float group_max(float v) {
+    if constexpr (G >= 2) v = fmaxf(v, dpp_f<kDppSwap1>(v));
+    if constexpr (G >= 4) v = fmaxf(v, dpp_f<kDppSwap2>(v));
+    if constexpr (G >= 8) v = fmaxf(v, dpp_f<kDppHalfMirror>(v));
+    if constexpr (G >= 16) v = fmaxf(v, dpp_f<kDppMirror>(v));
+    return v;
+}
+
+template <int G>
+__device__ __forceinline__ int group_min(int v) {
+    if constexpr (G >= 2) v = min(v, dpp_i<kDppSwap1>(v));
+    if constexpr (G >= 4) v = min(v, dpp_i<kDppSwap2>(v));
+    if constexpr (G >= 8) v = min(v, dpp_i<kDppHalfMirror>(v));
+    if constexpr (G >= 16) v = min(v, dpp_i<kDppMirror>(v));
+    return v;
+}
+
+// Sum of the values of the lanes before `sub` in the group (0 for sub 0):
+// an inclusive scan with row shifts, then one more shift.
+template <int G>
+__device__ __forceinline__ float group_prefix(float v, int sub) {
+    float inc = v;
+    if constexpr (G >= 2) { const float t = dpp_f<0x111>(inc); if (sub >= 1) inc += t; }
+    if constexpr (G >= 4) { const float t = dpp_f<0x112>(inc); if (sub >= 2) inc += t; }
+    if constexpr (G >= 8) { const float t = dpp_f<0x114>(inc); if (sub >= 4) inc += t; }
+    if constexpr (G >= 16) { const float t = dpp_f<0x118>(inc); if (sub >= 8) inc += t; }
+    if constexpr (G == 1) return 0.0f;
+    const float before = dpp_f<kDppShr1>(inc);
+    return sub == 0 ? 0.0f : before;
+}
+
+// Lanes per row for a tile of R rows served by `threads` threads, at most
+// `cap` (the lanes an environment can use).
+constexpr int lanes_per_row(int R, int threads, int cap) {
+    int g = 1;
+    while (g < cap && 2 * g * R <= threads) g *= 2;
+    return g;
+}
+
 }  // namespace wsx

@@ -20,7 +20,7 @@ struct EnvCtx {
 // Cart (mass 1) with a hinged uniform pole (mass 0.1, half-length 0.5), force
 // +-10, explicit Euler dt 0.02; ends when |x| > 2.4 or |theta| > 12 degrees.
 struct CartPole {
-    static constexpr int KIND = 1, SD = 4, OD = 4, NACT = 2;
+    static constexpr int KIND = 1, SD = 4, OD = 4, NACT = 2, LANES = 1;
     __device__ static void reset(float* s, const RngKey& key, uint32_t t, uint32_t row,
                                  const EnvCtx&) {
         const Words w = draw(key, t, row, PURPOSE_RESET, 0);
@@ -31,8 +31,9 @@ struct CartPole {
 #pragma unroll
         for (int i = 0; i < 4; ++i) o[i] = s[i];
     }
+    template <int G>
     __device__ static void step(float* s, int action, float, uint32_t, uint32_t, const RngKey&,
-                                const EnvCtx&, float& reward, bool& done) {
+                                const EnvCtx&, int, float& reward, bool& done) {
         const float gravity = 9.8f, m_pole = 0.1f, m_total = 1.1f, half_len = 0.5f;
         const float dt = 0.02f;
         const float force = action == 1 ? 10.0f : -10.0f;
@@ -63,7 +64,7 @@ __device__ __forceinline__ float wrap_pi(float a) {
 // Rod (m 1, l 1) under gravity 10 about its end, theta 0 upright, torque
 // clipped to 2; semi-implicit Euler dt 0.05, rate clipped to 8.
 struct Pendulum {
-    static constexpr int KIND = 2, SD = 2, OD = 3, NACT = 0;
+    static constexpr int KIND = 2, SD = 2, OD = 3, NACT = 0, LANES = 1;
     __device__ static void reset(float* s, const RngKey& key, uint32_t t, uint32_t row,
                                  const EnvCtx&) {
         const Words w = draw(key, t, row, PURPOSE_RESET, 0);
@@ -74,8 +75,9 @@ struct Pendulum {
         sincosf(s[0], &o[1], &o[0]);
         o[2] = s[1];
     }
+    template <int G>
     __device__ static void step(float* s, int, float torque, uint32_t, uint32_t, const RngKey&,
-                                const EnvCtx&, float& reward, bool& done) {
+                                const EnvCtx&, int, float& reward, bool& done) {
         const float u = fminf(fmaxf(torque, -2.0f), 2.0f);
         const float th = s[0], thd = s[1];
         const float a = wrap_pi(th);
@@ -94,7 +96,7 @@ struct Pendulum {
 // in [-1, 1], RK4 over dt 0.2; ends when the tip is more than one link length
 // above the base.
 struct Acrobot {
-    static constexpr int KIND = 3, SD = 4, OD = 6, NACT = 0;
+    static constexpr int KIND = 3, SD = 4, OD = 6, NACT = 0, LANES = 1;
     __device__ static void reset(float* s, const RngKey& key, uint32_t t, uint32_t row,
                                  const EnvCtx&) {
         const Words w = draw(key, t, row, PURPOSE_RESET, 0);
@@ -129,8 +131,9 @@ struct Acrobot {
         dq[2] = (m22 * rhs1 - m12 * rhs2) / det;
         dq[3] = (m11 * rhs2 - m12 * rhs1) / det;
     }
+    template <int G>
     __device__ static void step(float* s, int, float torque, uint32_t, uint32_t, const RngKey&,
-                                const EnvCtx&, float& reward, bool& done) {
+                                const EnvCtx&, int, float& reward, bool& done) {
         const float tau = fminf(fmaxf(torque, -1.0f), 1.0f);
         const float h = 0.2f;
         float k1[4], k2[4], k3[4], k4[4], y[4];
@@ -159,8 +162,9 @@ struct Acrobot {
 // -------------------------------------------------------------- Market --
 // Per agent: 32-d state; the env-wide demand and supply sums are formed by
 // the kernels (exactly, in integer units) between decide() and settle().
+// LANES: how many lanes of a group can share a row's sampling and dynamics.
 struct Market {
-    static constexpr int KIND = 4, SD = 32, OD = 32, NACT = 50;
+    static constexpr int KIND = 4, SD = 32, OD = 32, NACT = 50, LANES = 4;
     __device__ static void reset(float* s, const RngKey& key, uint32_t t, uint32_t row,
                                  const EnvCtx&) {
 #pragma unroll
@@ -210,38 +214,51 @@ struct Market {
 // plus 0.05 N(0,1) noise per evaluation. The LDS parameter block is A (400),
 // centres (64 x 20), -1/(2 w^2) (64), amplitudes (64).
 struct Reaction {
-    static constexpr int KIND = 5, SD = 21, OD = 20, NACT = 40, NDIM = 20, NG = 64;
+    static constexpr int KIND = 5, SD = 21, OD = 20, NACT = 40, NDIM = 20, NG = 64, LANES = 16;
     static constexpr int PARAM_FLOATS = NDIM * NDIM + NG * NDIM + NG + NG;
-    __device__ static float energy(const float* x, const float* p) {
+    // E(x) with its quadratic rows and its Gaussians dealt over the G lanes of
+    // the row's group (lane `sub` takes those congruent to sub mod G); every
+    // lane returns the same total.
+    template <int G>
+    __device__ static float energy(const float* x, const float* p, int sub) {
         const float* A = p;
         const float* cen = p + NDIM * NDIM;
         const float* nhw = cen + NG * NDIM;
         const float* amp = nhw + NG;
-        float quad = 0.0f;
-        for (int i = 0; i < NDIM; ++i) {
-            float row = 0.0f;
+        float part = 0.0f;
 #pragma unroll
-            for (int j = 0; j < NDIM; ++j) row += A[i * NDIM + j] * x[j];
-            quad += x[i] * row;
+        for (int m = 0; m < (NDIM + G - 1) / G; ++m) {
+            const int i = sub + m * G;
+            if (i < NDIM) {
+                float row = 0.0f, xi = 0.0f;
+#pragma unroll
+                for (int j = 0; j < NDIM; ++j) {
+                    row += A[i * NDIM + j] * x[j];
+                    xi = j == i ? x[j] : xi;
+                }
+                part += 0.5f * xi * row;
+            }
         }
-        float e = 0.5f * quad;
-        for (int k = 0; k < NG; ++k) {
+#pragma unroll
+        for (int m = 0; m < NG / G; ++m) {
+            const int k = sub + m * G;
             float d2 = 0.0f;
 #pragma unroll
             for (int i = 0; i < NDIM; ++i) {
                 const float d = x[i] - cen[k * NDIM + i];
                 d2 += d * d;
             }
-            e += amp[k] * expf(d2 * nhw[k]);
+            part += amp[k] * expf(d2 * nhw[k]);
         }
-        return e;
+        return group_sum<G>(part);
     }
+    template <int G>
     __device__ static float noisy_energy(const float* x, const RngKey& key, uint32_t t, uint32_t row,
-                                         const EnvCtx& c) {
+                                         const EnvCtx& c, int sub) {
         const Words w = draw(key, t, row, PURPOSE_NOISE, 0);
         float zc, zs;
         gauss_pair(unit_uniform(w.w[0]), unit_uniform(w.w[1]), zc, zs);
-        return energy(x, c.lds_params) + 0.05f * zc;
+        return energy<G>(x, c.lds_params, sub) + 0.05f * zc;
     }
     __device__ static void reset(float* s, const RngKey& key, uint32_t t, uint32_t row,
                                  const EnvCtx& c) {
@@ -251,20 +268,21 @@ struct Reaction {
 #pragma unroll
             for (int i = 0; i < 4; ++i) s[4 * sub + i] = -3.0f + 6.0f * unit_uniform(w.w[i]);
         }
-        s[20] = noisy_energy(s, key, t, row, c);
+        s[20] = noisy_energy<1>(s, key, t, row, c, 0);
     }
     __device__ static void observe(const float* s, float* o) {
 #pragma unroll
         for (int i = 0; i < 20; ++i) o[i] = s[i];
     }
+    template <int G>
     __device__ static void step(float* s, int a, float, uint32_t t, uint32_t row, const RngKey& key,
-                                const EnvCtx& c, float& reward, bool& done) {
+                                const EnvCtx& c, int sub, float& reward, bool& done) {
         const int coord = a >> 1;
         const float delta = (a & 1) ? -0.05f : 0.05f;
 #pragma unroll
         for (int i = 0; i < 20; ++i)
             if (i == coord) s[i] += delta;
-        const float e_new = noisy_energy(s, key, t + 1, row, c);
+        const float e_new = noisy_energy<G>(s, key, t + 1, row, c, sub);
         reward = -(e_new - s[20]);
         s[20] = e_new;
         done = false;

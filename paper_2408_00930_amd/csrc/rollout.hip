@@ -115,6 +115,15 @@ __device__ __forceinline__ void wave_lds_sync() {
     __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 }
 
+// Row tiles per accumulator block: up to 5 tiles in one block, larger counts
+// in blocks of the largest divisor <= 4 (bounds the accumulator registers).
+constexpr int row_tile_block(int nt) {
+    if (nt <= 5) return nt;
+    for (int b = 4; b > 1; --b)
+        if (nt % b == 0) return b;
+    return 1;
+}
+
 // HS selects how the head is spread over the waves. HS = 0 (split-K): wave w
 // multiplies its own h2 features by its K-slice of the head for every head
 // row, leaving NW partial sums per row (no extra barrier). HS = 1 (split-M):
@@ -141,7 +150,12 @@ struct Mlp {
     // split-M writes the head after a barrier that follows the last read of
     // h1, so its results reuse the h1 tile
     static constexpr int OFF_PART = HS ? OFF_H1 : OFF_H2 + R * P_H;
-    static constexpr int BYTES = HS ? OFF_H2 + R * P_H : OFF_PART + NPART * R * P_PART * 4;
+    // per-feature accumulator start (bias / output scale) and tanh factor
+    // (2 log2 e * output scale) of both hidden layers: [4][H] floats
+    static constexpr int OFF_TAB = HS ? OFF_H2 + R * P_H : OFF_PART + NPART * R * P_PART * 4;
+    static constexpr int BYTES = OFF_TAB + 4 * H * 4;
+    static constexpr int NTB = row_tile_block(NT);   // row tiles per accumulator block
+    static_assert(NT % NTB == 0, "row-tile blocking");
     static_assert(!HS || P_PART * 4 <= P_H, "head results fit in the h1 tile");
     static_assert(FPW % 16 == 0 && FPW % K == 0 && KIN % K == 0 && H % K == 0, "tile shape");
     static_assert(BYTES <= 160 * 1024, "LDS budget");
@@ -149,9 +163,6 @@ struct Mlp {
     Frag w1[MT][K1S];
     Frag w2[MT][K2S];
     Frag w3[NHW][KHS];
-    static constexpr int KXM = DT == DT_FP8 ? MT : 1;   // per-row tanh scales (FP8 only)
-    float init1[MT][4], init2[MT][4];  // bias / output scale: accumulator start
-    float kx1[KXM][4], kx2[KXM][4];    // 2 log2(e) * output scale (tanh argument)
     float o3[NHW][4];                  // head output scale
     float inv_q1, inv_q2;              // 1 / scale of the h1 and h2 quantisation
 
@@ -159,13 +170,24 @@ struct Mlp {
         return (s != nullptr && m < m_valid) ? s[m] : 1.0f;
     }
 
-    __device__ void load(const PolicyArgs& p, int wave, int lane) {
+    // Weights into registers and the per-feature table into LDS (the caller
+    // synchronises the workgroup before the first forward).
+    __device__ void load(const PolicyArgs& p, char* smem, int wave, int lane, int tid) {
         const int lr = lane & 15, kq = (lane >> 4) * KC;
         const float a0 = DT == DT_FP8 ? p.act_scale[0] : 1.0f;
         const float a1 = DT == DT_FP8 ? p.act_scale[1] : 1.0f;
         const float a2 = DT == DT_FP8 ? p.act_scale[2] : 1.0f;
         inv_q1 = 1.0f / a1;
         inv_q2 = 1.0f / a2;
+        float* tab = reinterpret_cast<float*>(smem + OFF_TAB);
+        for (int m = tid; m < H; m += NW * 64) {
+            const float sc1 = row_scale(p.s1, m, H) * a0;
+            const float sc2 = row_scale(p.s2, m, H) * a1;
+            tab[m] = p.b1[m] / sc1;
+            tab[H + m] = kTwoLog2e * sc1;
+            tab[2 * H + m] = p.b2[m] / sc2;
+            tab[3 * H + m] = kTwoLog2e * sc2;
+        }
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
             const int m = wave * FPW + mt * 16 + lr;
@@ -173,16 +195,6 @@ struct Mlp {
             for (int ks = 0; ks < K1S; ++ks) load_a(w1[mt][ks], p.w1, p.d_in, m, H, ks * K + kq, p.d_in);
 #pragma unroll
             for (int ks = 0; ks < K2S; ++ks) load_a(w2[mt][ks], p.w2, H, m, H, ks * K + kq, H);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int mc = wave * FPW + mt * 16 + 4 * (lane >> 4) + i;   // C row
-                const float sc1 = row_scale(p.s1, mc, H) * a0;
-                const float sc2 = row_scale(p.s2, mc, H) * a1;
-                init1[mt][i] = p.b1[mc] / sc1;
-                init2[mt][i] = p.b2[mc] / sc2;
-                kx1[DT == DT_FP8 ? mt : 0][i] = kTwoLog2e * sc1;
-                kx2[DT == DT_FP8 ? mt : 0][i] = kTwoLog2e * sc2;
-            }
         }
 #pragma unroll
         for (int hw = 0; hw < NHW; ++hw) {
@@ -197,49 +209,58 @@ struct Mlp {
         }
     }
 
-    // Dense layer of this wave's MT output tiles for all NT row tiles,
-    // then tanh and quantisation into `out` (row-major [R][H]).
+    // Dense layer of this wave's MT output tiles for all NT row tiles (in
+    // blocks of NTB), then tanh and quantisation into `out` ([R][H] rows).
+    // `tab` holds the layer's accumulator starts and tanh factors.
     template <int KS>
-    __device__ __forceinline__ void dense_tanh(const Frag (&w)[MT][KS], const float (&init)[MT][4],
-                                               const float (&kx)[KXM][4], const char* in, int p_in,
-                                               char* out, float inv_q, int wave, int lane) {
+    __device__ __forceinline__ void dense_tanh(const Frag (&w)[MT][KS], const float* tab,
+                                               const char* in, int p_in, char* out, float inv_q,
+                                               int wave, int lane) {
         const int lr = lane & 15, kq = (lane >> 4) * KC;
-        f32x4 acc[MT][NT];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
+        for (int nb = 0; nb < NT; nb += NTB) {
+            f32x4 acc[MT][NTB];
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
-                acc[mt][nt] = f32x4{init[mt][0], init[mt][1], init[mt][2], init[mt][3]};
+            for (int mt = 0; mt < MT; ++mt) {
+                const float4 ini = *reinterpret_cast<const float4*>(
+                    tab + wave * FPW + mt * 16 + 4 * (lane >> 4));
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            Frag b[NT];
+                for (int nt = 0; nt < NTB; ++nt) acc[mt][nt] = f32x4{ini.x, ini.y, ini.z, ini.w};
+            }
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
-                b[nt] = M::lds(in + (nt * 16 + lr) * p_in + (ks * K + kq) * EB);
+            for (int ks = 0; ks < KS; ++ks) {
+                Frag b[NTB];
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
+                for (int nt = 0; nt < NTB; ++nt)
+                    b[nt] = M::lds(in + ((nb + nt) * 16 + lr) * p_in + (ks * K + kq) * EB);
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = M::mma(w[mt][ks], b[nt], acc[mt][nt]);
-        }
+                for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            const int feat = wave * FPW + mt * 16 + 4 * (lane >> 4);
-            const int km = DT == DT_FP8 ? mt : 0;
+                    for (int nt = 0; nt < NTB; ++nt)
+                        acc[mt][nt] = M::mma(w[mt][ks], b[nt], acc[mt][nt]);
+            }
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const f32x4 a = acc[mt][nt];
-                store4<DT>(out + (nt * 16 + lr) * P_H + feat * EB, tanh_scaled(a[0], kx[km][0]),
-                           tanh_scaled(a[1], kx[km][1]), tanh_scaled(a[2], kx[km][2]),
-                           tanh_scaled(a[3], kx[km][3]), inv_q);
+            for (int mt = 0; mt < MT; ++mt) {
+                const int feat = wave * FPW + mt * 16 + 4 * (lane >> 4);
+                float4 kx = make_float4(kTwoLog2e, kTwoLog2e, kTwoLog2e, kTwoLog2e);
+                if constexpr (DT == DT_FP8) kx = *reinterpret_cast<const float4*>(tab + H + feat);
+#pragma unroll
+                for (int nt = 0; nt < NTB; ++nt) {
+                    const f32x4 a = acc[mt][nt];
+                    store4<DT>(out + ((nb + nt) * 16 + lr) * P_H + feat * EB,
+                               tanh_scaled(a[0], kx.x), tanh_scaled(a[1], kx.y),
+                               tanh_scaled(a[2], kx.z), tanh_scaled(a[3], kx.w), inv_q);
+                }
             }
         }
     }
 
     // Phases A-C. The caller synchronises the workgroup afterwards.
     __device__ void forward(char* smem, int wave, int lane) {
-        dense_tanh<K1S>(w1, init1, kx1, smem + OFF_IN, P_IN, smem + OFF_H1, inv_q1, wave, lane);
+        const float* tab = reinterpret_cast<const float*>(smem + OFF_TAB);
+        dense_tanh<K1S>(w1, tab, smem + OFF_IN, P_IN, smem + OFF_H1, inv_q1, wave, lane);
         __syncthreads();
-        dense_tanh<K2S>(w2, init2, kx2, smem + OFF_H1, P_H, smem + OFF_H2, inv_q2, wave, lane);
+        dense_tanh<K2S>(w2, tab + 2 * H, smem + OFF_H1, P_H, smem + OFF_H2, inv_q2, wave, lane);
         if constexpr (HS)
             __syncthreads();   // every wave reads all of h2
         else
@@ -304,42 +325,85 @@ struct Mlp {
         for (int j = 0; j < NH; ++j) h[j] += b3[j];
     }
 
-    // Quantised observation row into the input tile.
-    template <int OD>
-    __device__ static void put_obs(char* smem, int r, const float (&o)[OD], float inv_q0) {
+    // Head outputs [j0, j0 + C) (those below NH - 1) and the value output
+    // (index NH - 1) of tile row r, summed in the same order as head_row.
+    template <int NH, int C>
+    __device__ static void head_block(const char* smem, const float (&b3b)[C], float b3v, int r,
+                                      int j0, float (&hb)[C], float& hv) {
+        const float* part = reinterpret_cast<const float*>(smem + OFF_PART);
+        float acc[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] = 0.0f;
+        float accv = 0.0f;
+#pragma unroll
+        for (int w = 0; w < NPART; ++w) {
+            const float* pr = part + (w * R + r) * P_PART;
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (j0 + c < NH - 1) acc[c] += pr[j0 + c];
+            accv += pr[NH - 1];
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) hb[c] = acc[c] + b3b[c];
+        hv = accv + b3v;
+    }
+
+    // Quantised observation row into the input tile; lane `sub` of the row's
+    // G lanes writes the elements congruent to sub mod G.
+    template <int OD, int G>
+    __device__ static void put_obs(char* smem, int r, const float (&o)[OD], float inv_q0, int sub) {
         char* p = smem + OFF_IN + r * P_IN;
 #pragma unroll
-        for (int k = 0; k < OD; ++k) store1<DT>(p + k * EB, o[k], inv_q0);
+        for (int k = 0; k < OD; ++k)
+            if (k % G == sub) store1<DT>(p + k * EB, o[k], inv_q0);
     }
 };
 
 // ------------------------------------------------------------- sampling --
-// Categorical: softmax (max subtracted), CDF, a = min{k : u < C_k} else K-1.
-template <int K>
-__device__ __forceinline__ int sample_categorical(const float* logits, float u, float& logp) {
-    float mx = logits[0];
+// The head block of a row's lane: lane `sub` of G holds logits
+// [sub * C, sub * C + C) of a categorical head; a Gaussian head's mean is on
+// every lane.
+template <class E, int G>
+struct Block {
+    static constexpr int C = E::NACT ? (E::NACT + G - 1) / G : 1;
+    __device__ static int first(int sub) { return E::NACT ? sub * C : 0; }
+};
+
+// Categorical draw over the row's G lanes: softmax with the maximum
+// subtracted, CDF in index order, a = min{k : u < C_k} (K - 1 if none).
+// Every lane returns the same action and log-probability.
+template <int K, int G, int C>
+__device__ __forceinline__ int sample_categorical(const float (&lg)[C], int sub, float u,
+                                                  float& logp) {
+    const int j0 = sub * C;
+    float mx = -INFINITY;
 #pragma unroll
-    for (int k = 1; k < K; ++k) mx = fmaxf(mx, logits[k]);
-    float e[K];
-    float z = 0.0f;
+    for (int c = 0; c < C; ++c)
+        if (j0 + c < K) mx = fmaxf(mx, lg[c]);
+    mx = group_max<G>(mx);
+    float e[C];
+    float s = 0.0f;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        e[k] = expf(logits[k] - mx);
-        z += e[k];
+    for (int c = 0; c < C; ++c) {
+        e[c] = j0 + c < K ? expf(lg[c] - mx) : 0.0f;
+        s += e[c];
     }
+    const float z = group_sum<G>(s);
     const float inv_z = 1.0f / z;
-    int a = K - 1;
-    bool found = false;
-    float cdf = 0.0f, la = logits[K - 1];
+    float acc = group_prefix<G>(s, sub);
+    int cand = K;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        cdf += e[k] * inv_z;
-        if (!found && u < cdf) {
-            a = k;
-            la = logits[k];
-            found = true;
-        }
+    for (int c = 0; c < C; ++c) {
+        acc += e[c];
+        if (cand == K && j0 + c < K && u < acc * inv_z) cand = j0 + c;
     }
+    int a = group_min<G>(cand);
+    if (a >= K) a = K - 1;
+    float la = 0.0f;
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        if (j0 + c == a) la = lg[c];
+    la = group_sum<G>(la);   // only the owner contributes
     logp = (la - mx) - logf(z);
     return a;
 }
@@ -350,19 +414,19 @@ struct Act {
     float value;
 };
 
-// Draw the action of row `row` at step t from its head outputs.
-template <class E, int NH>
-__device__ __forceinline__ Act<E> choose(const float (&h)[NH], const RngKey& key, uint32_t t,
-                                         uint32_t row, float log_std, float& logp) {
+// Draw the action of row `row` at step t from its head block.
+template <class E, int G, int C>
+__device__ __forceinline__ Act<E> choose(const float (&hb)[C], int sub, const RngKey& key,
+                                         uint32_t t, uint32_t row, float log_std, float& logp) {
     const Words w = draw(key, t, row, PURPOSE_ACTION, 0);
     Act<E> act{0, 0.0f};
     if constexpr (E::NACT > 0) {
-        act.index = sample_categorical<E::NACT>(h, unit_uniform(w.w[0]), logp);
+        act.index = sample_categorical<E::NACT, G, C>(hb, sub, unit_uniform(w.w[0]), logp);
         act.value = (float)act.index;
     } else {
         float zc, zs;
         gauss_pair(unit_uniform(w.w[0]), unit_uniform(w.w[1]), zc, zs);
-        act.value = h[0] + expf(log_std) * zc;
+        act.value = hb[0] + expf(log_std) * zc;
         logp = -0.5f * zc * zc - log_std - 0.91893853320467274f;   // log(2 pi) / 2
     }
     return act;
@@ -393,10 +457,19 @@ __device__ __forceinline__ void load_state(const EnvArgs& env, int64_t row, floa
     for (int i = 0; i < E::SD; ++i) s[i] = env.state[(size_t)i * env.n_rows + row];
 }
 
-template <class E>
-__device__ __forceinline__ void save_state(const EnvArgs& env, int64_t row, const float (&s)[E::SD]) {
+template <class E, int G>
+__device__ __forceinline__ void save_state(const EnvArgs& env, int64_t row, const float (&s)[E::SD],
+                                           int sub) {
 #pragma unroll
-    for (int i = 0; i < E::SD; ++i) env.state[(size_t)i * env.n_rows + row] = s[i];
+    for (int i = 0; i < E::SD; ++i)
+        if (i % G == sub) env.state[(size_t)i * env.n_rows + row] = s[i];
+}
+
+template <int OD, int G>
+__device__ __forceinline__ void store_obs(float* dst, const float (&o)[OD], int sub) {
+#pragma unroll
+    for (int k = 0; k < OD; ++k)
+        if (k % G == sub) dst[k] = o[k];
 }
 
 // Stage the reaction potential in LDS: A, centres, -1/(2 w^2), amplitudes.
@@ -462,18 +535,24 @@ k_fused(Batch batch, PolicyArgs pol) {
     using L = Mlp<DT, H, NW, NT, kin_of<E, DT>(), HO::NHP, HS>;
     constexpr int R = L::R;
     constexpr int NTHR = NW * 64;
-    static_assert(R <= NTHR, "one thread per tile row");
+    constexpr int G = lanes_per_row(R, NTHR, E::LANES);   // lanes serving one row in phase D
+    using B = Block<E, G>;
+    constexpr int C = B::C;
+    static_assert(R * G <= NTHR, "G lanes per tile row");
     __shared__ __attribute__((aligned(16))) char smem[L::BYTES + extra_lds_bytes<E>(R)];
     char* extra = smem + L::BYTES;
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int rr = tid / G, sub = tid % G;   // tile row and lane within its group
     L mlp;
-    mlp.load(pol, wave, lane);
+    mlp.load(pol, smem, wave, lane, tid);
     const float inv_q0 = DT == DT_FP8 ? 1.0f / pol.act_scale[0] : 1.0f;
     const float log_std = (E::NACT == 0 && pol.log_std) ? pol.log_std[0] : 0.0f;
-    float b3[HO::NH];
+    const int j0 = B::first(sub);
+    float b3b[C];
 #pragma unroll
-    for (int j = 0; j < HO::NH; ++j) b3[j] = pol.b3[j];
+    for (int c = 0; c < C; ++c) b3b[c] = j0 + c < HO::NOUT ? pol.b3[j0 + c] : 0.0f;
+    const float b3v = pol.b3[HO::NOUT];
 
     EnvCtx ctx{reinterpret_cast<const float*>(extra)};
     const float* staged = nullptr;   // reaction: potential block now in LDS
@@ -499,9 +578,10 @@ k_fused(Batch batch, PolicyArgs pol) {
             }
         }
         const Tile tl = tile_of(env, tile - sg.tile_begin, R);
-        const int row = tl.row0 + tid;
-        const bool mine = tid < R;
+        const int row = tl.row0 + rr;
+        const bool mine = rr < R;
         const bool valid = mine && row < tl.row1;
+        const bool lead = valid && sub == 0;   // writes the row's scalar records
         float s[E::SD];
 #pragma unroll
         for (int i = 0; i < E::SD; ++i) s[i] = 0.0f;
@@ -514,10 +594,8 @@ k_fused(Batch batch, PolicyArgs pol) {
         if (mine) {
             float o[E::OD];
             E::observe(s, o);
-            L::template put_obs<E::OD>(smem, tid, o, inv_q0);
-            if (valid && horizon > 0)
-#pragma unroll
-                for (int k = 0; k < E::OD; ++k) tr.obs[(size_t)row * E::OD + k] = o[k];
+            L::template put_obs<E::OD, G>(smem, rr, o, inv_q0, sub);
+            if (valid && horizon > 0) store_obs<E::OD, G>(tr.obs + (size_t)row * E::OD, o, sub);
         }
         __syncthreads();
 
@@ -527,23 +605,27 @@ k_fused(Batch batch, PolicyArgs pol) {
             const uint32_t t = t0 + (uint32_t)step;
             const size_t idx = (size_t)step * env.n_rows + row;
             Act<E> act{0, 0.0f};
-            if (mine) {
-                float h[HO::NH];
-                L::template head_row<HO::NH>(smem, b3, tid, h);
+            if (valid) {
+                float hb[C], hv;
+                L::template head_block<HO::NH, C>(smem, b3b, b3v, rr, j0, hb, hv);
                 if (step == horizon) {
-                    if (valid) tr.last_value[row] = h[HO::NOUT];
-                } else if (valid) {
+                    if (lead) tr.last_value[row] = hv;
+                } else {
                     float logp;
-                    act = choose<E, HO::NH>(h, key, t, (uint32_t)row, log_std, logp);
-                    tr.value[idx] = h[HO::NOUT];
-                    tr.logp[idx] = logp;
-                    store_action<E>(tr, idx, act);
+                    act = choose<E, G, C>(hb, sub, key, t, (uint32_t)row, log_std, logp);
+                    if (lead) {
+                        tr.value[idx] = hv;
+                        tr.logp[idx] = logp;
+                        store_action<E>(tr, idx, act);
+                    }
                     if constexpr (E::KIND == Market::KIND) {
-                        int dh, s18;
-                        Market::decide(act.index, dh, s18);
-                        int* sl = sums + ((step & 1) * R + slot) * 2;
-                        atomicAdd(sl, dh);
-                        atomicAdd(sl + 1, s18);
+                        if (lead) {
+                            int dh, s18;
+                            Market::decide(act.index, dh, s18);
+                            int* sl = sums + ((step & 1) * R + slot) * 2;
+                            atomicAdd(sl, dh);
+                            atomicAdd(sl + 1, s18);
+                        }
                     }
                 }
             }
@@ -554,8 +636,10 @@ k_fused(Batch batch, PolicyArgs pol) {
                         const int* sl = sums + ((step & 1) * R + slot) * 2;
                         float reward;
                         Market::settle(s, act.index, sl[0], sl[1], reward);
-                        tr.reward[idx] = reward;
-                        tr.done[idx] = 0;
+                        if (lead) {
+                            tr.reward[idx] = reward;
+                            tr.done[idx] = 0;
+                        }
                     }
                     // the other parity's sums were last read in the previous step
                     for (int i = tid; i < 2 * R; i += NTHR) sums[((step + 1) & 1) * 2 * R + i] = 0;
@@ -564,25 +648,26 @@ k_fused(Batch batch, PolicyArgs pol) {
                 if (valid && step < horizon) {
                     float reward;
                     bool done;
-                    E::step(s, act.index, act.value, t, (uint32_t)row, key, ctx, reward, done);
+                    E::template step<G>(s, act.index, act.value, t, (uint32_t)row, key, ctx, sub,
+                                        reward, done);
                     if (done) E::reset(s, key, t + 1, (uint32_t)row, ctx);
-                    tr.reward[idx] = reward;
-                    tr.done[idx] = done ? 1 : 0;
+                    if (lead) {
+                        tr.reward[idx] = reward;
+                        tr.done[idx] = done ? 1 : 0;
+                    }
                 }
             }
             if (valid && step < horizon) {
                 float o[E::OD];
                 E::observe(s, o);
-                L::template put_obs<E::OD>(smem, tid, o, inv_q0);
-                if (step + 1 < horizon) {
-                    const size_t nidx = (size_t)(step + 1) * env.n_rows + row;
-#pragma unroll
-                    for (int k = 0; k < E::OD; ++k) tr.obs[nidx * E::OD + k] = o[k];
-                }
+                L::template put_obs<E::OD, G>(smem, rr, o, inv_q0, sub);
+                if (step + 1 < horizon)
+                    store_obs<E::OD, G>(tr.obs + ((size_t)(step + 1) * env.n_rows + row) * E::OD, o,
+                                        sub);
             }
             __syncthreads();
         }
-        if (valid) save_state<E>(env, row, s);
+        if (valid) save_state<E, G>(env, row, s, sub);
     }
 }
 
@@ -613,7 +698,7 @@ k_plain_policy(EnvArgs env, PolicyArgs pol) {
     __shared__ __attribute__((aligned(16))) char smem[L::BYTES];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     L mlp;
-    mlp.load(pol, wave, lane);
+    mlp.load(pol, smem, wave, lane, tid);
     const float inv_q0 = DT == DT_FP8 ? 1.0f / pol.act_scale[0] : 1.0f;
     for (int i = tid; i < R * L::P_IN / 4; i += NW * 64)
         reinterpret_cast<uint32_t*>(smem + L::OFF_IN)[i] = 0u;
@@ -625,7 +710,7 @@ k_plain_policy(EnvArgs env, PolicyArgs pol) {
         float o[E::OD];
 #pragma unroll
         for (int k = 0; k < E::OD; ++k) o[k] = env.obs_scratch[(size_t)row * E::OD + k];
-        L::template put_obs<E::OD>(smem, tid, o, inv_q0);
+        L::template put_obs<E::OD, 1>(smem, tid, o, inv_q0, 0);
     }
     __syncthreads();
     mlp.forward(smem, wave, lane);
@@ -641,41 +726,50 @@ k_plain_policy(EnvArgs env, PolicyArgs pol) {
     }
 }
 
-template <class E>
-__global__ void k_plain_sample(EnvArgs env, PolicyArgs pol, TrajArgs tr, int step) {
+// Plain sampling: G lanes per row, the same group code as the fused kernel.
+template <class E, int G>
+__global__ void __launch_bounds__(256) k_plain_sample(EnvArgs env, PolicyArgs pol, TrajArgs tr,
+                                                      int step) {
     using HO = HeadOf<E>;
-    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    using B = Block<E, G>;
+    constexpr int C = B::C;
+    const int sub = threadIdx.x % G;
+    const int64_t row = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
     if (row >= env.n_rows) return;
-    float h[HO::NH];
+    const int j0 = B::first(sub);
+    float hb[C];
 #pragma unroll
-    for (int j = 0; j < HO::NH; ++j) h[j] = env.head_scratch[row * HO::NH + j];
+    for (int c = 0; c < C; ++c)
+        hb[c] = j0 + c < HO::NOUT ? env.head_scratch[row * HO::NH + j0 + c] : 0.0f;
+    const float hv = env.head_scratch[row * HO::NH + HO::NOUT];
     const RngKey key{env.k0, env.k1, env.epoch};
     const uint32_t t = step_base(env) + (uint32_t)step;
     const float log_std = (E::NACT == 0 && pol.log_std) ? pol.log_std[0] : 0.0f;
     float logp;
-    const Act<E> a = choose<E, HO::NH>(h, key, t, (uint32_t)row, log_std, logp);
-    const size_t idx = (size_t)step * env.n_rows + row;
-    tr.value[idx] = h[HO::NOUT];
-    tr.logp[idx] = logp;
-    store_action<E>(tr, idx, a);
-}
-
-template <class E>
-__device__ __forceinline__ void finish_row(const EnvArgs& env, const TrajArgs& tr, int64_t row,
-                                           const float (&s)[E::SD], int step, int horizon) {
-    save_state<E>(env, row, s);
-    float o[E::OD];
-    E::observe(s, o);
-    const size_t nidx = (size_t)(step + 1) * env.n_rows + row;
-#pragma unroll
-    for (int k = 0; k < E::OD; ++k) {
-        env.obs_scratch[row * E::OD + k] = o[k];
-        if (step + 1 < horizon) tr.obs[nidx * E::OD + k] = o[k];
+    const Act<E> a = choose<E, G, C>(hb, sub, key, t, (uint32_t)row, log_std, logp);
+    if (sub == 0) {
+        const size_t idx = (size_t)step * env.n_rows + row;
+        tr.value[idx] = hv;
+        tr.logp[idx] = logp;
+        store_action<E>(tr, idx, a);
     }
 }
 
-template <class E>
-__global__ void k_plain_step(EnvArgs env, TrajArgs tr, int step, int horizon) {
+template <class E, int G>
+__device__ __forceinline__ void finish_row(const EnvArgs& env, const TrajArgs& tr, int64_t row,
+                                           const float (&s)[E::SD], int step, int horizon, int sub) {
+    save_state<E, G>(env, row, s, sub);
+    float o[E::OD];
+    E::observe(s, o);
+    store_obs<E::OD, G>(env.obs_scratch + row * E::OD, o, sub);
+    if (step + 1 < horizon)
+        store_obs<E::OD, G>(tr.obs + ((size_t)(step + 1) * env.n_rows + row) * E::OD, o, sub);
+}
+
+// Plain step: G lanes per row, the same group code as the fused kernel.
+template <class E, int G>
+__global__ void __launch_bounds__(256) k_plain_step(EnvArgs env, TrajArgs tr, int step,
+                                                    int horizon) {
     __shared__ float params[E::KIND == Reaction::KIND ? Reaction::PARAM_FLOATS : 1];
     EnvCtx ctx{nullptr};
     if constexpr (E::KIND == Reaction::KIND) {
@@ -684,7 +778,8 @@ __global__ void k_plain_step(EnvArgs env, TrajArgs tr, int step, int horizon) {
         ctx.lds_params = params;
     }
     __syncthreads();
-    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int sub = threadIdx.x % G;
+    const int64_t row = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
     if (row >= env.n_rows) return;
     const RngKey key{env.k0, env.k1, env.epoch};
     const uint32_t t = step_base(env) + (uint32_t)step;
@@ -694,11 +789,13 @@ __global__ void k_plain_step(EnvArgs env, TrajArgs tr, int step, int horizon) {
     const Act<E> a = load_action<E>(tr, idx);
     float reward;
     bool done;
-    E::step(s, a.index, a.value, t, (uint32_t)row, key, ctx, reward, done);
+    E::template step<G>(s, a.index, a.value, t, (uint32_t)row, key, ctx, sub, reward, done);
     if (done) E::reset(s, key, t + 1, (uint32_t)row, ctx);
-    tr.reward[idx] = reward;
-    tr.done[idx] = done ? 1 : 0;
-    finish_row<E>(env, tr, row, s, step, horizon);
+    if (sub == 0) {
+        tr.reward[idx] = reward;
+        tr.done[idx] = done ? 1 : 0;
+    }
+    finish_row<E, G>(env, tr, row, s, step, horizon, sub);
 }
 
 // Market step: one workgroup per tile of whole envs, exact integer sums.
@@ -733,7 +830,7 @@ __global__ void __launch_bounds__(256) k_plain_step_market(EnvArgs env, TrajArgs
         const size_t idx = (size_t)step * env.n_rows + row;
         tr.reward[idx] = reward;
         tr.done[idx] = 0;
-        finish_row<Market>(env, tr, row, s, step, horizon);
+        finish_row<Market, 1>(env, tr, row, s, step, horizon, 0);
     }
 }
 
@@ -762,7 +859,7 @@ __global__ void k_reset(EnvArgs env) {
     const RngKey key{env.k0, env.k1, env.epoch};
     float s[E::SD];
     E::reset(s, key, 0u, (uint32_t)row, ctx);
-    save_state<E>(env, row, s);
+    save_state<E, 1>(env, row, s, 0);
 }
 
 // -------------------------------------------------------- small kernels --
@@ -818,12 +915,26 @@ struct VariantEntry {
     Variant v;
     const void* fused;
     const void* policy;
+    const void* sample;   // plain-form sampling and step kernels with the same
+    const void* step;     // lanes per row as the fused kernel
+    int lanes;
 };
 
+template <class E, int G>
+const void* step_entry() {
+    if constexpr (E::KIND == Market::KIND)
+        return reinterpret_cast<const void*>(&k_plain_step_market);
+    else
+        return reinterpret_cast<const void*>(&k_plain_step<E, G>);
+}
+
+#define WSX_G(E, NW, NT) lanes_per_row(16 * (NT), 64 * (NW), E::LANES)
 #define WSX_ENTRY(E, DT, H, NW, NT, HS, OCC)                                          \
     {{E::KIND, DT, H, NW, 16 * NT, OCC},                                              \
      reinterpret_cast<const void*>(&k_fused<E, DT, H, NW, NT, HS, OCC>),              \
-     reinterpret_cast<const void*>(&k_plain_policy<E, DT, H, NW, NT, HS, OCC>)},
+     reinterpret_cast<const void*>(&k_plain_policy<E, DT, H, NW, NT, HS, OCC>),       \
+     reinterpret_cast<const void*>(&k_plain_sample<E, WSX_G(E, NW, NT)>),             \
+     step_entry<E, WSX_G(E, NW, NT)>(), WSX_G(E, NW, NT)},
 
 static const VariantEntry kVariants[] = {WSX_VARIANTS(WSX_ENTRY)};
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
@@ -863,6 +974,8 @@ static hipError_t plain_sequence(const VariantEntry* e, const EnvArgs& env, cons
                                  const TrajArgs& tr, int horizon, hipStream_t s) {
     const int threads = 256;
     const int blocks = (int)((env.n_rows + threads - 1) / threads);
+    const int rows_per_block = threads / e->lanes;
+    const int gblocks = (int)((env.n_rows + rows_per_block - 1) / rows_per_block);
     hipLaunchKernelGGL(k_plain_observe<E>, dim3(blocks), dim3(threads), 0, s, env, tr, horizon);
     void* pargs[] = {(void*)&env, (void*)&pol};
     for (int step = 0; step <= horizon; ++step) {
@@ -870,14 +983,15 @@ static hipError_t plain_sequence(const VariantEntry* e, const EnvArgs& env, cons
                                          pargs, 0, s);
         if (err != hipSuccess) return err;
         if (step == horizon) break;
-        hipLaunchKernelGGL(k_plain_sample<E>, dim3(blocks), dim3(threads), 0, s, env, pol, tr,
-                           step);
+        void* sargs[] = {(void*)&env, (void*)&pol, (void*)&tr, (void*)&step};
+        err = hipLaunchKernel(e->sample, dim3(gblocks), dim3(threads), sargs, 0, s);
+        if (err != hipSuccess) return err;
+        void* targs[] = {(void*)&env, (void*)&tr, (void*)&step, (void*)&horizon};
         if constexpr (E::KIND == Market::KIND)
-            hipLaunchKernelGGL(k_plain_step_market, dim3(env.n_tiles), dim3(256), 0, s, env, tr,
-                               step, horizon);
+            err = hipLaunchKernel(e->step, dim3(env.n_tiles), dim3(256), targs, 0, s);
         else
-            hipLaunchKernelGGL(k_plain_step<E>, dim3(blocks), dim3(threads), 0, s, env, tr, step,
-                               horizon);
+            err = hipLaunchKernel(e->step, dim3(gblocks), dim3(threads), targs, 0, s);
+        if (err != hipSuccess) return err;
     }
     hipLaunchKernelGGL(k_plain_last<E>, dim3(blocks), dim3(threads), 0, s, env, tr);
     return hipGetLastError();
