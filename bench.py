@@ -237,7 +237,9 @@ def main():
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--cpu-sample-envs", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="fused,plain,graph")
+    ap.add_argument("--forms", default="fused,plain,graph,fused_graph")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="run the built-in default kernel shapes instead of the autotuner's")
     ap.add_argument("--serve-requests", type=int, default=400,
                     help="measured requests of the serving load (0: skip serving)")
     ap.add_argument("--serve-warmup", type=int, default=50)
@@ -270,6 +272,21 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    tuned = {}
+    if args.autotune and not args.tile_rows:
+        # the library's autotuner picks each set's kernel shape (untimed here)
+        for key in WORKLOADS[args.workload]:
+            cfg = inputs.CONFIGS[key]
+            kind = cfg["kind"]
+            pol = wsx.DevicePolicy(inputs.policy_for(kind, cfg["dtype"], cfg["hidden"], seed=0))
+            t0 = time.perf_counter()
+            tuned[key] = wsx.autotune(
+                kind, cfg["n_envs"], pol, cfg["horizon"], reps=2, seed=0,
+                agent_offsets=inputs.agent_offsets(cfg["n_envs"], seed=0)
+                if kind == wsx.MARKET else None,
+                params=inputs.reaction_params(0) if kind == wsx.REACTION else None)
+            print(f"[bench] autotune {key}: {tuned[key]} in {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
     sets = [EnvSet(k, 0, args.tile_rows, wsx, inputs, torch) for k in WORKLOADS[args.workload]]
     env_steps = sum(s.n_envs * s.T for s in sets)
     forms = args.forms.split(",")
@@ -278,12 +295,13 @@ def main():
     el, lat, kern = run_form(sets, wsx.MODE_FUSED, args.steps, args.warmup, wsx, torch, 0)
     result["fused"] = (el, lat, kern)
     print(f"[bench] fused: {args.steps} steps in {el:.3f} s", file=sys.stderr, flush=True)
-    for name, mode in (("plain", wsx.MODE_PLAIN), ("graph", wsx.MODE_GRAPH)):
-        if name in forms and args.plain_steps > 0:
-            r = run_form(sets, mode, args.plain_steps, 1, wsx, torch, 1000)
-            result[name] = r
-            print(f"[bench] {name}: {args.plain_steps} steps in {r[0]:.3f} s", file=sys.stderr,
-                  flush=True)
+    for name, mode in (("plain", wsx.MODE_PLAIN), ("graph", wsx.MODE_GRAPH),
+                       ("fused_graph", wsx.MODE_FUSED_GRAPH)):
+        n = args.steps if name == "fused_graph" else args.plain_steps
+        if name in forms and n > 0:
+            r = run_form(sets, mode, n, 1, wsx, torch, 1000)
+            result[name] = r + (n,)
+            print(f"[bench] {name}: {n} steps in {r[0]:.3f} s", file=sys.stderr, flush=True)
 
     el, lat, kern = result["fused"]
     value = env_steps * args.steps / el
@@ -309,15 +327,19 @@ def main():
                    "horizon": max(s.T for s in sets), "sets": [s.key for s in sets],
                    "policy": {s.key: f"{s.policy.dtype} {s.policy.d_in}-{s.policy.h1}-"
                                      f"{s.policy.h2}-{s.policy.n_head}" for s in sets},
-                   "returns": "FP64 scan, FP32 outputs", "streams": len(sets)},
+                   "returns": "FP64 scan, FP32 outputs", "streams": len(sets),
+                   "kernel_shape": {s.key: dict(zip(("tile_rows", "waves", "occupancy",
+                                                     "chunk_steps"), wsx.env_shape(s.env)))
+                                    for s in sets},
+                   "autotuned": bool(tuned)},
         "latency_ms": {"p50": round(percentile(lat, 50), 4), "p99": round(percentile(lat, 99), 4)},
         "roofline": roofline,
     }
-    for name in ("plain", "graph"):
+    for name in ("plain", "graph", "fused_graph"):
         if name in result:
-            pel, plat, _ = result[name]
-            pv = env_steps * args.plain_steps / pel
-            out[name] = {"value": round(pv, 1), "ms_per_step": round(pel / args.plain_steps * 1e3, 3),
+            pel, plat, _, n = result[name]
+            pv = env_steps * n / pel
+            out[name] = {"value": round(pv, 1), "steps": n, "ms_per_step": round(pel / n * 1e3, 3),
                          "latency_ms": {"p50": round(percentile(plat, 50), 3),
                                         "p99": round(percentile(plat, 99), 3)}}
             out[f"fused_speedup_vs_{name}"] = round(value / pv, 2)

@@ -60,6 +60,9 @@ extern "C" {
 #define WSX_MODE_PLAIN 1   /* per step: policy, sample and step kernels           */
 #define WSX_MODE_GRAPH 2   /* the PLAIN launches captured once in a hipGraph and   */
                            /* replayed                                            */
+#define WSX_MODE_FUSED_GRAPH 3 /* the horizon as persistent fused kernels of      */
+                           /* chunk_steps steps each (wsx_env_set_chunk), captured */
+                           /* once in a hipGraph and replayed                     */
 
 typedef struct wsx_env wsx_env;   /* opaque host handle */
 
@@ -107,11 +110,13 @@ int wsx_env_state_bytes(int32_t kind, int64_t n_envs, int64_t n_rows, size_t* by
 
 typedef struct {
     int32_t kind;            /* WSX_CARTPOLE ... WSX_REACTION                     */
-    int32_t tile_rows;       /* rows per workgroup tile, 0 = the default          */
+    int32_t tile_rows;       /* rows per workgroup tile (market: agents), 0 = the */
+                             /* default; runs on the compiled kernel with the     */
+                             /* fewest row slots >= tile_rows                     */
     int32_t waves;           /* wavefronts per workgroup, 0 = any / the default   */
     int32_t occupancy;       /* min wavefronts per SIMD of the fused kernel, 0 =  */
                              /* any / the default; (tile_rows, waves, occupancy)  */
-                             /* must name a compiled variant (else EUNSUPPORTED)  */
+                             /* must match a compiled kernel (else EUNSUPPORTED)  */
     int64_t n_envs;
     uint64_t seed;           /* Philox key                                        */
     void* state;             /* device, wsx_env_state_bytes bytes, caller-owned,  */
@@ -150,6 +155,11 @@ int wsx_env_info(const wsx_env* env, int64_t* n_rows, uint32_t* step, uint32_t* 
 /* Sets the step counter (resuming from a saved state block). */
 int wsx_env_set_step(wsx_env* env, uint32_t step);
 
+/* Steps per fused launch in WSX_MODE_FUSED_GRAPH (0 = the whole horizon in
+ * one launch, the default); chunk_steps < 0 is WSX_EINVAL. Results do not
+ * depend on it. */
+int wsx_env_set_chunk(wsx_env* env, int32_t chunk_steps);
+
 /* Releases the host handle (and cached graphs); the state block is the
  * caller's. */
 int wsx_env_destroy(wsx_env* env);
@@ -175,6 +185,58 @@ int wsx_policy_forward(const wsx_policy* policy, const float* obs, int64_t rows,
  * RNE, saturating) with the device conversion the kernels use and returns
  * the real values as float. */
 int wsx_quantize(int32_t dtype, float scale, const float* x, float* y, int64_t n, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Autotuner for the persistent fused roll-out (App. B: every environment    */
+/* instance owns a GPU block, its agents the block's threads; here a tile of */
+/* rows per workgroup, whose best height depends on the set). Times the      */
+/* fused roll-out of one environment set on every compiled kernel shape      */
+/* (rows per workgroup tile -- including tile heights that spread the rows   */
+/* evenly over the compute units --, waves per workgroup, occupancy, hence   */
+/* the weight registers per wave) and then the chunk length of the graph     */
+/* mode, and records the fastest in the library's tuning table under (kind,  */
+/* n_envs, n_rows, compute units). wsx_env_create with tile_rows, waves and  */
+/* occupancy all 0 takes its shape and chunk from a matching table entry     */
+/* (else the built-in default). The table is process-wide and thread-safe;   */
+/* it persists only through wsx_tune_save / wsx_tune_load.                   */
+
+typedef struct {
+    int32_t tile_rows, waves, occupancy; /* the kernel shape                  */
+    int32_t chunk_steps;     /* steps per launch in WSX_MODE_FUSED_GRAPH       */
+    double us_per_step;      /* measured time of one step of the whole set     */
+} wsx_tune_entry;
+
+/* Bytes of device workspace wsx_autotune needs for this environment set (the
+ * state block and a trajectory of `horizon` steps). desc->state is ignored. */
+int wsx_autotune_workspace_bytes(const wsx_env_desc* desc, int32_t horizon, size_t* bytes);
+
+/* Runs the search on `stream` and waits for it (it is a host-synchronous
+ * call). desc->state is ignored; the workspace (device, caller-owned) holds
+ * the trial state and trajectory. Each candidate runs one untimed roll-out of
+ * `horizon` steps and `reps` (>= 1) timed ones; the median counts. `best`
+ * (optional) receives the winner. Errors: WSX_EINVAL (arguments, workspace
+ * too small, horizon < 1), WSX_EUNSUPPORTED (no kernel for the policy),
+ * WSX_EHIP. */
+int wsx_autotune(const wsx_env_desc* desc, const wsx_policy* policy, int32_t horizon,
+                 int32_t reps, void* workspace, size_t workspace_bytes, wsx_tune_entry* best,
+                 void* stream);
+
+/* The table entry for (kind, n_envs, n_rows, compute units): WSX_OK and *out
+ * filled, or WSX_EINVAL if there is none. */
+int wsx_tune_lookup(int32_t kind, int64_t n_envs, int64_t n_rows, int32_t cus,
+                    wsx_tune_entry* out);
+
+/* Writes the table as text (one entry per line: kind n_envs n_rows cus
+ * tile_rows waves occupancy chunk_steps us_per_step) / merges such a file into
+ * the table (later entries replace earlier ones with the same key). A line
+ * that does not parse, or names no compiled kernel shape, is WSX_EINVAL and
+ * nothing from the file is kept. */
+int wsx_tune_save(const char* path);
+int wsx_tune_load(const char* path);
+
+/* The kernel shape and chunk length an environment set runs with. */
+int wsx_env_shape(const wsx_env* env, int32_t* tile_rows, int32_t* waves, int32_t* occupancy,
+                  int32_t* chunk_steps);
 
 /* ------------------------------------------------------------------------ */
 /* Roll-out server: continuous batching of roll-out requests.                */

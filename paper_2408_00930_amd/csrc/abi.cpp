@@ -73,18 +73,23 @@ Layout layout_of(const KindInfo& k, int64_t n_envs, int64_t n_rows, bool market)
     return L;
 }
 
-// waves / occupancy 0 match any compiled value
+// The compiled kernel with the fewest row slots that holds tiles of
+// `tile_rows` rows; waves / occupancy 0 match any compiled value (the first
+// listed wins among kernels of the same row capacity).
 bool find_variant(int kind, int dtype, int hidden, int waves, int tile_rows, int occupancy,
                   Variant& out) {
+    bool found = false;
     for (int i = 0; i < n_variants(); ++i) {
         const Variant& v = variant(i);
-        if (v.kind == kind && v.dtype == dtype && v.hidden == hidden && v.tile_rows == tile_rows &&
-            (waves == 0 || v.waves == waves) && (occupancy == 0 || v.occupancy == occupancy)) {
+        if (v.kind == kind && v.dtype == dtype && v.hidden == hidden && tile_rows >= 1 &&
+            v.tile_rows >= tile_rows && (waves == 0 || v.waves == waves) &&
+            (occupancy == 0 || v.occupancy == occupancy) &&
+            (!found || v.tile_rows < out.tile_rows)) {
             out = v;
-            return true;
+            found = true;
         }
     }
-    return false;
+    return found;
 }
 
 }  // namespace wsx
@@ -103,11 +108,23 @@ EnvArgs wsx::env_args(const wsx_env* env) {
     a.n_rows = env->n_rows;
     a.n_envs = (int32_t)env->n_envs;
     a.n_tiles = env->n_tiles;
+    a.tile_rows = env->tile_rows;
     a.k0 = (uint32_t)(env->seed & 0xFFFFFFFFu);
     a.k1 = (uint32_t)(env->seed >> 32);
     a.epoch = env->epoch;
     a.t0 = env->step;
     return a;
+}
+
+TrajArgs wsx::traj_at(const TrajArgs& t, const KindInfo& k, size_t slots) {
+    TrajArgs o = t;
+    o.obs = t.obs + slots * (size_t)k.od;
+    o.action = static_cast<char*>(t.action) + slots * (k.nact ? 1 : 4);
+    o.reward = t.reward + slots;
+    o.done = t.done + slots;
+    o.value = t.value + slots;
+    o.logp = t.logp + slots;
+    return o;
 }
 
 int wsx::check_policy(const wsx_policy* p, const KindInfo& k, int kind) {
@@ -182,11 +199,22 @@ int wsx_env_create(const wsx_env_desc* d, wsx_env** out) {
         return fail(WSX_EINVAL, "agent_offsets is required for the market and only for it");
     if ((d->kind == WSX_REACTION) != (d->params != nullptr))
         return fail(WSX_EINVAL, "params is required for the reaction walk and only for it");
-    if (d->occupancy < 0) return fail(WSX_EINVAL, "occupancy must be >= 0");
+    if (d->occupancy < 0 || d->tile_rows < 0 || d->waves < 0)
+        return fail(WSX_EINVAL, "tile_rows, waves and occupancy must be >= 0");
     const bool deflt = !d->tile_rows && !d->waves && !d->occupancy;
-    const int tile_rows = d->tile_rows ? d->tile_rows : k.tile_rows;
-    const int waves = d->waves ? d->waves : (deflt ? k.waves : 0);
-    const int occupancy = d->occupancy ? d->occupancy : (deflt ? k.occupancy : 0);
+    if (market && d->agent_offsets[0] != 0) return fail(WSX_EINVAL, "agent_offsets[0] must be 0");
+    // the autotuner's shape for this set on this device, if it has tuned it
+    int device = 0, cus = 0;
+    wsx_tune_entry tuned{};
+    const bool use_tuned =
+        deflt && hipGetDevice(&device) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+        tune_lookup(d->kind, d->n_envs, market ? d->agent_offsets[d->n_envs] : d->n_envs, cus,
+                    tuned);
+    const int tile_rows = use_tuned ? tuned.tile_rows : d->tile_rows ? d->tile_rows : k.tile_rows;
+    const int waves = use_tuned ? tuned.waves : d->waves ? d->waves : (deflt ? k.waves : 0);
+    const int occupancy =
+        use_tuned ? tuned.occupancy : d->occupancy ? d->occupancy : (deflt ? k.occupancy : 0);
     Variant probe;
     if (!find_variant(d->kind, k.dtype, k.hidden, waves, tile_rows, occupancy, probe))
         return fail(WSX_EUNSUPPORTED,
@@ -197,7 +225,6 @@ int wsx_env_create(const wsx_env_desc* d, wsx_env** out) {
     std::vector<Tile> tiles;
     if (market) {
         const int32_t* off = d->agent_offsets;
-        if (off[0] != 0) return fail(WSX_EINVAL, "agent_offsets[0] must be 0");
         for (int64_t e = 0; e < d->n_envs; ++e) {
             const int64_t c = (int64_t)off[e + 1] - off[e];
             if (c < 1 || c > tile_rows)
@@ -233,6 +260,7 @@ int wsx_env_create(const wsx_env_desc* d, wsx_env** out) {
     env->waves = probe.waves;
     env->occupancy = probe.occupancy;
     env->n_tiles = market ? (int)tiles.size() : (int)((n_rows + tile_rows - 1) / tile_rows);
+    env->chunk = use_tuned ? tuned.chunk_steps : 0;
     env->graph = nullptr;
     env->capture_stream = nullptr;
     hipError_t e = hipGetDevice(&env->device);
@@ -272,6 +300,23 @@ int wsx_env_info(const wsx_env* env, int64_t* n_rows, uint32_t* step, uint32_t* 
 int wsx_env_set_step(wsx_env* env, uint32_t step) {
     if (!env) return fail(WSX_EINVAL, "env is NULL");
     env->step = step;
+    return WSX_OK;
+}
+
+int wsx_env_shape(const wsx_env* env, int32_t* tile_rows, int32_t* waves, int32_t* occupancy,
+                  int32_t* chunk_steps) {
+    if (!env) return fail(WSX_EINVAL, "env is NULL");
+    if (tile_rows) *tile_rows = env->tile_rows;
+    if (waves) *waves = env->waves;
+    if (occupancy) *occupancy = env->occupancy;
+    if (chunk_steps) *chunk_steps = env->chunk;
+    return WSX_OK;
+}
+
+int wsx_env_set_chunk(wsx_env* env, int32_t chunk_steps) {
+    if (!env) return fail(WSX_EINVAL, "env is NULL");
+    if (chunk_steps < 0) return fail(WSX_EINVAL, "chunk_steps must be >= 0");
+    env->chunk = chunk_steps;
     return WSX_OK;
 }
 
@@ -316,30 +361,39 @@ int wsx_rollout(wsx_env* env, const wsx_policy* policy, int32_t horizon, const w
     ta.logp = traj->logp;
     ta.last_value = traj->last_value;
     hipError_t e = hipSuccess;
-    if (mode == WSX_MODE_FUSED) {
-        const int per_cu = fused_blocks_per_cu(v);
-        const int grid = std::max(1, std::min(env->n_tiles, env->cus * per_cu));
+    const int grid = std::max(1, std::min(env->n_tiles, env->cus * fused_blocks_per_cu(v)));
+    // fused launch of `steps` steps from trajectory slot `first`
+    auto fused = [&](const EnvArgs& a, int first, int steps, bool last, hipStream_t st) {
         Batch b{};
         b.table = nullptr;
-        b.one.env = ea;
-        b.one.tr = ta;
-        b.one.steps = horizon;
+        b.one.env = a;
+        b.one.env.t0 += (uint32_t)first;
+        b.one.tr = traj_at(ta, env->info, (size_t)first * (size_t)env->n_rows);
+        b.one.tr.last_value = ta.last_value;
+        b.one.steps = steps;
         b.one.tile_begin = 0;
+        b.one.last = last ? 1 : 0;
         b.n_segs = 1;
         b.n_tiles = env->n_tiles;
-        e = launch_fused(v, b, pa, grid, s);
+        return launch_fused(v, b, pa, grid, st);
+    };
+    if (mode == WSX_MODE_FUSED) {
+        e = fused(ea, 0, horizon, true, s);
     } else if (mode == WSX_MODE_PLAIN) {
         e = launch_plain(v, ea, pa, ta, horizon, false, s);
-    } else if (mode == WSX_MODE_GRAPH) {
+    } else if (mode == WSX_MODE_GRAPH || mode == WSX_MODE_FUSED_GRAPH) {
         // the launches read the step counter from the state block, so one
         // captured graph serves every call with the same buffers and horizon
         EnvArgs ga = ea;
         ga.step_ptr = reinterpret_cast<const uint32_t*>(env->block + env->lay.step);
-        std::vector<char> key(sizeof(PolicyArgs) + sizeof(TrajArgs) + sizeof(int) + sizeof(Variant));
+        ga.t0 = 0;
+        const int chunk = mode == WSX_MODE_GRAPH ? 0 : env->chunk;
+        const int desc[3] = {horizon, mode, chunk};
+        std::vector<char> key(sizeof(PolicyArgs) + sizeof(TrajArgs) + sizeof desc + sizeof(Variant));
         std::memcpy(key.data(), &pa, sizeof pa);
         std::memcpy(key.data() + sizeof pa, &ta, sizeof ta);
-        std::memcpy(key.data() + sizeof pa + sizeof ta, &horizon, sizeof horizon);
-        std::memcpy(key.data() + sizeof pa + sizeof ta + sizeof horizon, &v, sizeof v);
+        std::memcpy(key.data() + sizeof pa + sizeof ta, desc, sizeof desc);
+        std::memcpy(key.data() + sizeof pa + sizeof ta + sizeof desc, &v, sizeof v);
         if (!env->graph || env->graph_key != key) {
             if (env->graph) {
                 (void)hipGraphExecDestroy(env->graph);
@@ -351,7 +405,18 @@ int wsx_rollout(wsx_env* env, const wsx_policy* policy, int32_t horizon, const w
             }
             e = hipStreamBeginCapture(env->capture_stream, hipStreamCaptureModeRelaxed);
             if (e != hipSuccess) return hip_fail(e, "wsx_rollout (begin capture)");
-            hipError_t le = launch_plain(v, ga, pa, ta, horizon, true, env->capture_stream);
+            hipError_t le = hipSuccess;
+            if (mode == WSX_MODE_GRAPH) {
+                le = launch_plain(v, ga, pa, ta, horizon, true, env->capture_stream);
+            } else {
+                const int c = chunk > 0 ? chunk : std::max(horizon, 1);
+                int first = 0;
+                do {
+                    const int steps = std::min(c, horizon - first);
+                    le = fused(ga, first, steps, first + steps == horizon, env->capture_stream);
+                    first += steps;
+                } while (le == hipSuccess && first < horizon);
+            }
             hipGraph_t g = nullptr;
             e = hipStreamEndCapture(env->capture_stream, &g);
             if (le != hipSuccess) e = le;

@@ -39,7 +39,7 @@ struct CartPole {
         const float force = action == 1 ? 10.0f : -10.0f;
         const float x = s[0], xd = s[1], th = s[2], thd = s[3];
         float sn, cs;
-        sincosf(th, &sn, &cs);
+        sin_cos(th, sn, cs);
         const float push = (force + m_pole * half_len * thd * thd * sn) / m_total;
         const float thdd =
             (gravity * sn - cs * push) / (half_len * (4.0f / 3.0f - m_pole * cs * cs / m_total));
@@ -72,7 +72,7 @@ struct Pendulum {
         s[1] = -1.0f + 2.0f * unit_uniform(w.w[1]);
     }
     __device__ static void observe(const float* s, float* o) {
-        sincosf(s[0], &o[1], &o[0]);
+        sin_cos(s[0], o[1], o[0]);
         o[2] = s[1];
     }
     template <int G>
@@ -83,7 +83,9 @@ struct Pendulum {
         const float a = wrap_pi(th);
         reward = -(a * a + 0.1f * thd * thd + 0.001f * u * u);
         // theta'' = 3 g / (2 l) sin(theta) + 3 u / (m l^2)
-        const float acc = 15.0f * sinf(th) + 3.0f * u;
+        float sn, cs;
+        sin_cos(th, sn, cs);
+        const float acc = 15.0f * sn + 3.0f * u;
         const float w = fminf(fmaxf(thd + acc * 0.05f, -8.0f), 8.0f);
         s[0] = th + w * 0.05f;
         s[1] = w;
@@ -104,32 +106,34 @@ struct Acrobot {
         for (int i = 0; i < 4; ++i) s[i] = -0.1f + 0.2f * unit_uniform(w.w[i]);
     }
     __device__ static void observe(const float* s, float* o) {
-        sincosf(s[0], &o[1], &o[0]);
-        sincosf(s[1], &o[3], &o[2]);
+        sin_cos(s[0], o[1], o[0]);
+        sin_cos(s[1], o[3], o[2]);
         o[4] = s[2];
         o[5] = s[3];
     }
     // Manipulator equations M(q) q'' + C(q, q') + G(q) = (0, tau) solved for
-    // q'' with the 2x2 inertia matrix of the two links.
+    // q'' with the 2x2 inertia matrix of the two links (Cramer's rule);
+    // sin(q1 + q2) by the angle-addition formula.
     __device__ static void deriv(const float* q, float tau, float* dq) {
         const float g = 9.8f;
-        float s2, c2;
-        sincosf(q[1], &s2, &c2);
+        float s1, c1, s2, c2;
+        sin_cos(q[0], s1, c1);
+        sin_cos(q[1], s2, c2);
         const float m11 = 0.25f + (1.0f + 0.25f + c2) + 2.0f;  // lc1^2 + (l1^2+lc2^2+2 l1 lc2 c2) + I1 + I2
         const float m12 = (0.25f + 0.5f * c2) + 1.0f;
         const float m22 = 0.25f + 1.0f;
         const float w1 = q[2], w2 = q[3];
         const float cor1 = -0.5f * s2 * (w2 * w2 + 2.0f * w1 * w2);
         const float cor2 = 0.5f * s2 * w1 * w1;
-        const float grav2 = 0.5f * g * sinf(q[0] + q[1]);
-        const float grav1 = 1.5f * g * sinf(q[0]) + grav2;
+        const float grav2 = 0.5f * g * __builtin_fmaf(s1, c2, c1 * s2);
+        const float grav1 = 1.5f * g * s1 + grav2;
         const float rhs1 = -(cor1 + grav1);
         const float rhs2 = tau - cor2 - grav2;
-        const float det = m11 * m22 - m12 * m12;
+        const float inv_det = 1.0f / (m11 * m22 - m12 * m12);
         dq[0] = w1;
         dq[1] = w2;
-        dq[2] = (m22 * rhs1 - m12 * rhs2) / det;
-        dq[3] = (m11 * rhs2 - m12 * rhs1) / det;
+        dq[2] = (m22 * rhs1 - m12 * rhs2) * inv_det;
+        dq[3] = (m11 * rhs2 - m12 * rhs1) * inv_det;
     }
     template <int G>
     __device__ static void step(float* s, int, float torque, uint32_t, uint32_t, const RngKey&,
@@ -153,7 +157,10 @@ struct Acrobot {
         s[1] = wrap_pi(y[1]);
         s[2] = fminf(fmaxf(y[2], -12.566370614359172f), 12.566370614359172f);
         s[3] = fminf(fmaxf(y[3], -28.274333882308138f), 28.274333882308138f);
-        const float tip = -cosf(s[0]) - cosf(s[0] + s[1]);
+        float s1, c1, s2, c2;
+        sin_cos(s[0], s1, c1);
+        sin_cos(s[1], s2, c2);
+        const float tip = -c1 - __builtin_fmaf(c1, c2, -s1 * s2);   // -cos q1 - cos(q1 + q2)
         done = tip > 1.0f;
         reward = done ? 0.0f : -1.0f;
     }
@@ -279,9 +286,13 @@ struct Reaction {
                                 const EnvCtx& c, int sub, float& reward, bool& done) {
         const int coord = a >> 1;
         const float delta = (a & 1) ? -0.05f : 0.05f;
+        // a select per coordinate keeps the state in registers (a branch on
+        // the coordinate would index the array dynamically)
 #pragma unroll
-        for (int i = 0; i < 20; ++i)
-            if (i == coord) s[i] += delta;
+        for (int i = 0; i < 20; ++i) {
+            const float moved = s[i] + delta;
+            s[i] = i == coord ? moved : s[i];
+        }
         const float e_new = noisy_energy<G>(s, key, t + 1, row, c, sub);
         reward = -(e_new - s[20]);
         s[20] = e_new;

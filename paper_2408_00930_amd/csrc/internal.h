@@ -32,9 +32,13 @@ struct Layout {
 };
 Layout layout_of(const KindInfo& k, int64_t n_envs, int64_t n_rows, bool market);
 
-// waves / occupancy 0 match any compiled value
+// The compiled kernel with the fewest row slots >= tile_rows; waves /
+// occupancy 0 match any compiled value.
 bool find_variant(int kind, int dtype, int hidden, int waves, int tile_rows, int occupancy,
                   Variant& out);
+
+// The autotuner's entry for an environment set, if there is one.
+bool tune_lookup(int32_t kind, int64_t n_envs, int64_t n_rows, int32_t cus, wsx_tune_entry& out);
 
 }  // namespace wsx
 
@@ -53,7 +57,8 @@ struct wsx_env {
     int occupancy;
     int device;
     int cus;
-    // graph cache (PLAIN launches of one horizon)
+    int chunk;   // steps per fused launch in WSX_MODE_FUSED_GRAPH (0 = horizon)
+    // graph cache (the launches of one horizon, one mode)
     hipGraphExec_t graph;
     hipStream_t capture_stream;
     std::vector<char> graph_key;
@@ -61,6 +66,8 @@ struct wsx_env {
 
 namespace wsx {
 EnvArgs env_args(const wsx_env* env);
+// trajectory pointers advanced by `slots` row-steps
+TrajArgs traj_at(const TrajArgs& t, const KindInfo& k, size_t slots);
 PolicyArgs policy_args(const wsx_policy* p);
 int check_policy(const wsx_policy* p, const KindInfo& k, int kind);
 }  // namespace wsx

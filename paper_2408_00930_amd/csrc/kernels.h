@@ -49,8 +49,10 @@ struct EnvArgs {
     int64_t n_rows;
     int32_t n_envs;
     int32_t n_tiles;
+    int32_t tile_rows;        // rows per tile (single-agent kinds), <= the kernel's
     uint32_t k0, k1, epoch;
-    uint32_t t0;              // step counter at the start of the launch
+    uint32_t t0;              // step counter at the start of the launch; with
+                              // step_ptr, its offset from the device counter
 };
 
 // One roll-out request inside a fused launch: its environment set, its
@@ -60,6 +62,7 @@ struct Segment {
     TrajArgs tr;
     int32_t steps;
     int32_t tile_begin;   // first tile of this segment in the launch
+    int32_t last;         // 1: also evaluate V(s_T) into tr.last_value after the steps
 };
 
 // The tiles of a fused launch: one inline segment, or a device table of them

@@ -115,21 +115,12 @@ __device__ __forceinline__ void wave_lds_sync() {
     __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 }
 
-// Row tiles per accumulator block: up to 5 tiles in one block, larger counts
-// in blocks of the largest divisor <= 4 (bounds the accumulator registers).
-constexpr int row_tile_block(int nt) {
-    if (nt <= 5) return nt;
-    for (int b = 4; b > 1; --b)
-        if (nt % b == 0) return b;
-    return 1;
-}
-
 // HS selects how the head is spread over the waves. HS = 0 (split-K): wave w
 // multiplies its own h2 features by its K-slice of the head for every head
 // row, leaving NW partial sums per row (no extra barrier). HS = 1 (split-M):
 // after a barrier, wave w computes head row tiles w, w + NW, ... over the whole
 // K (one result per row; for wide heads whose partials would not fit in LDS).
-template <int DT, int H, int NW, int NT, int KIN, int NHP, int HS>
+template <int DT, int H, int NW, int NT, int KIN, int NHP, int HS, bool PIPE>
 struct Mlp {
     using M = Mma<DT>;
     using Frag = typename M::frag;
@@ -154,11 +145,12 @@ struct Mlp {
     // (2 log2 e * output scale) of both hidden layers: [4][H] floats
     static constexpr int OFF_TAB = HS ? OFF_H2 + R * P_H : OFF_PART + NPART * R * P_PART * 4;
     static constexpr int BYTES = OFF_TAB + 4 * H * 4;
-    static constexpr int NTB = row_tile_block(NT);   // row tiles per accumulator block
-    static_assert(NT % NTB == 0, "row-tile blocking");
     static_assert(!HS || P_PART * 4 <= P_H, "head results fit in the h1 tile");
     static_assert(FPW % 16 == 0 && FPW % K == 0 && KIN % K == 0 && H % K == 0, "tile shape");
     static_assert(BYTES <= 160 * 1024, "LDS budget");
+
+    // software pipelining of the dense layers (see dense_tanh)
+    static constexpr bool PIPE_ON = PIPE && MT * K2S * (int)sizeof(Frag) / 4 <= 64;
 
     Frag w1[MT][K1S];
     Frag w2[MT][K2S];
@@ -209,48 +201,99 @@ struct Mlp {
         }
     }
 
-    // Dense layer of this wave's MT output tiles for all NT row tiles (in
-    // blocks of NTB), then tanh and quantisation into `out` ([R][H] rows).
+    // Accumulators of this wave's MT output tiles for row tile `nt`: the
+    // per-feature start `ini` plus W times the row tile's inputs.
+    template <int KS>
+    __device__ __forceinline__ static void mma_rows(f32x4 (&acc)[MT], const Frag (&w)[MT][KS],
+                                                    const float4 (&ini)[MT], const char* in,
+                                                    int p_in, int nt, int lane) {
+        const int lr = lane & 15, kq = (lane >> 4) * KC;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{ini[mt].x, ini[mt].y, ini[mt].z, ini[mt].w};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const Frag b = M::lds(in + (nt * 16 + lr) * p_in + (ks * K + kq) * EB);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[mt] = M::mma(w[mt][ks], b, acc[mt]);
+        }
+    }
+
+    // tanh of row tile `nt`'s accumulators, quantised into `out` ([R][H]).
+    __device__ __forceinline__ static void tanh_rows(const f32x4 (&acc)[MT], const float4 (&kx)[MT],
+                                                     char* out, float q, int nt, int wave, int lane) {
+        const int lr = lane & 15;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const int feat = wave * FPW + mt * 16 + 4 * (lane >> 4);
+            const f32x4 a = acc[mt];
+            char* p = out + (nt * 16 + lr) * P_H + feat * EB;
+            if constexpr (DT == DT_FP8) {
+                *reinterpret_cast<uint32_t*>(p) = pack_fp8x4(
+                    tanh_scaled_q(a[0], kx[mt].x, q), tanh_scaled_q(a[1], kx[mt].y, q),
+                    tanh_scaled_q(a[2], kx[mt].z, q), tanh_scaled_q(a[3], kx[mt].w, q));
+            } else {
+                store4<DT>(p, tanh_scaled(a[0], kx[mt].x), tanh_scaled(a[1], kx[mt].y),
+                           tanh_scaled(a[2], kx[mt].z), tanh_scaled(a[3], kx[mt].w), 1.0f);
+            }
+        }
+    }
+
+    // Dense layer of this wave's MT output tiles for all NT row tiles, then
+    // tanh and quantisation into `out`. With PIPE the loop is software-
+    // pipelined over row tiles: the MFMAs of row tile n + 1 are issued ahead
+    // of the tanh of row tile n, so the matrix core and the vector ALU of the
+    // SIMD work at the same time (this holds two tiles of accumulators and the
+    // next tile's operands in registers; without it -- kernels with four or
+    // more waves per SIMD, or whose layer-2 weights take more than 64
+    // registers per lane -- each row tile is multiplied, then activated).
     // `tab` holds the layer's accumulator starts and tanh factors.
     template <int KS>
     __device__ __forceinline__ void dense_tanh(const Frag (&w)[MT][KS], const float* tab,
                                                const char* in, int p_in, char* out, float inv_q,
                                                int wave, int lane) {
-        const int lr = lane & 15, kq = (lane >> 4) * KC;
-#pragma unroll
-        for (int nb = 0; nb < NT; nb += NTB) {
-            f32x4 acc[MT][NTB];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                const float4 ini = *reinterpret_cast<const float4*>(
-                    tab + wave * FPW + mt * 16 + 4 * (lane >> 4));
-#pragma unroll
-                for (int nt = 0; nt < NTB; ++nt) acc[mt][nt] = f32x4{ini.x, ini.y, ini.z, ini.w};
-            }
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                Frag b[NTB];
-#pragma unroll
-                for (int nt = 0; nt < NTB; ++nt)
-                    b[nt] = M::lds(in + ((nb + nt) * 16 + lr) * p_in + (ks * K + kq) * EB);
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                    for (int nt = 0; nt < NTB; ++nt)
-                        acc[mt][nt] = M::mma(w[mt][ks], b[nt], acc[mt][nt]);
-            }
+        float4 ini[MT], kx[MT];
+        auto per_feature = [&]() {
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
                 const int feat = wave * FPW + mt * 16 + 4 * (lane >> 4);
-                float4 kx = make_float4(kTwoLog2e, kTwoLog2e, kTwoLog2e, kTwoLog2e);
-                if constexpr (DT == DT_FP8) kx = *reinterpret_cast<const float4*>(tab + H + feat);
+                ini[mt] = *reinterpret_cast<const float4*>(tab + feat);
+                if constexpr (DT == DT_FP8)
+                    kx[mt] = *reinterpret_cast<const float4*>(tab + H + feat);
+                else
+                    kx[mt] = make_float4(kTwoLog2e, kTwoLog2e, kTwoLog2e, kTwoLog2e);
+            }
+        };
+        if constexpr (!PIPE_ON) {
 #pragma unroll
-                for (int nt = 0; nt < NTB; ++nt) {
-                    const f32x4 a = acc[mt][nt];
-                    store4<DT>(out + ((nb + nt) * 16 + lr) * P_H + feat * EB,
-                               tanh_scaled(a[0], kx.x), tanh_scaled(a[1], kx.y),
-                               tanh_scaled(a[2], kx.z), tanh_scaled(a[3], kx.w), inv_q);
+            for (int nt = 0; nt < NT; ++nt) {
+                f32x4 acc[MT];
+                per_feature();   // re-read per row tile: fewer live registers
+                mma_rows<KS>(acc, w, ini, in, p_in, nt, lane);
+                tanh_rows(acc, kx, out, inv_q, nt, wave, lane);
+            }
+            return;
+        }
+        per_feature();
+        f32x4 acc[2][MT];
+        mma_rows<KS>(acc[0], w, ini, in, p_in, 0, lane);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            if (nt + 1 < NT) mma_rows<KS>(acc[(nt + 1) & 1], w, ini, in, p_in, nt + 1, lane);
+            tanh_rows(acc[nt & 1], kx, out, inv_q, nt, wave, lane);
+            if (nt + 1 < NT) {
+                // all LDS reads of the next row tile first, a few vector
+                // instructions while they land, then one MFMA at a time, each
+                // followed by a share of the tanh's vector work
+                constexpr int NM = MT * KS, NVT = MT * 4 * 6, NV0 = 8;
+                constexpr int NV = (NVT - NV0 + NM - 1) / NM;
+                __builtin_amdgcn_sched_group_barrier(0x100, KS, 0);
+                __builtin_amdgcn_sched_group_barrier(0x002, NV0, 0);
+#pragma unroll
+                for (int i = 0; i < NM; ++i) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x002, NV, 0);
                 }
+                __builtin_amdgcn_sched_barrier(0);   // one scheduling region per row tile
             }
         }
     }
@@ -490,14 +533,15 @@ constexpr int extra_lds_bytes(int R) {
 }
 
 __device__ __forceinline__ uint32_t step_base(const EnvArgs& env) {
-    return env.step_ptr ? *env.step_ptr : env.t0;
+    return env.step_ptr ? *env.step_ptr + env.t0 : env.t0;
 }
 
-__device__ __forceinline__ Tile tile_of(const EnvArgs& env, int tile, int R) {
+__device__ __forceinline__ Tile tile_of(const EnvArgs& env, int tile) {
     if (env.tiles) return env.tiles[tile];
+    const int rows = env.tile_rows;   // <= the kernel's row capacity
     Tile t;
-    t.row0 = tile * R;
-    t.row1 = (int)min((int64_t)(tile + 1) * R, env.n_rows);
+    t.row0 = tile * rows;
+    t.row1 = (int)min((int64_t)(tile + 1) * rows, env.n_rows);
     t.env0 = t.row0;
     t.env1 = t.row1;
     return t;
@@ -532,7 +576,7 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(NW * 64, NW * 64),
                                amdgpu_waves_per_eu(OCC)))
 k_fused(Batch batch, PolicyArgs pol) {
     using HO = HeadOf<E>;
-    using L = Mlp<DT, H, NW, NT, kin_of<E, DT>(), HO::NHP, HS>;
+    using L = Mlp<DT, H, NW, NT, kin_of<E, DT>(), HO::NHP, HS, (OCC <= 2)>;
     constexpr int R = L::R;
     constexpr int NTHR = NW * 64;
     constexpr int G = lanes_per_row(R, NTHR, E::LANES);   // lanes serving one row in phase D
@@ -577,7 +621,7 @@ k_fused(Batch batch, PolicyArgs pol) {
                 __syncthreads();
             }
         }
-        const Tile tl = tile_of(env, tile - sg.tile_begin, R);
+        const Tile tl = tile_of(env, tile - sg.tile_begin);
         const int row = tl.row0 + rr;
         const bool mine = rr < R;
         const bool valid = mine && row < tl.row1;
@@ -599,7 +643,8 @@ k_fused(Batch batch, PolicyArgs pol) {
         }
         __syncthreads();
 
-        for (int step = 0; step <= horizon; ++step) {
+        const int passes = horizon + (sg.last ? 1 : 0);   // the extra pass evaluates V(s_T)
+        for (int step = 0; step < passes; ++step) {
             mlp.forward(smem, wave, lane);
             __syncthreads();
             const uint32_t t = t0 + (uint32_t)step;
@@ -693,7 +738,7 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(NW * 64, NW * 64),
                                amdgpu_waves_per_eu(OCC)))
 k_plain_policy(EnvArgs env, PolicyArgs pol) {
     using HO = HeadOf<E>;
-    using L = Mlp<DT, H, NW, NT, kin_of<E, DT>(), HO::NHP, HS>;
+    using L = Mlp<DT, H, NW, NT, kin_of<E, DT>(), HO::NHP, HS, (OCC <= 2)>;
     constexpr int R = L::R;
     __shared__ __attribute__((aligned(16))) char smem[L::BYTES];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -703,7 +748,7 @@ k_plain_policy(EnvArgs env, PolicyArgs pol) {
     for (int i = tid; i < R * L::P_IN / 4; i += NW * 64)
         reinterpret_cast<uint32_t*>(smem + L::OFF_IN)[i] = 0u;
     __syncthreads();
-    const Tile tl = tile_of(env, blockIdx.x, R);
+    const Tile tl = tile_of(env, blockIdx.x);
     const int row = tl.row0 + tid;
     const bool valid = tid < R && row < tl.row1;
     if (valid) {
@@ -907,6 +952,7 @@ __global__ void k_quantize(int dtype, float scale, const float* x, float* y, int
     X(Acrobot, DT_BF16, 256, 8, 3, 0, 4)     \
     X(Market, DT_BF16, 256, 4, 8, 1, 1)      \
     X(Market, DT_BF16, 256, 8, 8, 1, 2)      \
+    X(Reaction, DT_FP8, 512, 4, 1, 0, 1)     \
     X(Reaction, DT_FP8, 512, 8, 1, 0, 2)     \
     X(Reaction, DT_FP8, 512, 8, 2, 0, 2)     \
     X(Reaction, DT_FP8, 512, 8, 4, 1, 2)
@@ -1038,6 +1084,7 @@ hipError_t launch_policy_forward(const Variant& v, const PolicyArgs& pol, const 
     env.obs_scratch = const_cast<float*>(obs);
     env.head_scratch = head;
     env.n_rows = rows;
+    env.tile_rows = v.tile_rows;
     env.n_tiles = (int)((rows + v.tile_rows - 1) / v.tile_rows);
     void* args[] = {(void*)&env, (void*)&pol};
     return hipLaunchKernel(e->policy, dim3(env.n_tiles), dim3(v.waves * 64), args, 0, s);

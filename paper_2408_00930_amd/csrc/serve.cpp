@@ -342,6 +342,7 @@ bool launch_rounds(wsx_server* S) {
             sg.tr.last_value = r->traj.last_value;
             sg.steps = steps;
             sg.tile_begin = tiles;
+            sg.last = r->issued + steps == r->req.horizon ? 1 : 0;   // V(s_T) once, at the end
             tiles += env->n_tiles;
             g.host_table[i] = sg;
             env->step += (uint32_t)steps;

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libwsx.so")
 
 CARTPOLE, PENDULUM, ACROBOT, MARKET, REACTION = 1, 2, 3, 4, 5
 F32, BF16, FP8_E4M3, F64 = 0, 1, 2, 3
-MODE_FUSED, MODE_PLAIN, MODE_GRAPH = 0, 1, 2
+MODE_FUSED, MODE_PLAIN, MODE_GRAPH, MODE_FUSED_GRAPH = 0, 1, 2, 3
 DTYPE_CODE = {"f32": F32, "bf16": BF16, "fp8": FP8_E4M3}
 
 OBS_DIM = {CARTPOLE: 4, PENDULUM: 3, ACROBOT: 6, MARKET: 32, REACTION: 20}
@@ -54,7 +54,8 @@ class _EnvDesc(C.Structure):
 
 
 EXPORTS = ["wsx_env_state_bytes", "wsx_env_create", "wsx_env_reset", "wsx_rollout",
-           "wsx_env_info", "wsx_env_set_step", "wsx_env_destroy", "wsx_compute_returns",
+           "wsx_env_info", "wsx_env_set_step", "wsx_env_set_chunk", "wsx_env_destroy",
+           "wsx_compute_returns",
            "wsx_policy_forward", "wsx_quantize", "wsx_last_error"]
 
 _lib = None
@@ -75,6 +76,7 @@ def lib():
         L.wsx_rollout.argtypes = [vp, C.POINTER(_Policy), i32, C.POINTER(_Traj), i32, vp]
         L.wsx_env_info.argtypes = [vp, C.POINTER(i64), C.POINTER(u32), C.POINTER(u32)]
         L.wsx_env_set_step.argtypes = [vp, u32]
+        L.wsx_env_set_chunk.argtypes = [vp, i32]
         L.wsx_env_destroy.argtypes = [vp]
         L.wsx_compute_returns.argtypes = [vp, vp, vp, vp, i32, i64, f64, f64, i32, vp, vp, i32, vp]
         L.wsx_policy_forward.argtypes = [C.POINTER(_Policy), vp, i64, vp, vp]
@@ -196,6 +198,10 @@ class Env:
 
     def set_step(self, step):
         _check(lib().wsx_env_set_step(self.handle, step))
+
+    def set_chunk(self, chunk_steps):
+        """Steps per fused launch in MODE_FUSED_GRAPH (0 = the whole horizon)."""
+        _check(lib().wsx_env_set_chunk(self.handle, chunk_steps))
 
 
 def env_reset(env, epoch=0, stream=None):
@@ -370,3 +376,85 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------ autotuner ----
+
+class _TuneEntry(C.Structure):
+    _fields_ = [("tile_rows", C.c_int32), ("waves", C.c_int32), ("occupancy", C.c_int32),
+                ("chunk_steps", C.c_int32), ("us_per_step", C.c_double)]
+
+
+EXPORTS += ["wsx_autotune_workspace_bytes", "wsx_autotune", "wsx_tune_lookup", "wsx_tune_save",
+            "wsx_tune_load", "wsx_env_shape"]
+
+
+def _tune_sigs(L):
+    if getattr(L, "_tune_sigs", False):
+        return
+    vp = C.c_void_p
+    L.wsx_autotune_workspace_bytes.argtypes = [C.POINTER(_EnvDesc), C.c_int32,
+                                               C.POINTER(C.c_size_t)]
+    L.wsx_autotune.argtypes = [C.POINTER(_EnvDesc), C.POINTER(_Policy), C.c_int32, C.c_int32, vp,
+                               C.c_size_t, C.POINTER(_TuneEntry), vp]
+    L.wsx_tune_lookup.argtypes = [C.c_int32, C.c_int64, C.c_int64, C.c_int32,
+                                  C.POINTER(_TuneEntry)]
+    L.wsx_tune_save.argtypes = [C.c_char_p]
+    L.wsx_tune_load.argtypes = [C.c_char_p]
+    L.wsx_env_shape.argtypes = [vp] + [C.POINTER(C.c_int32)] * 4
+    L._tune_sigs = True
+
+
+def _entry(e):
+    return {k: getattr(e, k) for k, _ in _TuneEntry._fields_}
+
+
+def autotune(kind, n_envs, policy, horizon, reps=3, seed=0, agent_offsets=None, params=None,
+             stream=None):
+    """Time every compiled kernel shape (and the graph chunk length) for this
+    environment set and record the fastest in the library's table, so that an
+    Env created later with the default shape uses it. Returns the entry."""
+    L = lib()
+    _tune_sigs(L)
+    offs = None if agent_offsets is None else np.ascontiguousarray(agent_offsets, np.int32)
+    par = None if params is None else torch.from_numpy(
+        np.ascontiguousarray(params, np.float32)).cuda()
+    desc = _EnvDesc(kind, 0, 0, 0, n_envs, seed, None,
+                    None if offs is None else offs.ctypes.data,
+                    None if par is None else par.data_ptr())
+    need = C.c_size_t()
+    _check(L.wsx_autotune_workspace_bytes(C.byref(desc), horizon, C.byref(need)))
+    ws = torch.empty(need.value, dtype=torch.uint8, device="cuda")
+    out = _TuneEntry()
+    _check(L.wsx_autotune(C.byref(desc), C.byref(policy.c), horizon, reps, ws.data_ptr(),
+                          need.value, C.byref(out), _stream(stream)))
+    return _entry(out)
+
+
+def tune_lookup(kind, n_envs, n_rows, cus):
+    L = lib()
+    _tune_sigs(L)
+    out = _TuneEntry()
+    rc = L.wsx_tune_lookup(kind, n_envs, n_rows, cus, C.byref(out))
+    return None if rc != 0 else _entry(out)
+
+
+def tune_save(path):
+    L = lib()
+    _tune_sigs(L)
+    _check(L.wsx_tune_save(os.fsencode(path)))
+
+
+def tune_load(path):
+    L = lib()
+    _tune_sigs(L)
+    _check(L.wsx_tune_load(os.fsencode(path)))
+
+
+def env_shape(env):
+    """(tile_rows, waves, occupancy, chunk_steps) the set runs with."""
+    L = lib()
+    _tune_sigs(L)
+    v = [C.c_int32() for _ in range(4)]
+    _check(L.wsx_env_shape(env.handle, *[C.byref(x) for x in v]))
+    return tuple(x.value for x in v)

@@ -59,10 +59,12 @@ def test_create_validation_without_gpu():
     assert b"agent_offsets" in L.wsx_last_error()
     d = wsx._EnvDesc(wsx.REACTION, 0, 0, 0, 3, 0, 1234, None, None)
     assert L.wsx_env_create(C.byref(d), C.byref(h)) == -1           # reaction needs params
-    d = wsx._EnvDesc(wsx.PENDULUM, 112, 0, 0, 3, 0, 1234, None, None)
-    assert L.wsx_env_create(C.byref(d), C.byref(h)) == -2           # no 112-row tile kernel
+    d = wsx._EnvDesc(wsx.PENDULUM, 129, 0, 0, 3, 0, 1234, None, None)
+    assert L.wsx_env_create(C.byref(d), C.byref(h)) == -2           # no kernel holds 129-row tiles
     d = wsx._EnvDesc(wsx.PENDULUM, 0, 0, -1, 3, 0, 1234, None, None)
     assert L.wsx_env_create(C.byref(d), C.byref(h)) == -1           # negative occupancy
+    d = wsx._EnvDesc(wsx.PENDULUM, -16, 0, 0, 3, 0, 1234, None, None)
+    assert L.wsx_env_create(C.byref(d), C.byref(h)) == -1           # negative tile rows
     d = wsx._EnvDesc(wsx.PENDULUM, 0, 0, 0, 3, 0, None, None, None)
     assert L.wsx_env_create(C.byref(d), C.byref(h)) == -1           # no state block
 
@@ -70,6 +72,7 @@ def test_create_validation_without_gpu():
 def test_rollout_and_returns_validation_without_gpu():
     wsx, L = _lib()
     assert L.wsx_rollout(None, None, 1, None, 0, None) == -1
+    assert L.wsx_env_set_chunk(None, 4) == -1
     assert L.wsx_compute_returns(None, None, None, None, 10, 10, 1.5, 0.9, 1, None, None,
                                  wsx.F64, None) == -1
     assert L.wsx_compute_returns(None, None, None, None, 10, 10, 0.9, 0.9, 1, None, None,
@@ -91,3 +94,50 @@ def test_server_validation_without_gpu():
     d = wsx._ServerDesc(1234, 1024, 25, 64)
     assert L.wsx_server_create(C.byref(d), C.byref(h)) == -1      # smaller than launch tables
     assert L.wsx_server_submit(None, None, None) == -1
+
+
+def test_tuning_table_round_trip_and_rejects_bad_files(tmp_path):
+    wsx, L = _lib()
+    wsx._tune_sigs(L)
+    good = tmp_path / "tune.txt"
+    good.write_text("# kind n_envs n_rows cus tile_rows waves occupancy chunk_steps us_per_step\n"
+                    "2 10007 10007 256 40 8 2 0 6.5\n"
+                    "3 10007 10007 256 80 8 2 50 7.25\n"
+                    "2 10007 10007 256 48 8 2 0 6.0\n")      # replaces the first pendulum line
+    wsx.tune_load(str(good))
+    e = wsx.tune_lookup(wsx.PENDULUM, 10007, 10007, 256)
+    assert e == {"tile_rows": 48, "waves": 8, "occupancy": 2, "chunk_steps": 0,
+                 "us_per_step": 6.0}
+    assert wsx.tune_lookup(wsx.ACROBOT, 10007, 10007, 256)["chunk_steps"] == 50
+    assert wsx.tune_lookup(wsx.PENDULUM, 10007, 10007, 304) is None     # other device
+    out = tmp_path / "saved.txt"
+    wsx.tune_save(str(out))
+    lines = [l.split() for l in out.read_text().splitlines() if not l.startswith("#")]
+    assert ["2", "10007", "10007", "256", "48", "8", "2", "0", "6"] in lines
+    # a kernel shape that is not compiled, a malformed line: the file is refused whole
+    for bad in ("2 500 500 256 200 8 2 0 1.0\n", "2 500 500 256 48 8 2\n",
+                "9 500 500 256 48 8 2 0 1.0\n", "2 500 500 256 48 8 2 -1 1.0\n"):
+        p = tmp_path / "bad.txt"
+        p.write_text("2 777 777 256 48 8 2 0 1.0\n" + bad)
+        with pytest.raises(wsx.WsxError):
+            wsx.tune_load(str(p))
+        assert wsx.tune_lookup(wsx.PENDULUM, 777, 777, 256) is None
+    with pytest.raises(wsx.WsxError):
+        wsx.tune_load(str(tmp_path / "missing.txt"))
+
+
+def test_autotune_validation_without_gpu():
+    wsx, L = _lib()
+    wsx._tune_sigs(L)
+    n = C.c_size_t()
+    d = wsx._EnvDesc(wsx.PENDULUM, 0, 0, 0, 1000, 0, None, None, None)
+    assert L.wsx_autotune_workspace_bytes(C.byref(d), 50, C.byref(n)) == 0
+    # state block + 50 steps x 1000 rows x (obs 12 + action 4 + reward 4 + done 1 + value 4 +
+    # logp 4) bytes + last value, each part rounded up to 256 bytes
+    assert 50 * 1000 * 29 + 1000 * 4 <= n.value <= 50 * 1000 * 29 + 1000 * 4 + 64 * 1024
+    assert L.wsx_autotune_workspace_bytes(C.byref(d), 0, C.byref(n)) == -1
+    assert L.wsx_autotune(C.byref(d), None, 50, 3, 1234, n.value, None, None) == -1
+    pol = wsx._Policy()
+    assert L.wsx_autotune(C.byref(d), C.byref(pol), 50, 0, 1234, n.value, None, None) == -1
+    assert L.wsx_autotune(C.byref(d), C.byref(pol), 50, 3, 1234, 16, None, None) == -1
+    assert L.wsx_env_shape(None, None, None, None, None) == -1

@@ -310,6 +310,41 @@ def test_plain_and_graph_equal_fused_bitwise(kind, n):
 
 
 @pytest.mark.parametrize("kind,n", KINDS_SMALL)
+@pytest.mark.parametrize("chunk", [0, 4, 9])
+def test_fused_graph_chunks_equal_fused_bitwise(kind, n, chunk):
+    """The horizon as chunked fused launches in one graph, replayed three times
+    into the same buffers with eager work in between, equals one launch."""
+    import torch
+    wsx = _wsx()
+    c = Case(kind, n, seed=8)
+    say("fused graph chunks", kind, chunk)
+    f = _run(c, wsx.MODE_FUSED, 9, epoch=3)
+    c.env.set_chunk(chunk)
+    traj = wsx.Trajectory(kind, 9, c.rows)
+    for rep in range(3):
+        wsx.env_reset(c.env, 3)
+        wsx.rollout(c.env, c.dpol, 9, traj, wsx.MODE_FUSED_GRAPH)
+        g = traj.host()
+        g["state"] = c.gpu_state()
+        for k in f:
+            assert np.array_equal(f[k], g[k]), (rep, k)
+        traj.reward.fill_(-7.0)            # eager work between the replays
+        torch.cuda.synchronize()
+
+
+def test_fused_graph_horizon_zero_and_rejects_negative_chunk():
+    wsx = _wsx()
+    c = Case(O.PENDULUM, 40, seed=2)
+    say("fused graph horizon 0")
+    f = _run(c, wsx.MODE_FUSED, 0)
+    c.env.set_chunk(5)
+    g = _run(c, wsx.MODE_FUSED_GRAPH, 0)
+    assert np.array_equal(f["last_value"], g["last_value"])
+    with pytest.raises(wsx.WsxError):
+        c.env.set_chunk(-1)
+
+
+@pytest.mark.parametrize("kind,n", KINDS_SMALL)
 def test_resume_split_is_bitwise(kind, n):
     wsx = _wsx()
     c = Case(kind, n, seed=6)
