@@ -4,7 +4,8 @@
 One step = the whole hot path over one batch: env_reset, rollout(horizon)
 and compute_returns for every environment set of the workload. The default
 workload is 10,000 Pendulum + 10,000 Acrobot replicas, horizon 200, BF16
-policies obs-256-256-(1+1), the two sets on two streams. Prints one JSON line.
+policies obs-256-256-(1+1), both sets in one fused launch (rollout_batch)
+with the kernel shape chosen by the library's autotuner. Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME]
 """
@@ -44,7 +45,7 @@ def kernel_source_hash():
 
 
 class EnvSet:
-    def __init__(self, key, seed, tile_rows, wsx, inputs, torch):
+    def __init__(self, key, seed, tile_rows, wsx, inputs, torch, shape=None):
         cfg = inputs.CONFIGS[key]
         self.key = key
         self.kind = cfg["kind"]
@@ -54,8 +55,9 @@ class EnvSet:
         self.dp = wsx.DevicePolicy(self.policy)
         offsets = inputs.agent_offsets(self.n_envs, seed=seed) if self.kind == wsx.MARKET else None
         params = inputs.reaction_params(seed) if self.kind == wsx.REACTION else None
+        shape = shape or dict(tile_rows=tile_rows)
         self.env = wsx.Env(self.kind, self.n_envs, seed=seed, agent_offsets=offsets,
-                           params=params, tile_rows=tile_rows)
+                           params=params, **shape)
         self.rows = self.env.rows
         self.traj = wsx.Trajectory(self.kind, self.T, self.rows)
         self.ret = torch.empty((self.T, self.rows), dtype=torch.float32, device="cuda")
@@ -79,14 +81,43 @@ class EnvSet:
                                 self.ret, self.adv)
 
 
-def run_form(sets, mode, steps, warmup, wsx, torch, first_epoch):
+def batch_step(sets, i, wsx, torch, timed, k_events):
+    """All sets in ONE fused launch on the first set's stream (reset, batched
+    roll-out, returns per set)."""
+    st = sets[0].stream
+    with torch.cuda.stream(st):
+        for s in sets:
+            wsx.env_reset(s.env, epoch=i)
+        if timed:
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(st)
+        wsx.rollout_batch([s.env for s in sets], [s.dp for s in sets], sets[0].T,
+                          [s.traj for s in sets])
+        if timed:
+            b.record(st)
+            k_events.append((a, b))
+        for s in sets:
+            wsx.compute_returns(s.traj, s.T, 0.99, 0.95, True, torch.float32, s.ret, s.adv)
+
+
+def run_form(sets, mode, steps, warmup, wsx, torch, first_epoch, batched=False):
     main = torch.cuda.current_stream()
-    for i in range(warmup):
+    k_events = []
+
+    def one(i, timed):
+        if batched:
+            sets[0].stream.wait_stream(main)
+            batch_step(sets, i, wsx, torch, timed, k_events)
+            main.wait_stream(sets[0].stream)
+            return
         for s in sets:
             s.stream.wait_stream(main)
-            s.step(first_epoch + i, mode, wsx, torch, timed=False)
+            s.step(i, mode, wsx, torch, timed=timed)
         for s in sets:
             main.wait_stream(s.stream)
+
+    for i in range(warmup):
+        one(first_epoch + i, False)
     for s in sets:
         s.k_start, s.k_end = [], []
     torch.cuda.synchronize()
@@ -95,18 +126,17 @@ def run_form(sets, mode, steps, warmup, wsx, torch, first_epoch):
     for i in range(steps):
         a = torch.cuda.Event(enable_timing=True)
         a.record(main)
-        for s in sets:
-            s.stream.wait_stream(main)
-            s.step(first_epoch + warmup + i, mode, wsx, torch, timed=True)
-        for s in sets:
-            main.wait_stream(s.stream)
+        one(first_epoch + warmup + i, True)
         b = torch.cuda.Event(enable_timing=True)
         b.record(main)
         step_ev.append((a, b))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     lat = sorted(a.elapsed_time(b) for a, b in step_ev)
-    kern = {s.key: [a.elapsed_time(b) for a, b in zip(s.k_start, s.k_end)] for s in sets}
+    if batched:
+        kern = {"batch": [a.elapsed_time(b) for a, b in k_events]}
+    else:
+        kern = {s.key: [a.elapsed_time(b) for a, b in zip(s.k_start, s.k_end)] for s in sets}
     return elapsed, lat, kern
 
 
@@ -235,9 +265,13 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--workload", default="pendulum_acrobot_10k", choices=sorted(WORKLOADS))
     ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--shape", default="",
+                    help="ROWS,WAVES,OCCUPANCY kernel shape for every set (skips the autotuner)")
     ap.add_argument("--cpu-sample-envs", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="fused,plain,graph,fused_graph")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="run a multi-set workload as one launch per set on its own stream")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="run the built-in default kernel shapes instead of the autotuner's")
     ap.add_argument("--serve-requests", type=int, default=400,
@@ -272,27 +306,41 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    keys = WORKLOADS[args.workload]
+    batched = len(keys) > 1 and not args.no_batch
     tuned = {}
-    if args.autotune and not args.tile_rows:
-        # the library's autotuner picks each set's kernel shape (untimed here)
-        for key in WORKLOADS[args.workload]:
+    shape = dict(zip(("tile_rows", "waves", "occupancy"),
+                     (int(x) for x in args.shape.split(",")))) if args.shape else None
+    if args.autotune and not args.tile_rows and not shape:
+        # the library's autotuner picks the kernel shape (untimed here): for a
+        # batched workload one shape for the whole single launch
+        spec = []
+        for key in keys:
             cfg = inputs.CONFIGS[key]
             kind = cfg["kind"]
-            pol = wsx.DevicePolicy(inputs.policy_for(kind, cfg["dtype"], cfg["hidden"], seed=0))
-            t0 = time.perf_counter()
-            tuned[key] = wsx.autotune(
-                kind, cfg["n_envs"], pol, cfg["horizon"], reps=2, seed=0,
+            spec.append(dict(
+                kind=kind, n_envs=cfg["n_envs"], seed=0, horizon=cfg["horizon"],
+                policy=wsx.DevicePolicy(inputs.policy_for(kind, cfg["dtype"], cfg["hidden"], seed=0)),
                 agent_offsets=inputs.agent_offsets(cfg["n_envs"], seed=0)
                 if kind == wsx.MARKET else None,
-                params=inputs.reaction_params(0) if kind == wsx.REACTION else None)
-            print(f"[bench] autotune {key}: {tuned[key]} in {time.perf_counter() - t0:.1f} s",
-                  file=sys.stderr, flush=True)
-    sets = [EnvSet(k, 0, args.tile_rows, wsx, inputs, torch) for k in WORKLOADS[args.workload]]
+                params=inputs.reaction_params(0) if kind == wsx.REACTION else None))
+        t0 = time.perf_counter()
+        if batched:
+            tuned["batch"] = wsx.autotune_batch(spec, spec[0]["horizon"], reps=2)
+        else:
+            for key, d in zip(keys, spec):
+                tuned[key] = wsx.autotune(d["kind"], d["n_envs"], d["policy"], d["horizon"], reps=2,
+                                          seed=0, agent_offsets=d["agent_offsets"],
+                                          params=d["params"])
+        print(f"[bench] autotune: {tuned} in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+              flush=True)
+    sets = [EnvSet(k, 0, args.tile_rows, wsx, inputs, torch, shape) for k in keys]
     env_steps = sum(s.n_envs * s.T for s in sets)
     forms = args.forms.split(",")
 
     result = {}
-    el, lat, kern = run_form(sets, wsx.MODE_FUSED, args.steps, args.warmup, wsx, torch, 0)
+    el, lat, kern = run_form(sets, wsx.MODE_FUSED, args.steps, args.warmup, wsx, torch, 0,
+                             batched=batched)
     result["fused"] = (el, lat, kern)
     print(f"[bench] fused: {args.steps} steps in {el:.3f} s", file=sys.stderr, flush=True)
     for name, mode in (("plain", wsx.MODE_PLAIN), ("graph", wsx.MODE_GRAPH),
@@ -305,17 +353,25 @@ def main():
 
     el, lat, kern = result["fused"]
     value = env_steps * args.steps / el
-    # dominant kernel: the fused roll-out launch with the most total time
-    dom = max(sets, key=lambda s: sum(kern[s.key]))
-    avg_ms = sum(kern[dom.key]) / len(kern[dom.key])
-    dtype = dom.policy.dtype
-    achieved = dom.flop_per_launch / (avg_ms * 1e-3) / 1e12
-    kname = f"k_fused/{dom.key}"
+    # dominant kernel: the fused roll-out launch (the batched one, or the set's
+    # launch with the most total time)
+    if batched:
+        avg_ms = sum(kern["batch"]) / len(kern["batch"])
+        flop = sum(s.flop_per_launch for s in sets)
+        dtype = sets[0].policy.dtype
+        kname = f"k_fused/{args.workload}"
+    else:
+        dom = max(sets, key=lambda s: sum(kern[s.key]))
+        avg_ms = sum(kern[dom.key]) / len(kern[dom.key])
+        flop = dom.flop_per_launch
+        dtype = dom.policy.dtype
+        kname = f"k_fused/{dom.key}"
+    achieved = flop / (avg_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_TFLOPS[dtype],
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[dtype], 4),
                 "traffic": traffic_for(kname, "hbm_bytes_per_launch"),
                 "kernel": kname, "avg_launch_ms": round(avg_ms, 4),
-                "flop_per_launch": dom.flop_per_launch}
+                "flop_per_launch": flop}
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "env-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(el / args.steps * 1e3, 4),
@@ -327,11 +383,11 @@ def main():
                    "horizon": max(s.T for s in sets), "sets": [s.key for s in sets],
                    "policy": {s.key: f"{s.policy.dtype} {s.policy.d_in}-{s.policy.h1}-"
                                      f"{s.policy.h2}-{s.policy.n_head}" for s in sets},
-                   "returns": "FP64 scan, FP32 outputs", "streams": len(sets),
+                   "returns": "FP64 scan, FP32 outputs", "streams": 1 if batched else len(sets),
                    "kernel_shape": {s.key: dict(zip(("tile_rows", "waves", "occupancy",
                                                      "chunk_steps"), wsx.env_shape(s.env)))
                                     for s in sets},
-                   "autotuned": bool(tuned)},
+                   "autotuned": bool(tuned), "one_launch": batched},
         "latency_ms": {"p50": round(percentile(lat, 50), 4), "p99": round(percentile(lat, 99), 4)},
         "roofline": roofline,
     }

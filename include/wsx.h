@@ -152,6 +152,20 @@ int wsx_rollout(wsx_env* env, const wsx_policy* policy, int32_t horizon,
 /* Number of rows, current step counter and epoch of an environment set. */
 int wsx_env_info(const wsx_env* env, int64_t* n_rows, uint32_t* step, uint32_t* epoch);
 
+/* Several environment sets in ONE persistent fused launch (App. B: many
+ * environment instances advanced together, each in its own GPU blocks):
+ * set i runs `horizon` steps with policies[i] into trajs[i], with the same
+ * results as wsx_rollout(WSX_MODE_FUSED) of that set on a kernel with the
+ * same waves (rows never interact across sets). 1 <= n <= 4 distinct sets
+ * on one device; their kinds are one kind, or Pendulum and Acrobot together
+ * (compiled pair kernels); the policies share dtype and width. The launch
+ * uses the waves and occupancy of envs[0] and the smallest kernel that holds
+ * every set's tile height. Each set's step counter advances by `horizon`.
+ * Errors: WSX_EINVAL (arguments), WSX_EUNSUPPORTED (no kernel for the mix),
+ * WSX_EHIP. */
+int wsx_rollout_batch(wsx_env* const* envs, const wsx_policy* const* policies,
+                      const wsx_traj* const* trajs, int32_t n, int32_t horizon, void* stream);
+
 /* Sets the step counter (resuming from a saved state block). */
 int wsx_env_set_step(wsx_env* env, uint32_t step);
 
@@ -220,6 +234,18 @@ int wsx_autotune_workspace_bytes(const wsx_env_desc* desc, int32_t horizon, size
 int wsx_autotune(const wsx_env_desc* desc, const wsx_policy* policy, int32_t horizon,
                  int32_t reps, void* workspace, size_t workspace_bytes, wsx_tune_entry* best,
                  void* stream);
+
+/* The same search for a batch of 1..4 environment sets run together by
+ * wsx_rollout_batch (one shape for all: each set's tile height, waves and
+ * occupancy); the winner is recorded for every set of the batch, so sets
+ * created afterwards with the default shape run the batch on it. The
+ * workspace holds every set's trial state and trajectory (the sum of
+ * wsx_autotune_workspace_bytes, each rounded up to 256 bytes). */
+int wsx_autotune_batch_workspace_bytes(const wsx_env_desc* const* descs, int32_t n,
+                                       int32_t horizon, size_t* bytes);
+int wsx_autotune_batch(const wsx_env_desc* const* descs, const wsx_policy* const* policies,
+                       int32_t n, int32_t horizon, int32_t reps, void* workspace,
+                       size_t workspace_bytes, wsx_tune_entry* best, void* stream);
 
 /* The table entry for (kind, n_envs, n_rows, compute units): WSX_OK and *out
  * filled, or WSX_EINVAL if there is none. */

@@ -76,12 +76,15 @@ Layout layout_of(const KindInfo& k, int64_t n_envs, int64_t n_rows, bool market)
 // The compiled kernel with the fewest row slots that holds tiles of
 // `tile_rows` rows; waves / occupancy 0 match any compiled value (the first
 // listed wins among kernels of the same row capacity).
-bool find_variant(int kind, int dtype, int hidden, int waves, int tile_rows, int occupancy,
-                  Variant& out) {
+static bool find_any(int kind, int kind2, int dtype, int hidden, int waves, int tile_rows,
+                     int occupancy, Variant& out) {
     bool found = false;
     for (int i = 0; i < n_variants(); ++i) {
         const Variant& v = variant(i);
-        if (v.kind == kind && v.dtype == dtype && v.hidden == hidden && tile_rows >= 1 &&
+        const bool kinds = kind2 == 0 ? (v.kind == kind && v.kind2 == 0)
+                                      : ((v.kind == kind && v.kind2 == kind2) ||
+                                         (v.kind == kind2 && v.kind2 == kind));
+        if (kinds && v.dtype == dtype && v.hidden == hidden && tile_rows >= 1 &&
             v.tile_rows >= tile_rows && (waves == 0 || v.waves == waves) &&
             (occupancy == 0 || v.occupancy == occupancy) &&
             (!found || v.tile_rows < out.tile_rows)) {
@@ -92,10 +95,21 @@ bool find_variant(int kind, int dtype, int hidden, int waves, int tile_rows, int
     return found;
 }
 
+bool find_variant(int kind, int dtype, int hidden, int waves, int tile_rows, int occupancy,
+                  Variant& out) {
+    return find_any(kind, 0, dtype, hidden, waves, tile_rows, occupancy, out);
+}
+
+bool find_pair_variant(int kind, int kind2, int dtype, int hidden, int waves, int tile_rows,
+                       int occupancy, Variant& out) {
+    return find_any(kind, kind2, dtype, hidden, waves, tile_rows, occupancy, out);
+}
+
 }  // namespace wsx
 
 EnvArgs wsx::env_args(const wsx_env* env) {
     EnvArgs a{};
+    a.kind = env->kind;
     a.state = reinterpret_cast<float*>(env->block + env->lay.state);
     a.obs_scratch = reinterpret_cast<float*>(env->block + env->lay.obs);
     a.head_scratch = reinterpret_cast<float*>(env->block + env->lay.head);
@@ -125,6 +139,31 @@ TrajArgs wsx::traj_at(const TrajArgs& t, const KindInfo& k, size_t slots) {
     o.value = t.value + slots;
     o.logp = t.logp + slots;
     return o;
+}
+
+int wsx::check_traj(const wsx_env* env, const wsx_traj* traj, int32_t horizon) {
+    if (horizon < 0) return fail(WSX_EINVAL, "horizon must be >= 0");
+    if (!traj) return fail(WSX_EINVAL, "traj is NULL");
+    if (traj->capacity < horizon)
+        return fail(WSX_EINVAL, "traj capacity %d < horizon %d", traj->capacity, horizon);
+    if (!traj->last_value || (horizon > 0 && (!traj->obs || !traj->action || !traj->reward ||
+                                              !traj->done || !traj->value || !traj->logp)))
+        return fail(WSX_EINVAL, "trajectory pointer is NULL");
+    if ((uint64_t)env->step + (uint64_t)horizon > 0xFFFFFFFFull)
+        return fail(WSX_EINVAL, "step counter would wrap");
+    return WSX_OK;
+}
+
+TrajArgs wsx::traj_args(const wsx_traj* traj) {
+    TrajArgs ta{};
+    ta.obs = traj->obs;
+    ta.action = traj->action;
+    ta.reward = traj->reward;
+    ta.done = traj->done;
+    ta.value = traj->value;
+    ta.logp = traj->logp;
+    ta.last_value = traj->last_value;
+    return ta;
 }
 
 int wsx::check_policy(const wsx_policy* p, const KindInfo& k, int kind) {
@@ -337,14 +376,8 @@ int wsx_rollout(wsx_env* env, const wsx_policy* policy, int32_t horizon, const w
     if (!env) return fail(WSX_EINVAL, "env is NULL");
     int rc = check_policy(policy, env->info, env->kind);
     if (rc) return rc;
-    if (horizon < 0) return fail(WSX_EINVAL, "horizon must be >= 0");
-    if (!traj) return fail(WSX_EINVAL, "traj is NULL");
-    if (traj->capacity < horizon) return fail(WSX_EINVAL, "traj capacity %d < horizon %d", traj->capacity, horizon);
-    if (!traj->last_value || (horizon > 0 && (!traj->obs || !traj->action || !traj->reward ||
-                                              !traj->done || !traj->value || !traj->logp)))
-        return fail(WSX_EINVAL, "trajectory pointer is NULL");
-    if ((uint64_t)env->step + (uint64_t)horizon > 0xFFFFFFFFull)
-        return fail(WSX_EINVAL, "step counter would wrap");
+    rc = check_traj(env, traj, horizon);
+    if (rc) return rc;
     Variant v;
     if (!find_variant(env->kind, policy->dtype, policy->h1, env->waves, env->tile_rows,
                       env->occupancy, v))
@@ -352,30 +385,25 @@ int wsx_rollout(wsx_env* env, const wsx_policy* policy, int32_t horizon, const w
     hipStream_t s = static_cast<hipStream_t>(stream);
     const EnvArgs ea = env_args(env);
     const PolicyArgs pa = policy_args(policy);
-    TrajArgs ta{};
-    ta.obs = traj->obs;
-    ta.action = traj->action;
-    ta.reward = traj->reward;
-    ta.done = traj->done;
-    ta.value = traj->value;
-    ta.logp = traj->logp;
-    ta.last_value = traj->last_value;
+    const TrajArgs ta = traj_args(traj);
     hipError_t e = hipSuccess;
     const int grid = std::max(1, std::min(env->n_tiles, env->cus * fused_blocks_per_cu(v)));
     // fused launch of `steps` steps from trajectory slot `first`
     auto fused = [&](const EnvArgs& a, int first, int steps, bool last, hipStream_t st) {
         Batch b{};
         b.table = nullptr;
-        b.one.env = a;
-        b.one.env.t0 += (uint32_t)first;
-        b.one.tr = traj_at(ta, env->info, (size_t)first * (size_t)env->n_rows);
-        b.one.tr.last_value = ta.last_value;
-        b.one.steps = steps;
-        b.one.tile_begin = 0;
-        b.one.last = last ? 1 : 0;
+        Segment& sg = b.inl[0];
+        sg.env = a;
+        sg.env.t0 += (uint32_t)first;
+        sg.tr = traj_at(ta, env->info, (size_t)first * (size_t)env->n_rows);
+        sg.tr.last_value = ta.last_value;
+        sg.pol = pa;
+        sg.steps = steps;
+        sg.tile_begin = 0;
+        sg.last = last ? 1 : 0;
         b.n_segs = 1;
         b.n_tiles = env->n_tiles;
-        return launch_fused(v, b, pa, grid, st);
+        return launch_fused(v, b, grid, st);
     };
     if (mode == WSX_MODE_FUSED) {
         e = fused(ea, 0, horizon, true, s);
@@ -432,6 +460,64 @@ int wsx_rollout(wsx_env* env, const wsx_policy* policy, int32_t horizon, const w
     }
     if (e != hipSuccess) return hip_fail(e, "wsx_rollout");
     env->step += (uint32_t)horizon;
+    return WSX_OK;
+}
+
+int wsx_rollout_batch(wsx_env* const* envs, const wsx_policy* const* policies,
+                      const wsx_traj* const* trajs, int32_t n, int32_t horizon, void* stream) {
+    if (!envs || !policies || !trajs) return fail(WSX_EINVAL, "envs, policies, trajs must not be NULL");
+    if (n < 1 || n > kInlineSegments)
+        return fail(WSX_EINVAL, "a batch holds 1 to %d environment sets (got %d)", kInlineSegments, n);
+    int kinds[2] = {0, 0}, n_kinds = 0, tile_max = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!envs[i]) return fail(WSX_EINVAL, "envs[%d] is NULL", i);
+        int rc = check_policy(policies[i], envs[i]->info, envs[i]->kind);
+        if (rc) return rc;
+        rc = check_traj(envs[i], trajs[i], horizon);
+        if (rc) return rc;
+        for (int j = 0; j < i; ++j)
+            if (envs[j] == envs[i]) return fail(WSX_EINVAL, "envs[%d] repeats envs[%d]", i, j);
+        if (policies[i]->dtype != policies[0]->dtype || policies[i]->h1 != policies[0]->h1)
+            return fail(WSX_EUNSUPPORTED, "the policies of a batch share dtype and width");
+        if (envs[i]->device != envs[0]->device)
+            return fail(WSX_EINVAL, "the sets of a batch live on one device");
+        const int k = envs[i]->kind;
+        if (!(n_kinds > 0 && kinds[0] == k) && !(n_kinds > 1 && kinds[1] == k)) {
+            if (n_kinds == 2) return fail(WSX_EUNSUPPORTED, "a batch mixes at most two kinds");
+            kinds[n_kinds++] = k;
+        }
+        tile_max = std::max(tile_max, envs[i]->tile_rows);
+    }
+    Variant v;
+    const bool ok = n_kinds == 1
+                        ? find_variant(kinds[0], policies[0]->dtype, policies[0]->h1,
+                                       envs[0]->waves, tile_max, envs[0]->occupancy, v)
+                        : find_pair_variant(kinds[0], kinds[1], policies[0]->dtype,
+                                            policies[0]->h1, envs[0]->waves, tile_max,
+                                            envs[0]->occupancy, v);
+    if (!ok)
+        return fail(WSX_EUNSUPPORTED,
+                    "no fused kernel for kinds %d/%d with %d waves, occupancy %d, %d-row tiles",
+                    kinds[0], kinds[1], envs[0]->waves, envs[0]->occupancy, tile_max);
+    Batch b{};
+    b.table = nullptr;
+    int tiles = 0;
+    for (int i = 0; i < n; ++i) {
+        Segment& sg = b.inl[i];
+        sg.env = env_args(envs[i]);
+        sg.tr = traj_args(trajs[i]);
+        sg.pol = policy_args(policies[i]);
+        sg.steps = horizon;
+        sg.tile_begin = tiles;
+        sg.last = 1;
+        tiles += envs[i]->n_tiles;
+    }
+    b.n_segs = n;
+    b.n_tiles = tiles;
+    const int grid = std::max(1, std::min(tiles, envs[0]->cus * fused_blocks_per_cu(v)));
+    const hipError_t e = launch_fused(v, b, grid, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "wsx_rollout_batch");
+    for (int i = 0; i < n; ++i) envs[i]->step += (uint32_t)horizon;
     return WSX_OK;
 }
 

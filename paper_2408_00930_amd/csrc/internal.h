@@ -37,6 +37,10 @@ Layout layout_of(const KindInfo& k, int64_t n_envs, int64_t n_rows, bool market)
 bool find_variant(int kind, int dtype, int hidden, int waves, int tile_rows, int occupancy,
                   Variant& out);
 
+// The fused kernel over tiles of two kinds (either order), same rules.
+bool find_pair_variant(int kind, int kind2, int dtype, int hidden, int waves, int tile_rows,
+                       int occupancy, Variant& out);
+
 // The autotuner's entry for an environment set, if there is one.
 bool tune_lookup(int32_t kind, int64_t n_envs, int64_t n_rows, int32_t cus, wsx_tune_entry& out);
 
@@ -70,4 +74,6 @@ EnvArgs env_args(const wsx_env* env);
 TrajArgs traj_at(const TrajArgs& t, const KindInfo& k, size_t slots);
 PolicyArgs policy_args(const wsx_policy* p);
 int check_policy(const wsx_policy* p, const KindInfo& k, int kind);
+int check_traj(const wsx_env* env, const wsx_traj* traj, int32_t horizon);
+TrajArgs traj_args(const wsx_traj* traj);
 }  // namespace wsx

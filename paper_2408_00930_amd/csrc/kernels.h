@@ -39,6 +39,7 @@ struct Tile {
 };
 
 struct EnvArgs {
+    int32_t kind;             // environment kind (WSX_CARTPOLE ...)
     float* state;             // SoA [state_dim][n_rows]
     float* obs_scratch;       // [n_rows][obs_dim]    (plain mode)
     float* head_scratch;      // [n_rows][n_head]     (plain mode)
@@ -55,34 +56,38 @@ struct EnvArgs {
                               // step_ptr, its offset from the device counter
 };
 
-// One roll-out request inside a fused launch: its environment set, its
-// trajectory pointers (offset to the launch's first slot) and its steps.
+// One roll-out request inside a fused launch: its environment set, its policy,
+// its trajectory pointers (offset to the launch's first slot) and its steps.
 struct Segment {
     EnvArgs env;
     TrajArgs tr;
+    PolicyArgs pol;
     int32_t steps;
     int32_t tile_begin;   // first tile of this segment in the launch
     int32_t last;         // 1: also evaluate V(s_T) into tr.last_value after the steps
 };
 
-// The tiles of a fused launch: one inline segment, or a device table of them
-// sorted by tile_begin.
+// The tiles of a fused launch: up to kInlineSegments segments passed with the
+// launch, or a device table of them; sorted by tile_begin.
+constexpr int kInlineSegments = 4;
 struct Batch {
     const Segment* table;
-    Segment one;
+    Segment inl[kInlineSegments];
     int32_t n_segs;
     int32_t n_tiles;
 };
 
-// One compiled variant of the fused / plain kernels for an environment kind.
+// One compiled variant of the fused / plain kernels for an environment kind
+// (kind2 != 0: a fused kernel that also runs tiles of a second kind with the
+// same policy shape; it has no plain form).
 struct Variant {
     int32_t kind, dtype, hidden, waves, tile_rows, occupancy;   // occupancy: min waves/SIMD
+    int32_t kind2;
 };
 
 // Launchers (return hipError_t of the launch).
 hipError_t launch_reset(int kind, const EnvArgs& env, hipStream_t s);
-hipError_t launch_fused(const Variant& v, const Batch& batch, const PolicyArgs& pol, int grid,
-                        hipStream_t s);
+hipError_t launch_fused(const Variant& v, const Batch& batch, int grid, hipStream_t s);
 hipError_t launch_plain(const Variant& v, const EnvArgs& env, const PolicyArgs& pol,
                         const TrajArgs& tr, int horizon, bool counter_from_device,
                         hipStream_t s);

@@ -2,7 +2,8 @@
 // (arXiv 2408.00930, Sec. 3: actor-critic training consumes them; GAE of
 // Schulman et al. 2016).
 //
-// Both recursions are affine maps run backwards in time,
+// Two kernels. For sets with few rows and long horizons, a time-parallel
+// scan: both recursions are affine maps run backwards in time,
 //   A_t = delta_t + gamma lambda (1 - d_t) A_{t+1},  G_t = r_t + gamma (1 - d_t) G_{t+1},
 // so a block of consecutive steps composes into one map x -> b + c x with
 // (c1, b1) o (c2, b2) = (c1 c2, b1 + c1 b2). A workgroup owns 32 rows and
@@ -19,6 +20,8 @@ namespace wsx {
 
 constexpr int kRetRows = 32;   // rows per workgroup (128-byte rows of float)
 constexpr int kRetSteps = 64;  // steps per tile = lanes of a wave
+// sets with at least this many rows per CU take the row-parallel kernel
+constexpr int kRowsPerLaneMin = 24;
 
 __global__ void __launch_bounds__(256)
 k_returns(const float* __restrict__ reward, const float* __restrict__ value,
@@ -115,10 +118,58 @@ k_returns(const float* __restrict__ reward, const float* __restrict__ value,
     }
 }
 
+// Row-parallel form for sets with many rows: lane = row, the recursion run
+// backwards over the horizon in registers (the same FP64 operations as one
+// step of the scan), loads and stores coalesced over consecutive rows, eight
+// steps in flight per wave. With rows >= 64 waves' worth this keeps every CU
+// streaming, where the time-parallel scan above would stage each 64-step
+// tile through LDS.
+template <int OUT_F64>
+__global__ void __launch_bounds__(64)
+k_returns_rows(const float* __restrict__ reward, const float* __restrict__ value,
+               const uint8_t* __restrict__ done, const float* __restrict__ last_value, int T,
+               int64_t rows, double gamma, double lambda, int bootstrap, void* __restrict__ ret,
+               void* __restrict__ adv) {
+    const int64_t r = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (r >= rows) return;
+    const double gl = gamma * lambda;
+    const double vT = bootstrap ? (double)last_value[r] : 0.0;
+    double g = vT, a = 0.0, v_next = vT;
+#pragma unroll 8
+    for (int t = T - 1; t >= 0; --t) {
+        const size_t i = (size_t)t * rows + r;
+        const double rw = reward[i], v = value[i];
+        const double keep = done[i] ? 0.0 : 1.0;
+        a = (rw + gamma * keep * v_next - v) + gl * keep * a;
+        g = rw + gamma * keep * g;
+        v_next = v;
+        if (OUT_F64) {
+            static_cast<double*>(ret)[i] = g;
+            static_cast<double*>(adv)[i] = a;
+        } else {
+            static_cast<float*>(ret)[i] = (float)g;
+            static_cast<float*>(adv)[i] = (float)a;
+        }
+    }
+}
+
 hipError_t launch_returns(const float* reward, const float* value, const uint8_t* done,
                           const float* last_value, int horizon, int64_t rows, double gamma,
                           double lambda, int bootstrap, void* ret, void* adv, int out_f64,
                           hipStream_t s) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (rows >= (int64_t)kRowsPerLaneMin * cus) {
+        const unsigned blocks = (unsigned)((rows + 63) / 64);
+        if (out_f64)
+            hipLaunchKernelGGL(k_returns_rows<1>, dim3(blocks), dim3(64), 0, s, reward, value, done,
+                               last_value, horizon, rows, gamma, lambda, bootstrap, ret, adv);
+        else
+            hipLaunchKernelGGL(k_returns_rows<0>, dim3(blocks), dim3(64), 0, s, reward, value, done,
+                               last_value, horizon, rows, gamma, lambda, bootstrap, ret, adv);
+        return hipGetLastError();
+    }
     const unsigned blocks = (unsigned)((rows + kRetRows - 1) / kRetRows);
     hipLaunchKernelGGL(k_returns, dim3(blocks), dim3(256), 0, s, reward, value, done, last_value,
                        horizon, rows, gamma, lambda, bootstrap, ret, adv, out_f64);

@@ -15,6 +15,9 @@
 //      record, step the dynamics, auto-reset, next observation -> LDS | barrier
 // Plain form: per step a policy kernel, a sample kernel and a step kernel
 // with HBM round trips for the intermediates (the comparison baseline).
+#include <cstddef>
+#include <type_traits>
+
 #include "device.h"
 #include "envs.h"
 #include "kernels.h"
@@ -120,7 +123,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // row, leaving NW partial sums per row (no extra barrier). HS = 1 (split-M):
 // after a barrier, wave w computes head row tiles w, w + NW, ... over the whole
 // K (one result per row; for wide heads whose partials would not fit in LDS).
-template <int DT, int H, int NW, int NT, int KIN, int NHP, int HS, bool PIPE>
+template <int DT, int H, int NW, int NT, int KIN, int NHP, int HS, int OCC>
 struct Mlp {
     using M = Mma<DT>;
     using Frag = typename M::frag;
@@ -149,8 +152,14 @@ struct Mlp {
     static_assert(FPW % 16 == 0 && FPW % K == 0 && KIN % K == 0 && H % K == 0, "tile shape");
     static_assert(BYTES <= 160 * 1024, "LDS budget");
 
-    // software pipelining of the dense layers (see dense_tanh)
-    static constexpr bool PIPE_ON = PIPE && MT * K2S * (int)sizeof(Frag) / 4 <= 64;
+    static constexpr int DTYPE = DT;
+    // software pipelining of the dense layers (see dense_tanh): with at most
+    // two waves per SIMD and at most 64 registers of layer-2 weights per lane,
+    // or with one wave per SIMD and at most four output tiles per wave
+    static constexpr int WPS = (NW / 4 > OCC ? NW / 4 : OCC);   // waves per SIMD
+    static constexpr int W2_REGS = MT * K2S * (int)sizeof(Frag) / 4;
+    static constexpr bool PIPE_ON =
+        (WPS <= 2 && W2_REGS <= 64) || (WPS == 1 && MT <= 4);
 
     Frag w1[MT][K1S];
     Frag w2[MT][K2S];
@@ -561,35 +570,59 @@ __device__ __forceinline__ int env_slot(const EnvArgs& env, const Tile& tl, int 
 // The launch covers the tiles of one or more segments (roll-out requests that
 // share the policy): tile b of the launch belongs to the segment whose
 // tile_begin is the largest one <= b.
-__device__ __forceinline__ Segment segment_of(const Batch& b, int tile) {
-    if (!b.table) return b.one;
+// Index of the segment that tile `tile` of the launch belongs to.
+__device__ __forceinline__ int segment_index(const Batch& b, int tile) {
+    if (!b.table) {
+        int i = 0;
+        while (i + 1 < b.n_segs && b.inl[i + 1].tile_begin <= tile) ++i;
+        return i;
+    }
     int lo = 0, hi = b.n_segs - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (b.table[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
     }
-    return b.table[lo];
+    return lo;
 }
 
-template <class E, int DT, int H, int NW, int NT, int HS, int OCC>
-__global__ void __attribute__((amdgpu_flat_work_group_size(NW * 64, NW * 64),
-                               amdgpu_waves_per_eu(OCC)))
-k_fused(Batch batch, PolicyArgs pol) {
+// Copy segment i into LDS (`dst`), one dword per thread. The inline segments
+// are read through the kernel-argument segment pointer (the Batch is the
+// kernel's only argument, at offset 0): indexing the argument itself would
+// make the compiler copy all of it to scratch. The caller synchronises.
+__device__ __forceinline__ void stage_segment(const Batch& b, int i, Segment* dst, int tid,
+                                              int nthreads) {
+    typedef const __attribute__((address_space(4))) uint32_t KArgWord;
+    constexpr int NW32 = (int)(sizeof(Segment) / 4);
+    static_assert(sizeof(Segment) % 4 == 0, "segment of whole dwords");
+    uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+    if (b.table) {
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(b.table + i);
+        for (int k = tid; k < NW32; k += nthreads) d[k] = src[k];
+    } else {
+        KArgWord* src = (KArgWord*)((const __attribute__((address_space(4))) char*)
+                                        __builtin_amdgcn_kernarg_segment_ptr() +
+                                    offsetof(Batch, inl) + (size_t)i * sizeof(Segment));
+        for (int k = tid; k < NW32; k += nthreads) d[k] = src[k];
+    }
+}
+
+// One tile of a fused launch: rows [row0, row1) of segment `sg` for its
+// steps (plus the value pass), with the policy already in the registers of
+// `mlp` and its per-feature table in LDS.
+template <class E, class L, int NW>
+__device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, char* smem,
+                                           char* extra, const float*& staged, int tid, int wave,
+                                           int lane) {
     using HO = HeadOf<E>;
-    using L = Mlp<DT, H, NW, NT, kin_of<E, DT>(), HO::NHP, HS, (OCC <= 2)>;
+    constexpr int DT = L::DTYPE;
     constexpr int R = L::R;
     constexpr int NTHR = NW * 64;
     constexpr int G = lanes_per_row(R, NTHR, E::LANES);   // lanes serving one row in phase D
     using B = Block<E, G>;
     constexpr int C = B::C;
     static_assert(R * G <= NTHR, "G lanes per tile row");
-    __shared__ __attribute__((aligned(16))) char smem[L::BYTES + extra_lds_bytes<E>(R)];
-    char* extra = smem + L::BYTES;
-
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int rr = tid / G, sub = tid % G;   // tile row and lane within its group
-    L mlp;
-    mlp.load(pol, smem, wave, lane, tid);
+    const PolicyArgs& pol = sg.pol;
     const float inv_q0 = DT == DT_FP8 ? 1.0f / pol.act_scale[0] : 1.0f;
     const float log_std = (E::NACT == 0 && pol.log_std) ? pol.log_std[0] : 0.0f;
     const int j0 = B::first(sub);
@@ -597,122 +630,160 @@ k_fused(Batch batch, PolicyArgs pol) {
 #pragma unroll
     for (int c = 0; c < C; ++c) b3b[c] = j0 + c < HO::NOUT ? pol.b3[j0 + c] : 0.0f;
     const float b3v = pol.b3[HO::NOUT];
-
     EnvCtx ctx{reinterpret_cast<const float*>(extra)};
+    int* sums = reinterpret_cast<int*>(extra);   // market: [2][R][2]
+    const EnvArgs& env = sg.env;
+    const TrajArgs& tr = sg.tr;
+    const int horizon = sg.steps;
+    const RngKey key{env.k0, env.k1, env.epoch};
+    const uint32_t t0 = step_base(env);
+    if constexpr (E::KIND == Reaction::KIND) {
+        if (env.params != staged) {   // uniform over the workgroup
+            stage_params(reinterpret_cast<float*>(extra), env.params, tid, NTHR);
+            staged = env.params;
+            __syncthreads();
+        }
+    }
+    const Tile tl = tile_of(env, tile - sg.tile_begin);
+    const int row = tl.row0 + rr;
+    const bool mine = rr < R;
+    const bool valid = mine && row < tl.row1;
+    const bool lead = valid && sub == 0;   // writes the row's scalar records
+    float s[E::SD];
+#pragma unroll
+    for (int i = 0; i < E::SD; ++i) s[i] = 0.0f;
+    if (valid) load_state<E>(env, row, s);
+    int slot = 0;
+    if constexpr (E::KIND == Market::KIND) {
+        if (valid) slot = env_slot(env, tl, row);
+        for (int i = tid; i < 4 * R; i += NTHR) sums[i] = 0;
+    }
+    if (mine) {
+        float o[E::OD];
+        E::observe(s, o);
+        L::template put_obs<E::OD, G>(smem, rr, o, inv_q0, sub);
+        if (valid && horizon > 0) store_obs<E::OD, G>(tr.obs + (size_t)row * E::OD, o, sub);
+    }
+    __syncthreads();
+
+    const int passes = horizon + (sg.last ? 1 : 0);   // the extra pass evaluates V(s_T)
+    for (int step = 0; step < passes; ++step) {
+        mlp.forward(smem, wave, lane);
+        __syncthreads();
+        const uint32_t t = t0 + (uint32_t)step;
+        const size_t idx = (size_t)step * env.n_rows + row;
+        Act<E> act{0, 0.0f};
+        if (valid) {
+            float hb[C], hv;
+            L::template head_block<HO::NH, C>(smem, b3b, b3v, rr, j0, hb, hv);
+            if (step == horizon) {
+                if (lead) tr.last_value[row] = hv;
+            } else {
+                float logp;
+                act = choose<E, G, C>(hb, sub, key, t, (uint32_t)row, log_std, logp);
+                if (lead) {
+                    tr.value[idx] = hv;
+                    tr.logp[idx] = logp;
+                    store_action<E>(tr, idx, act);
+                }
+                if constexpr (E::KIND == Market::KIND) {
+                    if (lead) {
+                        int dh, s18;
+                        Market::decide(act.index, dh, s18);
+                        int* sl = sums + ((step & 1) * R + slot) * 2;
+                        atomicAdd(sl, dh);
+                        atomicAdd(sl + 1, s18);
+                    }
+                }
+            }
+        }
+        if constexpr (E::KIND == Market::KIND) {
+            __syncthreads();
+            if (step < horizon) {
+                if (valid) {
+                    const int* sl = sums + ((step & 1) * R + slot) * 2;
+                    float reward;
+                    Market::settle(s, act.index, sl[0], sl[1], reward);
+                    if (lead) {
+                        tr.reward[idx] = reward;
+                        tr.done[idx] = 0;
+                    }
+                }
+                // the other parity's sums were last read in the previous step
+                for (int i = tid; i < 2 * R; i += NTHR) sums[((step + 1) & 1) * 2 * R + i] = 0;
+            }
+        } else {
+            if (valid && step < horizon) {
+                float reward;
+                bool done;
+                E::template step<G>(s, act.index, act.value, t, (uint32_t)row, key, ctx, sub,
+                                    reward, done);
+                if (done) E::reset(s, key, t + 1, (uint32_t)row, ctx);
+                if (lead) {
+                    tr.reward[idx] = reward;
+                    tr.done[idx] = done ? 1 : 0;
+                }
+            }
+        }
+        if (valid && step < horizon) {
+            float o[E::OD];
+            E::observe(s, o);
+            L::template put_obs<E::OD, G>(smem, rr, o, inv_q0, sub);
+            if (step + 1 < horizon)
+                store_obs<E::OD, G>(tr.obs + ((size_t)(step + 1) * env.n_rows + row) * E::OD, o,
+                                    sub);
+        }
+        __syncthreads();
+    }
+    if (valid) save_state<E, G>(env, row, s, sub);
+}
+
+// Persistent fused roll-out: each workgroup walks tiles of the launch's
+// segments; E2 (if not E) is a second environment kind whose tiles share the
+// policy shape. The weights are (re)loaded when a tile's policy differs from
+// the one in the registers.
+template <class E, class E2, int DT, int H, int NW, int NT, int HS, int OCC>
+__global__ void __attribute__((amdgpu_flat_work_group_size(NW * 64, NW * 64),
+                               amdgpu_waves_per_eu(OCC)))
+k_fused(Batch batch) {
+    using HO = HeadOf<E>;
+    static_assert(HeadOf<E2>::NHP == HO::NHP && kin_of<E2, DT>() == kin_of<E, DT>(),
+                  "kinds of one kernel share the policy shape");
+    using L = Mlp<DT, H, NW, NT, kin_of<E, DT>(), HO::NHP, HS, OCC>;
+    constexpr int R = L::R;
+    constexpr int NTHR = NW * 64;
+    constexpr int EXTRA = extra_lds_bytes<E>(R) > extra_lds_bytes<E2>(R) ? extra_lds_bytes<E>(R)
+                                                                         : extra_lds_bytes<E2>(R);
+    __shared__ __attribute__((aligned(16))) char smem[L::BYTES + EXTRA];
+    char* extra = smem + L::BYTES;
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    L mlp;
+    int loaded = -1;                 // segment whose policy is in the registers
     const float* staged = nullptr;   // reaction: potential block now in LDS
     // zero the input tile once: its padding columns stay zero
     for (int i = tid; i < R * L::P_IN / 4; i += NTHR)
         reinterpret_cast<uint32_t*>(smem + L::OFF_IN)[i] = 0u;
-    __syncthreads();
 
-    int* sums = reinterpret_cast<int*>(extra);   // market: [2][R][2]
-
+    __shared__ Segment seg;          // the current tile's segment
     for (int tile = blockIdx.x; tile < batch.n_tiles; tile += gridDim.x) {
-        const Segment sg = segment_of(batch, tile);
-        const EnvArgs& env = sg.env;
-        const TrajArgs& tr = sg.tr;
-        const int horizon = sg.steps;
-        const RngKey key{env.k0, env.k1, env.epoch};
-        const uint32_t t0 = step_base(env);
-        if constexpr (E::KIND == Reaction::KIND) {
-            if (env.params != staged) {   // uniform over the workgroup
-                stage_params(reinterpret_cast<float*>(extra), env.params, tid, NTHR);
-                staged = env.params;
-                __syncthreads();
-            }
-        }
-        const Tile tl = tile_of(env, tile - sg.tile_begin);
-        const int row = tl.row0 + rr;
-        const bool mine = rr < R;
-        const bool valid = mine && row < tl.row1;
-        const bool lead = valid && sub == 0;   // writes the row's scalar records
-        float s[E::SD];
-#pragma unroll
-        for (int i = 0; i < E::SD; ++i) s[i] = 0.0f;
-        if (valid) load_state<E>(env, row, s);
-        int slot = 0;
-        if constexpr (E::KIND == Market::KIND) {
-            if (valid) slot = env_slot(env, tl, row);
-            for (int i = tid; i < 4 * R; i += NTHR) sums[i] = 0;
-        }
-        if (mine) {
-            float o[E::OD];
-            E::observe(s, o);
-            L::template put_obs<E::OD, G>(smem, rr, o, inv_q0, sub);
-            if (valid && horizon > 0) store_obs<E::OD, G>(tr.obs + (size_t)row * E::OD, o, sub);
-        }
+        const int si = segment_index(batch, tile);   // uniform over the workgroup
+        __syncthreads();   // the previous tile's last reads of `seg` and the table are done
+        stage_segment(batch, si, &seg, tid, NTHR);
         __syncthreads();
-
-        const int passes = horizon + (sg.last ? 1 : 0);   // the extra pass evaluates V(s_T)
-        for (int step = 0; step < passes; ++step) {
-            mlp.forward(smem, wave, lane);
-            __syncthreads();
-            const uint32_t t = t0 + (uint32_t)step;
-            const size_t idx = (size_t)step * env.n_rows + row;
-            Act<E> act{0, 0.0f};
-            if (valid) {
-                float hb[C], hv;
-                L::template head_block<HO::NH, C>(smem, b3b, b3v, rr, j0, hb, hv);
-                if (step == horizon) {
-                    if (lead) tr.last_value[row] = hv;
-                } else {
-                    float logp;
-                    act = choose<E, G, C>(hb, sub, key, t, (uint32_t)row, log_std, logp);
-                    if (lead) {
-                        tr.value[idx] = hv;
-                        tr.logp[idx] = logp;
-                        store_action<E>(tr, idx, act);
-                    }
-                    if constexpr (E::KIND == Market::KIND) {
-                        if (lead) {
-                            int dh, s18;
-                            Market::decide(act.index, dh, s18);
-                            int* sl = sums + ((step & 1) * R + slot) * 2;
-                            atomicAdd(sl, dh);
-                            atomicAdd(sl + 1, s18);
-                        }
-                    }
-                }
-            }
-            if constexpr (E::KIND == Market::KIND) {
-                __syncthreads();
-                if (step < horizon) {
-                    if (valid) {
-                        const int* sl = sums + ((step & 1) * R + slot) * 2;
-                        float reward;
-                        Market::settle(s, act.index, sl[0], sl[1], reward);
-                        if (lead) {
-                            tr.reward[idx] = reward;
-                            tr.done[idx] = 0;
-                        }
-                    }
-                    // the other parity's sums were last read in the previous step
-                    for (int i = tid; i < 2 * R; i += NTHR) sums[((step + 1) & 1) * 2 * R + i] = 0;
-                }
-            } else {
-                if (valid && step < horizon) {
-                    float reward;
-                    bool done;
-                    E::template step<G>(s, act.index, act.value, t, (uint32_t)row, key, ctx, sub,
-                                        reward, done);
-                    if (done) E::reset(s, key, t + 1, (uint32_t)row, ctx);
-                    if (lead) {
-                        tr.reward[idx] = reward;
-                        tr.done[idx] = done ? 1 : 0;
-                    }
-                }
-            }
-            if (valid && step < horizon) {
-                float o[E::OD];
-                E::observe(s, o);
-                L::template put_obs<E::OD, G>(smem, rr, o, inv_q0, sub);
-                if (step + 1 < horizon)
-                    store_obs<E::OD, G>(tr.obs + ((size_t)(step + 1) * env.n_rows + row) * E::OD, o,
-                                        sub);
-            }
+        const Segment& sg = seg;
+        if (si != loaded) {
+            mlp.load(sg.pol, smem, wave, lane, tid);
+            loaded = si;
             __syncthreads();
         }
-        if (valid) save_state<E, G>(env, row, s, sub);
+        if constexpr (!std::is_same<E, E2>::value) {
+            if (sg.env.kind == E2::KIND) {
+                fused_tile<E2, L, NW>(sg, tile, mlp, smem, extra, staged, tid, wave, lane);
+                continue;
+            }
+        }
+        fused_tile<E, L, NW>(sg, tile, mlp, smem, extra, staged, tid, wave, lane);
     }
 }
 
@@ -738,7 +809,7 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(NW * 64, NW * 64),
                                amdgpu_waves_per_eu(OCC)))
 k_plain_policy(EnvArgs env, PolicyArgs pol) {
     using HO = HeadOf<E>;
-    using L = Mlp<DT, H, NW, NT, kin_of<E, DT>(), HO::NHP, HS, (OCC <= 2)>;
+    using L = Mlp<DT, H, NW, NT, kin_of<E, DT>(), HO::NHP, HS, OCC>;
     constexpr int R = L::R;
     __shared__ __attribute__((aligned(16))) char smem[L::BYTES];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -976,13 +1047,29 @@ const void* step_entry() {
 
 #define WSX_G(E, NW, NT) lanes_per_row(16 * (NT), 64 * (NW), E::LANES)
 #define WSX_ENTRY(E, DT, H, NW, NT, HS, OCC)                                          \
-    {{E::KIND, DT, H, NW, 16 * NT, OCC},                                              \
-     reinterpret_cast<const void*>(&k_fused<E, DT, H, NW, NT, HS, OCC>),              \
+    {{E::KIND, DT, H, NW, 16 * NT, OCC, 0},                                           \
+     reinterpret_cast<const void*>(&k_fused<E, E, DT, H, NW, NT, HS, OCC>),           \
      reinterpret_cast<const void*>(&k_plain_policy<E, DT, H, NW, NT, HS, OCC>),       \
      reinterpret_cast<const void*>(&k_plain_sample<E, WSX_G(E, NW, NT)>),             \
      step_entry<E, WSX_G(E, NW, NT)>(), WSX_G(E, NW, NT)},
 
-static const VariantEntry kVariants[] = {WSX_VARIANTS(WSX_ENTRY)};
+// Fused kernels over tiles of two kinds with the same policy shape (one
+// launch for a Pendulum set and an Acrobot set).
+#define WSX_PAIR_VARIANTS(X)                                 \
+    X(Pendulum, Acrobot, DT_BF16, 256, 4, 2, 0, 2)          \
+    X(Pendulum, Acrobot, DT_BF16, 256, 4, 3, 0, 2)          \
+    X(Pendulum, Acrobot, DT_BF16, 256, 4, 5, 0, 1)          \
+    X(Pendulum, Acrobot, DT_BF16, 256, 8, 3, 0, 2)          \
+    X(Pendulum, Acrobot, DT_BF16, 256, 8, 4, 0, 2)          \
+    X(Pendulum, Acrobot, DT_BF16, 256, 8, 5, 0, 2)
+
+#define WSX_PAIR_ENTRY(E, E2, DT, H, NW, NT, HS, OCC)                                 \
+    {{E::KIND, DT, H, NW, 16 * NT, OCC, E2::KIND},                                    \
+     reinterpret_cast<const void*>(&k_fused<E, E2, DT, H, NW, NT, HS, OCC>), nullptr,  \
+     nullptr, nullptr, 0},
+
+static const VariantEntry kVariants[] = {WSX_VARIANTS(WSX_ENTRY)
+                                             WSX_PAIR_VARIANTS(WSX_PAIR_ENTRY)};
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 int n_variants() { return kNumVariants; }
@@ -992,7 +1079,7 @@ static const VariantEntry* find_entry(const Variant& v) {
     for (int i = 0; i < kNumVariants; ++i) {
         const Variant& w = kVariants[i].v;
         if (w.kind == v.kind && w.dtype == v.dtype && w.hidden == v.hidden && w.waves == v.waves &&
-            w.tile_rows == v.tile_rows && w.occupancy == v.occupancy)
+            w.tile_rows == v.tile_rows && w.occupancy == v.occupancy && w.kind2 == v.kind2)
             return &kVariants[i];
     }
     return nullptr;
@@ -1007,11 +1094,10 @@ int fused_blocks_per_cu(const Variant& v) {
     return n > 0 ? n : 1;
 }
 
-hipError_t launch_fused(const Variant& v, const Batch& batch, const PolicyArgs& pol, int grid,
-                        hipStream_t s) {
+hipError_t launch_fused(const Variant& v, const Batch& batch, int grid, hipStream_t s) {
     const VariantEntry* e = find_entry(v);
     if (!e) return hipErrorInvalidValue;
-    void* args[] = {(void*)&batch, (void*)&pol};
+    void* args[] = {(void*)&batch};
     return hipLaunchKernel(e->fused, dim3(grid), dim3(v.waves * 64), args, 0, s);
 }
 

@@ -340,6 +340,7 @@ bool launch_rounds(wsx_server* S) {
             sg.tr.value = r->traj.value + base;
             sg.tr.logp = r->traj.logp + base;
             sg.tr.last_value = r->traj.last_value;
+            sg.pol = policy_args(&r->policy);
             sg.steps = steps;
             sg.tile_begin = tiles;
             sg.last = r->issued + steps == r->req.horizon ? 1 : 0;   // V(s_T) once, at the end
@@ -357,7 +358,7 @@ bool launch_rounds(wsx_server* S) {
         b.n_tiles = tiles;
         const wsx_env* env0 = S->sessions[batch[0]->session].env;
         const int grid = std::max(1, std::min(tiles, env0->cus * fused_blocks_per_cu(v)));
-        if (e == hipSuccess) e = launch_fused(v, b, policy_args(&g.policy), grid, g.stream);
+        if (e == hipSuccess) e = launch_fused(v, b, grid, g.stream);
         if (e == hipSuccess) e = hipEventRecord(g.ev, g.stream);
         g.inflight = true;
         if (e != hipSuccess) {

@@ -153,7 +153,8 @@ int wsx_autotune(const wsx_env_desc* d, const wsx_policy* policy, int32_t horizo
             max_agents = std::max<int>(max_agents, d->agent_offsets[i + 1] - d->agent_offsets[i]);
     for (int i = 0; i < n_variants(); ++i) {
         const Variant& v = variant(i);
-        if (v.kind != d->kind || v.dtype != k.dtype || v.hidden != k.hidden) continue;
+        if (v.kind != d->kind || v.kind2 != 0 || v.dtype != k.dtype || v.hidden != k.hidden)
+            continue;
         if (market && v.tile_rows < max_agents) continue;
         add(v.tile_rows, v);
         if (!market)
@@ -235,6 +236,175 @@ int wsx_autotune(const wsx_env_desc* d, const wsx_policy* policy, int32_t horizo
     {
         std::lock_guard<std::mutex> lk(g_mu);
         put(g_table, Row{Key{d->kind, d->n_envs, n_rows, cus}, win});
+    }
+    if (best) *best = win;
+    return WSX_OK;
+}
+
+int wsx_autotune_batch_workspace_bytes(const wsx_env_desc* const* descs, int32_t n,
+                                       int32_t horizon, size_t* bytes) {
+    if (!descs || !bytes) return fail(WSX_EINVAL, "descs and bytes must not be NULL");
+    if (n < 1 || n > kInlineSegments)
+        return fail(WSX_EINVAL, "a batch holds 1 to %d environment sets", kInlineSegments);
+    size_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        size_t b = 0;
+        if (!descs[i]) return fail(WSX_EINVAL, "descs[%d] is NULL", i);
+        const int rc = wsx_autotune_workspace_bytes(descs[i], horizon, &b);
+        if (rc) return rc;
+        total += align256(b);
+    }
+    *bytes = total;
+    return WSX_OK;
+}
+
+int wsx_autotune_batch(const wsx_env_desc* const* descs, const wsx_policy* const* policies,
+                       int32_t n, int32_t horizon, int32_t reps, void* workspace,
+                       size_t workspace_bytes, wsx_tune_entry* best, void* stream) {
+    size_t need = 0;
+    int rc = wsx_autotune_batch_workspace_bytes(descs, n, horizon, &need);
+    if (rc) return rc;
+    if (!policies) return fail(WSX_EINVAL, "policies is NULL");
+    if (reps < 1) return fail(WSX_EINVAL, "reps must be >= 1");
+    if (!workspace || workspace_bytes < need)
+        return fail(WSX_EINVAL, "workspace of %zu bytes is smaller than the %zu needed",
+                    workspace_bytes, need);
+    int kinds[2] = {0, 0}, n_kinds = 0;
+    int64_t total_rows = 0;
+    for (int i = 0; i < n; ++i) {
+        KindInfo k;
+        kind_info(descs[i]->kind, k);
+        if (!policies[i] || policies[i]->dtype != k.dtype || policies[i]->h1 != k.hidden)
+            return fail(WSX_EUNSUPPORTED, "no compiled kernel for policies[%d]", i);
+        const int kd = descs[i]->kind;
+        if (!(n_kinds > 0 && kinds[0] == kd) && !(n_kinds > 1 && kinds[1] == kd)) {
+            if (n_kinds == 2) return fail(WSX_EUNSUPPORTED, "a batch mixes at most two kinds");
+            kinds[n_kinds++] = kd;
+        }
+        total_rows += rows_of(descs[i]);
+    }
+    KindInfo k0;
+    kind_info(kinds[0], k0);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "wsx_autotune_batch");
+
+    // per set: its state block and trajectory inside the workspace
+    std::vector<char*> base(n);
+    std::vector<wsx_traj> trs(n);
+    char* at = static_cast<char*>(workspace);
+    for (int i = 0; i < n; ++i) {
+        KindInfo k;
+        kind_info(descs[i]->kind, k);
+        const Trial T = trial_layout(k, descs[i]->kind, descs[i]->n_envs, rows_of(descs[i]), horizon);
+        base[i] = at;
+        wsx_traj& tr = trs[i];
+        tr = wsx_traj{};
+        tr.capacity = horizon;
+        tr.obs = reinterpret_cast<float*>(at + T.off[0]);
+        tr.action = at + T.off[1];
+        tr.reward = reinterpret_cast<float*>(at + T.off[2]);
+        tr.done = reinterpret_cast<uint8_t*>(at + T.off[3]);
+        tr.value = reinterpret_cast<float*>(at + T.off[4]);
+        tr.logp = reinterpret_cast<float*>(at + T.off[5]);
+        tr.last_value = reinterpret_cast<float*>(at + T.off[6]);
+        at += align256(T.total);
+    }
+
+    // candidate shapes: the fused kernels that run this mix, at full row
+    // capacity and at the tile heights that spread all rows evenly over the CUs
+    struct Cand {
+        int tile_rows, waves, occupancy;
+    };
+    std::vector<Cand> cands;
+    for (int i = 0; i < n_variants(); ++i) {
+        const Variant& v = variant(i);
+        const bool kinds_ok = n_kinds == 1 ? (v.kind == kinds[0] && v.kind2 == 0)
+                                           : ((v.kind == kinds[0] && v.kind2 == kinds[1]) ||
+                                              (v.kind == kinds[1] && v.kind2 == kinds[0]));
+        if (!kinds_ok || v.dtype != k0.dtype || v.hidden != k0.hidden) continue;
+        std::vector<int> heights = {v.tile_rows};
+        if (kinds[0] != WSX_MARKET)
+            for (int per = 1; per <= 8; ++per)
+                heights.push_back((int)((total_rows + (int64_t)per * cus - 1) / ((int64_t)per * cus)));
+        for (int t : heights) {
+            Variant w;
+            const bool runs_here =
+                t >= 1 && t <= v.tile_rows &&
+                (n_kinds == 1 ? find_variant(kinds[0], k0.dtype, k0.hidden, v.waves, t, v.occupancy, w)
+                              : find_pair_variant(kinds[0], kinds[1], k0.dtype, k0.hidden, v.waves,
+                                                  t, v.occupancy, w)) &&
+                w.tile_rows == v.tile_rows;
+            // every set must also have a single-kind kernel of this shape (env_create)
+            for (int j = 0; runs_here && j < n_kinds; ++j) {
+                Variant u;
+                if (!find_variant(kinds[j], k0.dtype, k0.hidden, v.waves, t, v.occupancy, u) ||
+                    u.waves != v.waves || u.occupancy != v.occupancy)
+                    t = 0;
+            }
+            bool dup = false;
+            for (const Cand& c : cands)
+                dup = dup || (c.tile_rows == t && c.waves == v.waves && c.occupancy == v.occupancy);
+            if (runs_here && t > 0 && !dup) cands.push_back({t, v.waves, v.occupancy});
+        }
+    }
+    if (cands.empty()) return fail(WSX_EUNSUPPORTED, "no fused kernel runs this mix of kinds");
+
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    e = hipEventCreate(&ev0);
+    if (e == hipSuccess) e = hipEventCreate(&ev1);
+    if (e != hipSuccess) return hip_fail(e, "wsx_autotune_batch (events)");
+    wsx_tune_entry win{};
+    double win_ms = 0.0;
+    std::vector<wsx_env*> envs(n, nullptr);
+    std::vector<const wsx_traj*> tp(n);
+    for (int i = 0; i < n; ++i) tp[i] = &trs[i];
+    for (const Cand& c : cands) {
+        for (int i = 0; i < n && !rc; ++i) {
+            wsx_env_desc dd = *descs[i];
+            dd.state = base[i];
+            dd.tile_rows = c.tile_rows;
+            dd.waves = c.waves;
+            dd.occupancy = c.occupancy;
+            rc = wsx_env_create(&dd, &envs[i]);
+            if (!rc) rc = wsx_env_reset(envs[i], 0, stream);
+        }
+        if (!rc) rc = wsx_rollout_batch(envs.data(), policies, tp.data(), n, horizon, stream);
+        std::vector<float> t;
+        for (int r = 0; !rc && r < reps; ++r) {
+            hipError_t he = hipEventRecord(ev0, s);
+            if (he == hipSuccess &&
+                (rc = wsx_rollout_batch(envs.data(), policies, tp.data(), n, horizon, stream)) == 0)
+                he = hipEventRecord(ev1, s);
+            if (he == hipSuccess && !rc) he = hipEventSynchronize(ev1);
+            float m = 0.0f;
+            if (he == hipSuccess && !rc) he = hipEventElapsedTime(&m, ev0, ev1);
+            if (he != hipSuccess && !rc) rc = hip_fail(he, "wsx_autotune_batch (timing)");
+            t.push_back(m);
+        }
+        for (int i = 0; i < n; ++i)
+            if (envs[i]) {
+                wsx_env_destroy(envs[i]);
+                envs[i] = nullptr;
+            }
+        if (rc) break;
+        std::sort(t.begin(), t.end());
+        const double ms = t[t.size() / 2];
+        if (win_ms == 0.0 || ms < win_ms) {
+            win_ms = ms;
+            win = {c.tile_rows, c.waves, c.occupancy, 0, 0.0};
+        }
+    }
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    if (rc) return rc;
+    win.us_per_step = win_ms * 1000.0 / horizon;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (int i = 0; i < n; ++i)
+            put(g_table, Row{Key{descs[i]->kind, descs[i]->n_envs, rows_of(descs[i]), cus}, win});
     }
     if (best) *best = win;
     return WSX_OK;

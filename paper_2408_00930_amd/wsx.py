@@ -54,6 +54,7 @@ class _EnvDesc(C.Structure):
 
 
 EXPORTS = ["wsx_env_state_bytes", "wsx_env_create", "wsx_env_reset", "wsx_rollout",
+           "wsx_rollout_batch",
            "wsx_env_info", "wsx_env_set_step", "wsx_env_set_chunk", "wsx_env_destroy",
            "wsx_compute_returns",
            "wsx_policy_forward", "wsx_quantize", "wsx_last_error"]
@@ -211,6 +212,20 @@ def env_reset(env, epoch=0, stream=None):
 def rollout(env, policy, horizon, traj, mode=MODE_FUSED, stream=None):
     _check(lib().wsx_rollout(env.handle, C.byref(policy.c), horizon, C.byref(traj.c), mode,
                              _stream(stream)))
+
+
+def rollout_batch(envs, policies, horizon, trajs, stream=None):
+    """Roll several environment sets out in one fused launch."""
+    n = len(envs)
+    L = lib()
+    if not getattr(L, "_batch_sigs", False):
+        L.wsx_rollout_batch.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                        C.c_int32, C.c_void_p]
+        L._batch_sigs = True
+    e = (C.c_void_p * n)(*[x.handle.value for x in envs])
+    p = (C.POINTER(_Policy) * n)(*[C.pointer(x.c) for x in policies])
+    t = (C.POINTER(_Traj) * n)(*[C.pointer(x.c) for x in trajs])
+    _check(L.wsx_rollout_batch(e, p, t, n, horizon, _stream(stream)))
 
 
 def compute_returns(traj, horizon, gamma, lam, bootstrap=True, out_dtype=torch.float64,
@@ -386,7 +401,8 @@ class _TuneEntry(C.Structure):
 
 
 EXPORTS += ["wsx_autotune_workspace_bytes", "wsx_autotune", "wsx_tune_lookup", "wsx_tune_save",
-            "wsx_tune_load", "wsx_env_shape"]
+            "wsx_tune_load", "wsx_env_shape", "wsx_autotune_batch_workspace_bytes",
+            "wsx_autotune_batch"]
 
 
 def _tune_sigs(L):
@@ -402,6 +418,10 @@ def _tune_sigs(L):
     L.wsx_tune_save.argtypes = [C.c_char_p]
     L.wsx_tune_load.argtypes = [C.c_char_p]
     L.wsx_env_shape.argtypes = [vp] + [C.POINTER(C.c_int32)] * 4
+    L.wsx_autotune_batch_workspace_bytes.argtypes = [vp, C.c_int32, C.c_int32,
+                                                     C.POINTER(C.c_size_t)]
+    L.wsx_autotune_batch.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, C.c_size_t,
+                                     C.POINTER(_TuneEntry), vp]
     L._tune_sigs = True
 
 
@@ -428,6 +448,33 @@ def autotune(kind, n_envs, policy, horizon, reps=3, seed=0, agent_offsets=None, 
     out = _TuneEntry()
     _check(L.wsx_autotune(C.byref(desc), C.byref(policy.c), horizon, reps, ws.data_ptr(),
                           need.value, C.byref(out), _stream(stream)))
+    return _entry(out)
+
+
+def autotune_batch(sets, horizon, reps=3, stream=None):
+    """The autotuner for sets rolled out together by rollout_batch. `sets` is a
+    list of dicts (kind, n_envs, policy, seed, agent_offsets, params)."""
+    L = lib()
+    _tune_sigs(L)
+    keep, descs = [], []
+    for d in sets:
+        offs = d.get("agent_offsets")
+        offs = None if offs is None else np.ascontiguousarray(offs, np.int32)
+        par = d.get("params")
+        par = None if par is None else torch.from_numpy(np.ascontiguousarray(par, np.float32)).cuda()
+        keep += [offs, par]
+        descs.append(_EnvDesc(d["kind"], 0, 0, 0, d["n_envs"], d.get("seed", 0), None,
+                              None if offs is None else offs.ctypes.data,
+                              None if par is None else par.data_ptr()))
+    n = len(descs)
+    dp = (C.POINTER(_EnvDesc) * n)(*[C.pointer(x) for x in descs])
+    pp = (C.POINTER(_Policy) * n)(*[C.pointer(d["policy"].c) for d in sets])
+    need = C.c_size_t()
+    _check(L.wsx_autotune_batch_workspace_bytes(dp, n, horizon, C.byref(need)))
+    ws = torch.empty(need.value, dtype=torch.uint8, device="cuda")
+    out = _TuneEntry()
+    _check(L.wsx_autotune_batch(dp, pp, n, horizon, reps, ws.data_ptr(), need.value,
+                                C.byref(out), _stream(stream)))
     return _entry(out)
 
 

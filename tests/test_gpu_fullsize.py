@@ -1,0 +1,98 @@
+"""Parity at the benchmark's full size and launch configuration: 10,000
+Pendulum + 10,000 Acrobot replicas, horizon 200, both sets in one fused
+launch with the autotuner's kernel shape, exactly as bench.py times them.
+
+The oracle cannot replay 4e6 env-steps in FP64 within a test, so it checks
+sampled steps for every row: the state at step t is recovered from the
+recorded observation (angles from their cosine and sine, rates as recorded),
+the oracle evaluates the policy there (value, Gaussian action from the same
+Philox draw, log-probability) and steps its dynamics with the GPU's action;
+the next recorded observation, the reward and the done flag must agree.
+Returns/GAE of the whole launch are checked on sampled rows."""
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_cases import DTYPE, HIDDEN, say
+from paper_2408_00930_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+N, T, EPOCH = 10000, 200, 7
+STEPS = (0, 1, 57, 133, 198)
+HEAD_HARD, HEAD_SOFT, HEAD_FRAC = 2e-2, 2e-3, 0.03    # BF16 policy (see test_gpu_parity)
+DYN = {O.PENDULUM: 2e-5, O.ACROBOT: 1e-4}
+
+
+def _state_from_obs(kind, o):
+    if kind == O.PENDULUM:
+        return np.stack([np.arctan2(o[:, 1], o[:, 0]), o[:, 2]], axis=1)
+    return np.stack([np.arctan2(o[:, 1], o[:, 0]), np.arctan2(o[:, 3], o[:, 2]), o[:, 4],
+                     o[:, 5]], axis=1)
+
+
+def test_bench_configuration_matches_oracle_on_sampled_steps():
+    import torch
+    from paper_2408_00930_amd import wsx
+    kinds = (O.PENDULUM, O.ACROBOT)
+    pols = {k: inputs.policy_for(k, DTYPE[k], HIDDEN[k], seed=0) for k in kinds}
+    dps = {k: wsx.DevicePolicy(pols[k]) for k in kinds}
+    say("full size: autotune", N, T)
+    best = wsx.autotune_batch([dict(kind=k, n_envs=N, policy=dps[k], seed=0) for k in kinds], T,
+                              reps=1)
+    envs = [wsx.Env(k, N, seed=0) for k in kinds]
+    print("shape", best, [wsx.env_shape(e) for e in envs], flush=True)
+    trs = [wsx.Trajectory(k, T, N) for k in kinds]
+    for e in envs:
+        wsx.env_reset(e, EPOCH)
+    say("full size: batched roll-out")
+    wsx.rollout_batch(envs, [dps[k] for k in kinds], T, trs)
+    rets = []
+    for tr in trs:
+        rets.append(wsx.compute_returns(tr, T, inputs.GAMMA, inputs.LAMBDA, True, torch.float64))
+    torch.cuda.synchronize()
+    for k, tr, (ret, adv) in zip(kinds, trs, rets):
+        g = tr.host()
+        assert np.isfinite(g["obs"]).all() and np.isfinite(g["value"]).all()
+        hold = O.env_hold(k, N)
+        mlp = O.mlp_hold(pols[k])
+        log_std = pols[k].exact("log_std")
+        flips = 0
+        for t in STEPS:
+            say("full size: oracle", k, "step", t)
+            obs = g["obs"][t].astype(np.float64)
+            st = _state_from_obs(k, obs)
+            ref = O.rollout(hold, mlp, 0, EPOCH, t, 1, st, log_std, margins=True)
+            assert np.allclose(ref["obs"][0], obs, rtol=0, atol=2e-6)
+            verr = np.abs(g["value"][t] - ref["value"][0])
+            aerr = np.abs(g["action"][t].astype(np.float64) - ref["action"][0])
+            print(f"  kind {k} t {t}: value err max {verr.max():.3g} p99 "
+                  f"{np.quantile(verr, 0.99):.3g}; action err max {aerr.max():.3g}", flush=True)
+            assert verr.max() <= HEAD_HARD and (verr > HEAD_SOFT).mean() <= HEAD_FRAC
+            assert aerr.max() <= HEAD_HARD and (aerr > HEAD_SOFT).mean() <= HEAD_FRAC
+            assert np.abs(g["logp"][t] - ref["logp"][0]).max() <= 1e-4
+            if t + 1 >= T:
+                continue
+            nxt_obs = g["obs"][t + 1].astype(np.float64)
+            for r in range(N):
+                nxt, rew, done, dm = O.env_step_row(hold, st[r], float(g["action"][t, r]), 0,
+                                                    EPOCH, t, r)
+                if bool(g["done"][t, r]) != done:
+                    assert dm < 1e-5, (k, t, r)
+                    flips += 1
+                    continue
+                if done:
+                    nxt = O.reset_row(hold, 0, EPOCH, t + 1, r)
+                o_ref = O.observe(k, nxt)
+                assert np.all(np.abs(nxt_obs[r] - o_ref) <= DYN[k] * np.maximum(1.0, np.abs(o_ref))), (k, t, r)
+                assert abs(g["reward"][t, r] - rew) <= DYN[k] * max(1.0, abs(rew)), (k, t, r)
+        print(f"  kind {k}: {flips} termination flips within 1e-5 of the threshold", flush=True)
+        # returns / GAE of the launch on sampled rows
+        rows = np.random.default_rng(k).choice(N, 256, replace=False)
+        want_g, want_a = O.returns_gae(g["reward"][:, rows], g["value"][:, rows],
+                                       g["done"][:, rows], g["last_value"][rows], inputs.GAMMA,
+                                       inputs.LAMBDA)
+        got_g = ret.cpu().numpy()[:, rows]
+        got_a = adv.cpu().numpy()[:, rows]
+        assert np.allclose(got_g, want_g, rtol=1e-12, atol=1e-12)
+        assert np.allclose(got_a, want_a, rtol=1e-12, atol=1e-12)

@@ -45,3 +45,32 @@ def test_autotune_records_a_shape_that_env_create_uses(kind, n):
     b = _roll(wsx, explicit, dp, kind, 12)
     for k in a:
         assert np.array_equal(a[k], b[k]), k
+
+
+def test_autotune_batch_records_one_shape_for_the_mix():
+    wsx = _wsx()
+    say("autotune batch")
+    pols = {k: wsx.DevicePolicy(inputs.policy_for(k, DTYPE[k], HIDDEN[k], seed=k)) for k in (2, 3)}
+    spec = [dict(kind=2, n_envs=3001, policy=pols[2], seed=1),
+            dict(kind=3, n_envs=2999, policy=pols[3], seed=2)]
+    best = wsx.autotune_batch(spec, horizon=10, reps=1)
+    print(best, flush=True)
+    envs = [wsx.Env(d["kind"], d["n_envs"], seed=d["seed"]) for d in spec]
+    for e in envs:
+        assert wsx.env_shape(e)[:3] == (best["tile_rows"], best["waves"], best["occupancy"])
+    T = 10
+    trs = [wsx.Trajectory(e.kind, T, e.rows) for e in envs]
+    for e in envs:
+        wsx.env_reset(e, 2)
+    wsx.rollout_batch(envs, [pols[2], pols[3]], T, trs)
+    for e, tr, d in zip(envs, trs, spec):
+        ref = _roll(wsx, wsx.Env(d["kind"], d["n_envs"], seed=d["seed"]), pols[d["kind"]],
+                    d["kind"], T)
+        # _roll resets with epoch 1; redo ours with the same epoch for the comparison
+        wsx.env_reset(e, 1)
+        mine = wsx.Trajectory(e.kind, T, e.rows)
+        wsx.rollout(e, pols[d["kind"]], T, mine)
+        got = mine.host()
+        for k in got:
+            assert np.array_equal(got[k], ref[k]), k
+        assert np.isfinite(tr.host()["value"]).all()
