@@ -83,22 +83,29 @@ __device__ __forceinline__ void load_a(long& f, const void* W, int ld, int m, in
     __builtin_memcpy(&f, v, 8);
 }
 
-// Store four consecutive features of one row (quantised for the next layer).
-template <int DT>
-__device__ __forceinline__ void store4(char* p, float a, float b, float c, float d, float inv_s);
-
-template <>
-__device__ __forceinline__ void store4<DT_F32>(char* p, float a, float b, float c, float d, float) {
-    *reinterpret_cast<float4*>(p) = make_float4(a, b, c, d);
-}
-template <>
-__device__ __forceinline__ void store4<DT_BF16>(char* p, float a, float b, float c, float d, float) {
-    *reinterpret_cast<uint2*>(p) = make_uint2(pack_bf16x2(a, b), pack_bf16x2(c, d));
-}
-template <>
-__device__ __forceinline__ void store4<DT_FP8>(char* p, float a, float b, float c, float d,
-                                               float inv_s) {
-    *reinterpret_cast<uint32_t*>(p) = pack_fp8x4(a * inv_s, b * inv_s, c * inv_s, d * inv_s);
+// An A fragment of KC weights W[m][col(e)], e < KC, at arbitrary columns
+// (the split-K head takes its K elements in the order the layer-2 outputs
+// sit in the accumulators); zero outside rows [0, m_valid).
+template <class F, class Col>
+__device__ __forceinline__ void load_a_cols(F& f, const void* W, int ld, int m, int m_valid,
+                                            Col col) {
+    constexpr int KC = sizeof(F) == 4 ? 1 : 8;
+    if constexpr (sizeof(F) == 4) {
+        const float* w = static_cast<const float*>(W);
+        f = m < m_valid ? w[(size_t)m * ld + col(0)] : 0.0f;
+    } else if constexpr (sizeof(F) == 16) {
+        const uint16_t* w = static_cast<const uint16_t*>(W);
+        uint16_t v[KC];
+#pragma unroll
+        for (int e = 0; e < KC; ++e) v[e] = m < m_valid ? w[(size_t)m * ld + col(e)] : (uint16_t)0;
+        __builtin_memcpy(&f, v, 16);
+    } else {
+        const uint8_t* w = static_cast<const uint8_t*>(W);
+        uint8_t v[KC];
+#pragma unroll
+        for (int e = 0; e < KC; ++e) v[e] = m < m_valid ? w[(size_t)m * ld + col(e)] : (uint8_t)0;
+        __builtin_memcpy(&f, v, 8);
+    }
 }
 
 // Store one quantised element (observations).
@@ -140,10 +147,11 @@ struct Mlp {
     static constexpr int P_PART = NHP + 4;       // floats
     static constexpr int OFF_IN = 0;
     static constexpr int OFF_H1 = OFF_IN + R * P_IN;
-    static constexpr int OFF_H2 = OFF_H1 + R * P_H;
+    static constexpr int OFF_H2 = OFF_H1 + R * P_H;   // split-M only
     // split-M writes the head after a barrier that follows the last read of
-    // h1, so its results reuse the h1 tile
-    static constexpr int OFF_PART = HS ? OFF_H1 : OFF_H2 + R * P_H;
+    // h1, so its results reuse the h1 tile; split-K takes each wave's h2
+    // features from its registers (no h2 tile) and writes partials there
+    static constexpr int OFF_PART = HS ? OFF_H1 : OFF_H2;
     // per-feature accumulator start (bias / output scale) and tanh factor
     // (2 log2 e * output scale) of both hidden layers: [4][H] floats
     static constexpr int OFF_TAB = HS ? OFF_H2 + R * P_H : OFF_PART + NPART * R * P_PART * 4;
@@ -201,10 +209,20 @@ struct Mlp {
         for (int hw = 0; hw < NHW; ++hw) {
             const int ht = HS ? wave + hw * NW : hw;   // head row tile
             const int m = ht * 16 + lr;
-            const int kbase = HS ? 0 : wave * FPW;
 #pragma unroll
-            for (int ks = 0; ks < KHS; ++ks)
-                load_a(w3[hw][ks], p.w3, H, m, p.n_head, kbase + ks * K + kq, H);
+            for (int ks = 0; ks < KHS; ++ks) {
+                if constexpr (HS) {
+                    load_a(w3[hw][ks], p.w3, H, m, p.n_head, ks * K + kq, H);
+                } else {
+                    // K element e of lane group q is this wave's layer-2 output
+                    // (tile mt, accumulator row i): idx = ks KC + e, mt = idx / 4
+                    const int q = lane >> 4;
+                    load_a_cols(w3[hw][ks], p.w3, H, m, p.n_head, [&](int e) {
+                        const int idx = ks * KC + e;
+                        return wave * FPW + (idx >> 2) * 16 + 4 * q + (idx & 3);
+                    });
+                }
+            }
 #pragma unroll
             for (int i = 0; i < 4; ++i) o3[hw][i] = row_scale(p.s3, ht * 16 + 4 * (lane >> 4) + i, p.n_head) * a2;
         }
@@ -227,39 +245,81 @@ struct Mlp {
         }
     }
 
-    // tanh of row tile `nt`'s accumulators, quantised into `out` ([R][H]).
-    __device__ __forceinline__ static void tanh_rows(const f32x4 (&acc)[MT], const float4 (&kx)[MT],
-                                                     char* out, float q, int nt, int wave, int lane) {
+    // Layer outputs of one accumulator tile, quantised for the next product:
+    // four BF16 (uint2), four FP8 codes (uint32) or four floats.
+    typedef typename std::conditional<
+        DT == DT_BF16, uint2, typename std::conditional<DT == DT_FP8, uint32_t, float4>::type>::type
+        Packed;
+
+    __device__ __forceinline__ static Packed tanh_pack(const f32x4& a, const float4& k, float q) {
+        if constexpr (DT == DT_FP8) {
+            return pack_fp8x4(tanh_scaled_q(a[0], k.x, q), tanh_scaled_q(a[1], k.y, q),
+                              tanh_scaled_q(a[2], k.z, q), tanh_scaled_q(a[3], k.w, q));
+        } else if constexpr (DT == DT_BF16) {
+            return make_uint2(pack_bf16x2(tanh_scaled(a[0], k.x), tanh_scaled(a[1], k.y)),
+                              pack_bf16x2(tanh_scaled(a[2], k.z), tanh_scaled(a[3], k.w)));
+        } else {
+            return make_float4(tanh_scaled(a[0], k.x), tanh_scaled(a[1], k.y),
+                               tanh_scaled(a[2], k.z), tanh_scaled(a[3], k.w));
+        }
+    }
+
+    // B fragment of head K-step ks from this wave's packed layer-2 outputs of
+    // one row tile (the order load() gave the head weights).
+    __device__ __forceinline__ static Frag head_frag(const Packed (&pk)[MT], int ks) {
+        if constexpr (DT == DT_BF16) {
+            const uint4 u = make_uint4(pk[2 * ks].x, pk[2 * ks].y, pk[2 * ks + 1].x, pk[2 * ks + 1].y);
+            return __builtin_bit_cast(Frag, u);
+        } else if constexpr (DT == DT_FP8) {
+            return (long)((uint64_t)pk[2 * ks] | ((uint64_t)pk[2 * ks + 1] << 32));
+        } else {
+            const float4 v = pk[ks >> 2];
+            const int i = ks & 3;
+            return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+        }
+    }
+
+    // tanh of row tile `nt`'s accumulators: quantised into `out` ([R][H]) for
+    // the next layer (layer 1, split-M layer 2), or fed to the split-K head
+    // MFMAs of this row tile (HEAD: layer 2 of a split-K head).
+    template <bool HEAD>
+    __device__ __forceinline__ void tanh_rows(const f32x4 (&acc)[MT], const float4 (&kx)[MT],
+                                              char* out, float q, int nt, int wave, int lane,
+                                              f32x4 (&acc3)[NHW][NT]) {
         const int lr = lane & 15;
+        Packed pk[MT];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            const int feat = wave * FPW + mt * 16 + 4 * (lane >> 4);
-            const f32x4 a = acc[mt];
-            char* p = out + (nt * 16 + lr) * P_H + feat * EB;
-            if constexpr (DT == DT_FP8) {
-                *reinterpret_cast<uint32_t*>(p) = pack_fp8x4(
-                    tanh_scaled_q(a[0], kx[mt].x, q), tanh_scaled_q(a[1], kx[mt].y, q),
-                    tanh_scaled_q(a[2], kx[mt].z, q), tanh_scaled_q(a[3], kx[mt].w, q));
-            } else {
-                store4<DT>(p, tanh_scaled(a[0], kx[mt].x), tanh_scaled(a[1], kx[mt].y),
-                           tanh_scaled(a[2], kx[mt].z), tanh_scaled(a[3], kx[mt].w), 1.0f);
+        for (int mt = 0; mt < MT; ++mt) pk[mt] = tanh_pack(acc[mt], kx[mt], DT == DT_FP8 ? q : 1.0f);
+        if constexpr (HEAD) {
+#pragma unroll
+            for (int ks = 0; ks < KHS; ++ks) {
+                const Frag b = head_frag(pk, ks);
+#pragma unroll
+                for (int hw = 0; hw < NHW; ++hw) acc3[hw][nt] = M::mma(w3[hw][ks], b, acc3[hw][nt]);
+            }
+        } else {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const int feat = wave * FPW + mt * 16 + 4 * (lane >> 4);
+                *reinterpret_cast<Packed*>(out + (nt * 16 + lr) * P_H + feat * EB) = pk[mt];
             }
         }
     }
 
     // Dense layer of this wave's MT output tiles for all NT row tiles, then
-    // tanh and quantisation into `out`. With PIPE the loop is software-
-    // pipelined over row tiles: the MFMAs of row tile n + 1 are issued ahead
-    // of the tanh of row tile n, so the matrix core and the vector ALU of the
-    // SIMD work at the same time (this holds two tiles of accumulators and the
-    // next tile's operands in registers; without it -- kernels with four or
-    // more waves per SIMD, or whose layer-2 weights take more than 64
-    // registers per lane -- each row tile is multiplied, then activated).
-    // `tab` holds the layer's accumulator starts and tanh factors.
-    template <int KS>
+    // tanh and quantisation (into `out`, or into the split-K head's MFMAs
+    // with HEAD). With PIPE_ON the loop is software-pipelined over row tiles:
+    // the MFMAs of row tile n + 1 are issued ahead of the tanh of row tile n,
+    // so the matrix core and the vector ALU of the SIMD work at the same time
+    // (this holds two tiles of accumulators and the next tile's operands in
+    // registers; without it -- kernels with four or more waves per SIMD, or
+    // whose layer-2 weights take more than 64 registers per lane -- each row
+    // tile is multiplied, then activated). `tab` holds the layer's
+    // accumulator starts and tanh factors.
+    template <int KS, bool HEAD>
     __device__ __forceinline__ void dense_tanh(const Frag (&w)[MT][KS], const float* tab,
                                                const char* in, int p_in, char* out, float inv_q,
-                                               int wave, int lane) {
+                                               int wave, int lane, f32x4 (&acc3)[NHW][NT]) {
         float4 ini[MT], kx[MT];
         auto per_feature = [&]() {
 #pragma unroll
@@ -278,7 +338,7 @@ struct Mlp {
                 f32x4 acc[MT];
                 per_feature();   // re-read per row tile: fewer live registers
                 mma_rows<KS>(acc, w, ini, in, p_in, nt, lane);
-                tanh_rows(acc, kx, out, inv_q, nt, wave, lane);
+                tanh_rows<HEAD>(acc, kx, out, inv_q, nt, wave, lane, acc3);
             }
             return;
         }
@@ -288,12 +348,13 @@ struct Mlp {
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             if (nt + 1 < NT) mma_rows<KS>(acc[(nt + 1) & 1], w, ini, in, p_in, nt + 1, lane);
-            tanh_rows(acc[nt & 1], kx, out, inv_q, nt, wave, lane);
+            tanh_rows<HEAD>(acc[nt & 1], kx, out, inv_q, nt, wave, lane, acc3);
             if (nt + 1 < NT) {
                 // all LDS reads of the next row tile first, a few vector
                 // instructions while they land, then one MFMA at a time, each
                 // followed by a share of the tanh's vector work
-                constexpr int NM = MT * KS, NVT = MT * 4 * 6, NV0 = 8;
+                constexpr int NM = MT * KS + (HEAD ? NHW * KHS : 0);
+                constexpr int NVT = MT * 4 * 6, NV0 = 8;
                 constexpr int NV = (NVT - NV0 + NM - 1) / NM;
                 __builtin_amdgcn_sched_group_barrier(0x100, KS, 0);
                 __builtin_amdgcn_sched_group_barrier(0x002, NV0, 0);
@@ -310,32 +371,35 @@ struct Mlp {
     // Phases A-C. The caller synchronises the workgroup afterwards.
     __device__ void forward(char* smem, int wave, int lane) {
         const float* tab = reinterpret_cast<const float*>(smem + OFF_TAB);
-        dense_tanh<K1S>(w1, tab, smem + OFF_IN, P_IN, smem + OFF_H1, inv_q1, wave, lane);
-        __syncthreads();
-        dense_tanh<K2S>(w2, tab + 2 * H, smem + OFF_H1, P_H, smem + OFF_H2, inv_q2, wave, lane);
-        if constexpr (HS)
-            __syncthreads();   // every wave reads all of h2
-        else
-            wave_lds_sync();   // each wave reads only its own h2 features
         const int lr = lane & 15, kq = (lane >> 4) * KC;
-        const int kbase = HS ? 0 : wave * FPW;
         f32x4 acc[NHW][NT];
 #pragma unroll
         for (int hw = 0; hw < NHW; ++hw)
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) acc[hw][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-        const char* h2 = smem + OFF_H2;
+        dense_tanh<K1S, false>(w1, tab, smem + OFF_IN, P_IN, smem + OFF_H1, inv_q1, wave, lane, acc);
+        __syncthreads();
+        if constexpr (!HS) {
+            // split-K: the head consumes each wave's own h2 from its registers
+            dense_tanh<K2S, true>(w2, tab + 2 * H, smem + OFF_H1, P_H, nullptr, inv_q2, wave, lane,
+                                  acc);
+        } else {
+            dense_tanh<K2S, false>(w2, tab + 2 * H, smem + OFF_H1, P_H, smem + OFF_H2, inv_q2, wave,
+                                   lane, acc);
+            __syncthreads();   // every wave reads all of h2
+            const char* h2 = smem + OFF_H2;
 #pragma unroll
-        for (int ks = 0; ks < KHS; ++ks) {
-            Frag b[NT];
+            for (int ks = 0; ks < KHS; ++ks) {
+                Frag b[NT];
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
-                b[nt] = M::lds(h2 + (nt * 16 + lr) * P_H + (kbase + ks * K + kq) * EB);
+                for (int nt = 0; nt < NT; ++nt)
+                    b[nt] = M::lds(h2 + (nt * 16 + lr) * P_H + (ks * K + kq) * EB);
 #pragma unroll
-            for (int hw = 0; hw < NHW; ++hw) {
-                if (HS && wave + hw * NW >= NHT) break;
+                for (int hw = 0; hw < NHW; ++hw) {
+                    if (wave + hw * NW >= NHT) break;
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) acc[hw][nt] = M::mma(w3[hw][ks], b[nt], acc[hw][nt]);
+                    for (int nt = 0; nt < NT; ++nt) acc[hw][nt] = M::mma(w3[hw][ks], b[nt], acc[hw][nt]);
+                }
             }
         }
         float* part = reinterpret_cast<float*>(smem + OFF_PART) + (HS ? 0 : wave * R * P_PART);
@@ -570,6 +634,20 @@ __device__ __forceinline__ int env_slot(const EnvArgs& env, const Tile& tl, int 
 // The launch covers the tiles of one or more segments (roll-out requests that
 // share the policy): tile b of the launch belongs to the segment whose
 // tile_begin is the largest one <= b.
+// A copy of a wave-uniform struct in scalar registers (every dword through
+// v_readfirstlane).
+template <class T>
+__device__ __forceinline__ T uniform(const T& v) {
+    static_assert(sizeof(T) % 4 == 0, "whole dwords");
+    uint32_t w[sizeof(T) / 4];
+    __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+    T out;
+    __builtin_memcpy(&out, w, sizeof(T));
+    return out;
+}
+
 // Index of the segment that tile `tile` of the launch belongs to.
 __device__ __forceinline__ int segment_index(const Batch& b, int tile) {
     if (!b.table) {
@@ -632,9 +710,11 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
     const float b3v = pol.b3[HO::NOUT];
     EnvCtx ctx{reinterpret_cast<const float*>(extra)};
     int* sums = reinterpret_cast<int*>(extra);   // market: [2][R][2]
-    const EnvArgs& env = sg.env;
-    const TrajArgs& tr = sg.tr;
-    const int horizon = sg.steps;
+    // the segment's fields the steps use, read once from LDS into scalar
+    // registers (they are uniform over the workgroup)
+    const EnvArgs env = uniform(sg.env);
+    const TrajArgs tr = uniform(sg.tr);
+    const int horizon = __builtin_amdgcn_readfirstlane(sg.steps);
     const RngKey key{env.k0, env.k1, env.epoch};
     const uint32_t t0 = step_base(env);
     if constexpr (E::KIND == Reaction::KIND) {
@@ -644,7 +724,7 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
             __syncthreads();
         }
     }
-    const Tile tl = tile_of(env, tile - sg.tile_begin);
+    const Tile tl = tile_of(env, tile - __builtin_amdgcn_readfirstlane(sg.tile_begin));
     const int row = tl.row0 + rr;
     const bool mine = rr < R;
     const bool valid = mine && row < tl.row1;
@@ -666,7 +746,7 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
     }
     __syncthreads();
 
-    const int passes = horizon + (sg.last ? 1 : 0);   // the extra pass evaluates V(s_T)
+    const int passes = horizon + (__builtin_amdgcn_readfirstlane(sg.last) ? 1 : 0);   // + V(s_T)
     for (int step = 0; step < passes; ++step) {
         mlp.forward(smem, wave, lane);
         __syncthreads();
@@ -1008,8 +1088,6 @@ __global__ void k_quantize(int dtype, float scale, const float* x, float* y, int
     X(Pendulum, DT_BF16, 256, 8, 3, 0, 2)    \
     X(Pendulum, DT_BF16, 256, 8, 4, 0, 2)    \
     X(Pendulum, DT_BF16, 256, 8, 5, 0, 2)    \
-    X(Pendulum, DT_BF16, 256, 8, 2, 0, 4)    \
-    X(Pendulum, DT_BF16, 256, 8, 3, 0, 4)    \
     X(Acrobot, DT_BF16, 256, 4, 2, 0, 1)     \
     X(Acrobot, DT_BF16, 256, 4, 4, 0, 1)     \
     X(Acrobot, DT_BF16, 256, 4, 5, 0, 1)     \
@@ -1019,8 +1097,6 @@ __global__ void k_quantize(int dtype, float scale, const float* x, float* y, int
     X(Acrobot, DT_BF16, 256, 8, 3, 0, 2)     \
     X(Acrobot, DT_BF16, 256, 8, 4, 0, 2)     \
     X(Acrobot, DT_BF16, 256, 8, 5, 0, 2)     \
-    X(Acrobot, DT_BF16, 256, 8, 2, 0, 4)     \
-    X(Acrobot, DT_BF16, 256, 8, 3, 0, 4)     \
     X(Market, DT_BF16, 256, 4, 8, 1, 1)      \
     X(Market, DT_BF16, 256, 8, 8, 1, 2)      \
     X(Reaction, DT_FP8, 512, 4, 1, 0, 1)     \
