@@ -5,7 +5,11 @@
 // equations; these follow the project's specification: Lagrangian mechanics
 // for the classic-control bodies, the market and reaction rules read from the
 // workload descriptions. Every function works on one row (agent) held in
-// registers; the market's cross-agent sums are done by the kernels.
+// registers; the market's cross-agent sums are done by the kernels. The
+// register state has SR >= SD entries: the SD stored ones, then values derived
+// from them (the sine and cosine of the angles, which observe() and the next
+// step use), filled by complete() after a load and kept current by reset()
+// and step().
 #pragma once
 
 #include "device.h"
@@ -20,7 +24,8 @@ struct EnvCtx {
 // Cart (mass 1) with a hinged uniform pole (mass 0.1, half-length 0.5), force
 // +-10, explicit Euler dt 0.02; ends when |x| > 2.4 or |theta| > 12 degrees.
 struct CartPole {
-    static constexpr int KIND = 1, SD = 4, OD = 4, NACT = 2, LANES = 1;
+    static constexpr int KIND = 1, SD = 4, SR = 4, OD = 4, NACT = 2, LANES = 1;
+    __device__ static void complete(float*) {}
     __device__ static void reset(float* s, const RngKey& key, uint32_t t, uint32_t row,
                                  const EnvCtx&) {
         const Words w = draw(key, t, row, PURPOSE_RESET, 0);
@@ -64,15 +69,19 @@ __device__ __forceinline__ float wrap_pi(float a) {
 // Rod (m 1, l 1) under gravity 10 about its end, theta 0 upright, torque
 // clipped to 2; semi-implicit Euler dt 0.05, rate clipped to 8.
 struct Pendulum {
-    static constexpr int KIND = 2, SD = 2, OD = 3, NACT = 0, LANES = 1;
+    // register state: theta, theta', sin theta, cos theta
+    static constexpr int KIND = 2, SD = 2, SR = 4, OD = 3, NACT = 0, LANES = 1;
+    __device__ static void complete(float* s) { sin_cos(s[0], s[2], s[3]); }
     __device__ static void reset(float* s, const RngKey& key, uint32_t t, uint32_t row,
                                  const EnvCtx&) {
         const Words w = draw(key, t, row, PURPOSE_RESET, 0);
         s[0] = -3.141592653589793f + 6.283185307179586f * unit_uniform(w.w[0]);
         s[1] = -1.0f + 2.0f * unit_uniform(w.w[1]);
+        complete(s);
     }
     __device__ static void observe(const float* s, float* o) {
-        sin_cos(s[0], o[1], o[0]);
+        o[0] = s[3];
+        o[1] = s[2];
         o[2] = s[1];
     }
     template <int G>
@@ -83,12 +92,11 @@ struct Pendulum {
         const float a = wrap_pi(th);
         reward = -(a * a + 0.1f * thd * thd + 0.001f * u * u);
         // theta'' = 3 g / (2 l) sin(theta) + 3 u / (m l^2)
-        float sn, cs;
-        sin_cos(th, sn, cs);
-        const float acc = 15.0f * sn + 3.0f * u;
+        const float acc = 15.0f * s[2] + 3.0f * u;
         const float w = fminf(fmaxf(thd + acc * 0.05f, -8.0f), 8.0f);
         s[0] = th + w * 0.05f;
         s[1] = w;
+        complete(s);
         done = false;
     }
 };
@@ -98,27 +106,33 @@ struct Pendulum {
 // in [-1, 1], RK4 over dt 0.2; ends when the tip is more than one link length
 // above the base.
 struct Acrobot {
-    static constexpr int KIND = 3, SD = 4, OD = 6, NACT = 0, LANES = 1;
+    // register state: theta1, theta2, rates, then sin / cos of both angles
+    static constexpr int KIND = 3, SD = 4, SR = 8, OD = 6, NACT = 0, LANES = 1;
+    __device__ static void complete(float* s) {
+        sin_cos(s[0], s[4], s[5]);
+        sin_cos(s[1], s[6], s[7]);
+    }
     __device__ static void reset(float* s, const RngKey& key, uint32_t t, uint32_t row,
                                  const EnvCtx&) {
         const Words w = draw(key, t, row, PURPOSE_RESET, 0);
 #pragma unroll
         for (int i = 0; i < 4; ++i) s[i] = -0.1f + 0.2f * unit_uniform(w.w[i]);
+        complete(s);
     }
     __device__ static void observe(const float* s, float* o) {
-        sin_cos(s[0], o[1], o[0]);
-        sin_cos(s[1], o[3], o[2]);
+        o[0] = s[5];
+        o[1] = s[4];
+        o[2] = s[7];
+        o[3] = s[6];
         o[4] = s[2];
         o[5] = s[3];
     }
     // Manipulator equations M(q) q'' + C(q, q') + G(q) = (0, tau) solved for
     // q'' with the 2x2 inertia matrix of the two links (Cramer's rule);
-    // sin(q1 + q2) by the angle-addition formula.
-    __device__ static void deriv(const float* q, float tau, float* dq) {
+    // sin(q1 + q2) by the angle-addition formula. s1..c2: sin / cos of q1, q2.
+    __device__ static void deriv(const float* q, float tau, float s1, float c1, float s2, float c2,
+                                 float* dq) {
         const float g = 9.8f;
-        float s1, c1, s2, c2;
-        sin_cos(q[0], s1, c1);
-        sin_cos(q[1], s2, c2);
         const float m11 = 0.25f + (1.0f + 0.25f + c2) + 2.0f;  // lc1^2 + (l1^2+lc2^2+2 l1 lc2 c2) + I1 + I2
         const float m12 = (0.25f + 0.5f * c2) + 1.0f;
         const float m22 = 0.25f + 1.0f;
@@ -141,25 +155,31 @@ struct Acrobot {
         const float tau = fminf(fmaxf(torque, -1.0f), 1.0f);
         const float h = 0.2f;
         float k1[4], k2[4], k3[4], k4[4], y[4];
-        deriv(s, tau, k1);
+        float a1, b1, a2, b2;   // sin / cos of a stage's angles
+        deriv(s, tau, s[4], s[5], s[6], s[7], k1);
 #pragma unroll
         for (int i = 0; i < 4; ++i) y[i] = s[i] + 0.5f * h * k1[i];
-        deriv(y, tau, k2);
+        sin_cos(y[0], a1, b1);
+        sin_cos(y[1], a2, b2);
+        deriv(y, tau, a1, b1, a2, b2, k2);
 #pragma unroll
         for (int i = 0; i < 4; ++i) y[i] = s[i] + 0.5f * h * k2[i];
-        deriv(y, tau, k3);
+        sin_cos(y[0], a1, b1);
+        sin_cos(y[1], a2, b2);
+        deriv(y, tau, a1, b1, a2, b2, k3);
 #pragma unroll
         for (int i = 0; i < 4; ++i) y[i] = s[i] + h * k3[i];
-        deriv(y, tau, k4);
+        sin_cos(y[0], a1, b1);
+        sin_cos(y[1], a2, b2);
+        deriv(y, tau, a1, b1, a2, b2, k4);
 #pragma unroll
         for (int i = 0; i < 4; ++i) y[i] = s[i] + (h / 6.0f) * (k1[i] + 2.0f * k2[i] + 2.0f * k3[i] + k4[i]);
         s[0] = wrap_pi(y[0]);
         s[1] = wrap_pi(y[1]);
         s[2] = fminf(fmaxf(y[2], -12.566370614359172f), 12.566370614359172f);
         s[3] = fminf(fmaxf(y[3], -28.274333882308138f), 28.274333882308138f);
-        float s1, c1, s2, c2;
-        sin_cos(s[0], s1, c1);
-        sin_cos(s[1], s2, c2);
+        complete(s);
+        const float s1 = s[4], c1 = s[5], s2 = s[6], c2 = s[7];
         const float tip = -c1 - __builtin_fmaf(c1, c2, -s1 * s2);   // -cos q1 - cos(q1 + q2)
         done = tip > 1.0f;
         reward = done ? 0.0f : -1.0f;
@@ -171,7 +191,8 @@ struct Acrobot {
 // the kernels (exactly, in integer units) between decide() and settle().
 // LANES: how many lanes of a group can share a row's sampling and dynamics.
 struct Market {
-    static constexpr int KIND = 4, SD = 32, OD = 32, NACT = 50, LANES = 4;
+    static constexpr int KIND = 4, SD = 32, SR = 32, OD = 32, NACT = 50, LANES = 4;
+    __device__ static void complete(float*) {}
     __device__ static void reset(float* s, const RngKey& key, uint32_t t, uint32_t row,
                                  const EnvCtx&) {
 #pragma unroll
@@ -221,7 +242,8 @@ struct Market {
 // plus 0.05 N(0,1) noise per evaluation. The LDS parameter block is A (400),
 // centres (64 x 20), -1/(2 w^2) (64), amplitudes (64).
 struct Reaction {
-    static constexpr int KIND = 5, SD = 21, OD = 20, NACT = 40, NDIM = 20, NG = 64, LANES = 16;
+    static constexpr int KIND = 5, SD = 21, SR = 21, OD = 20, NACT = 40, NDIM = 20, NG = 64, LANES = 16;
+    __device__ static void complete(float*) {}
     static constexpr int PARAM_FLOATS = NDIM * NDIM + NG * NDIM + NG + NG;
     // E(x) with its quadratic rows and its Gaussians dealt over the G lanes of
     // the row's group (lane `sub` takes those congruent to sub mod G); every

@@ -155,7 +155,18 @@ struct Mlp {
     // per-feature accumulator start (bias / output scale) and tanh factor
     // (2 log2 e * output scale) of both hidden layers: [4][H] floats
     static constexpr int OFF_TAB = HS ? OFF_H2 + R * P_H : OFF_PART + NPART * R * P_PART * 4;
-    static constexpr int BYTES = OFF_TAB + 4 * H * 4;
+    static constexpr int WPS = (NW / 4 > OCC ? NW / 4 : OCC);   // waves per SIMD
+    // Four-wave kernels sharing a SIMD with another workgroup keep W1 in LDS
+    // (read per step, so its registers are free outside layer 1): [wave][mt]
+    // [ks][lane] fragments, each lane reading its own 16 (8, 4) bytes.
+    static constexpr bool W1_LDS = NW == 4 && WPS >= 2;
+    static constexpr int OFF_W1 = OFF_TAB + 4 * H * 4;
+    static constexpr int W1_BYTES = W1_LDS ? NW * MT * K1S * 64 * (int)sizeof(Frag) : 0;
+    // the same for the head weights of the split-K head ([wave][hw][ks][lane])
+    static constexpr bool W3_LDS = W1_LDS && !HS;
+    static constexpr int OFF_W3 = OFF_W1 + W1_BYTES;
+    static constexpr int W3_BYTES = W3_LDS ? NW * NHW * KHS * 64 * (int)sizeof(Frag) : 0;
+    static constexpr int BYTES = OFF_W3 + W3_BYTES;
     static_assert(!HS || P_PART * 4 <= P_H, "head results fit in the h1 tile");
     static_assert(FPW % 16 == 0 && FPW % K == 0 && KIN % K == 0 && H % K == 0, "tile shape");
     static_assert(BYTES <= 160 * 1024, "LDS budget");
@@ -164,7 +175,6 @@ struct Mlp {
     // software pipelining of the dense layers (see dense_tanh): with at most
     // two waves per SIMD and at most 64 registers of layer-2 weights per lane,
     // or with one wave per SIMD and at most four output tiles per wave
-    static constexpr int WPS = (NW / 4 > OCC ? NW / 4 : OCC);   // waves per SIMD
     static constexpr int W2_REGS = MT * K2S * (int)sizeof(Frag) / 4;
     static constexpr bool PIPE_ON =
         (WPS <= 2 && W2_REGS <= 64) || (WPS == 1 && MT <= 4);
@@ -174,6 +184,13 @@ struct Mlp {
     Frag w3[NHW][KHS];
     float o3[NHW][4];                  // head output scale
     float inv_q1, inv_q2;              // 1 / scale of the h1 and h2 quantisation
+
+    __device__ static Frag& w1_lds(char* base, int wave, int mt, int ks, int lane) {
+        return reinterpret_cast<Frag*>(base)[((wave * MT + mt) * K1S + ks) * 64 + lane];
+    }
+    __device__ static Frag& w3_lds(char* base, int wave, int hw, int ks, int lane) {
+        return reinterpret_cast<Frag*>(base)[((wave * NHW + hw) * KHS + ks) * 64 + lane];
+    }
 
     __device__ static float row_scale(const float* s, int m, int m_valid) {
         return (s != nullptr && m < m_valid) ? s[m] : 1.0f;
@@ -201,7 +218,12 @@ struct Mlp {
         for (int mt = 0; mt < MT; ++mt) {
             const int m = wave * FPW + mt * 16 + lr;
 #pragma unroll
-            for (int ks = 0; ks < K1S; ++ks) load_a(w1[mt][ks], p.w1, p.d_in, m, H, ks * K + kq, p.d_in);
+            for (int ks = 0; ks < K1S; ++ks) {
+                load_a(w1[mt][ks], p.w1, p.d_in, m, H, ks * K + kq, p.d_in);
+                if constexpr (W1_LDS)
+                    w1_lds(reinterpret_cast<char*>(tab) + (OFF_W1 - OFF_TAB), wave, mt, ks, lane) =
+                        w1[mt][ks];
+            }
 #pragma unroll
             for (int ks = 0; ks < K2S; ++ks) load_a(w2[mt][ks], p.w2, H, m, H, ks * K + kq, H);
         }
@@ -221,6 +243,9 @@ struct Mlp {
                         const int idx = ks * KC + e;
                         return wave * FPW + (idx >> 2) * 16 + 4 * q + (idx & 3);
                     });
+                    if constexpr (W3_LDS)
+                        w3_lds(reinterpret_cast<char*>(tab) + (OFF_W3 - OFF_TAB), wave, hw, ks,
+                               lane) = w3[hw][ks];
                 }
             }
 #pragma unroll
@@ -377,9 +402,26 @@ struct Mlp {
         for (int hw = 0; hw < NHW; ++hw)
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) acc[hw][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-        dense_tanh<K1S, false>(w1, tab, smem + OFF_IN, P_IN, smem + OFF_H1, inv_q1, wave, lane, acc);
+        if constexpr (W1_LDS) {
+            Frag w1r[MT][K1S];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int ks = 0; ks < K1S; ++ks) w1r[mt][ks] = w1_lds(smem + OFF_W1, wave, mt, ks, lane);
+            dense_tanh<K1S, false>(w1r, tab, smem + OFF_IN, P_IN, smem + OFF_H1, inv_q1, wave, lane,
+                                   acc);
+        } else {
+            dense_tanh<K1S, false>(w1, tab, smem + OFF_IN, P_IN, smem + OFF_H1, inv_q1, wave, lane,
+                                   acc);
+        }
         __syncthreads();
         if constexpr (!HS) {
+            if constexpr (W3_LDS) {   // head weights back from LDS for this step
+#pragma unroll
+                for (int hw = 0; hw < NHW; ++hw)
+#pragma unroll
+                    for (int ks = 0; ks < KHS; ++ks) w3[hw][ks] = w3_lds(smem + OFF_W3, wave, hw, ks, lane);
+            }
             // split-K: the head consumes each wave's own h2 from its registers
             dense_tanh<K2S, true>(w2, tab + 2 * H, smem + OFF_H1, P_H, nullptr, inv_q2, wave, lane,
                                   acc);
@@ -568,13 +610,14 @@ __device__ __forceinline__ Act<E> load_action(const TrajArgs& tr, size_t idx) {
 
 // ------------------------------------------------------------- env glue --
 template <class E>
-__device__ __forceinline__ void load_state(const EnvArgs& env, int64_t row, float (&s)[E::SD]) {
+__device__ __forceinline__ void load_state(const EnvArgs& env, int64_t row, float (&s)[E::SR]) {
 #pragma unroll
     for (int i = 0; i < E::SD; ++i) s[i] = env.state[(size_t)i * env.n_rows + row];
+    E::complete(s);   // derived register-state entries (sin / cos of the angles)
 }
 
 template <class E, int G>
-__device__ __forceinline__ void save_state(const EnvArgs& env, int64_t row, const float (&s)[E::SD],
+__device__ __forceinline__ void save_state(const EnvArgs& env, int64_t row, const float (&s)[E::SR],
                                            int sub) {
 #pragma unroll
     for (int i = 0; i < E::SD; ++i)
@@ -729,9 +772,9 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
     const bool mine = rr < R;
     const bool valid = mine && row < tl.row1;
     const bool lead = valid && sub == 0;   // writes the row's scalar records
-    float s[E::SD];
+    float s[E::SR];
 #pragma unroll
-    for (int i = 0; i < E::SD; ++i) s[i] = 0.0f;
+    for (int i = 0; i < E::SR; ++i) s[i] = 0.0f;
     if (valid) load_state<E>(env, row, s);
     int slot = 0;
     if constexpr (E::KIND == Market::KIND) {
@@ -872,7 +915,7 @@ template <class E>
 __global__ void k_plain_observe(EnvArgs env, TrajArgs tr, int horizon) {
     const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= env.n_rows) return;
-    float s[E::SD];
+    float s[E::SR];
     load_state<E>(env, row, s);
     float o[E::OD];
     E::observe(s, o);
@@ -953,7 +996,7 @@ __global__ void __launch_bounds__(256) k_plain_sample(EnvArgs env, PolicyArgs po
 
 template <class E, int G>
 __device__ __forceinline__ void finish_row(const EnvArgs& env, const TrajArgs& tr, int64_t row,
-                                           const float (&s)[E::SD], int step, int horizon, int sub) {
+                                           const float (&s)[E::SR], int step, int horizon, int sub) {
     save_state<E, G>(env, row, s, sub);
     float o[E::OD];
     E::observe(s, o);
@@ -979,7 +1022,7 @@ __global__ void __launch_bounds__(256) k_plain_step(EnvArgs env, TrajArgs tr, in
     if (row >= env.n_rows) return;
     const RngKey key{env.k0, env.k1, env.epoch};
     const uint32_t t = step_base(env) + (uint32_t)step;
-    float s[E::SD];
+    float s[E::SR];
     load_state<E>(env, row, s);
     const size_t idx = (size_t)step * env.n_rows + row;
     const Act<E> a = load_action<E>(tr, idx);
@@ -1053,7 +1096,7 @@ __global__ void k_reset(EnvArgs env) {
     const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= env.n_rows) return;
     const RngKey key{env.k0, env.k1, env.epoch};
-    float s[E::SD];
+    float s[E::SR];
     E::reset(s, key, 0u, (uint32_t)row, ctx);
     save_state<E, 1>(env, row, s, 0);
 }
