@@ -58,6 +58,10 @@ def test_bench_configuration_matches_oracle_on_sampled_steps():
         mlp = O.mlp_hold(pols[k])
         log_std = pols[k].exact("log_std")
         flips = 0
+        prec = {"kind": k, "rows": N, "steps_checked": list(STEPS)}
+
+        def worst(key, v):
+            prec[key] = max(prec.get(key, 0.0), float(np.max(v, initial=0.0)))
         for t in STEPS:
             say("full size: oracle", k, "step", t)
             obs = g["obs"][t].astype(np.float64)
@@ -71,6 +75,10 @@ def test_bench_configuration_matches_oracle_on_sampled_steps():
             assert verr.max() <= HEAD_HARD and (verr > HEAD_SOFT).mean() <= HEAD_FRAC
             assert aerr.max() <= HEAD_HARD and (aerr > HEAD_SOFT).mean() <= HEAD_FRAC
             assert np.abs(g["logp"][t] - ref["logp"][0]).max() <= 1e-4
+            worst("value_abs", verr)
+            worst("value_abs_p99", np.quantile(verr, 0.99))
+            worst("action_abs", aerr)
+            worst("logp_abs", np.abs(g["logp"][t] - ref["logp"][0]))
             if t + 1 >= T:
                 continue
             nxt_obs = g["obs"][t + 1].astype(np.float64)
@@ -84,8 +92,12 @@ def test_bench_configuration_matches_oracle_on_sampled_steps():
                 if done:
                     nxt = O.reset_row(hold, 0, EPOCH, t + 1, r)
                 o_ref = O.observe(k, nxt)
-                assert np.all(np.abs(nxt_obs[r] - o_ref) <= DYN[k] * np.maximum(1.0, np.abs(o_ref))), (k, t, r)
-                assert abs(g["reward"][t, r] - rew) <= DYN[k] * max(1.0, abs(rew)), (k, t, r)
+                oerr = np.abs(nxt_obs[r] - o_ref) / np.maximum(1.0, np.abs(o_ref))
+                rerr = abs(g["reward"][t, r] - rew) / max(1.0, abs(rew))
+                assert np.all(oerr <= DYN[k]), (k, t, r)
+                assert rerr <= DYN[k], (k, t, r)
+                worst("next_obs_rel", oerr)
+                worst("reward_rel", rerr)
         print(f"  kind {k}: {flips} termination flips within 1e-5 of the threshold", flush=True)
         # returns / GAE of the launch on sampled rows
         rows = np.random.default_rng(k).choice(N, 256, replace=False)
@@ -96,3 +108,8 @@ def test_bench_configuration_matches_oracle_on_sampled_steps():
         got_a = adv.cpu().numpy()[:, rows]
         assert np.allclose(got_g, want_g, rtol=1e-12, atol=1e-12)
         assert np.allclose(got_a, want_a, rtol=1e-12, atol=1e-12)
+        worst("G_rel", np.abs(got_g - want_g) / np.maximum(1.0, np.abs(want_g)))
+        worst("A_rel", np.abs(got_a - want_a) / np.maximum(1.0, np.abs(want_a)))
+        prec["termination_flips"] = flips
+        import json
+        print("PRECISION " + json.dumps(prec), flush=True)

@@ -119,6 +119,10 @@ def test_returns_match_oracle(T, rows, boot):
     gw, aw = O.returns_gae(r, v, d, lv, GAMMA, LAM, boot)
     assert np.allclose(g, gw, rtol=1e-12, atol=1e-12)
     assert np.allclose(a, aw, rtol=1e-12, atol=1e-12)
+    if boot and T >= 200:
+        import json
+        print("PRECISION " + json.dumps({"returns": [T, rows], "G_rel": float(_rel(g, gw).max()),
+                                         "A_rel": float(_rel(a, aw).max())}), flush=True)
     # FP32 outputs: the FP64 result rounded once (a last-bit FP64 difference can
     # round the other way, so one FP32 ulp is allowed)
     g32, a32 = wsx.compute_returns_raw(*dev, GAMMA, LAM, boot, out_dtype=torch.float32)
@@ -166,10 +170,15 @@ def _close(a, b, tol):
     return np.abs(a - b) <= tol * np.maximum(1.0, np.abs(b))
 
 
-def lockstep(case, T, epoch=1, start=None):
+def _rel(a, b):
+    return np.abs(a - b) / np.maximum(1.0, np.abs(b))
+
+
+def lockstep(case, T, epoch=1, start=None, stats=None):
     """Step the GPU one step per call; validate each step against the oracle.
 
-    Returns (n_decisions, n_excused)."""
+    Returns (n_decisions, n_excused); `stats` (a dict), if given, receives the
+    largest errors seen per field."""
     wsx = _wsx()
     kind = case.kind
     dtype = case.policy.dtype
@@ -178,6 +187,10 @@ def lockstep(case, T, epoch=1, start=None):
     if start is not None:
         case.set_gpu_state(start)
     n_dec = n_exc = 0
+    st = stats if stats is not None else {}
+
+    def worst(key, v):
+        st[key] = max(st.get(key, 0.0), float(np.max(v, initial=0.0)))
     for t in range(T):
         s = case.gpu_state()
         say("lockstep", kind, "step", t, "rows", case.rows)
@@ -187,11 +200,14 @@ def lockstep(case, T, epoch=1, start=None):
         ref = O.rollout(case.ohold, case.mlp, case.seed, epoch, t, 1, s, case.log_std)
         # observation of the state the step started from
         assert np.allclose(g["obs"][0], ref["obs"][0], rtol=0, atol=2e-6)
+        worst("obs_abs", np.abs(g["obs"][0] - ref["obs"][0]))
         # policy: value, action, log-probability
         hard, soft, frac = HEAD_TOL[dtype]
         verr = np.abs(g["value"][0] - ref["value"][0])
         print(f"  value err max {verr.max():.3g}, beyond {soft}: {(verr > soft).mean():.3f}")
         assert verr.max() <= hard and (verr > soft).mean() <= frac
+        worst("value_abs", verr)
+        st["value_abs_p99"] = max(st.get("value_abs_p99", 0.0), float(np.quantile(verr, 0.99)))
         act_g = g["action"][0].astype(np.float64)
         act_o = ref["action"][0]
         if O.n_actions(kind):
@@ -203,11 +219,14 @@ def lockstep(case, T, epoch=1, start=None):
             same = ~diff
             lerr = np.abs(g["logp"][0] - ref["logp"][0])[same]
             assert lerr.max(initial=0) <= {"f32": 1e-4, "bf16": 5e-2, "fp8": 0.5}[dtype]
+            st["action_mismatch"] = st.get("action_mismatch", 0) + int(diff.sum())
         else:
             aerr = np.abs(act_g - act_o)
             assert aerr.max() <= hard
+            worst("action_abs", aerr)
             lerr = np.abs(g["logp"][0] - ref["logp"][0])
             assert lerr.max() <= 1e-4    # the normal draw itself, FP32 vs FP64
+        worst("logp_abs", lerr)
         # dynamics of the GPU's own action from the GPU's state
         tol = DYN_TOL[kind]
         if kind == O.MARKET:
@@ -215,6 +234,8 @@ def lockstep(case, T, epoch=1, start=None):
                 nxt, rew, _ = O.market_step(s[r0:r1], act_g[r0:r1].astype(np.int32))
                 assert np.all(_close(s_next[r0:r1], nxt, tol))
                 assert np.all(_close(g["reward"][0][r0:r1], rew, tol))
+                worst("state_rel", _rel(s_next[r0:r1], nxt))
+                worst("reward_rel", _rel(g["reward"][0][r0:r1], rew))
             assert not g["done"].any()
         else:
             for r in range(case.rows):
@@ -228,6 +249,8 @@ def lockstep(case, T, epoch=1, start=None):
                     nxt = O.reset_row(case.ohold, case.seed, epoch, t + 1, r)
                 assert np.all(_close(s_next[r], nxt, tol)), (r, s_next[r], nxt)
                 assert _close(g["reward"][0][r], rew, tol)
+                worst("state_rel", _rel(s_next[r], nxt))
+                worst("reward_rel", _rel(g["reward"][0][r], rew))
     return n_dec, n_exc
 
 
@@ -235,9 +258,14 @@ def lockstep(case, T, epoch=1, start=None):
                                            (O.ACROBOT, 100, 30), (O.MARKET, 6, 12),
                                            (O.REACTION, 40, 20)])
 def test_lockstep_matches_oracle(kind, n_envs, T):
+    import json
     c = Case(kind, n_envs, seed=11)
-    n_dec, n_exc = lockstep(c, T)
+    stats = {}
+    n_dec, n_exc = lockstep(c, T, stats=stats)
     print(f"kind {kind}: {n_dec} decisions, {n_exc} excused", flush=True)
+    stats.update(kind=kind, dtype=c.policy.dtype, rows=c.rows, steps=T, excused=n_exc,
+                 decisions=n_dec)
+    print("PRECISION " + json.dumps(stats), flush=True)
 
 
 def test_lockstep_acrobot_terminations():
