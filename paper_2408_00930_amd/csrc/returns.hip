@@ -13,6 +13,8 @@
 // Hillis-Steele scan over wavefront shuffles (6 rounds of 64-bit shuffles),
 // applies them to the carry from the later tile, and leaves the carry of the
 // tile's first step for the next (earlier) tile.
+#include <type_traits>
+
 #include "device.h"
 #include "kernels.h"
 
@@ -120,10 +122,14 @@ k_returns(const float* __restrict__ reward, const float* __restrict__ value,
 
 // Row-parallel form for sets with many rows: lane = row, the recursion run
 // backwards over the horizon in registers (the same FP64 operations as one
-// step of the scan), loads and stores coalesced over consecutive rows, eight
-// steps in flight per wave. With rows >= 64 waves' worth this keeps every CU
-// streaming, where the time-parallel scan above would stage each 64-step
-// tile through LDS.
+// step of the scan), loads and stores coalesced over consecutive rows. A set
+// of 10,000 rows is only ~160 waves, too few to hide HBM latency by
+// occupancy, so each lane keeps the next block of kRowBlock steps' loads in
+// flight while it runs the current block. With rows >= 64 waves' worth this
+// keeps every CU streaming, where the time-parallel scan above would stage
+// each 64-step tile through LDS.
+constexpr int kRowBlock = 16;
+
 template <int OUT_F64>
 __global__ void __launch_bounds__(64)
 k_returns_rows(const float* __restrict__ reward, const float* __restrict__ value,
@@ -135,21 +141,61 @@ k_returns_rows(const float* __restrict__ reward, const float* __restrict__ value
     const double gl = gamma * lambda;
     const double vT = bootstrap ? (double)last_value[r] : 0.0;
     double g = vT, a = 0.0, v_next = vT;
-#pragma unroll 8
-    for (int t = T - 1; t >= 0; --t) {
-        const size_t i = (size_t)t * rows + r;
-        const double rw = reward[i], v = value[i];
-        const double keep = done[i] ? 0.0 : 1.0;
-        a = (rw + gamma * keep * v_next - v) + gl * keep * a;
-        g = rw + gamma * keep * g;
-        v_next = v;
-        if (OUT_F64) {
-            static_cast<double*>(ret)[i] = g;
-            static_cast<double*>(adv)[i] = a;
-        } else {
-            static_cast<float*>(ret)[i] = (float)g;
-            static_cast<float*>(adv)[i] = (float)a;
+    // a block holds steps t_hi, t_hi - 1, ..., t_hi - kRowBlock + 1; only the
+    // last (lowest) block of the horizon may be partial (FULL false: steps
+    // below 0 are skipped)
+    float rw[2][kRowBlock], vv[2][kRowBlock];
+    uint8_t dd[2][kRowBlock];
+    auto load = [&](auto full, int t_hi, int buf) {
+#pragma unroll
+        for (int j = 0; j < kRowBlock; ++j) {
+            const int t = t_hi - j;
+            if (decltype(full)::value || t >= 0) {
+                const size_t i = (size_t)t * rows + r;
+                rw[buf][j] = reward[i];
+                vv[buf][j] = value[i];
+                dd[buf][j] = done[i];
+            }
         }
+    };
+    auto run = [&](auto full, int t_hi, int buf) {
+#pragma unroll
+        for (int j = 0; j < kRowBlock; ++j) {
+            const int t = t_hi - j;
+            if (decltype(full)::value || t >= 0) {
+                const size_t i = (size_t)t * rows + r;
+                const double rt = rw[buf][j], v = vv[buf][j];
+                const double keep = dd[buf][j] ? 0.0 : 1.0;
+                a = (rt + gamma * keep * v_next - v) + gl * keep * a;
+                g = rt + gamma * keep * g;
+                v_next = v;
+                if (OUT_F64) {
+                    static_cast<double*>(ret)[i] = g;
+                    static_cast<double*>(adv)[i] = a;
+                } else {
+                    static_cast<float*>(ret)[i] = (float)g;
+                    static_cast<float*>(adv)[i] = (float)a;
+                }
+            }
+        }
+    };
+    const std::true_type full{};
+    const std::false_type part{};
+    const int nb = T / kRowBlock;   // full blocks, from the end of the horizon
+    const int rem = T - nb * kRowBlock;
+    if (nb > 0) load(full, T - 1, 0);
+    // two blocks per iteration so the buffers keep fixed registers; the next
+    // block's loads are issued before the current block's recursion
+    for (int k = 0; k < nb; k += 2) {
+        if (k + 1 < nb) load(full, T - 1 - (k + 1) * kRowBlock, 1);
+        run(full, T - 1 - k * kRowBlock, 0);
+        if (k + 1 >= nb) break;
+        if (k + 2 < nb) load(full, T - 1 - (k + 2) * kRowBlock, 0);
+        run(full, T - 1 - (k + 1) * kRowBlock, 1);
+    }
+    if (rem > 0) {   // steps rem - 1 .. 0
+        load(part, rem - 1, 0);
+        run(part, rem - 1, 0);
     }
 }
 

@@ -572,22 +572,51 @@ struct Act {
     float value;
 };
 
+// The part of a draw that does not depend on the policy's outputs: the
+// categorical uniform, or the Gaussian's standard normal and log-probability.
+// The fused kernel computes it for step t + 1 beside the dynamics of step t.
+template <class E>
+struct Pre {
+    float u;      // categorical: the uniform; Gaussian: z
+    float logp;   // Gaussian: log-probability of z
+};
+
+template <class E>
+__device__ __forceinline__ Pre<E> prepare(const RngKey& key, uint32_t t, uint32_t row,
+                                          float log_std) {
+    const Words w = draw(key, t, row, PURPOSE_ACTION, 0);
+    Pre<E> p{0.0f, 0.0f};
+    if constexpr (E::NACT > 0) {
+        p.u = unit_uniform(w.w[0]);
+    } else {
+        float zc, zs;
+        gauss_pair(unit_uniform(w.w[0]), unit_uniform(w.w[1]), zc, zs);
+        p.u = zc;
+        p.logp = -0.5f * zc * zc - log_std - 0.91893853320467274f;   // log(2 pi) / 2
+    }
+    return p;
+}
+
+// The action from the head block and the prepared draw.
+template <class E, int G, int C>
+__device__ __forceinline__ Act<E> decide(const float (&hb)[C], int sub, const Pre<E>& p,
+                                         float sigma, float& logp) {
+    Act<E> act{0, 0.0f};
+    if constexpr (E::NACT > 0) {
+        act.index = sample_categorical<E::NACT, G, C>(hb, sub, p.u, logp);
+        act.value = (float)act.index;
+    } else {
+        act.value = hb[0] + sigma * p.u;
+        logp = p.logp;
+    }
+    return act;
+}
+
 // Draw the action of row `row` at step t from its head block.
 template <class E, int G, int C>
 __device__ __forceinline__ Act<E> choose(const float (&hb)[C], int sub, const RngKey& key,
                                          uint32_t t, uint32_t row, float log_std, float& logp) {
-    const Words w = draw(key, t, row, PURPOSE_ACTION, 0);
-    Act<E> act{0, 0.0f};
-    if constexpr (E::NACT > 0) {
-        act.index = sample_categorical<E::NACT, G, C>(hb, sub, unit_uniform(w.w[0]), logp);
-        act.value = (float)act.index;
-    } else {
-        float zc, zs;
-        gauss_pair(unit_uniform(w.w[0]), unit_uniform(w.w[1]), zc, zs);
-        act.value = hb[0] + expf(log_std) * zc;
-        logp = -0.5f * zc * zc - log_std - 0.91893853320467274f;   // log(2 pi) / 2
-    }
-    return act;
+    return decide<E, G, C>(hb, sub, prepare<E>(key, t, row, log_std), expf(log_std), logp);
 }
 
 template <class E>
@@ -787,6 +816,8 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
         L::template put_obs<E::OD, G>(smem, rr, o, inv_q0, sub);
         if (valid && horizon > 0) store_obs<E::OD, G>(tr.obs + (size_t)row * E::OD, o, sub);
     }
+    const float sigma = expf(log_std);
+    Pre<E> pre = prepare<E>(key, t0, (uint32_t)row, log_std);   // step 0's draw
     __syncthreads();
 
     const int passes = horizon + (__builtin_amdgcn_readfirstlane(sg.last) ? 1 : 0);   // + V(s_T)
@@ -803,7 +834,7 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
                 if (lead) tr.last_value[row] = hv;
             } else {
                 float logp;
-                act = choose<E, G, C>(hb, sub, key, t, (uint32_t)row, log_std, logp);
+                act = decide<E, G, C>(hb, sub, pre, sigma, logp);
                 if (lead) {
                     tr.value[idx] = hv;
                     tr.logp[idx] = logp;
@@ -824,9 +855,11 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
             __syncthreads();
             if (step < horizon) {
                 if (valid) {
+                    const Pre<E> nxt = prepare<E>(key, t + 1, (uint32_t)row, log_std);
                     const int* sl = sums + ((step & 1) * R + slot) * 2;
                     float reward;
                     Market::settle(s, act.index, sl[0], sl[1], reward);
+                    pre = nxt;
                     if (lead) {
                         tr.reward[idx] = reward;
                         tr.done[idx] = 0;
@@ -837,10 +870,13 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
             }
         } else {
             if (valid && step < horizon) {
+                // the next step's draw, independent of this step's dynamics
+                const Pre<E> nxt = prepare<E>(key, t + 1, (uint32_t)row, log_std);
                 float reward;
                 bool done;
                 E::template step<G>(s, act.index, act.value, t, (uint32_t)row, key, ctx, sub,
                                     reward, done);
+                pre = nxt;
                 if (done) E::reset(s, key, t + 1, (uint32_t)row, ctx);
                 if (lead) {
                     tr.reward[idx] = reward;
