@@ -118,6 +118,11 @@ def _declare(L):
         getattr(L, name).argtypes = [C.c_int32, C.c_int64, dp, dp, C.c_void_p, dp,
                                      C.c_double, C.c_double, C.c_int32, dp, dp]
     L.orc_num_threads.restype = C.c_int
+    L.orc_ac_grad.argtypes = [C.POINTER(_Mlp), C.c_int, dp, C.c_int64, dp, dp, dp, dp,
+                              C.c_double, C.c_double, C.c_int, dp, dp, dp, dp, dp, dp, dp]
+    L.orc_ac_grad.restype = C.c_int
+    L.orc_adam.argtypes = [C.c_int64, dp, dp, dp, dp, C.c_int32, C.c_double, C.c_double,
+                           C.c_double, C.c_double]
 
 
 def _f64(a):
@@ -381,3 +386,43 @@ def gae_bruteforce(reward, value, done, last_value, gamma, lam, bootstrap=True):
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+# ------------------------------------------------------ actor-critic update ----
+
+def ac_grad(policy, n_act, obs, action, adv, ret, value_coef=0.5, entropy_coef=0.0,
+            quant_backward=True, log_std=None):
+    """Gradients of the actor-critic loss over the samples (obs [n, d_in],
+    action [n], advantage [n], return [n]) as a dict of FP64 arrays shaped like
+    the weights: w1 [h1][d_in], b1, w2 [h2][h1], b2, w3 [n_head][h2], b3 and,
+    for Gaussian policies (n_act == 0), log_std."""
+    h = mlp_hold(policy) if not isinstance(policy, _MlpHold) else policy
+    s = h.s
+    obs = _f64(np.atleast_2d(obs))
+    n = obs.shape[0]
+    action, adv, ret = _f64(action).reshape(n), _f64(adv).reshape(n), _f64(ret).reshape(n)
+    if log_std is None:
+        log_std = policy.exact("log_std") if hasattr(policy, "exact") else np.zeros(1)
+    ls = _f64(np.atleast_1d(log_std))
+    out = {"w1": np.zeros((s.h1, s.d_in)), "b1": np.zeros(s.h1), "w2": np.zeros((s.h2, s.h1)),
+           "b2": np.zeros(s.h2), "w3": np.zeros((s.n_head, s.h2)), "b3": np.zeros(s.n_head),
+           "log_std": np.zeros(1)}
+    rc = lib().orc_ac_grad(C.byref(s), int(n_act), _ptr(ls), n, _ptr(obs), _ptr(action),
+                           _ptr(adv), _ptr(ret), float(value_coef), float(entropy_coef),
+                           1 if quant_backward else 0,
+                           *[_ptr(out[k]) for k in ("w1", "b1", "w2", "b2", "w3", "b3",
+                                                    "log_std")])
+    if rc != 0:
+        raise ValueError("actor-critic gradient not defined for this policy format")
+    if n_act:
+        del out["log_std"]
+    return out
+
+
+def adam(theta, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step in place on FP64 arrays (theta, m, v updated)."""
+    for a in (theta, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = _f64(g)
+    lib().orc_adam(theta.size, _ptr(theta), _ptr(g), _ptr(m), _ptr(v), int(t), float(lr),
+                   float(b1), float(b2), float(eps))

@@ -834,6 +834,138 @@ void orc_gae_bruteforce(int32_t T, int64_t rows, const double* reward, const dou
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Actor-critic update (Sec. 3: actor-critic training for discrete and       */
+/* continuous actions, consuming the roll-out data in place; App. A: the     */
+/* roll-out feeds the trainer on the device).                                */
+/* Reading (the paper names the method, not the loss): the advantage         */
+/* actor-critic loss averaged over the n = horizon x rows samples,           */
+/*   L = (1/n) sum_i [ -A_i log pi(a_i | o_i) + (c_v / 2) (V(o_i) - G_i)^2   */
+/*                     - c_e H(pi(. | o_i)) ],                               */
+/* with A and G from the returns/GAE pass (constants of the loss). Gaussian  */
+/* actions: log pi = -(a - mu)^2 / (2 sigma^2) - log sigma - log(2 pi) / 2,  */
+/* sigma = exp(log_std), H = log sigma + (1 + log(2 pi)) / 2. Categorical:   */
+/* log pi = l_a - log sum_k exp(l_k), H = -sum_k p_k log p_k.                */
+/* The gradient is taken through the policy as the roll-out evaluates it:    */
+/* the forward pass has the same quantisation points as orc_mlp_forward and */
+/* the rounding is passed straight through (the derivative of tanh is taken  */
+/* at the unrounded activation). With quant_backward (BF16 policies) the     */
+/* operands of the backward products are rounded to BF16 as well: the head  */
+/* gradient before it meets W3 and h2, and dz2 and dz1 before they meet the  */
+/* weights and the layer inputs; bias gradients use the unrounded values.    */
+/* Returns 0, or -1 for FP8 policies (not covered).                          */
+/* ------------------------------------------------------------------------ */
+
+static double ac_round(int on, double x) { return on ? orc_round_bf16(x) : x; }
+
+int orc_ac_grad(const orc_mlp* p, int n_act, const double* log_std, int64_t n,
+                const double* obs, const double* action, const double* adv,
+                const double* ret, double value_coef, double entropy_coef,
+                int quant_backward, double* gW1, double* gb1, double* gW2, double* gb2,
+                double* gW3, double* gb3, double* glog_std)
+{
+    if (p->dtype == ORC_FP8) return -1;
+    const int din = p->d_in, H1 = p->h1, H2 = p->h2, NH = p->n_head;
+    const int qb = quant_backward && p->dtype == ORC_BF16;
+    memset(gW1, 0, sizeof(double) * H1 * din);
+    memset(gb1, 0, sizeof(double) * H1);
+    memset(gW2, 0, sizeof(double) * H2 * H1);
+    memset(gb2, 0, sizeof(double) * H2);
+    memset(gW3, 0, sizeof(double) * NH * H2);
+    memset(gb3, 0, sizeof(double) * NH);
+    if (n_act == 0) glog_std[0] = 0.0;
+    double* x0 = (double*)malloc(sizeof(double) * din);
+    double* t1 = (double*)malloc(sizeof(double) * H1);
+    double* x1 = (double*)malloc(sizeof(double) * H1);
+    double* t2 = (double*)malloc(sizeof(double) * H2);
+    double* x2 = (double*)malloc(sizeof(double) * H2);
+    double* head = (double*)malloc(sizeof(double) * NH);
+    double* dh = (double*)malloc(sizeof(double) * NH);
+    double* dhq = (double*)malloc(sizeof(double) * NH);
+    double* dz2 = (double*)malloc(sizeof(double) * H2);
+    double* dz1 = (double*)malloc(sizeof(double) * H1);
+    const double inv_n = 1.0 / (double)n;
+    for (int64_t i = 0; i < n; ++i) {
+        /* forward, keeping the activations */
+        quantize_inputs(p->dtype, p->act_scale[0], obs + (size_t)i * din, din, x0);
+        dense(p->W1, p->b1, H1, din, x0, t1);
+        for (int j = 0; j < H1; ++j) t1[j] = tanh(t1[j]);
+        quantize_inputs(p->dtype, p->act_scale[1], t1, H1, x1);
+        dense(p->W2, p->b2, H2, H1, x1, t2);
+        for (int j = 0; j < H2; ++j) t2[j] = tanh(t2[j]);
+        quantize_inputs(p->dtype, p->act_scale[2], t2, H2, x2);
+        dense(p->W3, p->b3, NH, H2, x2, head);
+        /* dL_i / d head */
+        const double A = adv[i], V = head[NH - 1];
+        for (int o = 0; o < NH; ++o) dh[o] = 0.0;
+        if (n_act == 0) {
+            const double mu = head[0], sigma = exp(log_std[0]);
+            const double d = (action[i] - mu) / sigma;
+            dh[0] = -A * d / sigma * inv_n;
+            glog_std[0] += (-A * (d * d - 1.0) - entropy_coef) * inv_n;
+        } else {
+            double mx = head[0];
+            for (int k = 1; k < n_act; ++k) mx = head[k] > mx ? head[k] : mx;
+            double z = 0.0;
+            for (int k = 0; k < n_act; ++k) z += exp(head[k] - mx);
+            double ent = 0.0;
+            for (int k = 0; k < n_act; ++k) {
+                const double pk = exp(head[k] - mx) / z;
+                ent -= pk * log(pk);
+            }
+            const int a = (int)action[i];
+            for (int k = 0; k < n_act; ++k) {
+                const double pk = exp(head[k] - mx) / z;
+                dh[k] = (A * (pk - (k == a ? 1.0 : 0.0)) + entropy_coef * pk * (log(pk) + ent)) *
+                        inv_n;
+            }
+        }
+        dh[NH - 1] = value_coef * (V - ret[i]) * inv_n;
+        /* head layer */
+        for (int o = 0; o < NH; ++o) {
+            dhq[o] = ac_round(qb, dh[o]);
+            gb3[o] += dh[o];
+            for (int j = 0; j < H2; ++j) gW3[(size_t)o * H2 + j] += dhq[o] * x2[j];
+        }
+        /* layer 2 */
+        for (int j = 0; j < H2; ++j) {
+            double s = 0.0;
+            for (int o = 0; o < NH; ++o) s += p->W3[(size_t)o * H2 + j] * dhq[o];
+            dz2[j] = s * (1.0 - t2[j] * t2[j]);
+            gb2[j] += dz2[j];
+            const double dq = ac_round(qb, dz2[j]);
+            for (int k = 0; k < H1; ++k) gW2[(size_t)j * H1 + k] += dq * x1[k];
+            dz2[j] = dq;   /* the rounded value feeds layer 1 */
+        }
+        /* layer 1 */
+        for (int k = 0; k < H1; ++k) {
+            double s = 0.0;
+            for (int j = 0; j < H2; ++j) s += p->W2[(size_t)j * H1 + k] * dz2[j];
+            dz1[k] = s * (1.0 - t1[k] * t1[k]);
+            gb1[k] += dz1[k];
+            const double dq = ac_round(qb, dz1[k]);
+            for (int m = 0; m < din; ++m) gW1[(size_t)k * din + m] += dq * x0[m];
+        }
+    }
+    free(x0); free(t1); free(x1); free(t2); free(x2); free(head); free(dh); free(dhq);
+    free(dz2); free(dz1);
+    return 0;
+}
+
+/* Adam (Kingma and Ba, ICLR 2015, Algorithm 1) on one tensor, step t >= 1:  */
+/* m <- b1 m + (1 - b1) g, v <- b2 v + (1 - b2) g^2,                         */
+/* theta <- theta - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).     */
+void orc_adam(int64_t n, double* theta, const double* g, double* m, double* v, int32_t t,
+              double lr, double b1, double b2, double eps)
+{
+    const double c1 = 1.0 - pow(b1, t), c2 = 1.0 - pow(b2, t);
+    for (int64_t i = 0; i < n; ++i) {
+        m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+        theta[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+    }
+}
+
 /* Threads the OpenMP loops over environments use (1 without OpenMP).        */
 int orc_num_threads(void)
 {
