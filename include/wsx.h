@@ -201,6 +201,64 @@ int wsx_policy_forward(const wsx_policy* policy, const float* obs, int64_t rows,
 int wsx_quantize(int32_t dtype, float scale, const float* x, float* y, int64_t n, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* Actor-critic update on the roll-out data in place (Sec. 3: actor-critic  */
+/* training for discrete and continuous actions; App. A: the trainer reads   */
+/* the roll-out where it was written). The loss, averaged over `samples`     */
+/* samples i (a trajectory's horizon x rows, its fields passed as flat       */
+/* arrays), is                                                               */
+/*   L = (1/n) sum_i [ -A_i log pi(a_i|o_i) + (value_coef/2) (V(o_i) - G_i)^2 */
+/*                     - entropy_coef H(pi(.|o_i)) ]                         */
+/* with A and G from wsx_compute_returns (WSX_F32 outputs). Gaussian         */
+/* policies (log_std set): log pi = -(a - mu)^2 / (2 sigma^2) - log sigma -  */
+/* log(2 pi)/2 with sigma = exp(log_std[0]); categorical: softmax of the     */
+/* logits. The policy is evaluated as the roll-out evaluates it and the      */
+/* rounding of its inputs is passed straight through (tanh' at the unrounded */
+/* FP32 activation); for BF16 policies the operands of the backward products */
+/* are rounded to BF16 (head gradient, dz2, dz1), bias gradients are not.    */
+/* FP32 and BF16 policies of the compiled shapes (FP32 hidden 64, BF16 hidden */
+/* 256; n_head <= 16, or <= 64 for BF16) -- else WSX_EUNSUPPORTED (FP8).     */
+/* ------------------------------------------------------------------------ */
+
+/* FP32 gradients, device, caller-owned, the policy's shapes and layouts. */
+typedef struct {
+    float* w1;               /* [h1][d_in]                                        */
+    float* b1;               /* [h1]                                              */
+    float* w2;               /* [h2][h1]                                          */
+    float* b2;               /* [h2]                                              */
+    float* w3;               /* [n_head][h2]                                      */
+    float* b3;               /* [n_head]                                          */
+    float* log_std;          /* [1] for Gaussian policies; ignored for categorical */
+} wsx_grads;
+
+/* Device workspace wsx_ac_grad needs for `samples` samples on the current
+ * device (per sample two rows of h1 in the policy's format, plus
+ * per-workgroup partial sums). */
+int wsx_ac_grad_workspace_bytes(const wsx_policy* policy, int64_t samples, size_t* bytes);
+
+/* Writes the gradient of L into `grads` (overwritten, not accumulated).
+ * n_actions: K >= 2 for a categorical policy over K actions (n_head == K + 1,
+ * action uint8), 0 for a Gaussian policy (n_head == 2, policy->log_std
+ * required, action float). obs: device [samples][d_in] float; action
+ * [samples]; returns, advantages: float [samples]. samples >= 1. The
+ * workspace (device, at least wsx_ac_grad_workspace_bytes) is scratch for
+ * the call; calls that share a workspace must be ordered on one stream. */
+int wsx_ac_grad(const wsx_policy* policy, int32_t n_actions, const float* obs,
+                const void* action, const float* returns, const float* advantages,
+                int64_t samples, float value_coef, float entropy_coef,
+                const wsx_grads* grads, void* workspace, size_t workspace_bytes, void* stream);
+
+/* One Adam step (Kingma and Ba, ICLR 2015, Algorithm 1) on n FP32 master
+ * parameters in place, step t >= 1 (bias corrections 1 - beta^t):
+ *   m <- b1 m + (1 - b1) g,  v <- b2 v + (1 - b2) g^2,
+ *   p <- p - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+ * If `store` is not NULL the updated parameter is also written there in
+ * store_dtype (WSX_F32, or WSX_BF16 rounded to nearest even): the policy's
+ * own weight buffer, so the next roll-out uses the new weights. */
+int wsx_adam_step(float* param, const float* grad, float* m, float* v, int64_t n, int32_t step,
+                  float lr, float beta1, float beta2, float eps, void* store,
+                  int32_t store_dtype, void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* Autotuner for the persistent fused roll-out (App. B: every environment    */
 /* instance owns a GPU block, its agents the block's threads; here a tile of */
 /* rows per workgroup, whose best height depends on the set). Times the      */

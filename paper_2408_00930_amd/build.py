@@ -20,7 +20,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libwsx.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["rollout.hip", "returns.hip", "abi.cpp", "serve.cpp", "tune.cpp"]
+SOURCES = ["rollout.hip", "returns.hip", "update.hip", "abi.cpp", "serve.cpp", "tune.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
          "-Wall", "-Wno-unused-variable", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-I", INCLUDE]

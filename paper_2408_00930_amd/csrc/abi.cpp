@@ -585,4 +585,108 @@ int wsx_quantize(int32_t dtype, float scale, const float* x, float* y, int64_t n
     return WSX_OK;
 }
 
+// ------------------------------------------------------------- update --
+static int ac_grid(int64_t samples) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t tiles = (samples + 31) / 32;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, cus));
+}
+
+static int check_ac_policy(const wsx_policy* p) {
+    if (!p) return fail(WSX_EINVAL, "policy is NULL");
+    if (p->dtype == WSX_FP8_E4M3)
+        return fail(WSX_EUNSUPPORTED, "the update covers FP32 and BF16 policies");
+    if (p->dtype != WSX_F32 && p->dtype != WSX_BF16) return fail(WSX_EINVAL, "unknown dtype %d", p->dtype);
+    if (p->h1 != p->h2) return fail(WSX_EUNSUPPORTED, "hidden layers of different widths");
+    if (p->d_in < 1 || p->n_head < 2) return fail(WSX_EINVAL, "policy d_in < 1 or n_head < 2");
+    if (!ac_supported(p->dtype, p->h1, p->d_in, p->n_head))
+        return fail(WSX_EUNSUPPORTED, "no update kernel for dtype %d, hidden %d, d_in %d, n_head %d",
+                    p->dtype, p->h1, p->d_in, p->n_head);
+    if (!p->w1 || !p->w2 || !p->w3 || !p->b1 || !p->b2 || !p->b3)
+        return fail(WSX_EINVAL, "policy weight or bias pointer is NULL");
+    return WSX_OK;
+}
+
+int wsx_ac_grad_workspace_bytes(const wsx_policy* policy, int64_t samples, size_t* bytes) {
+    if (const int rc = check_ac_policy(policy)) return rc;
+    if (samples < 1) return fail(WSX_EINVAL, "samples must be >= 1");
+    if (!bytes) return fail(WSX_EINVAL, "bytes is NULL");
+    const int g = ac_grid(samples);
+    *bytes = ac_workspace_bytes(policy->dtype, policy->h1, samples, g, g);
+    return WSX_OK;
+}
+
+int wsx_ac_grad(const wsx_policy* policy, int32_t n_actions, const float* obs,
+                const void* action, const float* returns, const float* advantages,
+                int64_t samples, float value_coef, float entropy_coef, const wsx_grads* grads,
+                void* workspace, size_t workspace_bytes, void* stream) {
+    if (const int rc = check_ac_policy(policy)) return rc;
+    if (n_actions == 0) {
+        if (policy->n_head != 2)
+            return fail(WSX_EUNSUPPORTED, "Gaussian policies with %d action dimensions",
+                        policy->n_head - 1);
+        if (!policy->log_std) return fail(WSX_EINVAL, "Gaussian policy needs log_std");
+    } else if (n_actions < 2 || n_actions > 255 || policy->n_head != n_actions + 1) {
+        return fail(WSX_EINVAL, "n_actions %d does not match n_head %d (categorical: 2..255)",
+                    n_actions, policy->n_head);
+    }
+    if (samples < 1) return fail(WSX_EINVAL, "samples must be >= 1");
+    if (!obs || !action || !returns || !advantages)
+        return fail(WSX_EINVAL, "obs, action, returns or advantages is NULL");
+    if (!std::isfinite(value_coef) || !std::isfinite(entropy_coef))
+        return fail(WSX_EINVAL, "loss coefficients must be finite");
+    if (!grads || !grads->w1 || !grads->b1 || !grads->w2 || !grads->b2 || !grads->w3 ||
+        !grads->b3)
+        return fail(WSX_EINVAL, "gradient pointer is NULL");
+    if (n_actions == 0 && !grads->log_std)
+        return fail(WSX_EINVAL, "Gaussian policy: grads->log_std is NULL");
+    const int g = ac_grid(samples);
+    const size_t need = ac_workspace_bytes(policy->dtype, policy->h1, samples, g, g);
+    if (!workspace || workspace_bytes < need)
+        return fail(WSX_EINVAL, "workspace of %zu bytes < %zu needed", workspace_bytes, need);
+    AcLaunch l{};
+    l.args.pol = policy_args(policy);
+    l.args.obs = obs;
+    l.args.action = action;
+    l.args.ret = returns;
+    l.args.adv = advantages;
+    l.args.n = samples;
+    l.args.n_act = n_actions;
+    l.args.value_coef = value_coef;
+    l.args.entropy_coef = entropy_coef;
+    l.args.inv_n = (float)(1.0 / (double)samples);
+    l.dtype = policy->dtype;
+    l.workspace = workspace;
+    l.grid1 = g;
+    l.grid2 = g;
+    l.out = AcOut{grads->w1, grads->b1, grads->w2, grads->b2, grads->w3, grads->b3,
+                  n_actions == 0 ? grads->log_std : nullptr};
+    const hipError_t e = launch_ac_grad(l, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "wsx_ac_grad");
+    return WSX_OK;
+}
+
+int wsx_adam_step(float* param, const float* grad, float* m, float* v, int64_t n, int32_t step,
+                  float lr, float beta1, float beta2, float eps, void* store, int32_t store_dtype,
+                  void* stream) {
+    if (n < 0) return fail(WSX_EINVAL, "n < 0");
+    if (step < 1) return fail(WSX_EINVAL, "step must be >= 1");
+    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f))
+        return fail(WSX_EINVAL, "betas must lie in [0, 1)");
+    if (!std::isfinite(lr) || !(eps >= 0.0f) || !std::isfinite(eps))
+        return fail(WSX_EINVAL, "lr must be finite and eps finite and >= 0");
+    if (store && store_dtype != WSX_F32 && store_dtype != WSX_BF16)
+        return fail(WSX_EINVAL, "store_dtype must be WSX_F32 or WSX_BF16");
+    if (n == 0) return WSX_OK;
+    if (!param || !grad || !m || !v) return fail(WSX_EINVAL, "param, grad, m or v is NULL");
+    const float c1 = (float)(1.0 - std::pow((double)beta1, step));
+    const float c2 = (float)(1.0 - std::pow((double)beta2, step));
+    const hipError_t e = launch_adam(param, grad, m, v, n, lr, beta1, beta2, eps, c1, c2, store,
+                                     store_dtype, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "wsx_adam_step");
+    return WSX_OK;
+}
+
 }  // extern "C"

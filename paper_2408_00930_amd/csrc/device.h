@@ -213,6 +213,89 @@ __device__ __forceinline__ float tanh_scaled_q(float acc, float k2, float q) {
 
 constexpr float kTwoLog2e = 2.8853900817779268f;  // 2 / ln 2
 
+// ------------------------------------------------- operand loading --
+template <class T>
+__device__ __forceinline__ T zero_frag() {
+    T t;
+    __builtin_memset(&t, 0, sizeof(T));
+    return t;
+}
+
+// KC consecutive weights W[m][k0 .. k0+KC) as an A fragment; zero outside
+// rows [0, m_valid) and columns [0, k_valid).
+__device__ __forceinline__ void load_a(float& f, const void* W, int ld, int m, int m_valid, int k0,
+                                       int k_valid) {
+    const float* w = static_cast<const float*>(W);
+    f = (m < m_valid && k0 < k_valid) ? w[(size_t)m * ld + k0] : 0.0f;
+}
+
+__device__ __forceinline__ void load_a(bf16x8& f, const void* W, int ld, int m, int m_valid, int k0,
+                                       int k_valid) {
+    const uint16_t* w = static_cast<const uint16_t*>(W);
+    uint16_t v[8];
+    if (m < m_valid && k0 + 8 <= k_valid && (ld % 8) == 0) {
+        const uint4 q = *reinterpret_cast<const uint4*>(w + (size_t)m * ld + k0);
+        __builtin_memcpy(v, &q, 16);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            v[i] = (m < m_valid && k0 + i < k_valid) ? w[(size_t)m * ld + k0 + i] : (uint16_t)0;
+    }
+    __builtin_memcpy(&f, v, 16);
+}
+
+__device__ __forceinline__ void load_a(long& f, const void* W, int ld, int m, int m_valid, int k0,
+                                       int k_valid) {
+    const uint8_t* w = static_cast<const uint8_t*>(W);
+    uint8_t v[8];
+    if (m < m_valid && k0 + 8 <= k_valid && (ld % 8) == 0) {
+        const uint2 q = *reinterpret_cast<const uint2*>(w + (size_t)m * ld + k0);
+        __builtin_memcpy(v, &q, 8);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            v[i] = (m < m_valid && k0 + i < k_valid) ? w[(size_t)m * ld + k0 + i] : (uint8_t)0;
+    }
+    __builtin_memcpy(&f, v, 8);
+}
+
+// An A fragment of KC weights W[m][col(e)], e < KC, at arbitrary columns
+// (the split-K head takes its K elements in the order the layer-2 outputs
+// sit in the accumulators); zero outside rows [0, m_valid).
+template <class F, class Col>
+__device__ __forceinline__ void load_a_cols(F& f, const void* W, int ld, int m, int m_valid,
+                                            Col col) {
+    constexpr int KC = sizeof(F) == 4 ? 1 : 8;
+    if constexpr (sizeof(F) == 4) {
+        const float* w = static_cast<const float*>(W);
+        f = m < m_valid ? w[(size_t)m * ld + col(0)] : 0.0f;
+    } else if constexpr (sizeof(F) == 16) {
+        const uint16_t* w = static_cast<const uint16_t*>(W);
+        uint16_t v[KC];
+#pragma unroll
+        for (int e = 0; e < KC; ++e) v[e] = m < m_valid ? w[(size_t)m * ld + col(e)] : (uint16_t)0;
+        __builtin_memcpy(&f, v, 16);
+    } else {
+        const uint8_t* w = static_cast<const uint8_t*>(W);
+        uint8_t v[KC];
+#pragma unroll
+        for (int e = 0; e < KC; ++e) v[e] = m < m_valid ? w[(size_t)m * ld + col(e)] : (uint8_t)0;
+        __builtin_memcpy(&f, v, 8);
+    }
+}
+
+// Store one quantised element (observations).
+template <int DT>
+__device__ __forceinline__ void store1(char* p, float v, float inv_s) {
+    if constexpr (DT == DT_F32) {
+        *reinterpret_cast<float*>(p) = v;
+    } else if constexpr (DT == DT_BF16) {
+        *reinterpret_cast<__bf16*>(p) = (__bf16)v;
+    } else {
+        *reinterpret_cast<uint8_t*>(p) = (uint8_t)(pack_fp8x4(v * inv_s, 0.f, 0.f, 0.f) & 0xFFu);
+    }
+}
+
 // ------------------------------------------------------- lane groups --
 // A row of a tile is served by G consecutive lanes (G a power of two <= 16,
 // groups aligned within a 16-lane row of the wave). The reductions use DPP

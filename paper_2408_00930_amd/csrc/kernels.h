@@ -85,6 +85,40 @@ struct Variant {
     int32_t kind2;
 };
 
+// Actor-critic update (update.hip). AcArgs are the kernels' arguments; the
+// workspace pointers are filled in by launch_ac_grad.
+struct AcArgs {
+    PolicyArgs pol;
+    const float* obs;        // [n][d_in]
+    const void* action;      // uint8 (discrete) or float (Gaussian) [n]
+    const float* ret;        // [n]
+    const float* adv;        // [n]
+    int64_t n;
+    int32_t n_act;           // 0: Gaussian
+    float value_coef, entropy_coef, inv_n;
+    char* h1_rows;           // workspace [n][H] in the policy format
+    char* dz2_rows;          // workspace [n][H]
+    float* part_fwd;         // per-workgroup partial sums of the kernels
+    float* part_bwd;
+    float* part_w2;
+};
+struct AcOut {               // FP32 gradients, the policy's shapes
+    float *w1, *b1, *w2, *b2, *w3, *b3, *log_std;
+};
+struct AcLaunch {
+    AcArgs args;
+    int dtype;
+    void* workspace;
+    int grid1, grid2;        // workgroups of the per-tile kernels and of dW2
+    AcOut out;
+};
+bool ac_supported(int dtype, int hidden, int d_in, int n_head);
+size_t ac_workspace_bytes(int dtype, int hidden, int64_t n, int grid1, int grid2);
+hipError_t launch_ac_grad(const AcLaunch& l, hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
+                       float b1, float b2, float eps, float c1, float c2, void* store,
+                       int store_dtype, hipStream_t s);
+
 // Launchers (return hipError_t of the launch).
 hipError_t launch_reset(int kind, const EnvArgs& env, hipStream_t s);
 hipError_t launch_fused(const Variant& v, const Batch& batch, int grid, hipStream_t s);

@@ -1,0 +1,669 @@
+// update.hip -- actor-critic gradient and Adam on the device (arXiv
+// 2408.00930, Sec. 3: actor-critic training for discrete and continuous
+// actions on the roll-out data kept in device memory; App. A: the trainer
+// consumes the roll-out where it was written).
+//
+// Loss (a reading: the paper names the method, not the loss), averaged over
+// the n samples (horizon x rows of one trajectory):
+//   L = (1/n) sum_i [ -A_i log pi(a_i|o_i) + (c_v/2) (V(o_i) - G_i)^2 - c_e H(pi(.|o_i)) ]
+// The policy is evaluated as the roll-out evaluates it (BF16 or FP32 inputs
+// of every product, FP32 accumulation) and the gradient passes the rounding
+// straight through, the derivative of tanh taken at the unrounded FP32
+// activation. The operands of the backward products are rounded to the
+// policy's format: the head gradient before it meets W3 and h2, dz2 and dz1
+// before they meet the weights and the layer inputs; bias gradients sum the
+// unrounded values.
+//
+// Four kernels:
+//  k_ac_fwd   per 32-sample tile: forward (layer 1, layer 2, head), head
+//             gradient, dz2 = (dhead W3) (1 - t2^2); accumulates dW3, db3,
+//             db2 and the log-std gradient; writes h1 and dz2 rows to the
+//             workspace.
+//  k_ac_bwd1  per tile: layer 1 again, dz1 = (dz2 W2) (1 - t1^2); accumulates
+//             dW1 and db1.
+//  k_ac_dw2   dW2 = sum_i dz2_i h1_i^T, split over the samples (split-K).
+//  k_ac_sum   per-workgroup partial sums -> the gradients.
+// The products run with samples as the MFMA rows (the weight fragments the
+// roll-out loads as A operands serve unchanged as B operands), so the
+// accumulators hold [sample][feature] tiles: lane l has feature l mod 16 and
+// samples 4 (l / 16) + i of each 16-sample row tile. Those tiles feed the
+// weight-gradient products (K = samples) directly, taking the K elements in
+// accumulator order; the other operand is read from LDS in the same order.
+#include <type_traits>
+
+#include "device.h"
+#include "kernels.h"
+
+namespace wsx {
+
+namespace {
+
+constexpr int kAcRows = 32;   // samples per tile (two row tiles of 16)
+
+// KC elements of a B fragment down column `col` of a row-major [k][ld]
+// matrix: W[(k0 + e) * ld + col], zero for rows >= k_valid.
+__device__ __forceinline__ void load_col(float& f, const void* W, int ld, int col, int k0,
+                                         int k_valid) {
+    const float* w = static_cast<const float*>(W);
+    f = k0 < k_valid ? w[(size_t)k0 * ld + col] : 0.0f;
+}
+__device__ __forceinline__ void load_col(bf16x8& f, const void* W, int ld, int col, int k0,
+                                         int k_valid) {
+    const uint16_t* w = static_cast<const uint16_t*>(W);
+    uint16_t v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+        v[e] = k0 + e < k_valid ? w[(size_t)(k0 + e) * ld + col] : (uint16_t)0;
+    __builtin_memcpy(&f, v, 16);
+}
+
+template <int DT>
+__device__ __forceinline__ float round_to(float x) {
+    if constexpr (DT == DT_BF16) return (float)(__bf16)x;
+    return x;
+}
+
+// One element of the policy format at byte address p (rounded to nearest
+// even for BF16).
+template <int DT>
+__device__ __forceinline__ void put(char* p, float v) {
+    if constexpr (DT == DT_BF16)
+        *reinterpret_cast<__bf16*>(p) = (__bf16)v;
+    else
+        *reinterpret_cast<float*>(p) = v;
+}
+
+// BF16 fragment whose K elements are samples in accumulator order: elements
+// 0-3 are row tile 0's i = 0..3, elements 4-7 row tile 1's.
+__device__ __forceinline__ bf16x8 pack_acc_k(const f32x4& a0, const f32x4& a1) {
+    const uint4 u = make_uint4(pack_bf16x2(a0[0], a0[1]), pack_bf16x2(a0[2], a0[3]),
+                               pack_bf16x2(a1[0], a1[1]), pack_bf16x2(a1[2], a1[3]));
+    return __builtin_bit_cast(bf16x8, u);
+}
+
+// The matching BF16 fragment from a transposed LDS tile T[c][sample]: row c,
+// samples 4 q .. 4 q + 3 and 16 + 4 q .. 16 + 4 q + 3.
+__device__ __forceinline__ bf16x8 lds_k_perm(const char* T, int pitch, int c, int q) {
+    const uint2 lo = *reinterpret_cast<const uint2*>(T + c * pitch + (4 * q) * 2);
+    const uint2 hi = *reinterpret_cast<const uint2*>(T + c * pitch + (16 + 4 * q) * 2);
+    return __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
+}
+
+__device__ __forceinline__ float act_tanh(float z) { return tanh_scaled(z, kTwoLog2e); }
+
+template <int DT, int H, int KIN, int NHP>
+struct AcShape {
+    using M = Mma<DT>;
+    using Frag = typename M::frag;
+    static constexpr int K = M::K, KC = M::KC, EB = M::EB;
+    static constexpr int NW = H >= 256 ? 8 : H / 16;   // waves; each owns FPW features
+    static constexpr int NTHR = NW * 64;
+    static constexpr int FPW = H / NW, MT = FPW / 16;
+    static constexpr int K1S = KIN / K, K2S = H / K;
+    static constexpr int NHT = NHP / 16;
+    static constexpr int NHK = (NHP + K - 1) / K * K;   // head width padded to K
+    static constexpr int KO = NHK / K;
+    static constexpr int KT = (KIN + 15) / 16;          // 16-column tiles of dW1
+    static constexpr int R = kAcRows;
+    static constexpr int P_IN = KIN * EB + 16, P_H = H * EB + 16, P_DH = NHK * EB + 16;
+    static constexpr int P_T = R * EB + 16;   // transposed tiles: [feature][sample]
+    static constexpr int KINP = KIN;
+    static constexpr int FWD_FLOATS = NHP * H + H + NHP + 1;   // dW3, db2, db3, dlog_std
+    static constexpr int BWD_FLOATS = H * KIN + H;             // dW1, db1
+    static_assert(FPW % 16 == 0 && H % K == 0 && KIN % K == 0, "tile shape");
+    static_assert(NHT * 2 <= NW, "one wave per head tile and row tile");
+};
+
+// Observation rows of a tile into LDS (zero beyond d_in and beyond n), and
+// their transpose if x0T is set.
+template <class S, int DT>
+__device__ __forceinline__ void stage_obs(const AcArgs& a, int64_t base, char* x0, char* x0T,
+                                          int tid) {
+    constexpr int KIN = S::KINP;
+    const int d_in = a.pol.d_in;
+    for (int e = tid; e < S::R * KIN; e += S::NTHR) {
+        const int r = e / KIN, i = e % KIN;
+        const int64_t n = base + r;
+        const float v = (n < a.n && i < d_in) ? a.obs[n * d_in + i] : 0.0f;
+        put<DT>(x0 + r * S::P_IN + i * S::EB, v);
+        if (x0T) put<DT>(x0T + i * S::P_T + r * S::EB, v);
+    }
+}
+
+template <int DT, int H, int KIN, int NHP>
+__global__ void __launch_bounds__((AcShape<DT, H, KIN, NHP>::NTHR))
+k_ac_fwd(AcArgs a) {
+    using S = AcShape<DT, H, KIN, NHP>;
+    using M = typename S::M;
+    using Frag = typename S::Frag;
+    constexpr int R = S::R, MT = S::MT, K = S::K, KC = S::KC, EB = S::EB;
+    __shared__ __attribute__((aligned(16))) char x0[R * S::P_IN];
+    __shared__ __attribute__((aligned(16))) char h1[R * S::P_H];
+    __shared__ __attribute__((aligned(16))) char h2[R * S::P_H];
+    __shared__ __attribute__((aligned(16))) char dz[R * S::P_H];
+    __shared__ __attribute__((aligned(16))) char dh[R * S::P_DH];
+    __shared__ __attribute__((aligned(16))) char dhT[NHP * S::P_T];
+    __shared__ float hd[R][NHP + 1];
+    __shared__ float db3s[NHP];
+    __shared__ float dlss;
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lr = lane & 15, q = lane >> 4;
+    const int kq = q * KC;
+    const PolicyArgs& p = a.pol;
+    // weights: layer 1 and 2 rows of this wave's features (B operands), the
+    // head's columns of these features (B of the dz2 product), and the head
+    // rows of this wave's head job
+    Frag w1[MT][S::K1S], w2[MT][S::K2S], w3t[MT][S::KO], w3[S::K2S];
+    float b1v[MT], b2v[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const int f = wave * S::FPW + mt * 16 + lr;
+#pragma unroll
+        for (int ks = 0; ks < S::K1S; ++ks) load_a(w1[mt][ks], p.w1, p.d_in, f, H, ks * K + kq, p.d_in);
+#pragma unroll
+        for (int ks = 0; ks < S::K2S; ++ks) load_a(w2[mt][ks], p.w2, H, f, H, ks * K + kq, H);
+#pragma unroll
+        for (int ks = 0; ks < S::KO; ++ks) load_col(w3t[mt][ks], p.w3, H, f, ks * K + kq, p.n_head);
+        b1v[mt] = p.b1[f];
+        b2v[mt] = p.b2[f];
+    }
+    const bool head_job = wave < S::NHT * 2;
+    const int jht = wave >> 1, jnt = wave & 1;
+#pragma unroll
+    for (int ks = 0; ks < S::K2S; ++ks)
+        load_a(w3[ks], p.w3, H, head_job ? jht * 16 + lr : p.n_head, p.n_head, ks * K + kq, H);
+    const float b3v = (head_job && jht * 16 + lr < p.n_head) ? p.b3[jht * 16 + lr] : 0.0f;
+    const float log_std = a.n_act == 0 ? p.log_std[0] : 0.0f;
+    const float sigma = expf(log_std);
+
+    f32x4 dw3[S::NHT][MT];
+    float db2a[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        db2a[mt] = 0.0f;
+#pragma unroll
+        for (int ht = 0; ht < S::NHT; ++ht) dw3[ht][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    if (tid < NHP) db3s[tid] = 0.0f;
+    if (tid == 0) dlss = 0.0f;
+    // head-gradient padding (columns >= n_head) stays zero
+    for (int e = tid; e < R * S::NHK; e += S::NTHR) put<DT>(dh + (e / S::NHK) * S::P_DH + (e % S::NHK) * EB, 0.0f);
+    for (int e = tid; e < NHP * R; e += S::NTHR) put<DT>(dhT + (e / R) * S::P_T + (e % R) * EB, 0.0f);
+
+    const int64_t n_tiles = (a.n + R - 1) / R;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t base = tile * R;
+        __syncthreads();   // the previous tile's LDS reads are done
+        stage_obs<S, DT>(a, base, x0, nullptr, tid);
+        __syncthreads();
+        // layer 1
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const int f = wave * S::FPW + mt * 16 + lr;
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                f32x4 acc = {b1v[mt], b1v[mt], b1v[mt], b1v[mt]};
+#pragma unroll
+                for (int ks = 0; ks < S::K1S; ++ks)
+                    acc = M::mma(M::lds(x0 + (nt * 16 + lr) * S::P_IN + (ks * K + kq) * EB), w1[mt][ks], acc);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    put<DT>(h1 + (nt * 16 + 4 * q + i) * S::P_H + f * EB, act_tanh(acc[i]));
+            }
+        }
+        __syncthreads();
+        // layer 2, keeping the unrounded activations
+        f32x4 t2[MT][2];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const int f = wave * S::FPW + mt * 16 + lr;
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                f32x4 acc = {b2v[mt], b2v[mt], b2v[mt], b2v[mt]};
+#pragma unroll
+                for (int ks = 0; ks < S::K2S; ++ks)
+                    acc = M::mma(M::lds(h1 + (nt * 16 + lr) * S::P_H + (ks * K + kq) * EB), w2[mt][ks], acc);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    t2[mt][nt][i] = act_tanh(acc[i]);
+                    put<DT>(h2 + (nt * 16 + 4 * q + i) * S::P_H + f * EB, t2[mt][nt][i]);
+                }
+            }
+        }
+        __syncthreads();
+        // head: wave (ht, nt) of the 2 NHT jobs
+        if (head_job) {
+            f32x4 acc = {b3v, b3v, b3v, b3v};
+#pragma unroll
+            for (int ks = 0; ks < S::K2S; ++ks)
+                acc = M::mma(M::lds(h2 + (jnt * 16 + lr) * S::P_H + (ks * K + kq) * EB), w3[ks], acc);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) hd[jnt * 16 + 4 * q + i][jht * 16 + lr] = acc[i];
+        }
+        __syncthreads();
+        // gradient of the loss at the head, one thread per sample
+        if (tid < R) {
+            const int r = tid;
+            const int64_t n = base + r;
+            const bool ok = n < a.n;
+            const float A = ok ? a.adv[n] : 0.0f;
+            const int NH = p.n_head;
+            auto set = [&](int o, float g) {
+                atomicAdd(&db3s[o], g);
+                const float gq = round_to<DT>(g);
+                put<DT>(dh + r * S::P_DH + o * EB, gq);
+                put<DT>(dhT + o * S::P_T + r * EB, gq);
+            };
+            if (a.n_act == 0) {
+                const float mu = hd[r][0];
+                const float act = ok ? static_cast<const float*>(a.action)[n] : mu;
+                const float d = (act - mu) / sigma;
+                set(0, ok ? -A * d / sigma * a.inv_n : 0.0f);
+                if (ok) atomicAdd(&dlss, (-A * (d * d - 1.0f) - a.entropy_coef) * a.inv_n);
+            } else {
+                const int KA = a.n_act;
+                float mx = hd[r][0];
+                for (int k = 1; k < KA; ++k) mx = fmaxf(mx, hd[r][k]);
+                float z = 0.0f;
+                for (int k = 0; k < KA; ++k) z += expf(hd[r][k] - mx);
+                const float lz = logf(z);
+                float ent = 0.0f;
+                for (int k = 0; k < KA; ++k) {
+                    const float lp = hd[r][k] - mx - lz;
+                    ent -= expf(lp) * lp;
+                }
+                const int act = ok ? (int)static_cast<const uint8_t*>(a.action)[n] : -1;
+                for (int k = 0; k < KA; ++k) {
+                    const float lp = hd[r][k] - mx - lz, pk = expf(lp);
+                    const float g = (A * (pk - (k == act ? 1.0f : 0.0f)) + a.entropy_coef * pk * (lp + ent)) *
+                                    a.inv_n;
+                    set(k, ok ? g : 0.0f);
+                }
+            }
+            set(NH - 1, ok ? a.value_coef * (hd[r][NH - 1] - a.ret[n]) * a.inv_n : 0.0f);
+        }
+        __syncthreads();
+        // dz2 = (dhead W3) (1 - t2^2) for this wave's features; dW3 += dhead^T h2
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const int f = wave * S::FPW + mt * 16 + lr;
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < S::KO; ++ks)
+                    acc = M::mma(M::lds(dh + (nt * 16 + lr) * S::P_DH + (ks * K + kq) * EB), w3t[mt][ks], acc);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float t = t2[mt][nt][i];
+                    const float g = acc[i] * (1.0f - t * t);
+                    db2a[mt] += g;
+                    put<DT>(dz + (nt * 16 + 4 * q + i) * S::P_H + f * EB, g);
+                }
+            }
+#pragma unroll
+            for (int ht = 0; ht < S::NHT; ++ht) {
+                if constexpr (DT == DT_BF16) {
+                    const Frag A_ = lds_k_perm(dhT, S::P_T, ht * 16 + lr, q);
+                    const Frag B_ = pack_acc_k(t2[mt][0], t2[mt][1]);
+                    dw3[ht][mt] = M::mma(A_, B_, dw3[ht][mt]);
+                } else {
+#pragma unroll
+                    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const float A_ = *reinterpret_cast<const float*>(
+                                dhT + (ht * 16 + lr) * S::P_T + (16 * nt + 4 * q + i) * EB);
+                            dw3[ht][mt] = M::mma(A_, t2[mt][nt][i], dw3[ht][mt]);
+                        }
+                }
+            }
+        }
+        __syncthreads();
+        // h1 and dz2 rows of the tile to the workspace (consecutive samples)
+        const int rows = (int)min((int64_t)R, a.n - base);
+        constexpr int CH = H * EB / 16;
+        for (int e = tid; e < rows * CH; e += S::NTHR) {
+            const int r = e / CH, c = e % CH;
+            const size_t off = (size_t)(base + r) * (H * EB) + (size_t)c * 16;
+            *reinterpret_cast<uint4*>(a.h1_rows + off) =
+                *reinterpret_cast<const uint4*>(h1 + r * S::P_H + c * 16);
+            *reinterpret_cast<uint4*>(a.dz2_rows + off) =
+                *reinterpret_cast<const uint4*>(dz + r * S::P_H + c * 16);
+        }
+    }
+    // this workgroup's partial sums
+    float* out = a.part_fwd + (size_t)blockIdx.x * S::FWD_FLOATS;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const int f = wave * S::FPW + mt * 16 + lr;
+#pragma unroll
+        for (int ht = 0; ht < S::NHT; ++ht)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) out[(ht * 16 + 4 * q + i) * H + f] = dw3[ht][mt][i];
+        float v = db2a[mt];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        if (q == 0) out[NHP * H + f] = v;
+    }
+    __syncthreads();
+    if (tid < NHP) out[NHP * H + H + tid] = db3s[tid];
+    if (tid == 0) out[NHP * H + H + NHP] = dlss;
+}
+
+template <int DT, int H, int KIN, int NHP>
+__global__ void __launch_bounds__((AcShape<DT, H, KIN, NHP>::NTHR))
+k_ac_bwd1(AcArgs a) {
+    using S = AcShape<DT, H, KIN, NHP>;
+    using M = typename S::M;
+    using Frag = typename S::Frag;
+    constexpr int R = S::R, MT = S::MT, K = S::K, KC = S::KC, EB = S::EB;
+    __shared__ __attribute__((aligned(16))) char x0[R * S::P_IN];
+    __shared__ __attribute__((aligned(16))) char x0T[S::KT * 16 * S::P_T];
+    __shared__ __attribute__((aligned(16))) char dz[R * S::P_H];
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lr = lane & 15, q = lane >> 4;
+    const int kq = q * KC;
+    const PolicyArgs& p = a.pol;
+    // layer-1 rows of this wave's features, and the columns of W2 at these
+    // features (B of dh1 = dz2 W2: K runs over layer-2 features)
+    Frag w1[MT][S::K1S], w2t[MT][S::K2S];
+    float b1v[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const int f = wave * S::FPW + mt * 16 + lr;
+#pragma unroll
+        for (int ks = 0; ks < S::K1S; ++ks) load_a(w1[mt][ks], p.w1, p.d_in, f, H, ks * K + kq, p.d_in);
+#pragma unroll
+        for (int ks = 0; ks < S::K2S; ++ks) load_col(w2t[mt][ks], p.w2, H, f, ks * K + kq, H);
+        b1v[mt] = p.b1[f];
+    }
+    f32x4 dw1[MT][S::KT];
+    float db1a[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        db1a[mt] = 0.0f;
+#pragma unroll
+        for (int it = 0; it < S::KT; ++it) dw1[mt][it] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    // transposed-input rows >= KIN stay zero
+    for (int e = tid; e < (S::KT * 16 - KIN) * R; e += S::NTHR)
+        put<DT>(x0T + (KIN + e / R) * S::P_T + (e % R) * EB, 0.0f);
+
+    const int64_t n_tiles = (a.n + R - 1) / R;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t base = tile * R;
+        __syncthreads();
+        stage_obs<S, DT>(a, base, x0, x0T, tid);
+        const int rows = (int)min((int64_t)R, a.n - base);
+        constexpr int CH = H * EB / 16;
+        for (int e = tid; e < R * CH; e += S::NTHR) {
+            const int r = e / CH, c = e % CH;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (r < rows)
+                v = *reinterpret_cast<const uint4*>(a.dz2_rows + (size_t)(base + r) * (H * EB) +
+                                                    (size_t)c * 16);
+            *reinterpret_cast<uint4*>(dz + r * S::P_H + c * 16) = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            f32x4 dz1[2];
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                f32x4 acc = {b1v[mt], b1v[mt], b1v[mt], b1v[mt]};
+#pragma unroll
+                for (int ks = 0; ks < S::K1S; ++ks)
+                    acc = M::mma(M::lds(x0 + (nt * 16 + lr) * S::P_IN + (ks * K + kq) * EB), w1[mt][ks], acc);
+                f32x4 g = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < S::K2S; ++ks)
+                    g = M::mma(M::lds(dz + (nt * 16 + lr) * S::P_H + (ks * K + kq) * EB), w2t[mt][ks], g);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float t = act_tanh(acc[i]);
+                    dz1[nt][i] = g[i] * (1.0f - t * t);
+                    db1a[mt] += dz1[nt][i];
+                }
+            }
+            // dW1 += dz1^T x0 (K = the tile's samples in accumulator order)
+#pragma unroll
+            for (int it = 0; it < S::KT; ++it) {
+                if constexpr (DT == DT_BF16) {
+                    dw1[mt][it] = M::mma(pack_acc_k(dz1[0], dz1[1]),
+                                         lds_k_perm(x0T, S::P_T, it * 16 + lr, q), dw1[mt][it]);
+                } else {
+#pragma unroll
+                    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const float B_ = *reinterpret_cast<const float*>(
+                                x0T + (it * 16 + lr) * S::P_T + (16 * nt + 4 * q + i) * EB);
+                            dw1[mt][it] = M::mma(dz1[nt][i], B_, dw1[mt][it]);
+                        }
+                }
+            }
+        }
+    }
+    float* out = a.part_bwd + (size_t)blockIdx.x * S::BWD_FLOATS;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const int f0 = wave * S::FPW + mt * 16;
+#pragma unroll
+        for (int it = 0; it < S::KT; ++it)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (it * 16 + lr < KIN) out[(f0 + 4 * q + i) * KIN + it * 16 + lr] = dw1[mt][it][i];
+        float v = db1a[mt];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        if (q == 0) out[H * KIN + f0 + lr] = v;
+    }
+}
+
+// dW2[j][k] = sum_i dz2[i][j] h1[i][k] over this workgroup's tiles: the two
+// row tiles are transposed into LDS ([feature][sample]) so both operands
+// read K = samples contiguously.
+template <int DT, int H, int KIN, int NHP>
+__global__ void __launch_bounds__((AcShape<DT, H, KIN, NHP>::NTHR))
+k_ac_dw2(AcArgs a) {
+    using S = AcShape<DT, H, KIN, NHP>;
+    using M = typename S::M;
+    constexpr int R = S::R, MT = S::MT, K = S::K, KC = S::KC, EB = S::EB, NKT = H / 16;
+    __shared__ __attribute__((aligned(16))) char dzT[H * S::P_T];
+    __shared__ __attribute__((aligned(16))) char h1T[H * S::P_T];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lr = lane & 15, q = lane >> 4;
+    const int kq = q * KC;
+    f32x4 acc[MT][NKT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int kt = 0; kt < NKT; ++kt) acc[mt][kt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int64_t n_tiles = (a.n + R - 1) / R;
+    constexpr int PER = 16 / EB;   // elements per 16-byte chunk
+    constexpr int CH = H / PER;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t base = tile * R;
+        const int rows = (int)min((int64_t)R, a.n - base);
+        __syncthreads();
+        for (int e = tid; e < R * CH; e += S::NTHR) {
+            const int r = e / CH, c = e % CH;
+            uint4 vd = make_uint4(0u, 0u, 0u, 0u), vh = vd;
+            if (r < rows) {
+                const size_t off = (size_t)(base + r) * (H * EB) + (size_t)c * 16;
+                vd = *reinterpret_cast<const uint4*>(a.dz2_rows + off);
+                vh = *reinterpret_cast<const uint4*>(a.h1_rows + off);
+            }
+            if constexpr (EB == 2) {
+                uint16_t d16[8], h16[8];
+                __builtin_memcpy(d16, &vd, 16);
+                __builtin_memcpy(h16, &vh, 16);
+#pragma unroll
+                for (int x = 0; x < 8; ++x) {
+                    *reinterpret_cast<uint16_t*>(dzT + (c * 8 + x) * S::P_T + r * 2) = d16[x];
+                    *reinterpret_cast<uint16_t*>(h1T + (c * 8 + x) * S::P_T + r * 2) = h16[x];
+                }
+            } else {
+                uint32_t d32[4], h32[4];
+                __builtin_memcpy(d32, &vd, 16);
+                __builtin_memcpy(h32, &vh, 16);
+#pragma unroll
+                for (int x = 0; x < 4; ++x) {
+                    *reinterpret_cast<uint32_t*>(dzT + (c * 4 + x) * S::P_T + r * 4) = d32[x];
+                    *reinterpret_cast<uint32_t*>(h1T + (c * 4 + x) * S::P_T + r * 4) = h32[x];
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < R / K; ++ks) {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const auto A_ = M::lds(dzT + (wave * S::FPW + mt * 16 + lr) * S::P_T + (ks * K + kq) * EB);
+#pragma unroll
+                for (int kt = 0; kt < NKT; ++kt)
+                    acc[mt][kt] = M::mma(A_, M::lds(h1T + (kt * 16 + lr) * S::P_T + (ks * K + kq) * EB),
+                                         acc[mt][kt]);
+            }
+        }
+    }
+    float* out = a.part_w2 + (size_t)blockIdx.x * H * H;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int kt = 0; kt < NKT; ++kt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                out[(size_t)(wave * S::FPW + mt * 16 + 4 * q + i) * H + kt * 16 + lr] = acc[mt][kt][i];
+}
+
+// out[r][c] = sum over parts g of part[g * stride + off + r * cols_in + c],
+// r < rows, c < cols.
+__global__ void __launch_bounds__(256)
+k_ac_sum(const float* __restrict__ part, int64_t stride, int nparts, int64_t off, int rows,
+         int cols, int cols_in, float* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)rows * cols) return;
+    const int r = (int)(e / cols), c = (int)(e % cols);
+    const float* src = part + off + (int64_t)r * cols_in + c;
+    float s = 0.0f;
+    for (int g = 0; g < nparts; ++g) s += src[(size_t)g * stride];
+    out[e] = s;
+}
+
+// Adam (Kingma and Ba 2015, Algorithm 1), one element per thread; c1 and c2
+// are the bias corrections 1 - beta^t. The updated parameter is also stored
+// in the policy's format (`store`, NULL to skip).
+__global__ void __launch_bounds__(256)
+k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+       float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float c1,
+       float c2, void* __restrict__ store, int store_dtype) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = pi;
+    if (store) {
+        if (store_dtype == DT_BF16)
+            static_cast<__bf16*>(store)[i] = (__bf16)pi;
+        else
+            static_cast<float*>(store)[i] = pi;
+    }
+}
+
+template <int DT, int H, int KIN, int NHP>
+struct AcVariant {
+    using S = AcShape<DT, H, KIN, NHP>;
+    static hipError_t run(const AcArgs& a, int grid1, int grid2, const AcOut& o, hipStream_t s) {
+        hipLaunchKernelGGL((k_ac_fwd<DT, H, KIN, NHP>), dim3(grid1), dim3(S::NTHR), 0, s, a);
+        hipLaunchKernelGGL((k_ac_bwd1<DT, H, KIN, NHP>), dim3(grid1), dim3(S::NTHR), 0, s, a);
+        hipLaunchKernelGGL((k_ac_dw2<DT, H, KIN, NHP>), dim3(grid2), dim3(S::NTHR), 0, s, a);
+        const PolicyArgs& p = a.pol;
+        auto sum = [&](const float* part, int64_t stride, int nparts, int64_t off, int rows,
+                       int cols, int cols_in, float* out) {
+            const int64_t total = (int64_t)rows * cols;
+            hipLaunchKernelGGL(k_ac_sum, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                               part, stride, nparts, off, rows, cols, cols_in, out);
+        };
+        const int F = S::FWD_FLOATS, B = S::BWD_FLOATS;
+        sum(a.part_fwd, F, grid1, 0, p.n_head, H, H, o.w3);
+        sum(a.part_fwd, F, grid1, (int64_t)NHP * H, 1, H, H, o.b2);
+        sum(a.part_fwd, F, grid1, (int64_t)NHP * H + H, 1, p.n_head, p.n_head, o.b3);
+        if (o.log_std) sum(a.part_fwd, F, grid1, (int64_t)NHP * H + H + NHP, 1, 1, 1, o.log_std);
+        sum(a.part_bwd, B, grid1, 0, H, p.d_in, KIN, o.w1);
+        sum(a.part_bwd, B, grid1, (int64_t)H * KIN, 1, H, H, o.b1);
+        sum(a.part_w2, (int64_t)H * H, grid2, 0, H, H, H, o.w2);
+        return hipGetLastError();
+    }
+    static size_t part_floats(int grid1, int grid2) {
+        return (size_t)grid1 * (S::FWD_FLOATS + S::BWD_FLOATS) + (size_t)grid2 * H * H;
+    }
+};
+
+// (dtype, hidden, padded input width, padded head width) of the compiled
+// update kernels: CartPole's FP32 policy, the BF16 policies with narrow and
+// wide heads.
+template <class F>
+hipError_t with_variant(int dtype, int hidden, int d_in, int n_head, F&& f) {
+    if (dtype == DT_F32 && hidden == 64 && d_in <= 4 && n_head <= 16)
+        return f(AcVariant<DT_F32, 64, 4, 16>{});
+    if (dtype == DT_BF16 && hidden == 256 && d_in <= 32 && n_head <= 16)
+        return f(AcVariant<DT_BF16, 256, 32, 16>{});
+    if (dtype == DT_BF16 && hidden == 256 && d_in <= 32 && n_head <= 64)
+        return f(AcVariant<DT_BF16, 256, 32, 64>{});
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+bool ac_supported(int dtype, int hidden, int d_in, int n_head) {
+    return with_variant(dtype, hidden, d_in, n_head, [](auto) { return hipSuccess; }) ==
+           hipSuccess;
+}
+
+size_t ac_workspace_bytes(int dtype, int hidden, int64_t n, int grid1, int grid2) {
+    const size_t al = 256;
+    const size_t rows = (size_t)n * hidden * (dtype == DT_BF16 ? 2 : 4);
+    // partial sums of the widest head compiled for this format and width
+    size_t part = 0;
+    if (dtype == DT_F32 && hidden == 64)
+        part = AcVariant<DT_F32, 64, 4, 16>::part_floats(grid1, grid2);
+    else if (dtype == DT_BF16 && hidden == 256)
+        part = AcVariant<DT_BF16, 256, 32, 64>::part_floats(grid1, grid2);
+    return al + 2 * ((rows + al - 1) / al * al) + part * sizeof(float);
+}
+
+hipError_t launch_ac_grad(const AcLaunch& l, hipStream_t s) {
+    const PolicyArgs& p = l.args.pol;
+    return with_variant(l.dtype, p.hidden, p.d_in, p.n_head, [&](auto v) {
+        using V = decltype(v);
+        AcArgs a = l.args;
+        // carve the workspace: h1 rows, dz2 rows, partial sums
+        const size_t al = 256;
+        const size_t rows = (size_t)a.n * p.hidden * (l.dtype == DT_BF16 ? 2 : 4);
+        char* w = reinterpret_cast<char*>(((uintptr_t)l.workspace + al - 1) / al * al);
+        a.h1_rows = w;
+        w += (rows + al - 1) / al * al;
+        a.dz2_rows = w;
+        w += (rows + al - 1) / al * al;
+        using S = typename V::S;
+        a.part_fwd = reinterpret_cast<float*>(w);
+        a.part_bwd = a.part_fwd + (size_t)l.grid1 * S::FWD_FLOATS;
+        a.part_w2 = a.part_bwd + (size_t)l.grid1 * S::BWD_FLOATS;
+        return V::run(a, l.grid1, l.grid2, l.out, s);
+    });
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
+                       float b1, float b2, float eps, float c1, float c2, void* store,
+                       int store_dtype, hipStream_t s) {
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, g, m, v, n,
+                       lr, b1, b2, eps, c1, c2, store, store_dtype);
+    return hipGetLastError();
+}
+
+}  // namespace wsx

@@ -505,3 +505,85 @@ def env_shape(env):
     v = [C.c_int32() for _ in range(4)]
     _check(L.wsx_env_shape(env.handle, *[C.byref(x) for x in v]))
     return tuple(x.value for x in v)
+
+
+# ------------------------------------------------------ actor-critic update ----
+
+class _Grads(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("w1", "b1", "w2", "b2", "w3", "b3", "log_std")]
+
+
+EXPORTS += ["wsx_ac_grad_workspace_bytes", "wsx_ac_grad", "wsx_adam_step"]
+
+
+def _update_sigs(L):
+    if getattr(L, "_update_sigs", False):
+        return
+    vp = C.c_void_p
+    L.wsx_ac_grad_workspace_bytes.argtypes = [C.POINTER(_Policy), C.c_int64,
+                                              C.POINTER(C.c_size_t)]
+    L.wsx_ac_grad.argtypes = [C.POINTER(_Policy), C.c_int32, vp, vp, vp, vp, C.c_int64,
+                              C.c_float, C.c_float, C.POINTER(_Grads), vp, C.c_size_t, vp]
+    L.wsx_adam_step.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int32, C.c_float, C.c_float,
+                                C.c_float, C.c_float, vp, C.c_int32, vp]
+    L._update_sigs = True
+
+
+class Grads:
+    """FP32 gradient tensors shaped like a policy's weights (device)."""
+
+    NAMES = ("w1", "b1", "w2", "b2", "w3", "b3", "log_std")
+
+    def __init__(self, policy, device="cuda"):
+        h = policy.host if isinstance(policy, DevicePolicy) else policy
+        shapes = {"w1": (h.h1, h.d_in), "b1": (h.h1,), "w2": (h.h2, h.h1), "b2": (h.h2,),
+                  "w3": (h.n_head, h.h2), "b3": (h.n_head,), "log_std": (1,)}
+        self.tensors = {n: torch.zeros(shapes[n], dtype=torch.float32, device=device)
+                        for n in self.NAMES}
+        self.c = _Grads(*[self.tensors[n].data_ptr() for n in self.NAMES])
+
+    def __getitem__(self, name):
+        return self.tensors[name]
+
+
+def ac_grad(policy, n_actions, obs, action, returns, advantages, value_coef=0.5,
+            entropy_coef=0.0, grads=None, workspace=None, stream=None):
+    """Gradient of the actor-critic loss over the samples (flat views of a
+    trajectory's fields: obs [n][d_in], action [n], returns and advantages
+    [n] float32, all on the device). n_actions: K for a categorical policy,
+    0 for a Gaussian one. Returns a Grads."""
+    L = lib()
+    _update_sigs(L)
+    n = int(returns.numel())
+    for t in (obs, action, returns, advantages):
+        assert t.is_cuda and t.is_contiguous()
+    assert obs.numel() == n * policy.host.d_in and action.numel() == n and advantages.numel() == n
+    need = C.c_size_t()
+    _check(L.wsx_ac_grad_workspace_bytes(C.byref(policy.c), n, C.byref(need)))
+    if workspace is None or workspace.numel() < need.value:
+        workspace = torch.empty(need.value, dtype=torch.uint8, device="cuda")
+    grads = grads or Grads(policy)
+    _check(L.wsx_ac_grad(C.byref(policy.c), int(n_actions), obs.data_ptr(), action.data_ptr(),
+                         returns.data_ptr(), advantages.data_ptr(), n, float(value_coef),
+                         float(entropy_coef), C.byref(grads.c), workspace.data_ptr(),
+                         workspace.numel(), _stream(stream)))
+    return grads
+
+
+def adam_step(param, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, store=None,
+              stream=None):
+    """One Adam step on FP32 device tensors in place; `store` (optional) is a
+    tensor of the same size in float32 or bfloat16 that receives the new
+    values (a policy's own weight buffer)."""
+    L = lib()
+    _update_sigs(L)
+    n = param.numel()
+    for t in (param, grad, m, v):
+        assert t.is_cuda and t.is_contiguous() and t.dtype == torch.float32 and t.numel() == n
+    sd = F32
+    if store is not None:
+        assert store.numel() == n and store.is_contiguous()
+        sd = BF16 if store.dtype in (torch.bfloat16, torch.int16, torch.uint16) else F32
+    _check(L.wsx_adam_step(param.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(), n,
+                           int(step), float(lr), float(beta1), float(beta2), float(eps),
+                           None if store is None else store.data_ptr(), sd, _stream(stream)))

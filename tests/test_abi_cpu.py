@@ -141,3 +141,44 @@ def test_autotune_validation_without_gpu():
     assert L.wsx_autotune(C.byref(d), C.byref(pol), 50, 0, 1234, n.value, None, None) == -1
     assert L.wsx_autotune(C.byref(d), C.byref(pol), 50, 3, 1234, 16, None, None) == -1
     assert L.wsx_env_shape(None, None, None, None, None) == -1
+
+
+def _fake_policy(wsx, dtype, d_in, h, n_head, log_std=True):
+    p = 0x1000   # never dereferenced: validation rejects before any launch
+    return wsx._Policy(dtype, d_in, h, h, n_head, p, p, p, p, p, p, None, None, None,
+                       (C.c_float * 3)(1.0, 1.0, 1.0), p if log_std else None)
+
+
+def test_update_validation_without_gpu():
+    wsx, L = _lib()
+    wsx._update_sigs(L)
+    out = C.c_size_t()
+    pend = _fake_policy(wsx, wsx.BF16, 3, 256, 2)
+    assert L.wsx_ac_grad_workspace_bytes(C.byref(pend), 0, C.byref(out)) == -1
+    assert L.wsx_ac_grad_workspace_bytes(C.byref(pend), 1000, C.byref(out)) == 0
+    assert out.value >= 2 * 1000 * 256 * 2                    # h1 and dz2 rows, BF16
+    fp8 = _fake_policy(wsx, wsx.FP8_E4M3, 20, 512, 41)
+    assert L.wsx_ac_grad_workspace_bytes(C.byref(fp8), 10, C.byref(out)) == -2
+    wide = _fake_policy(wsx, wsx.BF16, 3, 512, 2)
+    assert L.wsx_ac_grad_workspace_bytes(C.byref(wide), 10, C.byref(out)) == -2
+    g = wsx._Grads(*([0x1000] * 7))
+    p = 0x1000
+    # n_actions must match the head: Gaussian needs n_head 2, categorical K + 1
+    assert L.wsx_ac_grad(C.byref(pend), 3, p, p, p, p, 10, 0.5, 0.0, C.byref(g), p, 1 << 30,
+                         None) == -1
+    cart = _fake_policy(wsx, wsx.F32, 4, 64, 3, log_std=False)
+    assert L.wsx_ac_grad(C.byref(cart), 0, p, p, p, p, 10, 0.5, 0.0, C.byref(g), p, 1 << 30,
+                         None) == -2
+    assert L.wsx_ac_grad(C.byref(pend), 0, p, p, p, p, 10, 0.5, 0.0, C.byref(g), p, 16,
+                         None) == -1                            # workspace too small
+    assert b"workspace" in L.wsx_last_error()
+    assert L.wsx_ac_grad(C.byref(pend), 0, None, p, p, p, 10, 0.5, 0.0, C.byref(g), p, 1 << 30,
+                         None) == -1
+    assert L.wsx_ac_grad(C.byref(pend), 0, p, p, p, p, 10, float("nan"), 0.0, C.byref(g), p,
+                         1 << 30, None) == -1
+    # Adam
+    assert L.wsx_adam_step(p, p, p, p, 10, 0, 1e-3, 0.9, 0.999, 1e-8, None, 0, None) == -1
+    assert L.wsx_adam_step(p, p, p, p, 10, 1, 1e-3, 1.0, 0.999, 1e-8, None, 0, None) == -1
+    assert L.wsx_adam_step(p, p, p, p, 10, 1, 1e-3, 0.9, 0.999, 1e-8, p, 2, None) == -1
+    assert L.wsx_adam_step(None, None, None, None, 0, 1, 1e-3, 0.9, 0.999, 1e-8, None, 0,
+                           None) == 0

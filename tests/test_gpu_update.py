@@ -1,0 +1,178 @@
+"""The actor-critic update on the device (wsx_ac_grad, wsx_adam_step) against
+the FP64 oracle, on trajectories the GPU rolled out itself.
+
+Tolerance (per gradient tensor, relative to the tensor's largest entry):
+FP32 policy 1e-5 (FP32 against FP64 sums over a few hundred samples;
+observed <= 2.4e-7); BF16 policies 2e-3: the GPU's FP32 pre-activations and
+the oracle's FP64 ones round to different BF16 neighbours near midpoints (the
+forward's known flips), and each backward operand the GPU rounds (head
+gradient, dz2, dz1) can round the other way for the same reason; every flip
+moves one term by one BF16 step (2^-8 relative) (observed <= 3.8e-4)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_cases import DTYPE, HIDDEN, say
+from paper_2408_00930_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-5, "bf16": 2e-3}
+CV, CE = 0.5, 0.01
+
+
+def _wsx():
+    from paper_2408_00930_amd import wsx
+    return wsx
+
+
+def _rollout(kind, n_envs, T, seed):
+    import torch
+    wsx = _wsx()
+    pol = inputs.policy_for(kind, DTYPE[kind], HIDDEN[kind], seed=seed)
+    offs = inputs.agent_offsets(n_envs, seed=seed) if kind == O.MARKET else None
+    env = wsx.Env(kind, n_envs, seed=seed, agent_offsets=offs)
+    dp = wsx.DevicePolicy(pol)
+    tr = wsx.Trajectory(kind, T, env.rows)
+    wsx.env_reset(env, 1)
+    wsx.rollout(env, dp, T, tr)
+    ret, adv = wsx.compute_returns(tr, T, inputs.GAMMA, inputs.LAMBDA, True, torch.float32)
+    torch.cuda.synchronize()
+    return pol, dp, tr, ret, adv, env.rows
+
+
+def _oracle(pol, kind, tr, ret, adv):
+    n_act = O.n_actions(kind)
+    obs = tr.obs.reshape(-1, pol.d_in).cpu().numpy().astype(np.float64)
+    act = tr.action.reshape(-1).cpu().numpy().astype(np.float64)
+    return O.ac_grad(pol, n_act, obs, act, adv.reshape(-1).cpu().numpy(),
+                     ret.reshape(-1).cpu().numpy(), CV, CE, quant_backward=True,
+                     log_std=pol.exact("log_std")[:1])
+
+
+def _compare(got, want, dtype, what):
+    worst = 0.0
+    for k, w in want.items():
+        g = got[k].cpu().numpy().astype(np.float64).reshape(w.shape)
+        scale = max(np.abs(w).max(), 1e-30)
+        err = np.abs(g - w).max() / scale
+        worst = max(worst, err)
+        print(f"  {what} {k}: max |grad| {scale:.3g}, max error / max |grad| {err:.3g}",
+              flush=True)
+        assert err <= TOL[dtype], (what, k, err)
+    return worst
+
+
+@pytest.mark.parametrize("kind,n_envs,T", [(O.CARTPOLE, 45, 9), (O.PENDULUM, 53, 7),
+                                           (O.ACROBOT, 40, 5), (O.MARKET, 3, 3)])
+def test_ac_grad_matches_oracle(kind, n_envs, T):
+    import json
+    wsx = _wsx()
+    say("ac_grad", kind, n_envs, T)
+    pol, dp, tr, ret, adv, rows = _rollout(kind, n_envs, T, seed=kind)
+    n_act = O.n_actions(kind)
+    g = wsx.ac_grad(dp, n_act, tr.obs.reshape(-1, pol.d_in), tr.action.reshape(-1),
+                    ret.reshape(-1), adv.reshape(-1), CV, CE)
+    want = _oracle(pol, kind, tr, ret, adv)
+    worst = _compare(g, want, pol.dtype, f"kind {kind}")
+    print("PRECISION " + json.dumps({"update": kind, "dtype": pol.dtype, "samples": rows * T,
+                                     "grad_rel_max": worst}), flush=True)
+
+
+def test_ac_grad_one_sample_and_ragged_counts():
+    wsx = _wsx()
+    say("ac_grad small counts")
+    pol, dp, tr, ret, adv, rows = _rollout(O.PENDULUM, 50, 2, seed=4)
+    obs, act = tr.obs.reshape(-1, pol.d_in), tr.action.reshape(-1)
+    r, a = ret.reshape(-1), adv.reshape(-1)
+    for n in (1, 31, 33, 95):
+        g = wsx.ac_grad(dp, 0, obs[:n].contiguous(), act[:n].contiguous(), r[:n].contiguous(),
+                        a[:n].contiguous(), CV, CE)
+        want = O.ac_grad(pol, 0, obs[:n].cpu().numpy().astype(np.float64),
+                         act[:n].cpu().numpy().astype(np.float64), a[:n].cpu().numpy(),
+                         r[:n].cpu().numpy(), CV, CE, True, pol.exact("log_std")[:1])
+        _compare(g, want, pol.dtype, f"n={n}")
+
+
+def test_ac_grad_full_size_is_the_sample_weighted_mean_of_its_halves():
+    """At the benchmark's size (10,000 Pendulum rows x 200 steps) the gradient
+    over all samples equals the sample-weighted mean of the gradients over the
+    two halves (every launch averages over its own samples)."""
+    import torch
+    wsx = _wsx()
+    say("ac_grad full size")
+    pol, dp, tr, ret, adv, rows = _rollout(O.PENDULUM, 10000, 200, seed=0)
+    obs, act = tr.obs.reshape(-1, pol.d_in), tr.action.reshape(-1)
+    r, a = ret.reshape(-1), adv.reshape(-1)
+    n = r.numel()
+    h = n // 2 + 17
+    full = wsx.ac_grad(dp, 0, obs, act, r, a, CV, CE)
+    g1 = wsx.ac_grad(dp, 0, obs[:h].contiguous(), act[:h].contiguous(), r[:h].contiguous(),
+                     a[:h].contiguous(), CV, CE)
+    g2 = wsx.ac_grad(dp, 0, obs[h:].contiguous(), act[h:].contiguous(), r[h:].contiguous(),
+                     a[h:].contiguous(), CV, CE)
+    torch.cuda.synchronize()
+    for k in wsx.Grads.NAMES:
+        f = full[k].double()
+        mix = (g1[k].double() * h + g2[k].double() * (n - h)) / n
+        scale = f.abs().max().item()
+        assert torch.isfinite(f).all()
+        assert (f - mix).abs().max().item() <= 5e-4 * scale + 1e-12, k
+    # and the first 512 samples against the oracle
+    m = 512
+    g = wsx.ac_grad(dp, 0, obs[:m].contiguous(), act[:m].contiguous(), r[:m].contiguous(),
+                    a[:m].contiguous(), CV, CE)
+    want = O.ac_grad(pol, 0, obs[:m].cpu().numpy().astype(np.float64),
+                     act[:m].cpu().numpy().astype(np.float64), a[:m].cpu().numpy(),
+                     r[:m].cpu().numpy(), CV, CE, True, pol.exact("log_std")[:1])
+    _compare(g, want, pol.dtype, "full-size prefix")
+
+
+def test_adam_matches_oracle_and_stores_bf16():
+    import torch
+    wsx = _wsx()
+    say("adam")
+    rng = np.random.default_rng(2)
+    n = 70001
+    theta = rng.normal(0, 0.1, n)
+    m, v = np.zeros(n), np.zeros(n)
+    p_d = torch.from_numpy(theta.astype(np.float32)).cuda()
+    m_d, v_d = torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda")
+    store = torch.zeros(n, dtype=torch.bfloat16, device="cuda")
+    th = p_d.double().cpu().numpy().copy()
+    for step in (1, 2, 3):
+        g = rng.normal(0, 1e-3, n)
+        g_d = torch.from_numpy(g.astype(np.float32)).cuda()
+        wsx.adam_step(p_d, g_d, m_d, v_d, step, 1e-3, store=store)
+        O.adam(th, g_d.double().cpu().numpy(), m, v, step, 1e-3)
+        got = p_d.double().cpu().numpy()
+        assert np.allclose(got, th, rtol=1e-5, atol=1e-6), step
+        assert torch.equal(store, p_d.to(torch.bfloat16))
+
+
+def test_update_step_changes_the_policy_the_rollout_uses():
+    """Gradient, Adam into the policy's own BF16 weights, and a new roll-out
+    that sees them: the next policy's forward equals the oracle's forward with
+    the updated weights."""
+    import torch
+    wsx = _wsx()
+    say("update loop")
+    pol, dp, tr, ret, adv, rows = _rollout(O.PENDULUM, 64, 6, seed=9)
+    g = wsx.ac_grad(dp, 0, tr.obs.reshape(-1, pol.d_in), tr.action.reshape(-1),
+                    ret.reshape(-1), adv.reshape(-1), CV, CE)
+    masters = {k: torch.from_numpy(pol.exact(k).astype(np.float32)).cuda().reshape(-1)
+               for k in ("w1", "w2", "w3")}
+    for k in ("w1", "w2", "w3"):
+        mk, vk = torch.zeros_like(masters[k]), torch.zeros_like(masters[k])
+        wsx.adam_step(masters[k], g[k].reshape(-1), mk, vk, 1, 1e-2, store=dp.tensors[k].reshape(-1))
+    torch.cuda.synchronize()
+    obs = torch.randn(40, pol.d_in, device="cuda")
+    head = wsx.policy_forward(dp, obs).cpu().numpy()
+    w_new = {k: O.round_bf16(masters[k].double().cpu().numpy()).reshape(getattr(pol, k).shape)
+             for k in ("w1", "w2", "w3")}
+    hold = O._MlpHold("bf16", w_new["w1"], pol.exact("b1"), w_new["w2"], pol.exact("b2"),
+                      w_new["w3"], pol.exact("b3"))
+    want = O.mlp_forward(hold, obs.cpu().numpy().astype(np.float64))
+    assert np.abs(head - want).max() <= 2e-2
+    old = O.mlp_forward(pol, obs.cpu().numpy().astype(np.float64))
+    assert np.abs(head - old).max() > 1e-3     # the update moved the policy
