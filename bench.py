@@ -35,6 +35,69 @@ def policy_flops(pol):
     return 2 * (pol.d_in * pol.h1 + pol.h1 * pol.h2 + pol.h2 * pol.n_head)
 
 
+def update_flops(pol):
+    """Algorithmic FLOP of one sample of the actor-critic update: the forward
+    pass again, then dz2 = dhead W3, dh1 = dz2 W2 and the weight gradients
+    dW3, dW2, dW1 (unpadded MACs, two FLOP each)."""
+    back = 2 * (2 * pol.n_head * pol.h2 + 2 * pol.h1 * pol.h2 + pol.h1 * pol.d_in)
+    return policy_flops(pol) + back
+
+
+def update_leg(sets, steps, wsx, torch):
+    """The on-device actor-critic update over each set's last trajectory and
+    returns: the gradient over every sample (wsx_ac_grad), then one Adam step
+    per tensor into FP32 masters that write the policy's own weights. One
+    untimed pass, then `steps` passes timed with events on the stream."""
+    legs = []
+    for s in sets:
+        if s.policy.dtype not in ("f32", "bf16"):
+            continue
+        obs = s.traj.obs.reshape(-1, s.policy.d_in)
+        act = s.traj.action.reshape(-1)
+        r, a = s.ret.reshape(-1), s.adv.reshape(-1)
+        g = wsx.Grads(s.dp)
+        need = wsx.ac_grad_workspace_bytes(s.dp, r.numel())
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+        names = ["w1", "b1", "w2", "b2", "w3", "b3"] + (["log_std"] if not wsx.N_ACTIONS[s.kind] else [])
+        master = {k: torch.from_numpy(s.policy.exact(k).astype("float32")).cuda().reshape(-1)
+                  for k in names}
+        if "log_std" in master:
+            master["log_std"] = master["log_std"][:1].clone()
+        mom = {k: (torch.zeros_like(v), torch.zeros_like(v)) for k, v in master.items()}
+        store = {k: s.dp.tensors[k].reshape(-1)[:master[k].numel()] for k in names}
+        legs.append((s, obs, act, r, a, g, ws, names, master, mom, store))
+
+    def one(t):
+        for s, obs, act, r, a, g, ws, names, master, mom, store in legs:
+            wsx.ac_grad(s.dp, wsx.N_ACTIONS[s.kind], obs, act, r, a, 0.5, 0.01, grads=g,
+                        workspace=ws)
+            for k in names:
+                wsx.adam_step(master[k], g[k].reshape(-1)[:master[k].numel()], mom[k][0],
+                              mom[k][1], t, 3e-4, store=store[k])
+    if not legs:
+        return None
+    one(1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for t in range(steps):
+        one(t + 2)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    samples = sum(l[3].numel() for l in legs)
+    flop = sum(update_flops(l[0].policy) * l[3].numel() for l in legs)
+    dtype = legs[0][0].policy.dtype
+    tflops = flop / (ms * 1e-3) / 1e12
+    return {"samples": samples, "steps": steps, "ms_per_update": round(ms, 4),
+            "samples_per_s": round(samples / ms * 1e3, 1),
+            "flop_per_sample": {l[0].key: update_flops(l[0].policy) for l in legs},
+            "achieved_tflops": round(tflops, 2), "peak_tflops": PEAK_TFLOPS[dtype],
+            "frac": round(tflops / PEAK_TFLOPS[dtype], 4),
+            "what": "gradient of the actor-critic loss over every sample of the sets' "
+                    "trajectories plus one Adam step per tensor into the policy weights"}
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2408_00930_amd", "csrc")
@@ -274,6 +337,9 @@ def main():
                     help="run a multi-set workload as one launch per set on its own stream")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="run the built-in default kernel shapes instead of the autotuner's")
+    ap.add_argument("--update-steps", type=int, default=5,
+                    help="timed passes of the actor-critic update after the roll-out legs "
+                         "(0: skip)")
     ap.add_argument("--serve-requests", type=int, default=400,
                     help="measured requests of the serving load (0: skip serving)")
     ap.add_argument("--serve-warmup", type=int, default=50)
@@ -403,6 +469,12 @@ def main():
         out["serving"] = serving(args, wsx, inputs, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sets, args.cpu_sample_envs)
+    if args.update_steps > 0:   # last: it writes new weights into the policies
+        upd = update_leg(sets, args.update_steps, wsx, torch)
+        if upd:
+            out["update"] = upd
+            print(f"[bench] update: {upd['ms_per_update']} ms per update", file=sys.stderr,
+                  flush=True)
     print(json.dumps(out), flush=True)
 
 

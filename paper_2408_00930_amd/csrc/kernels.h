@@ -96,8 +96,9 @@ struct AcArgs {
     int64_t n;
     int32_t n_act;           // 0: Gaussian
     float value_coef, entropy_coef, inv_n;
-    char* h1_rows;           // workspace [n][H] in the policy format
-    char* dz2_rows;          // workspace [n][H]
+    char* dz2_rows;          // workspace [n][H] in the policy format
+    char* h1_blk;            // workspace: per 32-sample tile a [H][32] block
+    char* dz2_blk;           // (feature-major) of h1 and of dz2
     float* part_fwd;         // per-workgroup partial sums of the kernels
     float* part_bwd;
     float* part_w2;

@@ -17,18 +17,20 @@
 // Four kernels:
 //  k_ac_fwd   per 32-sample tile: forward (layer 1, layer 2, head), head
 //             gradient, dz2 = (dhead W3) (1 - t2^2); accumulates dW3, db3,
-//             db2 and the log-std gradient; writes h1 and dz2 rows to the
-//             workspace.
+//             db2 and the log-std gradient; writes dz2 rows, and h1 and dz2
+//             as feature-major [H][32] blocks per tile, to the workspace.
 //  k_ac_bwd1  per tile: layer 1 again, dz1 = (dz2 W2) (1 - t1^2); accumulates
 //             dW1 and db1.
-//  k_ac_dw2   dW2 = sum_i dz2_i h1_i^T, split over the samples (split-K).
-//  k_ac_sum   per-workgroup partial sums -> the gradients.
+//  k_ac_dw2   dW2 = sum_i dz2_i h1_i^T from the blocks, split over the samples
+//             (split-K).
+//  k_ac_sum   per-workgroup partial sums -> the gradients, one launch.
 // The products run with samples as the MFMA rows (the weight fragments the
 // roll-out loads as A operands serve unchanged as B operands), so the
 // accumulators hold [sample][feature] tiles: lane l has feature l mod 16 and
 // samples 4 (l / 16) + i of each 16-sample row tile. Those tiles feed the
 // weight-gradient products (K = samples) directly, taking the K elements in
 // accumulator order; the other operand is read from LDS in the same order.
+#include <algorithm>
 #include <type_traits>
 
 #include "device.h"
@@ -91,6 +93,16 @@ __device__ __forceinline__ bf16x8 lds_k_perm(const char* T, int pitch, int c, in
 
 __device__ __forceinline__ float act_tanh(float z) { return tanh_scaled(z, kTwoLog2e); }
 
+// Four consecutive samples of one feature (an accumulator's four values) into
+// a feature-major block, rounded to the policy format.
+template <int DT>
+__device__ __forceinline__ void put4(char* p, float a0, float a1, float a2, float a3) {
+    if constexpr (DT == DT_BF16)
+        *reinterpret_cast<uint2*>(p) = make_uint2(pack_bf16x2(a0, a1), pack_bf16x2(a2, a3));
+    else
+        *reinterpret_cast<float4*>(p) = make_float4(a0, a1, a2, a3);
+}
+
 template <int DT, int H, int KIN, int NHP>
 struct AcShape {
     using M = Mma<DT>;
@@ -114,21 +126,36 @@ struct AcShape {
     static_assert(NHT * 2 <= NW, "one wave per head tile and row tile");
 };
 
-// Observation rows of a tile into LDS (zero beyond d_in and beyond n), and
-// their transpose if x0T is set.
-template <class S, int DT>
-__device__ __forceinline__ void stage_obs(const AcArgs& a, int64_t base, char* x0, char* x0T,
-                                          int tid) {
-    constexpr int KIN = S::KINP;
-    const int d_in = a.pol.d_in;
-    for (int e = tid; e < S::R * KIN; e += S::NTHR) {
-        const int r = e / KIN, i = e % KIN;
-        const int64_t n = base + r;
-        const float v = (n < a.n && i < d_in) ? a.obs[n * d_in + i] : 0.0f;
-        put<DT>(x0 + r * S::P_IN + i * S::EB, v);
-        if (x0T) put<DT>(x0T + i * S::P_T + r * S::EB, v);
+// Observation elements of a tile, loaded into registers one tile ahead (the
+// load latency hides behind the current tile), then stored into LDS rows (and
+// their transpose if x0T is set); zero beyond d_in and beyond n.
+template <class S>
+struct ObsPrefetch {
+    static constexpr int KIN = S::KINP;
+    static constexpr int PER = (S::R * KIN + S::NTHR - 1) / S::NTHR;
+    float v[PER];
+    __device__ __forceinline__ void load(const AcArgs& a, int64_t tile, int tid) {
+        const int d_in = a.pol.d_in;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = tid + u * S::NTHR;
+            const int r = e / KIN, i = e % KIN;
+            const int64_t n = tile * S::R + r;
+            v[u] = (e < S::R * KIN && n < a.n && i < d_in) ? a.obs[n * d_in + i] : 0.0f;
+        }
     }
-}
+    template <int DT>
+    __device__ __forceinline__ void store(char* x0, char* x0T, int tid) const {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = tid + u * S::NTHR;
+            if (e >= S::R * KIN) break;
+            const int r = e / KIN, i = e % KIN;
+            put<DT>(x0 + r * S::P_IN + i * S::EB, v[u]);
+            if (x0T) put<DT>(x0T + i * S::P_T + r * S::EB, v[u]);
+        }
+    }
+};
 
 template <int DT, int H, int KIN, int NHP>
 __global__ void __launch_bounds__((AcShape<DT, H, KIN, NHP>::NTHR))
@@ -144,8 +171,8 @@ k_ac_fwd(AcArgs a) {
     __shared__ __attribute__((aligned(16))) char dh[R * S::P_DH];
     __shared__ __attribute__((aligned(16))) char dhT[NHP * S::P_T];
     __shared__ float hd[R][NHP + 1];
-    __shared__ float db3s[NHP];
-    __shared__ float dlss;
+    __shared__ float db3p[R][NHP + 1];   // per sample lane: sums over its samples
+    __shared__ float dlsp[R];
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lr = lane & 15, q = lane >> 4;
     const int kq = q * KC;
@@ -184,17 +211,32 @@ k_ac_fwd(AcArgs a) {
 #pragma unroll
         for (int ht = 0; ht < S::NHT; ++ht) dw3[ht][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
-    if (tid < NHP) db3s[tid] = 0.0f;
-    if (tid == 0) dlss = 0.0f;
+    for (int e = tid; e < R * (NHP + 1); e += S::NTHR) db3p[e / (NHP + 1)][e % (NHP + 1)] = 0.0f;
+    if (tid < R) dlsp[tid] = 0.0f;
     // head-gradient padding (columns >= n_head) stays zero
     for (int e = tid; e < R * S::NHK; e += S::NTHR) put<DT>(dh + (e / S::NHK) * S::P_DH + (e % S::NHK) * EB, 0.0f);
     for (int e = tid; e < NHP * R; e += S::NTHR) put<DT>(dhT + (e / R) * S::P_T + (e % R) * EB, 0.0f);
 
     const int64_t n_tiles = (a.n + R - 1) / R;
+    ObsPrefetch<S> obs;
+    obs.load(a, blockIdx.x, tid);
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t base = tile * R;
+        char* h1b = a.h1_blk + (size_t)tile * H * R * EB;    // this tile's blocks
+        char* dzb = a.dz2_blk + (size_t)tile * H * R * EB;
         __syncthreads();   // the previous tile's LDS reads are done
-        stage_obs<S, DT>(a, base, x0, nullptr, tid);
+        obs.template store<DT>(x0, nullptr, tid);
+        // this tile's per-sample inputs (used after the head) and the next
+        // tile's observations, in flight while the layers run
+        float s_adv = 0.0f, s_ret = 0.0f, s_act = 0.0f;
+        if (tid < R && base + tid < a.n) {
+            const int64_t n = base + tid;
+            s_adv = a.adv[n];
+            s_ret = a.ret[n];
+            s_act = a.n_act == 0 ? static_cast<const float*>(a.action)[n]
+                                 : (float)static_cast<const uint8_t*>(a.action)[n];
+        }
+        obs.load(a, tile + gridDim.x, tid);
         __syncthreads();
         // layer 1
 #pragma unroll
@@ -206,9 +248,13 @@ k_ac_fwd(AcArgs a) {
 #pragma unroll
                 for (int ks = 0; ks < S::K1S; ++ks)
                     acc = M::mma(M::lds(x0 + (nt * 16 + lr) * S::P_IN + (ks * K + kq) * EB), w1[mt][ks], acc);
+                float t[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    put<DT>(h1 + (nt * 16 + 4 * q + i) * S::P_H + f * EB, act_tanh(acc[i]));
+                for (int i = 0; i < 4; ++i) {
+                    t[i] = act_tanh(acc[i]);
+                    put<DT>(h1 + (nt * 16 + 4 * q + i) * S::P_H + f * EB, t[i]);
+                }
+                put4<DT>(h1b + (size_t)(f * R + nt * 16 + 4 * q) * EB, t[0], t[1], t[2], t[3]);
             }
         }
         __syncthreads();
@@ -246,20 +292,20 @@ k_ac_fwd(AcArgs a) {
             const int r = tid;
             const int64_t n = base + r;
             const bool ok = n < a.n;
-            const float A = ok ? a.adv[n] : 0.0f;
+            const float A = s_adv;
             const int NH = p.n_head;
             auto set = [&](int o, float g) {
-                atomicAdd(&db3s[o], g);
+                db3p[r][o] += g;
                 const float gq = round_to<DT>(g);
                 put<DT>(dh + r * S::P_DH + o * EB, gq);
                 put<DT>(dhT + o * S::P_T + r * EB, gq);
             };
             if (a.n_act == 0) {
                 const float mu = hd[r][0];
-                const float act = ok ? static_cast<const float*>(a.action)[n] : mu;
+                const float act = ok ? s_act : mu;
                 const float d = (act - mu) / sigma;
                 set(0, ok ? -A * d / sigma * a.inv_n : 0.0f);
-                if (ok) atomicAdd(&dlss, (-A * (d * d - 1.0f) - a.entropy_coef) * a.inv_n);
+                if (ok) dlsp[r] += (-A * (d * d - 1.0f) - a.entropy_coef) * a.inv_n;
             } else {
                 const int KA = a.n_act;
                 float mx = hd[r][0];
@@ -272,7 +318,7 @@ k_ac_fwd(AcArgs a) {
                     const float lp = hd[r][k] - mx - lz;
                     ent -= expf(lp) * lp;
                 }
-                const int act = ok ? (int)static_cast<const uint8_t*>(a.action)[n] : -1;
+                const int act = ok ? (int)s_act : -1;
                 for (int k = 0; k < KA; ++k) {
                     const float lp = hd[r][k] - mx - lz, pk = expf(lp);
                     const float g = (A * (pk - (k == act ? 1.0f : 0.0f)) + a.entropy_coef * pk * (lp + ent)) *
@@ -280,7 +326,7 @@ k_ac_fwd(AcArgs a) {
                     set(k, ok ? g : 0.0f);
                 }
             }
-            set(NH - 1, ok ? a.value_coef * (hd[r][NH - 1] - a.ret[n]) * a.inv_n : 0.0f);
+            set(NH - 1, ok ? a.value_coef * (hd[r][NH - 1] - s_ret) * a.inv_n : 0.0f);
         }
         __syncthreads();
         // dz2 = (dhead W3) (1 - t2^2) for this wave's features; dW3 += dhead^T h2
@@ -293,13 +339,15 @@ k_ac_fwd(AcArgs a) {
 #pragma unroll
                 for (int ks = 0; ks < S::KO; ++ks)
                     acc = M::mma(M::lds(dh + (nt * 16 + lr) * S::P_DH + (ks * K + kq) * EB), w3t[mt][ks], acc);
+                float g[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const float t = t2[mt][nt][i];
-                    const float g = acc[i] * (1.0f - t * t);
-                    db2a[mt] += g;
-                    put<DT>(dz + (nt * 16 + 4 * q + i) * S::P_H + f * EB, g);
+                    g[i] = acc[i] * (1.0f - t * t);
+                    db2a[mt] += g[i];
+                    put<DT>(dz + (nt * 16 + 4 * q + i) * S::P_H + f * EB, g[i]);
                 }
+                put4<DT>(dzb + (size_t)(f * R + nt * 16 + 4 * q) * EB, g[0], g[1], g[2], g[3]);
             }
 #pragma unroll
             for (int ht = 0; ht < S::NHT; ++ht) {
@@ -320,14 +368,12 @@ k_ac_fwd(AcArgs a) {
             }
         }
         __syncthreads();
-        // h1 and dz2 rows of the tile to the workspace (consecutive samples)
+        // dz2 rows of the tile to the workspace (consecutive samples)
         const int rows = (int)min((int64_t)R, a.n - base);
         constexpr int CH = H * EB / 16;
         for (int e = tid; e < rows * CH; e += S::NTHR) {
             const int r = e / CH, c = e % CH;
             const size_t off = (size_t)(base + r) * (H * EB) + (size_t)c * 16;
-            *reinterpret_cast<uint4*>(a.h1_rows + off) =
-                *reinterpret_cast<const uint4*>(h1 + r * S::P_H + c * 16);
             *reinterpret_cast<uint4*>(a.dz2_rows + off) =
                 *reinterpret_cast<const uint4*>(dz + r * S::P_H + c * 16);
         }
@@ -347,8 +393,16 @@ k_ac_fwd(AcArgs a) {
         if (q == 0) out[NHP * H + f] = v;
     }
     __syncthreads();
-    if (tid < NHP) out[NHP * H + H + tid] = db3s[tid];
-    if (tid == 0) out[NHP * H + H + NHP] = dlss;
+    if (tid < NHP) {
+        float v = 0.0f;
+        for (int r = 0; r < R; ++r) v += db3p[r][tid];
+        out[NHP * H + H + tid] = v;
+    }
+    if (tid == 0) {
+        float v = 0.0f;
+        for (int r = 0; r < R; ++r) v += dlsp[r];
+        out[NHP * H + H + NHP] = v;
+    }
 }
 
 template <int DT, int H, int KIN, int NHP>
@@ -391,20 +445,35 @@ k_ac_bwd1(AcArgs a) {
         put<DT>(x0T + (KIN + e / R) * S::P_T + (e % R) * EB, 0.0f);
 
     const int64_t n_tiles = (a.n + R - 1) / R;
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const int64_t base = tile * R;
-        __syncthreads();
-        stage_obs<S, DT>(a, base, x0, x0T, tid);
-        const int rows = (int)min((int64_t)R, a.n - base);
-        constexpr int CH = H * EB / 16;
-        for (int e = tid; e < R * CH; e += S::NTHR) {
+    // the next tile's observations and dz2 rows are loaded while this tile runs
+    constexpr int CH = H * EB / 16;
+    constexpr int DPER = (R * CH + S::NTHR - 1) / S::NTHR;
+    uint4 dzv[DPER];
+    auto load_dz = [&](int64_t tile) {
+#pragma unroll
+        for (int u = 0; u < DPER; ++u) {
+            const int e = tid + u * S::NTHR;
             const int r = e / CH, c = e % CH;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (r < rows)
-                v = *reinterpret_cast<const uint4*>(a.dz2_rows + (size_t)(base + r) * (H * EB) +
-                                                    (size_t)c * 16);
-            *reinterpret_cast<uint4*>(dz + r * S::P_H + c * 16) = v;
+            const int64_t n = tile * R + r;
+            dzv[u] = make_uint4(0u, 0u, 0u, 0u);
+            if (e < R * CH && n < a.n)
+                dzv[u] = *reinterpret_cast<const uint4*>(a.dz2_rows + (size_t)n * (H * EB) +
+                                                         (size_t)c * 16);
         }
+    };
+    ObsPrefetch<S> obs;
+    obs.load(a, blockIdx.x, tid);
+    load_dz(blockIdx.x);
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        __syncthreads();
+        obs.template store<DT>(x0, x0T, tid);
+#pragma unroll
+        for (int u = 0; u < DPER; ++u) {
+            const int e = tid + u * S::NTHR;
+            if (e < R * CH) *reinterpret_cast<uint4*>(dz + (e / CH) * S::P_H + (e % CH) * 16) = dzv[u];
+        }
+        obs.load(a, tile + gridDim.x, tid);
+        load_dz(tile + gridDim.x);
         __syncthreads();
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
@@ -461,16 +530,18 @@ k_ac_bwd1(AcArgs a) {
     }
 }
 
-// dW2[j][k] = sum_i dz2[i][j] h1[i][k] over this workgroup's tiles: the two
-// row tiles are transposed into LDS ([feature][sample]) so both operands
-// read K = samples contiguously.
+// dW2[j][k] = sum_i dz2[i][j] h1[i][k] over this workgroup's tiles, from the
+// feature-major blocks: the A fragments (rows j, K = samples) come straight
+// from the dz2 block, the B fragments from the h1 block copied to LDS (every
+// wave reads all of it).
 template <int DT, int H, int KIN, int NHP>
 __global__ void __launch_bounds__((AcShape<DT, H, KIN, NHP>::NTHR))
 k_ac_dw2(AcArgs a) {
     using S = AcShape<DT, H, KIN, NHP>;
     using M = typename S::M;
+    using Frag = typename S::Frag;
     constexpr int R = S::R, MT = S::MT, K = S::K, KC = S::KC, EB = S::EB, NKT = H / 16;
-    __shared__ __attribute__((aligned(16))) char dzT[H * S::P_T];
+    constexpr int RB = R * EB;   // bytes of one block row
     __shared__ __attribute__((aligned(16))) char h1T[H * S::P_T];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lr = lane & 15, q = lane >> 4;
     const int kq = q * KC;
@@ -480,52 +551,37 @@ k_ac_dw2(AcArgs a) {
 #pragma unroll
         for (int kt = 0; kt < NKT; ++kt) acc[mt][kt] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int64_t n_tiles = (a.n + R - 1) / R;
-    constexpr int PER = 16 / EB;   // elements per 16-byte chunk
-    constexpr int CH = H / PER;
+    constexpr int CPR = RB / 16;   // 16-byte chunks per block row
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const int64_t base = tile * R;
-        const int rows = (int)min((int64_t)R, a.n - base);
-        __syncthreads();
-        for (int e = tid; e < R * CH; e += S::NTHR) {
-            const int r = e / CH, c = e % CH;
-            uint4 vd = make_uint4(0u, 0u, 0u, 0u), vh = vd;
-            if (r < rows) {
-                const size_t off = (size_t)(base + r) * (H * EB) + (size_t)c * 16;
-                vd = *reinterpret_cast<const uint4*>(a.dz2_rows + off);
-                vh = *reinterpret_cast<const uint4*>(a.h1_rows + off);
-            }
-            if constexpr (EB == 2) {
-                uint16_t d16[8], h16[8];
-                __builtin_memcpy(d16, &vd, 16);
-                __builtin_memcpy(h16, &vh, 16);
+        const char* hb = a.h1_blk + (size_t)tile * H * RB;
+        const char* db = a.dz2_blk + (size_t)tile * H * RB;
+        // this wave's A fragments, issued before the block copy
+        Frag A_[MT][R / K];
 #pragma unroll
-                for (int x = 0; x < 8; ++x) {
-                    *reinterpret_cast<uint16_t*>(dzT + (c * 8 + x) * S::P_T + r * 2) = d16[x];
-                    *reinterpret_cast<uint16_t*>(h1T + (c * 8 + x) * S::P_T + r * 2) = h16[x];
-                }
-            } else {
-                uint32_t d32[4], h32[4];
-                __builtin_memcpy(d32, &vd, 16);
-                __builtin_memcpy(h32, &vh, 16);
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                for (int x = 0; x < 4; ++x) {
-                    *reinterpret_cast<uint32_t*>(dzT + (c * 4 + x) * S::P_T + r * 4) = d32[x];
-                    *reinterpret_cast<uint32_t*>(h1T + (c * 4 + x) * S::P_T + r * 4) = h32[x];
-                }
+            for (int ks = 0; ks < R / K; ++ks) {
+                const char* src = db + (size_t)(wave * S::FPW + mt * 16 + lr) * RB + (ks * K + kq) * EB;
+                if constexpr (EB == 2)
+                    A_[mt][ks] = __builtin_bit_cast(Frag, *reinterpret_cast<const uint4*>(src));
+                else
+                    A_[mt][ks] = *reinterpret_cast<const float*>(src);
             }
+        __syncthreads();   // the previous tile's reads of h1T are done
+        for (int e = tid; e < H * CPR; e += S::NTHR) {
+            const int row = e / CPR, c = e % CPR;
+            *reinterpret_cast<uint4*>(h1T + row * S::P_T + c * 16) =
+                *reinterpret_cast<const uint4*>(hb + (size_t)row * RB + c * 16);
         }
         __syncthreads();
 #pragma unroll
-        for (int ks = 0; ks < R / K; ++ks) {
+        for (int ks = 0; ks < R / K; ++ks)
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                const auto A_ = M::lds(dzT + (wave * S::FPW + mt * 16 + lr) * S::P_T + (ks * K + kq) * EB);
+            for (int kt = 0; kt < NKT; ++kt) {
+                const Frag B_ = M::lds(h1T + (kt * 16 + lr) * S::P_T + (ks * K + kq) * EB);
 #pragma unroll
-                for (int kt = 0; kt < NKT; ++kt)
-                    acc[mt][kt] = M::mma(A_, M::lds(h1T + (kt * 16 + lr) * S::P_T + (ks * K + kq) * EB),
-                                         acc[mt][kt]);
+                for (int mt = 0; mt < MT; ++mt) acc[mt][kt] = M::mma(A_[mt][ks], B_, acc[mt][kt]);
             }
-        }
     }
     float* out = a.part_w2 + (size_t)blockIdx.x * H * H;
 #pragma unroll
@@ -537,18 +593,37 @@ k_ac_dw2(AcArgs a) {
                 out[(size_t)(wave * S::FPW + mt * 16 + 4 * q + i) * H + kt * 16 + lr] = acc[mt][kt][i];
 }
 
-// out[r][c] = sum over parts g of part[g * stride + off + r * cols_in + c],
-// r < rows, c < cols.
-__global__ void __launch_bounds__(256)
-k_ac_sum(const float* __restrict__ part, int64_t stride, int nparts, int64_t off, int rows,
-         int cols, int cols_in, float* __restrict__ out) {
+// Reduction of the per-workgroup partial sums, one launch for every
+// gradient tensor: segment y sums, for r < rows and c < cols,
+// out[r][c] = sum over parts g (in order) of part[g * stride + off + r * cols_in + c].
+struct SumSeg {
+    const float* part;
+    float* out;
+    int64_t stride, off;
+    int nparts, rows, cols, cols_in;
+};
+constexpr int kMaxSeg = 8;
+struct SumTable {
+    SumSeg seg[kMaxSeg];
+};
+
+__global__ void __launch_bounds__(256) k_ac_sum(SumTable t) {
+    const SumSeg& sg = t.seg[blockIdx.y];
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= (int64_t)rows * cols) return;
-    const int r = (int)(e / cols), c = (int)(e % cols);
-    const float* src = part + off + (int64_t)r * cols_in + c;
+    if (e >= (int64_t)sg.rows * sg.cols) return;
+    const int r = (int)(e / sg.cols), c = (int)(e % sg.cols);
+    const float* src = sg.part + sg.off + (int64_t)r * sg.cols_in + c;
     float s = 0.0f;
-    for (int g = 0; g < nparts; ++g) s += src[(size_t)g * stride];
-    out[e] = s;
+    int g = 0;
+    for (; g + 8 <= sg.nparts; g += 8) {   // eight loads in flight, summed in order
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = src[(size_t)(g + u) * sg.stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; g < sg.nparts; ++g) s += src[(size_t)g * sg.stride];
+    sg.out[e] = s;
 }
 
 // Adam (Kingma and Ba 2015, Algorithm 1), one element per thread; c1 and c2
@@ -583,20 +658,23 @@ struct AcVariant {
         hipLaunchKernelGGL((k_ac_bwd1<DT, H, KIN, NHP>), dim3(grid1), dim3(S::NTHR), 0, s, a);
         hipLaunchKernelGGL((k_ac_dw2<DT, H, KIN, NHP>), dim3(grid2), dim3(S::NTHR), 0, s, a);
         const PolicyArgs& p = a.pol;
-        auto sum = [&](const float* part, int64_t stride, int nparts, int64_t off, int rows,
-                       int cols, int cols_in, float* out) {
-            const int64_t total = (int64_t)rows * cols;
-            hipLaunchKernelGGL(k_ac_sum, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
-                               part, stride, nparts, off, rows, cols, cols_in, out);
-        };
         const int F = S::FWD_FLOATS, B = S::BWD_FLOATS;
-        sum(a.part_fwd, F, grid1, 0, p.n_head, H, H, o.w3);
-        sum(a.part_fwd, F, grid1, (int64_t)NHP * H, 1, H, H, o.b2);
-        sum(a.part_fwd, F, grid1, (int64_t)NHP * H + H, 1, p.n_head, p.n_head, o.b3);
-        if (o.log_std) sum(a.part_fwd, F, grid1, (int64_t)NHP * H + H + NHP, 1, 1, 1, o.log_std);
-        sum(a.part_bwd, B, grid1, 0, H, p.d_in, KIN, o.w1);
-        sum(a.part_bwd, B, grid1, (int64_t)H * KIN, 1, H, H, o.b1);
-        sum(a.part_w2, (int64_t)H * H, grid2, 0, H, H, H, o.w2);
+        SumTable t{};
+        int ns = 0;
+        int64_t most = 0;
+        auto seg = [&](const float* part, int64_t stride, int nparts, int64_t off, int rows,
+                       int cols, int cols_in, float* out) {
+            t.seg[ns++] = SumSeg{part, out, stride, off, nparts, rows, cols, cols_in};
+            most = std::max<int64_t>(most, (int64_t)rows * cols);
+        };
+        seg(a.part_fwd, F, grid1, 0, p.n_head, H, H, o.w3);
+        seg(a.part_fwd, F, grid1, (int64_t)NHP * H, 1, H, H, o.b2);
+        seg(a.part_fwd, F, grid1, (int64_t)NHP * H + H, 1, p.n_head, p.n_head, o.b3);
+        if (o.log_std) seg(a.part_fwd, F, grid1, (int64_t)NHP * H + H + NHP, 1, 1, 1, o.log_std);
+        seg(a.part_bwd, B, grid1, 0, H, p.d_in, KIN, o.w1);
+        seg(a.part_bwd, B, grid1, (int64_t)H * KIN, 1, H, H, o.b1);
+        seg(a.part_w2, (int64_t)H * H, grid2, 0, H, H, H, o.w2);
+        hipLaunchKernelGGL(k_ac_sum, dim3((unsigned)((most + 255) / 256), ns), dim3(256), 0, s, t);
         return hipGetLastError();
     }
     static size_t part_floats(int grid1, int grid2) {
@@ -625,32 +703,39 @@ bool ac_supported(int dtype, int hidden, int d_in, int n_head) {
            hipSuccess;
 }
 
+// Workspace: dz2 rows [n][H], the h1 and dz2 blocks (whole tiles), the
+// partial sums; each part 256-byte aligned.
+static size_t ac_round_up(size_t b) { return (b + 255) / 256 * 256; }
+
 size_t ac_workspace_bytes(int dtype, int hidden, int64_t n, int grid1, int grid2) {
-    const size_t al = 256;
-    const size_t rows = (size_t)n * hidden * (dtype == DT_BF16 ? 2 : 4);
+    const size_t eb = dtype == DT_BF16 ? 2 : 4;
+    const size_t rows = (size_t)n * hidden * eb;
+    const size_t blk = (size_t)((n + kAcRows - 1) / kAcRows) * kAcRows * hidden * eb;
     // partial sums of the widest head compiled for this format and width
     size_t part = 0;
     if (dtype == DT_F32 && hidden == 64)
         part = AcVariant<DT_F32, 64, 4, 16>::part_floats(grid1, grid2);
     else if (dtype == DT_BF16 && hidden == 256)
         part = AcVariant<DT_BF16, 256, 32, 64>::part_floats(grid1, grid2);
-    return al + 2 * ((rows + al - 1) / al * al) + part * sizeof(float);
+    return 256 + ac_round_up(rows) + 2 * ac_round_up(blk) + part * sizeof(float);
 }
 
 hipError_t launch_ac_grad(const AcLaunch& l, hipStream_t s) {
     const PolicyArgs& p = l.args.pol;
     return with_variant(l.dtype, p.hidden, p.d_in, p.n_head, [&](auto v) {
         using V = decltype(v);
-        AcArgs a = l.args;
-        // carve the workspace: h1 rows, dz2 rows, partial sums
-        const size_t al = 256;
-        const size_t rows = (size_t)a.n * p.hidden * (l.dtype == DT_BF16 ? 2 : 4);
-        char* w = reinterpret_cast<char*>(((uintptr_t)l.workspace + al - 1) / al * al);
-        a.h1_rows = w;
-        w += (rows + al - 1) / al * al;
-        a.dz2_rows = w;
-        w += (rows + al - 1) / al * al;
         using S = typename V::S;
+        AcArgs a = l.args;
+        const size_t eb = S::EB;
+        const size_t rows = (size_t)a.n * p.hidden * eb;
+        const size_t blk = (size_t)((a.n + kAcRows - 1) / kAcRows) * kAcRows * p.hidden * eb;
+        char* w = reinterpret_cast<char*>(((uintptr_t)l.workspace + 255) / 256 * 256);
+        a.dz2_rows = w;
+        w += ac_round_up(rows);
+        a.h1_blk = w;
+        w += ac_round_up(blk);
+        a.dz2_blk = w;
+        w += ac_round_up(blk);
         a.part_fwd = reinterpret_cast<float*>(w);
         a.part_bwd = a.part_fwd + (size_t)l.grid1 * S::FWD_FLOATS;
         a.part_w2 = a.part_bwd + (size_t)l.grid1 * S::BWD_FLOATS;

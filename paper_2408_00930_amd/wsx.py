@@ -546,6 +546,14 @@ class Grads:
         return self.tensors[name]
 
 
+def ac_grad_workspace_bytes(policy, samples):
+    L = lib()
+    _update_sigs(L)
+    need = C.c_size_t()
+    _check(L.wsx_ac_grad_workspace_bytes(C.byref(policy.c), int(samples), C.byref(need)))
+    return need.value
+
+
 def ac_grad(policy, n_actions, obs, action, returns, advantages, value_coef=0.5,
             entropy_coef=0.0, grads=None, workspace=None, stream=None):
     """Gradient of the actor-critic loss over the samples (flat views of a
