@@ -231,8 +231,10 @@ typedef struct {
 } wsx_grads;
 
 /* Device workspace wsx_ac_grad needs for `samples` samples on the current
- * device (per sample two rows of h1 in the policy's format, plus
- * per-workgroup partial sums). */
+ * device: per sample of a chunk three rows of `h1` elements in the policy's
+ * format, plus per-workgroup partial sums. Sets of more than 2^21 samples run
+ * in chunks of 2^21, so the size stops growing there (about 3 GiB for a BF16
+ * policy of width 256). */
 int wsx_ac_grad_workspace_bytes(const wsx_policy* policy, int64_t samples, size_t* bytes);
 
 /* Writes the gradient of L into `grads` (overwritten, not accumulated).

@@ -590,7 +590,7 @@ static int ac_grid(int64_t samples) {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const int64_t tiles = (samples + 31) / 32;
+    const int64_t tiles = (ac_chunk_samples(samples) + 31) / 32;
     return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, cus));
 }
 

@@ -95,7 +95,8 @@ struct AcArgs {
     const float* adv;        // [n]
     int64_t n;
     int32_t n_act;           // 0: Gaussian
-    float value_coef, entropy_coef, inv_n;
+    float value_coef, entropy_coef, inv_n;   // inv_n: 1 / all samples of the call
+    bool accumulate;         // add to the workgroups' partial sums (later chunks)
     char* dz2_rows;          // workspace [n][H] in the policy format
     char* h1_blk;            // workspace: per 32-sample tile a [H][32] block
     char* dz2_blk;           // (feature-major) of h1 and of dz2
@@ -114,6 +115,7 @@ struct AcLaunch {
     AcOut out;
 };
 bool ac_supported(int dtype, int hidden, int d_in, int n_head);
+int64_t ac_chunk_samples(int64_t n);   // samples per chunk of a call over n
 size_t ac_workspace_bytes(int dtype, int hidden, int64_t n, int grid1, int grid2);
 hipError_t launch_ac_grad(const AcLaunch& l, hipStream_t s);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,

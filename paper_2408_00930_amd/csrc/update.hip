@@ -41,6 +41,9 @@ namespace wsx {
 namespace {
 
 constexpr int kAcRows = 32;   // samples per tile (two row tiles of 16)
+// samples per pass over the workspace: larger sets run in chunks, so the
+// workspace stays bounded (3 GiB for BF16 hidden 256)
+constexpr int64_t kAcChunk = int64_t(1) << 21;
 
 // KC elements of a B fragment down column `col` of a row-major [k][ld]
 // matrix: W[(k0 + e) * ld + col], zero for rows >= k_valid.
@@ -92,6 +95,10 @@ __device__ __forceinline__ bf16x8 lds_k_perm(const char* T, int pitch, int c, in
 }
 
 __device__ __forceinline__ float act_tanh(float z) { return tanh_scaled(z, kTwoLog2e); }
+
+// A workgroup's partial sum: written by the first chunk of samples, added to
+// by later chunks (each workgroup owns its slot; chunks run in stream order).
+__device__ __forceinline__ void part_out(float* p, float v, bool acc) { *p = acc ? *p + v : v; }
 
 // Four consecutive samples of one feature (an accumulator's four values) into
 // a feature-major block, rounded to the policy format.
@@ -386,22 +393,22 @@ k_ac_fwd(AcArgs a) {
 #pragma unroll
         for (int ht = 0; ht < S::NHT; ++ht)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) out[(ht * 16 + 4 * q + i) * H + f] = dw3[ht][mt][i];
+            for (int i = 0; i < 4; ++i) part_out(&out[(ht * 16 + 4 * q + i) * H + f], dw3[ht][mt][i], a.accumulate);
         float v = db2a[mt];
         v += __shfl_xor(v, 16);
         v += __shfl_xor(v, 32);
-        if (q == 0) out[NHP * H + f] = v;
+        if (q == 0) part_out(&out[NHP * H + f], v, a.accumulate);
     }
     __syncthreads();
     if (tid < NHP) {
         float v = 0.0f;
         for (int r = 0; r < R; ++r) v += db3p[r][tid];
-        out[NHP * H + H + tid] = v;
+        part_out(&out[NHP * H + H + tid], v, a.accumulate);
     }
     if (tid == 0) {
         float v = 0.0f;
         for (int r = 0; r < R; ++r) v += dlsp[r];
-        out[NHP * H + H + NHP] = v;
+        part_out(&out[NHP * H + H + NHP], v, a.accumulate);
     }
 }
 
@@ -522,11 +529,12 @@ k_ac_bwd1(AcArgs a) {
         for (int it = 0; it < S::KT; ++it)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                if (it * 16 + lr < KIN) out[(f0 + 4 * q + i) * KIN + it * 16 + lr] = dw1[mt][it][i];
+                if (it * 16 + lr < KIN)
+                    part_out(&out[(f0 + 4 * q + i) * KIN + it * 16 + lr], dw1[mt][it][i], a.accumulate);
         float v = db1a[mt];
         v += __shfl_xor(v, 16);
         v += __shfl_xor(v, 32);
-        if (q == 0) out[H * KIN + f0 + lr] = v;
+        if (q == 0) part_out(&out[H * KIN + f0 + lr], v, a.accumulate);
     }
 }
 
@@ -590,7 +598,8 @@ k_ac_dw2(AcArgs a) {
         for (int kt = 0; kt < NKT; ++kt)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                out[(size_t)(wave * S::FPW + mt * 16 + 4 * q + i) * H + kt * 16 + lr] = acc[mt][kt][i];
+                part_out(&out[(size_t)(wave * S::FPW + mt * 16 + 4 * q + i) * H + kt * 16 + lr],
+                         acc[mt][kt][i], a.accumulate);
 }
 
 // Reduction of the per-workgroup partial sums, one launch for every
@@ -653,10 +662,14 @@ k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m
 template <int DT, int H, int KIN, int NHP>
 struct AcVariant {
     using S = AcShape<DT, H, KIN, NHP>;
-    static hipError_t run(const AcArgs& a, int grid1, int grid2, const AcOut& o, hipStream_t s) {
+    // the three per-tile kernels over one chunk of samples
+    static void chunk(const AcArgs& a, int grid1, int grid2, hipStream_t s) {
         hipLaunchKernelGGL((k_ac_fwd<DT, H, KIN, NHP>), dim3(grid1), dim3(S::NTHR), 0, s, a);
         hipLaunchKernelGGL((k_ac_bwd1<DT, H, KIN, NHP>), dim3(grid1), dim3(S::NTHR), 0, s, a);
         hipLaunchKernelGGL((k_ac_dw2<DT, H, KIN, NHP>), dim3(grid2), dim3(S::NTHR), 0, s, a);
+    }
+    // the partial sums of every workgroup -> the gradients
+    static hipError_t sum(const AcArgs& a, int grid1, int grid2, const AcOut& o, hipStream_t s) {
         const PolicyArgs& p = a.pol;
         const int F = S::FWD_FLOATS, B = S::BWD_FLOATS;
         SumTable t{};
@@ -707,7 +720,10 @@ bool ac_supported(int dtype, int hidden, int d_in, int n_head) {
 // partial sums; each part 256-byte aligned.
 static size_t ac_round_up(size_t b) { return (b + 255) / 256 * 256; }
 
+int64_t ac_chunk_samples(int64_t n) { return std::min<int64_t>(n, kAcChunk); }
+
 size_t ac_workspace_bytes(int dtype, int hidden, int64_t n, int grid1, int grid2) {
+    n = ac_chunk_samples(n);
     const size_t eb = dtype == DT_BF16 ? 2 : 4;
     const size_t rows = (size_t)n * hidden * eb;
     const size_t blk = (size_t)((n + kAcRows - 1) / kAcRows) * kAcRows * hidden * eb;
@@ -725,10 +741,11 @@ hipError_t launch_ac_grad(const AcLaunch& l, hipStream_t s) {
     return with_variant(l.dtype, p.hidden, p.d_in, p.n_head, [&](auto v) {
         using V = decltype(v);
         using S = typename V::S;
-        AcArgs a = l.args;
+        const int64_t chunk = std::min<int64_t>(l.args.n, kAcChunk);
         const size_t eb = S::EB;
-        const size_t rows = (size_t)a.n * p.hidden * eb;
-        const size_t blk = (size_t)((a.n + kAcRows - 1) / kAcRows) * kAcRows * p.hidden * eb;
+        const size_t rows = (size_t)chunk * p.hidden * eb;
+        const size_t blk = (size_t)((chunk + kAcRows - 1) / kAcRows) * kAcRows * p.hidden * eb;
+        AcArgs a = l.args;
         char* w = reinterpret_cast<char*>(((uintptr_t)l.workspace + 255) / 256 * 256);
         a.dz2_rows = w;
         w += ac_round_up(rows);
@@ -739,7 +756,18 @@ hipError_t launch_ac_grad(const AcLaunch& l, hipStream_t s) {
         a.part_fwd = reinterpret_cast<float*>(w);
         a.part_bwd = a.part_fwd + (size_t)l.grid1 * S::FWD_FLOATS;
         a.part_w2 = a.part_bwd + (size_t)l.grid1 * S::BWD_FLOATS;
-        return V::run(a, l.grid1, l.grid2, l.out, s);
+        // chunks of samples in stream order; inv_n stays 1 / (all samples)
+        for (int64_t c0 = 0; c0 < l.args.n; c0 += chunk) {
+            AcArgs c = a;
+            c.n = std::min<int64_t>(chunk, l.args.n - c0);
+            c.obs = l.args.obs + (size_t)c0 * p.d_in;
+            c.action = static_cast<const char*>(l.args.action) + (size_t)c0 * (l.args.n_act ? 1 : 4);
+            c.ret = l.args.ret + c0;
+            c.adv = l.args.adv + c0;
+            c.accumulate = c0 > 0;
+            V::chunk(c, l.grid1, l.grid2, s);
+        }
+        return V::sum(a, l.grid1, l.grid2, l.out, s);
     });
 }
 

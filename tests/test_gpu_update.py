@@ -128,6 +128,34 @@ def test_ac_grad_full_size_is_the_sample_weighted_mean_of_its_halves():
     _compare(g, want, pol.dtype, "full-size prefix")
 
 
+def test_ac_grad_in_chunks_equals_the_weighted_halves():
+    """More samples than one pass over the workspace holds (2^21): the call
+    runs in chunks that add to the same partial sums, and equals the
+    sample-weighted mean of two single-chunk calls."""
+    import torch
+    wsx = _wsx()
+    say("ac_grad chunked")
+    pol, dp, tr, ret, adv, rows = _rollout(O.ACROBOT, 11000, 200, seed=6)
+    obs, act = tr.obs.reshape(-1, pol.d_in), tr.action.reshape(-1)
+    r, a = ret.reshape(-1), adv.reshape(-1)
+    n = r.numel()
+    assert n > (1 << 21)
+    h = n // 2
+    need = wsx.ac_grad_workspace_bytes(dp, n)
+    assert need == wsx.ac_grad_workspace_bytes(dp, 1 << 22)     # bounded by the chunk
+    full = wsx.ac_grad(dp, 0, obs, act, r, a, CV, CE)
+    g1 = wsx.ac_grad(dp, 0, obs[:h].contiguous(), act[:h].contiguous(), r[:h].contiguous(),
+                     a[:h].contiguous(), CV, CE)
+    g2 = wsx.ac_grad(dp, 0, obs[h:].contiguous(), act[h:].contiguous(), r[h:].contiguous(),
+                     a[h:].contiguous(), CV, CE)
+    torch.cuda.synchronize()
+    for k in wsx.Grads.NAMES:
+        f = full[k].double()
+        mix = (g1[k].double() * h + g2[k].double() * (n - h)) / n
+        assert torch.isfinite(f).all()
+        assert (f - mix).abs().max().item() <= 5e-4 * f.abs().max().item() + 1e-12, k
+
+
 def test_adam_matches_oracle_and_stores_bf16():
     import torch
     wsx = _wsx()
