@@ -98,6 +98,60 @@ def update_leg(sets, steps, wsx, torch):
                     "trajectories plus one Adam step per tensor into the policy weights"}
 
 
+def sweep(kind_key, counts, steps, wsx, inputs, torch):
+    """Env-count sweep (the paper's throughput-vs-environments curves): for each
+    count, the fused roll-out (autotuned shape) and the full training
+    iteration (reset, roll-out, returns/GAE, gradient, Adam), one JSON line per
+    count on stdout. Not part of the benchmark contract line."""
+    cfg = inputs.CONFIGS[kind_key]
+    kind, T = cfg["kind"], cfg["horizon"]
+    pol = inputs.policy_for(kind, cfg["dtype"], cfg["hidden"], seed=0)
+    for n in counts:
+        dp = wsx.DevicePolicy(pol)
+        wsx.autotune(kind, n, dp, T, reps=1, seed=0)
+        env = wsx.Env(kind, n, seed=0)
+        tr = wsx.Trajectory(kind, T, env.rows)
+        ret = torch.empty((T, env.rows), dtype=torch.float32, device="cuda")
+        adv = torch.empty_like(ret)
+        g = wsx.Grads(dp)
+        ws = torch.empty(wsx.ac_grad_workspace_bytes(dp, T * env.rows), dtype=torch.uint8,
+                         device="cuda")
+        names = ["w1", "b1", "w2", "b2", "w3", "b3"] + ([] if wsx.N_ACTIONS[kind] else ["log_std"])
+        master = {k: torch.from_numpy(pol.exact(k).astype("float32")).cuda().reshape(-1)[:dp.tensors[k].numel()]
+                  for k in names}
+        mom = {k: (torch.zeros_like(v), torch.zeros_like(v)) for k, v in master.items()}
+
+        def roll(i):
+            wsx.env_reset(env, epoch=i)
+            wsx.rollout(env, dp, T, tr)
+
+        def train(i):
+            roll(i)
+            wsx.compute_returns(tr, T, 0.99, 0.95, True, torch.float32, ret, adv)
+            wsx.ac_grad(dp, wsx.N_ACTIONS[kind], tr.obs.reshape(-1, pol.d_in),
+                        tr.action.reshape(-1), ret.reshape(-1), adv.reshape(-1), 0.5, 0.01,
+                        grads=g, workspace=ws)
+            for k in names:
+                wsx.adam_step(master[k], g[k].reshape(-1)[:master[k].numel()], mom[k][0],
+                              mom[k][1], i + 1, 3e-4, store=dp.tensors[k].reshape(-1))
+
+        row = {"kind": kind_key.split("_")[0], "envs": n, "horizon": T,
+               "shape": wsx.env_shape(env)}
+        for name, fn in (("rollout", roll), ("train_iteration", train)):
+            fn(0)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for i in range(steps):
+                fn(i + 1)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            row[name] = {"ms": round(ms, 4), "env_steps_per_s": round(n * T / ms * 1e3, 1)}
+        print(json.dumps(row), flush=True)
+        del env, tr, ret, adv, ws, g
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2408_00930_amd", "csrc")
@@ -350,6 +404,10 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a kernel of "
                          "known traffic for scaling HBM byte counters)")
+    ap.add_argument("--sweep", default="",
+                    help="instead of the benchmark: env-count sweep of this workload key "
+                         "(e.g. pendulum_10k), one JSON line per count")
+    ap.add_argument("--sweep-counts", default="10,100,1000,10000,100000,1000000")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -372,6 +430,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.sweep:
+        sweep(args.sweep, [int(x) for x in args.sweep_counts.split(",")], args.steps, wsx, inputs,
+              torch)
+        return
     keys = WORKLOADS[args.workload]
     batched = len(keys) > 1 and not args.no_batch
     tuned = {}
