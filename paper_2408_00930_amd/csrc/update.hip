@@ -96,6 +96,16 @@ __device__ __forceinline__ bf16x8 lds_k_perm(const char* T, int pitch, int c, in
 
 __device__ __forceinline__ float act_tanh(float z) { return tanh_scaled(z, kTwoLog2e); }
 
+// Workgroup barrier for LDS traffic only: this wave's LDS operations complete,
+// then s_barrier. Unlike __syncthreads() it does not wait for the wave's
+// global loads and stores, so loads issued for the next tile stay in flight
+// across it (no wave reads another wave's global writes inside these kernels).
+__device__ __forceinline__ void lds_barrier() {
+    __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    __asm__ volatile("" ::: "memory");
+}
+
 // A workgroup's partial sum: written by the first chunk of samples, added to
 // by later chunks (each workgroup owns its slot; chunks run in stream order).
 __device__ __forceinline__ void part_out(float* p, float v, bool acc) { *p = acc ? *p + v : v; }
@@ -231,8 +241,9 @@ k_ac_fwd(AcArgs a) {
         const int64_t base = tile * R;
         char* h1b = a.h1_blk + (size_t)tile * H * R * EB;    // this tile's blocks
         char* dzb = a.dz2_blk + (size_t)tile * H * R * EB;
-        __syncthreads();   // the previous tile's LDS reads are done
+        lds_barrier();   // the previous tile's LDS reads are done
         obs.template store<DT>(x0, nullptr, tid);
+        lds_barrier();
         // this tile's per-sample inputs (used after the head) and the next
         // tile's observations, in flight while the layers run
         float s_adv = 0.0f, s_ret = 0.0f, s_act = 0.0f;
@@ -244,7 +255,6 @@ k_ac_fwd(AcArgs a) {
                                  : (float)static_cast<const uint8_t*>(a.action)[n];
         }
         obs.load(a, tile + gridDim.x, tid);
-        __syncthreads();
         // layer 1
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
@@ -264,7 +274,7 @@ k_ac_fwd(AcArgs a) {
                 put4<DT>(h1b + (size_t)(f * R + nt * 16 + 4 * q) * EB, t[0], t[1], t[2], t[3]);
             }
         }
-        __syncthreads();
+        lds_barrier();
         // layer 2, keeping the unrounded activations
         f32x4 t2[MT][2];
 #pragma unroll
@@ -283,7 +293,7 @@ k_ac_fwd(AcArgs a) {
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
         // head: wave (ht, nt) of the 2 NHT jobs
         if (head_job) {
             f32x4 acc = {b3v, b3v, b3v, b3v};
@@ -293,7 +303,7 @@ k_ac_fwd(AcArgs a) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) hd[jnt * 16 + 4 * q + i][jht * 16 + lr] = acc[i];
         }
-        __syncthreads();
+        lds_barrier();
         // gradient of the loss at the head, one thread per sample
         if (tid < R) {
             const int r = tid;
@@ -335,7 +345,7 @@ k_ac_fwd(AcArgs a) {
             }
             set(NH - 1, ok ? a.value_coef * (hd[r][NH - 1] - s_ret) * a.inv_n : 0.0f);
         }
-        __syncthreads();
+        lds_barrier();
         // dz2 = (dhead W3) (1 - t2^2) for this wave's features; dW3 += dhead^T h2
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
@@ -374,7 +384,7 @@ k_ac_fwd(AcArgs a) {
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
         // dz2 rows of the tile to the workspace (consecutive samples)
         const int rows = (int)min((int64_t)R, a.n - base);
         constexpr int CH = H * EB / 16;
@@ -399,7 +409,7 @@ k_ac_fwd(AcArgs a) {
         v += __shfl_xor(v, 32);
         if (q == 0) part_out(&out[NHP * H + f], v, a.accumulate);
     }
-    __syncthreads();
+    lds_barrier();
     if (tid < NHP) {
         float v = 0.0f;
         for (int r = 0; r < R; ++r) v += db3p[r][tid];
@@ -472,7 +482,7 @@ k_ac_bwd1(AcArgs a) {
     obs.load(a, blockIdx.x, tid);
     load_dz(blockIdx.x);
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        __syncthreads();
+        lds_barrier();
         obs.template store<DT>(x0, x0T, tid);
 #pragma unroll
         for (int u = 0; u < DPER; ++u) {
@@ -481,7 +491,7 @@ k_ac_bwd1(AcArgs a) {
         }
         obs.load(a, tile + gridDim.x, tid);
         load_dz(tile + gridDim.x);
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
             f32x4 dz1[2];
@@ -575,13 +585,13 @@ k_ac_dw2(AcArgs a) {
                 else
                     A_[mt][ks] = *reinterpret_cast<const float*>(src);
             }
-        __syncthreads();   // the previous tile's reads of h1T are done
+        lds_barrier();   // the previous tile's reads of h1T are done
         for (int e = tid; e < H * CPR; e += S::NTHR) {
             const int row = e / CPR, c = e % CPR;
             *reinterpret_cast<uint4*>(h1T + row * S::P_T + c * 16) =
                 *reinterpret_cast<const uint4*>(hb + (size_t)row * RB + c * 16);
         }
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
         for (int ks = 0; ks < R / K; ++ks)
 #pragma unroll
