@@ -261,6 +261,45 @@ int wsx_adam_step(float* param, const float* grad, float* m, float* v, int64_t n
                   int32_t store_dtype, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* User environment kinds (Sec. 2: the framework is environment-agnostic;    */
+/* App. B: user environments are compiled for the device and run in the same */
+/* GPU-resident loop). `source` defines, in C++ for HIP, a `struct UserEnv`  */
+/* with the interface of the built-in kinds:                                 */
+/*   static constexpr int KIND = WSX_USER_KIND, SD, SR, OD, NACT, LANES;    */
+/*     SD state floats per row kept in the state block, SR >= SD in          */
+/*     registers, OD observation size, NACT actions (0: one continuous       */
+/*     action), LANES lanes that may share a row (1 unless the step uses the */
+/*     group reductions);                                                    */
+/*   __device__ static void complete(float* s);   derived register entries   */
+/*   __device__ static void reset(float* s, const RngKey& key, uint32_t t,   */
+/*                                uint32_t row, const EnvCtx& ctx);          */
+/*   __device__ static void observe(const float* s, float* o);               */
+/*   template <int G> __device__ static void step(float* s, int a, float av, */
+/*       uint32_t t, uint32_t row, const RngKey& key, const EnvCtx& ctx,     */
+/*       int sub, float& reward, bool& done);                                */
+/* It may use the library's device helpers (Philox `draw`, `unit_uniform`,   */
+/* `sin_cos`, `wrap_pi`, ...). The call compiles the fused roll-out and the  */
+/* reset kernel for it with the HIP run-time compiler for the current device */
+/* (a second or so), loads them, and returns a new kind (>= 100) that works  */
+/* with wsx_env_state_bytes, wsx_env_create (without agent_offsets and       */
+/* params), wsx_env_reset, wsx_rollout in WSX_MODE_FUSED and                 */
+/* WSX_MODE_FUSED_GRAPH, wsx_rollout_batch of sets of this kind, and the     */
+/* returns and update calls. Policies: FP32 width 64 with <= 16 head         */
+/* outputs, or BF16 width 256. A source that does not compile returns        */
+/* WSX_EINVAL with the compiler's log in wsx_last_error(). Kinds stay        */
+/* registered until the process ends.                                        */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t state_dim;       /* SD                                                */
+    int32_t obs_dim;         /* OD                                                */
+    int32_t n_actions;       /* NACT: 0, or 2..255                                */
+    int32_t dtype;           /* policy format: WSX_F32 or WSX_BF16                */
+    int32_t hidden;          /* policy width: 64 (FP32) or 256 (BF16)             */
+} wsx_user_kind_desc;
+
+int wsx_user_kind_register(const wsx_user_kind_desc* desc, const char* source, int32_t* kind);
+
+/* ------------------------------------------------------------------------ */
 /* Autotuner for the persistent fused roll-out (App. B: every environment    */
 /* instance owns a GPU block, its agents the block's threads; here a tile of */
 /* rows per workgroup, whose best height depends on the set). Times the      */

@@ -47,7 +47,7 @@ bool kind_info(int kind, KindInfo& k) {
     case WSX_MARKET: k = {32, 32, 50, WSX_BF16, 256, 128, 4, 1}; return true;
     case WSX_REACTION: k = {21, 20, 40, WSX_FP8_E4M3, 512, 16, 8, 2}; return true;
     }
-    return false;
+    return user_kind_info(kind, k);
 }
 
 int n_head_of(const KindInfo& k) { return (k.nact ? k.nact : 1) + 1; }
@@ -78,6 +78,15 @@ Layout layout_of(const KindInfo& k, int64_t n_envs, int64_t n_rows, bool market)
 // listed wins among kernels of the same row capacity).
 static bool find_any(int kind, int kind2, int dtype, int hidden, int waves, int tile_rows,
                      int occupancy, Variant& out) {
+    if (kind >= kUserKindBase || kind2 >= kUserKindBase) {   // one compiled shape per user kind
+        Variant v;
+        if (kind2 != 0 || !user_variant(kind, v)) return false;
+        if (v.dtype != dtype || v.hidden != hidden || tile_rows < 1 || v.tile_rows < tile_rows ||
+            (waves != 0 && v.waves != waves) || (occupancy != 0 && v.occupancy != occupancy))
+            return false;
+        out = v;
+        return true;
+    }
     bool found = false;
     for (int i = 0; i < n_variants(); ++i) {
         const Variant& v = variant(i);
@@ -405,6 +414,8 @@ int wsx_rollout(wsx_env* env, const wsx_policy* policy, int32_t horizon, const w
         b.n_tiles = env->n_tiles;
         return launch_fused(v, b, grid, st);
     };
+    if (env->kind >= kUserKindBase && (mode == WSX_MODE_PLAIN || mode == WSX_MODE_GRAPH))
+        return fail(WSX_EUNSUPPORTED, "user kinds run the fused modes only");
     if (mode == WSX_MODE_FUSED) {
         e = fused(ea, 0, horizon, true, s);
     } else if (mode == WSX_MODE_PLAIN) {

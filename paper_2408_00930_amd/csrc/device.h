@@ -5,7 +5,9 @@
 // from the published definitions; nothing here is shared with the oracle.
 #pragma once
 
+#ifndef __HIPCC_RTC__   // the run-time compiler provides the runtime itself
 #include <hip/hip_runtime.h>
+#endif
 #include <stdint.h>
 
 namespace wsx {

@@ -3,7 +3,9 @@
 // layer (abi.cpp). Internal to the library.
 #pragma once
 
+#ifndef __HIPCC_RTC__   // the run-time compiler provides the runtime itself
 #include <hip/hip_runtime.h>
+#endif
 #include <stdint.h>
 
 namespace wsx {
@@ -114,6 +116,7 @@ struct AcLaunch {
     int grid1, grid2;        // workgroups of the per-tile kernels and of dW2
     AcOut out;
 };
+#ifndef __HIPCC_RTC__   // host-side launchers
 bool ac_supported(int dtype, int hidden, int d_in, int n_head);
 int64_t ac_chunk_samples(int64_t n);   // samples per chunk of a call over n
 size_t ac_workspace_bytes(int dtype, int hidden, int64_t n, int grid1, int grid2);
@@ -121,6 +124,16 @@ hipError_t launch_ac_grad(const AcLaunch& l, hipStream_t s);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
                        float b1, float b2, float eps, float c1, float c2, void* store,
                        int store_dtype, hipStream_t s);
+
+// User environment kinds compiled at run time (compose.cpp): kinds
+// kUserKindBase, kUserKindBase + 1, ...
+constexpr int kUserKindBase = 100;
+struct KindInfo;
+bool user_kind_info(int kind, KindInfo& k);
+bool user_variant(int kind, Variant& v);
+hipError_t launch_user_fused(const Variant& v, const Batch& batch, int grid, hipStream_t s);
+hipError_t launch_user_reset(int kind, const EnvArgs& env, hipStream_t s);
+int user_blocks_per_cu(const Variant& v);
 
 // Launchers (return hipError_t of the launch).
 hipError_t launch_reset(int kind, const EnvArgs& env, hipStream_t s);
@@ -142,5 +155,7 @@ hipError_t launch_returns(const float* reward, const float* value, const uint8_t
 int n_variants();
 const Variant& variant(int i);
 int fused_blocks_per_cu(const Variant& v);
+
+#endif
 
 }  // namespace wsx

@@ -1,0 +1,889 @@
+// rollout_kernels.h -- the fused roll-out's device code (arXiv 2408.00930,
+// Sec. 2 and App. B: replicas step in place on the GPU, agents sample actions
+// from a policy in device memory, roll-out data are stored in place).
+//
+// Templates over the environment kind: the library instantiates them for the
+// built-in kinds (rollout.hip), and the user-kind composer compiles them at
+// run time for an environment given as source (compose.cpp), so a user's
+// environment runs in the same persistent kernel.
+//
+// Fused form: one persistent kernel runs the whole horizon. A workgroup owns a
+// tile of R rows (env replicas, or the agents of whole market envs) and keeps
+// their state in registers for all steps. The policy weights stay resident in
+// VGPRs as MFMA A-operands (weight-stationary: wave w owns output features
+// [w*H/NW, (w+1)*H/NW) of both hidden layers and a K-slice of the head);
+// activations go through LDS as B-operands. Per step:
+//   A  layer 1 (all waves)            -> h1 tile in LDS        | barrier
+//   B  layer 2 (all waves)            -> own h2 slice in LDS   | wave-local
+//   C  head partial over own K-slice  -> partials in LDS       | barrier
+//   D  one thread per row: head = bias + sum of partials, sample, store the
+//      record, step the dynamics, auto-reset, next observation -> LDS | barrier
+#pragma once
+
+#include <type_traits>
+
+#include "device.h"
+#include "envs.h"
+#include "kernels.h"
+
+namespace wsx {
+
+// ------------------------------------------------------ per-kind shapes --
+template <class E>
+struct HeadOf {
+    static constexpr int NOUT = E::NACT ? E::NACT : 1;   // logits or one mean
+    static constexpr int NH = NOUT + 1;                   // + value
+    static constexpr int NHP = (NH + 15) / 16 * 16;
+};
+
+template <class E, int DT>
+constexpr int kin_of() {
+    return (E::OD + Mma<DT>::K - 1) / Mma<DT>::K * Mma<DT>::K;
+}
+
+// ------------------------------------------------------------ MLP tile --
+__device__ __forceinline__ void wave_lds_sync() {
+    // LDS writes of this wave complete before its later LDS reads of them.
+    __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
+// HS selects how the head is spread over the waves. HS = 0 (split-K): wave w
+// multiplies its own h2 features by its K-slice of the head for every head
+// row, leaving NW partial sums per row (no extra barrier). HS = 1 (split-M):
+// after a barrier, wave w computes head row tiles w, w + NW, ... over the whole
+// K (one result per row; for wide heads whose partials would not fit in LDS).
+template <int DT, int H, int NW, int NT, int KIN, int NHP, int HS, int OCC>
+struct Mlp {
+    using M = Mma<DT>;
+    using Frag = typename M::frag;
+    static constexpr int K = M::K, KC = M::KC, EB = M::EB;
+    static constexpr int FPW = H / NW;   // hidden features owned by a wave
+    static constexpr int MT = FPW / 16;
+    static constexpr int K1S = KIN / K, K2S = H / K, K3S = FPW / K, NHT = NHP / 16;
+    static constexpr int NHW = HS ? (NHT + NW - 1) / NW : NHT;   // head tiles held by a wave
+    static constexpr int KHS = HS ? K2S : K3S;                   // head K-steps of a wave
+    static constexpr int NPART = HS ? 1 : NW;                    // head results per row
+    static constexpr int R = 16 * NT;
+    static constexpr int P_IN = KIN * EB + 16;   // LDS row pitches (bytes)
+    static constexpr int P_H = H * EB + 16;
+    static constexpr int P_PART = NHP + 4;       // floats
+    static constexpr int OFF_IN = 0;
+    static constexpr int OFF_H1 = OFF_IN + R * P_IN;
+    static constexpr int OFF_H2 = OFF_H1 + R * P_H;   // split-M only
+    // split-M writes the head after a barrier that follows the last read of
+    // h1, so its results reuse the h1 tile; split-K takes each wave's h2
+    // features from its registers (no h2 tile) and writes partials there
+    static constexpr int OFF_PART = HS ? OFF_H1 : OFF_H2;
+    // per-feature accumulator start (bias / output scale) and tanh factor
+    // (2 log2 e * output scale) of both hidden layers: [4][H] floats
+    static constexpr int OFF_TAB = HS ? OFF_H2 + R * P_H : OFF_PART + NPART * R * P_PART * 4;
+    static constexpr int WPS = (NW / 4 > OCC ? NW / 4 : OCC);   // waves per SIMD
+    // Four-wave kernels sharing a SIMD with another workgroup keep W1 in LDS
+    // (read per step, so its registers are free outside layer 1): [wave][mt]
+    // [ks][lane] fragments, each lane reading its own 16 (8, 4) bytes.
+    static constexpr bool W1_LDS = NW == 4 && WPS >= 2;
+    static constexpr int OFF_W1 = OFF_TAB + 4 * H * 4;
+    static constexpr int W1_BYTES = W1_LDS ? NW * MT * K1S * 64 * (int)sizeof(Frag) : 0;
+    // the same for the head weights of the split-K head ([wave][hw][ks][lane])
+    static constexpr bool W3_LDS = W1_LDS && !HS;
+    static constexpr int OFF_W3 = OFF_W1 + W1_BYTES;
+    static constexpr int W3_BYTES = W3_LDS ? NW * NHW * KHS * 64 * (int)sizeof(Frag) : 0;
+    static constexpr int BYTES = OFF_W3 + W3_BYTES;
+    static_assert(!HS || P_PART * 4 <= P_H, "head results fit in the h1 tile");
+    static_assert(FPW % 16 == 0 && FPW % K == 0 && KIN % K == 0 && H % K == 0, "tile shape");
+    static_assert(BYTES <= 160 * 1024, "LDS budget");
+
+    static constexpr int DTYPE = DT;
+    // software pipelining of the dense layers (see dense_tanh): with at most
+    // two waves per SIMD and at most 64 registers of layer-2 weights per lane,
+    // or with one wave per SIMD and at most four output tiles per wave
+    static constexpr int W2_REGS = MT * K2S * (int)sizeof(Frag) / 4;
+    static constexpr bool PIPE_ON =
+        (WPS <= 2 && W2_REGS <= 64) || (WPS == 1 && MT <= 4);
+
+    Frag w1[MT][K1S];
+    Frag w2[MT][K2S];
+    Frag w3[NHW][KHS];
+    float o3[NHW][4];                  // head output scale
+    float inv_q1, inv_q2;              // 1 / scale of the h1 and h2 quantisation
+
+    __device__ static Frag& w1_lds(char* base, int wave, int mt, int ks, int lane) {
+        return reinterpret_cast<Frag*>(base)[((wave * MT + mt) * K1S + ks) * 64 + lane];
+    }
+    __device__ static Frag& w3_lds(char* base, int wave, int hw, int ks, int lane) {
+        return reinterpret_cast<Frag*>(base)[((wave * NHW + hw) * KHS + ks) * 64 + lane];
+    }
+
+    __device__ static float row_scale(const float* s, int m, int m_valid) {
+        return (s != nullptr && m < m_valid) ? s[m] : 1.0f;
+    }
+
+    // Weights into registers and the per-feature table into LDS (the caller
+    // synchronises the workgroup before the first forward).
+    __device__ void load(const PolicyArgs& p, char* smem, int wave, int lane, int tid) {
+        const int lr = lane & 15, kq = (lane >> 4) * KC;
+        const float a0 = DT == DT_FP8 ? p.act_scale[0] : 1.0f;
+        const float a1 = DT == DT_FP8 ? p.act_scale[1] : 1.0f;
+        const float a2 = DT == DT_FP8 ? p.act_scale[2] : 1.0f;
+        inv_q1 = 1.0f / a1;
+        inv_q2 = 1.0f / a2;
+        float* tab = reinterpret_cast<float*>(smem + OFF_TAB);
+        for (int m = tid; m < H; m += NW * 64) {
+            const float sc1 = row_scale(p.s1, m, H) * a0;
+            const float sc2 = row_scale(p.s2, m, H) * a1;
+            tab[m] = p.b1[m] / sc1;
+            tab[H + m] = kTwoLog2e * sc1;
+            tab[2 * H + m] = p.b2[m] / sc2;
+            tab[3 * H + m] = kTwoLog2e * sc2;
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const int m = wave * FPW + mt * 16 + lr;
+#pragma unroll
+            for (int ks = 0; ks < K1S; ++ks) {
+                load_a(w1[mt][ks], p.w1, p.d_in, m, H, ks * K + kq, p.d_in);
+                if constexpr (W1_LDS)
+                    w1_lds(reinterpret_cast<char*>(tab) + (OFF_W1 - OFF_TAB), wave, mt, ks, lane) =
+                        w1[mt][ks];
+            }
+#pragma unroll
+            for (int ks = 0; ks < K2S; ++ks) load_a(w2[mt][ks], p.w2, H, m, H, ks * K + kq, H);
+        }
+#pragma unroll
+        for (int hw = 0; hw < NHW; ++hw) {
+            const int ht = HS ? wave + hw * NW : hw;   // head row tile
+            const int m = ht * 16 + lr;
+#pragma unroll
+            for (int ks = 0; ks < KHS; ++ks) {
+                if constexpr (HS) {
+                    load_a(w3[hw][ks], p.w3, H, m, p.n_head, ks * K + kq, H);
+                } else {
+                    // K element e of lane group q is this wave's layer-2 output
+                    // (tile mt, accumulator row i): idx = ks KC + e, mt = idx / 4
+                    const int q = lane >> 4;
+                    load_a_cols(w3[hw][ks], p.w3, H, m, p.n_head, [&](int e) {
+                        const int idx = ks * KC + e;
+                        return wave * FPW + (idx >> 2) * 16 + 4 * q + (idx & 3);
+                    });
+                    if constexpr (W3_LDS)
+                        w3_lds(reinterpret_cast<char*>(tab) + (OFF_W3 - OFF_TAB), wave, hw, ks,
+                               lane) = w3[hw][ks];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) o3[hw][i] = row_scale(p.s3, ht * 16 + 4 * (lane >> 4) + i, p.n_head) * a2;
+        }
+    }
+
+    // Accumulators of this wave's MT output tiles for row tile `nt`: the
+    // per-feature start `ini` plus W times the row tile's inputs.
+    template <int KS>
+    __device__ __forceinline__ static void mma_rows(f32x4 (&acc)[MT], const Frag (&w)[MT][KS],
+                                                    const float4 (&ini)[MT], const char* in,
+                                                    int p_in, int nt, int lane) {
+        const int lr = lane & 15, kq = (lane >> 4) * KC;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{ini[mt].x, ini[mt].y, ini[mt].z, ini[mt].w};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const Frag b = M::lds(in + (nt * 16 + lr) * p_in + (ks * K + kq) * EB);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[mt] = M::mma(w[mt][ks], b, acc[mt]);
+        }
+    }
+
+    // Layer outputs of one accumulator tile, quantised for the next product:
+    // four BF16 (uint2), four FP8 codes (uint32) or four floats.
+    typedef typename std::conditional<
+        DT == DT_BF16, uint2, typename std::conditional<DT == DT_FP8, uint32_t, float4>::type>::type
+        Packed;
+
+    __device__ __forceinline__ static Packed tanh_pack(const f32x4& a, const float4& k, float q) {
+        if constexpr (DT == DT_FP8) {
+            return pack_fp8x4(tanh_scaled_q(a[0], k.x, q), tanh_scaled_q(a[1], k.y, q),
+                              tanh_scaled_q(a[2], k.z, q), tanh_scaled_q(a[3], k.w, q));
+        } else if constexpr (DT == DT_BF16) {
+            return make_uint2(pack_bf16x2(tanh_scaled(a[0], k.x), tanh_scaled(a[1], k.y)),
+                              pack_bf16x2(tanh_scaled(a[2], k.z), tanh_scaled(a[3], k.w)));
+        } else {
+            return make_float4(tanh_scaled(a[0], k.x), tanh_scaled(a[1], k.y),
+                               tanh_scaled(a[2], k.z), tanh_scaled(a[3], k.w));
+        }
+    }
+
+    // B fragment of head K-step ks from this wave's packed layer-2 outputs of
+    // one row tile (the order load() gave the head weights).
+    __device__ __forceinline__ static Frag head_frag(const Packed (&pk)[MT], int ks) {
+        if constexpr (DT == DT_BF16) {
+            const uint4 u = make_uint4(pk[2 * ks].x, pk[2 * ks].y, pk[2 * ks + 1].x, pk[2 * ks + 1].y);
+            return __builtin_bit_cast(Frag, u);
+        } else if constexpr (DT == DT_FP8) {
+            return (long)((uint64_t)pk[2 * ks] | ((uint64_t)pk[2 * ks + 1] << 32));
+        } else {
+            const float4 v = pk[ks >> 2];
+            const int i = ks & 3;
+            return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+        }
+    }
+
+    // tanh of row tile `nt`'s accumulators: quantised into `out` ([R][H]) for
+    // the next layer (layer 1, split-M layer 2), or fed to the split-K head
+    // MFMAs of this row tile (HEAD: layer 2 of a split-K head).
+    template <bool HEAD>
+    __device__ __forceinline__ void tanh_rows(const f32x4 (&acc)[MT], const float4 (&kx)[MT],
+                                              char* out, float q, int nt, int wave, int lane,
+                                              f32x4 (&acc3)[NHW][NT]) {
+        const int lr = lane & 15;
+        Packed pk[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) pk[mt] = tanh_pack(acc[mt], kx[mt], DT == DT_FP8 ? q : 1.0f);
+        if constexpr (HEAD) {
+#pragma unroll
+            for (int ks = 0; ks < KHS; ++ks) {
+                const Frag b = head_frag(pk, ks);
+#pragma unroll
+                for (int hw = 0; hw < NHW; ++hw) acc3[hw][nt] = M::mma(w3[hw][ks], b, acc3[hw][nt]);
+            }
+        } else {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const int feat = wave * FPW + mt * 16 + 4 * (lane >> 4);
+                *reinterpret_cast<Packed*>(out + (nt * 16 + lr) * P_H + feat * EB) = pk[mt];
+            }
+        }
+    }
+
+    // Dense layer of this wave's MT output tiles for all NT row tiles, then
+    // tanh and quantisation (into `out`, or into the split-K head's MFMAs
+    // with HEAD). With PIPE_ON the loop is software-pipelined over row tiles:
+    // the MFMAs of row tile n + 1 are issued ahead of the tanh of row tile n,
+    // so the matrix core and the vector ALU of the SIMD work at the same time
+    // (this holds two tiles of accumulators and the next tile's operands in
+    // registers; without it -- kernels with four or more waves per SIMD, or
+    // whose layer-2 weights take more than 64 registers per lane -- each row
+    // tile is multiplied, then activated). `tab` holds the layer's
+    // accumulator starts and tanh factors.
+    template <int KS, bool HEAD>
+    __device__ __forceinline__ void dense_tanh(const Frag (&w)[MT][KS], const float* tab,
+                                               const char* in, int p_in, char* out, float inv_q,
+                                               int wave, int lane, f32x4 (&acc3)[NHW][NT]) {
+        float4 ini[MT], kx[MT];
+        auto per_feature = [&]() {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const int feat = wave * FPW + mt * 16 + 4 * (lane >> 4);
+                ini[mt] = *reinterpret_cast<const float4*>(tab + feat);
+                if constexpr (DT == DT_FP8)
+                    kx[mt] = *reinterpret_cast<const float4*>(tab + H + feat);
+                else
+                    kx[mt] = make_float4(kTwoLog2e, kTwoLog2e, kTwoLog2e, kTwoLog2e);
+            }
+        };
+        if constexpr (!PIPE_ON) {
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                f32x4 acc[MT];
+                per_feature();   // re-read per row tile: fewer live registers
+                mma_rows<KS>(acc, w, ini, in, p_in, nt, lane);
+                tanh_rows<HEAD>(acc, kx, out, inv_q, nt, wave, lane, acc3);
+            }
+            return;
+        }
+        per_feature();
+        f32x4 acc[2][MT];
+        mma_rows<KS>(acc[0], w, ini, in, p_in, 0, lane);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            if (nt + 1 < NT) mma_rows<KS>(acc[(nt + 1) & 1], w, ini, in, p_in, nt + 1, lane);
+            tanh_rows<HEAD>(acc[nt & 1], kx, out, inv_q, nt, wave, lane, acc3);
+            if (nt + 1 < NT) {
+                // all LDS reads of the next row tile first, a few vector
+                // instructions while they land, then one MFMA at a time, each
+                // followed by a share of the tanh's vector work
+                constexpr int NM = MT * KS + (HEAD ? NHW * KHS : 0);
+                constexpr int NVT = MT * 4 * 6, NV0 = 8;
+                constexpr int NV = (NVT - NV0 + NM - 1) / NM;
+                __builtin_amdgcn_sched_group_barrier(0x100, KS, 0);
+                __builtin_amdgcn_sched_group_barrier(0x002, NV0, 0);
+#pragma unroll
+                for (int i = 0; i < NM; ++i) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x002, NV, 0);
+                }
+                __builtin_amdgcn_sched_barrier(0);   // one scheduling region per row tile
+            }
+        }
+    }
+
+    // Phases A-C. The caller synchronises the workgroup afterwards.
+    __device__ void forward(char* smem, int wave, int lane) {
+        const float* tab = reinterpret_cast<const float*>(smem + OFF_TAB);
+        const int lr = lane & 15, kq = (lane >> 4) * KC;
+        f32x4 acc[NHW][NT];
+#pragma unroll
+        for (int hw = 0; hw < NHW; ++hw)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[hw][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        if constexpr (W1_LDS) {
+            Frag w1r[MT][K1S];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int ks = 0; ks < K1S; ++ks) w1r[mt][ks] = w1_lds(smem + OFF_W1, wave, mt, ks, lane);
+            dense_tanh<K1S, false>(w1r, tab, smem + OFF_IN, P_IN, smem + OFF_H1, inv_q1, wave, lane,
+                                   acc);
+        } else {
+            dense_tanh<K1S, false>(w1, tab, smem + OFF_IN, P_IN, smem + OFF_H1, inv_q1, wave, lane,
+                                   acc);
+        }
+        __syncthreads();
+        if constexpr (!HS) {
+            if constexpr (W3_LDS) {   // head weights back from LDS for this step
+#pragma unroll
+                for (int hw = 0; hw < NHW; ++hw)
+#pragma unroll
+                    for (int ks = 0; ks < KHS; ++ks) w3[hw][ks] = w3_lds(smem + OFF_W3, wave, hw, ks, lane);
+            }
+            // split-K: the head consumes each wave's own h2 from its registers
+            dense_tanh<K2S, true>(w2, tab + 2 * H, smem + OFF_H1, P_H, nullptr, inv_q2, wave, lane,
+                                  acc);
+        } else {
+            dense_tanh<K2S, false>(w2, tab + 2 * H, smem + OFF_H1, P_H, smem + OFF_H2, inv_q2, wave,
+                                   lane, acc);
+            __syncthreads();   // every wave reads all of h2
+            const char* h2 = smem + OFF_H2;
+#pragma unroll
+            for (int ks = 0; ks < KHS; ++ks) {
+                Frag b[NT];
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    b[nt] = M::lds(h2 + (nt * 16 + lr) * P_H + (ks * K + kq) * EB);
+#pragma unroll
+                for (int hw = 0; hw < NHW; ++hw) {
+                    if (wave + hw * NW >= NHT) break;
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) acc[hw][nt] = M::mma(w3[hw][ks], b[nt], acc[hw][nt]);
+                }
+            }
+        }
+        float* part = reinterpret_cast<float*>(smem + OFF_PART) + (HS ? 0 : wave * R * P_PART);
+#pragma unroll
+        for (int hw = 0; hw < NHW; ++hw) {
+            const int ht = HS ? wave + hw * NW : hw;
+            if (HS && ht >= NHT) break;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const f32x4 a = acc[hw][nt];
+                const int j = ht * 16 + 4 * (lane >> 4);
+                *reinterpret_cast<float4*>(part + (nt * 16 + lr) * P_PART + j) =
+                    make_float4(a[0] * o3[hw][0], a[1] * o3[hw][1], a[2] * o3[hw][2], a[3] * o3[hw][3]);
+            }
+        }
+    }
+
+    // Head outputs of tile row r: bias + partials summed in wave order (split-K)
+    // or bias + the one result (split-M).
+    template <int NH>
+    __device__ static void head_row(const char* smem, const float* b3, int r, float (&h)[NH]) {
+        const float* part = reinterpret_cast<const float*>(smem + OFF_PART);
+#pragma unroll
+        for (int j = 0; j < NH; ++j) h[j] = 0.0f;
+#pragma unroll
+        for (int w = 0; w < NPART; ++w) {
+            const float* pr = part + (w * R + r) * P_PART;
+#pragma unroll
+            for (int j4 = 0; j4 < NHP / 4; ++j4) {
+                if (j4 * 4 >= NH) break;
+                const float4 v = *reinterpret_cast<const float4*>(pr + j4 * 4);
+                if (j4 * 4 + 0 < NH) h[j4 * 4 + 0] += v.x;
+                if (j4 * 4 + 1 < NH) h[j4 * 4 + 1] += v.y;
+                if (j4 * 4 + 2 < NH) h[j4 * 4 + 2] += v.z;
+                if (j4 * 4 + 3 < NH) h[j4 * 4 + 3] += v.w;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NH; ++j) h[j] += b3[j];
+    }
+
+    // Head outputs [j0, j0 + C) (those below NH - 1) and the value output
+    // (index NH - 1) of tile row r, summed in the same order as head_row.
+    template <int NH, int C>
+    __device__ static void head_block(const char* smem, const float (&b3b)[C], float b3v, int r,
+                                      int j0, float (&hb)[C], float& hv) {
+        const float* part = reinterpret_cast<const float*>(smem + OFF_PART);
+        float acc[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] = 0.0f;
+        float accv = 0.0f;
+#pragma unroll
+        for (int w = 0; w < NPART; ++w) {
+            const float* pr = part + (w * R + r) * P_PART;
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (j0 + c < NH - 1) acc[c] += pr[j0 + c];
+            accv += pr[NH - 1];
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) hb[c] = acc[c] + b3b[c];
+        hv = accv + b3v;
+    }
+
+    // Quantised observation row into the input tile; lane `sub` of the row's
+    // G lanes writes the elements congruent to sub mod G.
+    template <int OD, int G>
+    __device__ static void put_obs(char* smem, int r, const float (&o)[OD], float inv_q0, int sub) {
+        char* p = smem + OFF_IN + r * P_IN;
+#pragma unroll
+        for (int k = 0; k < OD; ++k)
+            if (k % G == sub) store1<DT>(p + k * EB, o[k], inv_q0);
+    }
+};
+
+// ------------------------------------------------------------- sampling --
+// The head block of a row's lane: lane `sub` of G holds logits
+// [sub * C, sub * C + C) of a categorical head; a Gaussian head's mean is on
+// every lane.
+template <class E, int G>
+struct Block {
+    static constexpr int C = E::NACT ? (E::NACT + G - 1) / G : 1;
+    __device__ static int first(int sub) { return E::NACT ? sub * C : 0; }
+};
+
+// Categorical draw over the row's G lanes: softmax with the maximum
+// subtracted, CDF in index order, a = min{k : u < C_k} (K - 1 if none).
+// Every lane returns the same action and log-probability.
+template <int K, int G, int C>
+__device__ __forceinline__ int sample_categorical(const float (&lg)[C], int sub, float u,
+                                                  float& logp) {
+    const int j0 = sub * C;
+    float mx = -__builtin_inff();
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        if (j0 + c < K) mx = fmaxf(mx, lg[c]);
+    mx = group_max<G>(mx);
+    float e[C];
+    float s = 0.0f;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        e[c] = j0 + c < K ? expf(lg[c] - mx) : 0.0f;
+        s += e[c];
+    }
+    const float z = group_sum<G>(s);
+    const float inv_z = 1.0f / z;
+    float acc = group_prefix<G>(s, sub);
+    int cand = K;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        acc += e[c];
+        if (cand == K && j0 + c < K && u < acc * inv_z) cand = j0 + c;
+    }
+    int a = group_min<G>(cand);
+    if (a >= K) a = K - 1;
+    float la = 0.0f;
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        if (j0 + c == a) la = lg[c];
+    la = group_sum<G>(la);   // only the owner contributes
+    logp = (la - mx) - logf(z);
+    return a;
+}
+
+template <class E>
+struct Act {
+    int index;
+    float value;
+};
+
+// The part of a draw that does not depend on the policy's outputs: the
+// categorical uniform, or the Gaussian's standard normal and log-probability.
+// The fused kernel computes it for step t + 1 beside the dynamics of step t.
+template <class E>
+struct Pre {
+    float u;      // categorical: the uniform; Gaussian: z
+    float logp;   // Gaussian: log-probability of z
+};
+
+template <class E>
+__device__ __forceinline__ Pre<E> prepare(const RngKey& key, uint32_t t, uint32_t row,
+                                          float log_std) {
+    const Words w = draw(key, t, row, PURPOSE_ACTION, 0);
+    Pre<E> p{0.0f, 0.0f};
+    if constexpr (E::NACT > 0) {
+        p.u = unit_uniform(w.w[0]);
+    } else {
+        float zc, zs;
+        gauss_pair(unit_uniform(w.w[0]), unit_uniform(w.w[1]), zc, zs);
+        p.u = zc;
+        p.logp = -0.5f * zc * zc - log_std - 0.91893853320467274f;   // log(2 pi) / 2
+    }
+    return p;
+}
+
+// The action from the head block and the prepared draw.
+template <class E, int G, int C>
+__device__ __forceinline__ Act<E> decide(const float (&hb)[C], int sub, const Pre<E>& p,
+                                         float sigma, float& logp) {
+    Act<E> act{0, 0.0f};
+    if constexpr (E::NACT > 0) {
+        act.index = sample_categorical<E::NACT, G, C>(hb, sub, p.u, logp);
+        act.value = (float)act.index;
+    } else {
+        act.value = hb[0] + sigma * p.u;
+        logp = p.logp;
+    }
+    return act;
+}
+
+// Draw the action of row `row` at step t from its head block.
+template <class E, int G, int C>
+__device__ __forceinline__ Act<E> choose(const float (&hb)[C], int sub, const RngKey& key,
+                                         uint32_t t, uint32_t row, float log_std, float& logp) {
+    return decide<E, G, C>(hb, sub, prepare<E>(key, t, row, log_std), expf(log_std), logp);
+}
+
+template <class E>
+__device__ __forceinline__ void store_action(const TrajArgs& tr, size_t idx, const Act<E>& a) {
+    if constexpr (E::NACT > 0)
+        static_cast<uint8_t*>(tr.action)[idx] = (uint8_t)a.index;
+    else
+        static_cast<float*>(tr.action)[idx] = a.value;
+}
+
+template <class E>
+__device__ __forceinline__ Act<E> load_action(const TrajArgs& tr, size_t idx) {
+    Act<E> a{0, 0.0f};
+    if constexpr (E::NACT > 0)
+        a.index = static_cast<const uint8_t*>(tr.action)[idx];
+    else
+        a.value = static_cast<const float*>(tr.action)[idx];
+    return a;
+}
+
+// ------------------------------------------------------------- env glue --
+template <class E>
+__device__ __forceinline__ void load_state(const EnvArgs& env, int64_t row, float (&s)[E::SR]) {
+#pragma unroll
+    for (int i = 0; i < E::SD; ++i) s[i] = env.state[(size_t)i * env.n_rows + row];
+    E::complete(s);   // derived register-state entries (sin / cos of the angles)
+}
+
+template <class E, int G>
+__device__ __forceinline__ void save_state(const EnvArgs& env, int64_t row, const float (&s)[E::SR],
+                                           int sub) {
+#pragma unroll
+    for (int i = 0; i < E::SD; ++i)
+        if (i % G == sub) env.state[(size_t)i * env.n_rows + row] = s[i];
+}
+
+template <int OD, int G>
+__device__ __forceinline__ void store_obs(float* dst, const float (&o)[OD], int sub) {
+#pragma unroll
+    for (int k = 0; k < OD; ++k)
+        if (k % G == sub) dst[k] = o[k];
+}
+
+// Stage the reaction potential in LDS: A, centres, -1/(2 w^2), amplitudes.
+__device__ __forceinline__ void stage_params(float* dst, const float* src, int tid, int nthreads) {
+    constexpr int NA = Reaction::NDIM * Reaction::NDIM + Reaction::NG * Reaction::NDIM;
+    for (int i = tid; i < Reaction::PARAM_FLOATS; i += nthreads) {
+        float v = src[i];
+        if (i >= NA && i < NA + Reaction::NG) v = -0.5f / (v * v);
+        dst[i] = v;
+    }
+}
+
+template <class E>
+constexpr int extra_lds_bytes(int R) {
+    if constexpr (E::KIND == Reaction::KIND) return Reaction::PARAM_FLOATS * 4;
+    if constexpr (E::KIND == Market::KIND) return 2 * R * 2 * 4;   // [parity][slot][D, S]
+    return 0;
+}
+
+__device__ __forceinline__ uint32_t step_base(const EnvArgs& env) {
+    return env.step_ptr ? *env.step_ptr + env.t0 : env.t0;
+}
+
+__device__ __forceinline__ Tile tile_of(const EnvArgs& env, int tile) {
+    if (env.tiles) return env.tiles[tile];
+    const int rows = env.tile_rows;   // <= the kernel's row capacity
+    Tile t;
+    t.row0 = tile * rows;
+    t.row1 = (int)min((int64_t)(tile + 1) * rows, env.n_rows);
+    t.env0 = t.row0;
+    t.env1 = t.row1;
+    return t;
+}
+
+// Market: slot of row r (global) among the tile's envs (binary search).
+__device__ __forceinline__ int env_slot(const EnvArgs& env, const Tile& tl, int r) {
+    int lo = tl.env0, hi = tl.env1 - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (env.offsets[mid] <= r) lo = mid; else hi = mid - 1;
+    }
+    return lo - tl.env0;
+}
+
+// ---------------------------------------------------------- fused form --
+// The launch covers the tiles of one or more segments (roll-out requests that
+// share the policy): tile b of the launch belongs to the segment whose
+// tile_begin is the largest one <= b.
+// A copy of a wave-uniform struct in scalar registers (every dword through
+// v_readfirstlane).
+template <class T>
+__device__ __forceinline__ T uniform(const T& v) {
+    static_assert(sizeof(T) % 4 == 0, "whole dwords");
+    uint32_t w[sizeof(T) / 4];
+    __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+    T out;
+    __builtin_memcpy(&out, w, sizeof(T));
+    return out;
+}
+
+// Index of the segment that tile `tile` of the launch belongs to.
+__device__ __forceinline__ int segment_index(const Batch& b, int tile) {
+    if (!b.table) {
+        int i = 0;
+        while (i + 1 < b.n_segs && b.inl[i + 1].tile_begin <= tile) ++i;
+        return i;
+    }
+    int lo = 0, hi = b.n_segs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (b.table[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Copy segment i into LDS (`dst`), one dword per thread. The inline segments
+// are read through the kernel-argument segment pointer (the Batch is the
+// kernel's only argument, at offset 0): indexing the argument itself would
+// make the compiler copy all of it to scratch. The caller synchronises.
+__device__ __forceinline__ void stage_segment(const Batch& b, int i, Segment* dst, int tid,
+                                              int nthreads) {
+    typedef const __attribute__((address_space(4))) uint32_t KArgWord;
+    constexpr int NW32 = (int)(sizeof(Segment) / 4);
+    static_assert(sizeof(Segment) % 4 == 0, "segment of whole dwords");
+    uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+    if (b.table) {
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(b.table + i);
+        for (int k = tid; k < NW32; k += nthreads) d[k] = src[k];
+    } else {
+        KArgWord* src = (KArgWord*)((const __attribute__((address_space(4))) char*)
+                                        __builtin_amdgcn_kernarg_segment_ptr() +
+                                    __builtin_offsetof(Batch, inl) + (size_t)i * sizeof(Segment));
+        for (int k = tid; k < NW32; k += nthreads) d[k] = src[k];
+    }
+}
+
+// One tile of a fused launch: rows [row0, row1) of segment `sg` for its
+// steps (plus the value pass), with the policy already in the registers of
+// `mlp` and its per-feature table in LDS.
+template <class E, class L, int NW>
+__device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, char* smem,
+                                           char* extra, const float*& staged, int tid, int wave,
+                                           int lane) {
+    using HO = HeadOf<E>;
+    constexpr int DT = L::DTYPE;
+    constexpr int R = L::R;
+    constexpr int NTHR = NW * 64;
+    constexpr int G = lanes_per_row(R, NTHR, E::LANES);   // lanes serving one row in phase D
+    using B = Block<E, G>;
+    constexpr int C = B::C;
+    static_assert(R * G <= NTHR, "G lanes per tile row");
+    const int rr = tid / G, sub = tid % G;   // tile row and lane within its group
+    const PolicyArgs& pol = sg.pol;
+    const float inv_q0 = DT == DT_FP8 ? 1.0f / pol.act_scale[0] : 1.0f;
+    const float log_std = (E::NACT == 0 && pol.log_std) ? pol.log_std[0] : 0.0f;
+    const int j0 = B::first(sub);
+    float b3b[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) b3b[c] = j0 + c < HO::NOUT ? pol.b3[j0 + c] : 0.0f;
+    const float b3v = pol.b3[HO::NOUT];
+    EnvCtx ctx{reinterpret_cast<const float*>(extra)};
+    int* sums = reinterpret_cast<int*>(extra);   // market: [2][R][2]
+    // the segment's fields the steps use, read once from LDS into scalar
+    // registers (they are uniform over the workgroup)
+    const EnvArgs env = uniform(sg.env);
+    const TrajArgs tr = uniform(sg.tr);
+    const int horizon = __builtin_amdgcn_readfirstlane(sg.steps);
+    const RngKey key{env.k0, env.k1, env.epoch};
+    const uint32_t t0 = step_base(env);
+    if constexpr (E::KIND == Reaction::KIND) {
+        if (env.params != staged) {   // uniform over the workgroup
+            stage_params(reinterpret_cast<float*>(extra), env.params, tid, NTHR);
+            staged = env.params;
+            __syncthreads();
+        }
+    }
+    const Tile tl = tile_of(env, tile - __builtin_amdgcn_readfirstlane(sg.tile_begin));
+    const int row = tl.row0 + rr;
+    const bool mine = rr < R;
+    const bool valid = mine && row < tl.row1;
+    const bool lead = valid && sub == 0;   // writes the row's scalar records
+    float s[E::SR];
+#pragma unroll
+    for (int i = 0; i < E::SR; ++i) s[i] = 0.0f;
+    if (valid) load_state<E>(env, row, s);
+    int slot = 0;
+    if constexpr (E::KIND == Market::KIND) {
+        if (valid) slot = env_slot(env, tl, row);
+        for (int i = tid; i < 4 * R; i += NTHR) sums[i] = 0;
+    }
+    if (mine) {
+        float o[E::OD];
+        E::observe(s, o);
+        L::template put_obs<E::OD, G>(smem, rr, o, inv_q0, sub);
+        if (valid && horizon > 0) store_obs<E::OD, G>(tr.obs + (size_t)row * E::OD, o, sub);
+    }
+    const float sigma = expf(log_std);
+    Pre<E> pre = prepare<E>(key, t0, (uint32_t)row, log_std);   // step 0's draw
+    __syncthreads();
+
+    const int passes = horizon + (__builtin_amdgcn_readfirstlane(sg.last) ? 1 : 0);   // + V(s_T)
+    for (int step = 0; step < passes; ++step) {
+        mlp.forward(smem, wave, lane);
+        __syncthreads();
+        const uint32_t t = t0 + (uint32_t)step;
+        const size_t idx = (size_t)step * env.n_rows + row;
+        Act<E> act{0, 0.0f};
+        if (valid) {
+            float hb[C], hv;
+            L::template head_block<HO::NH, C>(smem, b3b, b3v, rr, j0, hb, hv);
+            if (step == horizon) {
+                if (lead) tr.last_value[row] = hv;
+            } else {
+                float logp;
+                act = decide<E, G, C>(hb, sub, pre, sigma, logp);
+                if (lead) {
+                    tr.value[idx] = hv;
+                    tr.logp[idx] = logp;
+                    store_action<E>(tr, idx, act);
+                }
+                if constexpr (E::KIND == Market::KIND) {
+                    if (lead) {
+                        int dh, s18;
+                        Market::decide(act.index, dh, s18);
+                        int* sl = sums + ((step & 1) * R + slot) * 2;
+                        atomicAdd(sl, dh);
+                        atomicAdd(sl + 1, s18);
+                    }
+                }
+            }
+        }
+        if constexpr (E::KIND == Market::KIND) {
+            __syncthreads();
+            if (step < horizon) {
+                if (valid) {
+                    const Pre<E> nxt = prepare<E>(key, t + 1, (uint32_t)row, log_std);
+                    const int* sl = sums + ((step & 1) * R + slot) * 2;
+                    float reward;
+                    Market::settle(s, act.index, sl[0], sl[1], reward);
+                    pre = nxt;
+                    if (lead) {
+                        tr.reward[idx] = reward;
+                        tr.done[idx] = 0;
+                    }
+                }
+                // the other parity's sums were last read in the previous step
+                for (int i = tid; i < 2 * R; i += NTHR) sums[((step + 1) & 1) * 2 * R + i] = 0;
+            }
+        } else {
+            if (valid && step < horizon) {
+                // the next step's draw, independent of this step's dynamics
+                const Pre<E> nxt = prepare<E>(key, t + 1, (uint32_t)row, log_std);
+                float reward;
+                bool done;
+                E::template step<G>(s, act.index, act.value, t, (uint32_t)row, key, ctx, sub,
+                                    reward, done);
+                pre = nxt;
+                if (done) E::reset(s, key, t + 1, (uint32_t)row, ctx);
+                if (lead) {
+                    tr.reward[idx] = reward;
+                    tr.done[idx] = done ? 1 : 0;
+                }
+            }
+        }
+        if (valid && step < horizon) {
+            float o[E::OD];
+            E::observe(s, o);
+            L::template put_obs<E::OD, G>(smem, rr, o, inv_q0, sub);
+            if (step + 1 < horizon)
+                store_obs<E::OD, G>(tr.obs + ((size_t)(step + 1) * env.n_rows + row) * E::OD, o,
+                                    sub);
+        }
+        __syncthreads();
+    }
+    if (valid) save_state<E, G>(env, row, s, sub);
+}
+
+// Persistent fused roll-out: each workgroup walks tiles of the launch's
+// segments; E2 (if not E) is a second environment kind whose tiles share the
+// policy shape. The weights are (re)loaded when a tile's policy differs from
+// the one in the registers.
+template <class E, class E2, int DT, int H, int NW, int NT, int HS, int OCC>
+__global__ void __attribute__((amdgpu_flat_work_group_size(NW * 64, NW * 64),
+                               amdgpu_waves_per_eu(OCC)))
+k_fused(Batch batch) {
+    using HO = HeadOf<E>;
+    static_assert(HeadOf<E2>::NHP == HO::NHP && kin_of<E2, DT>() == kin_of<E, DT>(),
+                  "kinds of one kernel share the policy shape");
+    using L = Mlp<DT, H, NW, NT, kin_of<E, DT>(), HO::NHP, HS, OCC>;
+    constexpr int R = L::R;
+    constexpr int NTHR = NW * 64;
+    constexpr int EXTRA = extra_lds_bytes<E>(R) > extra_lds_bytes<E2>(R) ? extra_lds_bytes<E>(R)
+                                                                         : extra_lds_bytes<E2>(R);
+    __shared__ __attribute__((aligned(16))) char smem[L::BYTES + EXTRA];
+    char* extra = smem + L::BYTES;
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    L mlp;
+    int loaded = -1;                 // segment whose policy is in the registers
+    const float* staged = nullptr;   // reaction: potential block now in LDS
+    // zero the input tile once: its padding columns stay zero
+    for (int i = tid; i < R * L::P_IN / 4; i += NTHR)
+        reinterpret_cast<uint32_t*>(smem + L::OFF_IN)[i] = 0u;
+
+    __shared__ Segment seg;          // the current tile's segment
+    for (int tile = blockIdx.x; tile < batch.n_tiles; tile += gridDim.x) {
+        const int si = segment_index(batch, tile);   // uniform over the workgroup
+        __syncthreads();   // the previous tile's last reads of `seg` and the table are done
+        stage_segment(batch, si, &seg, tid, NTHR);
+        __syncthreads();
+        const Segment& sg = seg;
+        if (si != loaded) {
+            mlp.load(sg.pol, smem, wave, lane, tid);
+            loaded = si;
+            __syncthreads();
+        }
+        if constexpr (!std::is_same<E, E2>::value) {
+            if (sg.env.kind == E2::KIND) {
+                fused_tile<E2, L, NW>(sg, tile, mlp, smem, extra, staged, tid, wave, lane);
+                continue;
+            }
+        }
+        fused_tile<E, L, NW>(sg, tile, mlp, smem, extra, staged, tid, wave, lane);
+    }
+}
+
+// -------------------------------------------------------------- reset --
+template <class E>
+__global__ void k_reset(EnvArgs env) {
+    __shared__ float params[E::KIND == Reaction::KIND ? Reaction::PARAM_FLOATS : 1];
+    EnvCtx ctx{nullptr};
+    if constexpr (E::KIND == Reaction::KIND) {
+        stage_params(params, env.params, threadIdx.x, blockDim.x);
+        ctx.lds_params = params;
+    }
+    __syncthreads();
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= env.n_rows) return;
+    const RngKey key{env.k0, env.k1, env.epoch};
+    float s[E::SR];
+    E::reset(s, key, 0u, (uint32_t)row, ctx);
+    save_state<E, 1>(env, row, s, 0);
+}
+
+}  // namespace wsx

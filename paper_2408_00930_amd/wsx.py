@@ -595,3 +595,30 @@ def adam_step(param, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, sto
     _check(L.wsx_adam_step(param.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(), n,
                            int(step), float(lr), float(beta1), float(beta2), float(eps),
                            None if store is None else store.data_ptr(), sd, _stream(stream)))
+
+
+# ----------------------------------------------------------- user kinds ----
+
+class _UserKindDesc(C.Structure):
+    _fields_ = [("state_dim", C.c_int32), ("obs_dim", C.c_int32), ("n_actions", C.c_int32),
+                ("dtype", C.c_int32), ("hidden", C.c_int32)]
+
+
+EXPORTS += ["wsx_user_kind_register"]
+
+
+def user_kind_register(source, state_dim, obs_dim, n_actions, dtype, hidden):
+    """Compile a user environment (C++ source of `struct UserEnv`) into the
+    fused roll-out and return its new kind; the kind's sizes are recorded so
+    Env and Trajectory work with it."""
+    L = lib()
+    L.wsx_user_kind_register.argtypes = [C.POINTER(_UserKindDesc), C.c_char_p,
+                                         C.POINTER(C.c_int32)]
+    d = _UserKindDesc(state_dim, obs_dim, n_actions,
+                      DTYPE_CODE[dtype] if isinstance(dtype, str) else dtype, hidden)
+    k = C.c_int32()
+    _check(L.wsx_user_kind_register(C.byref(d), source.encode(), C.byref(k)))
+    OBS_DIM[k.value] = obs_dim
+    STATE_DIM[k.value] = state_dim
+    N_ACTIONS[k.value] = n_actions
+    return k.value

@@ -182,3 +182,20 @@ def test_update_validation_without_gpu():
     assert L.wsx_adam_step(p, p, p, p, 10, 1, 1e-3, 0.9, 0.999, 1e-8, p, 2, None) == -1
     assert L.wsx_adam_step(None, None, None, None, 0, 1, 1e-3, 0.9, 0.999, 1e-8, None, 0,
                            None) == 0
+
+
+def test_user_kind_validation_and_compile_errors_without_gpu():
+    wsx, L = _lib()
+    import user_envs
+    with pytest.raises(wsx.WsxError, match="state_dim"):
+        wsx.user_kind_register(user_envs.POINT_MASS, 0, 2, 0, "bf16", 256)
+    with pytest.raises(wsx.WsxError, match="user kinds run"):
+        wsx.user_kind_register(user_envs.POINT_MASS, 2, 2, 0, "fp8", 512)
+    with pytest.raises(wsx.WsxError, match="does not compile"):
+        wsx.user_kind_register("struct UserEnv { int x = ; };", 2, 2, 0, "bf16", 256)
+    # sizes that disagree with the descriptor are a compile-time error too
+    with pytest.raises(wsx.WsxError, match="sizes differ"):
+        wsx.user_kind_register(user_envs.POINT_MASS, 3, 2, 0, "bf16", 256)
+    # a valid source compiles here; loading needs a GPU
+    with pytest.raises(wsx.WsxError, match="no HIP device"):
+        wsx.user_kind_register(user_envs.POINT_MASS, 2, 2, 0, "bf16", 256)
