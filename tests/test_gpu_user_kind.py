@@ -135,3 +135,36 @@ def test_user_kind_sets_batch_in_one_launch():
         got = tr.host()
         for f in got:
             assert np.array_equal(got[f], ref[i][f]), (i, f)
+
+
+def test_user_kind_served_with_builtin_requests():
+    """A request of the user Pendulum served in a mix with built-in Pendulum
+    and Acrobot requests returns the built-in Pendulum's direct results."""
+    import torch
+    wsx = _wsx()
+    k = _kind("pendulum")
+    say("user kind served")
+    dp = wsx.DevicePolicy(inputs.policy_for(2, "bf16", 256, seed=7))
+    acro = wsx.DevicePolicy(inputs.policy_for(3, "bf16", 256, seed=8))
+    T, n = 45, 150
+    env = wsx.Env(2, n, seed=5)
+    tr = wsx.Trajectory(2, T, env.rows)
+    wsx.env_reset(env, 2)
+    wsx.rollout(env, dp, T, tr)
+    ret, adv = wsx.compute_returns(tr, T, 0.99, 0.95, True, torch.float32)
+    want = tr.host()
+    want["returns"], want["advantages"] = ret.cpu().numpy(), adv.cpu().numpy()
+    srv = wsx.Server(1 << 30, chunk_steps=16, max_batch=32)
+    others = [srv.submit(kind=2, policy=dp, horizon=30, n_envs=90, seed=11),
+              srv.submit(kind=3, policy=acro, horizon=60, n_envs=200, seed=12)]
+    rid = srv.submit(kind=k, policy=dp, horizon=T, n_envs=n, seed=5, epoch=2)
+    r = srv.wait(rid, 60000)
+    got = {f: v.cpu().numpy() for f, v in srv.view(r, k).items()}
+    for o in others:
+        srv.wait(o, 60000)
+        srv.release(o)
+    srv.release(rid)
+    srv.close()
+    for f in ("obs", "action", "reward", "done", "value", "logp", "last_value", "returns",
+              "advantages"):
+        assert np.array_equal(got[f], want[f]), f
