@@ -683,8 +683,8 @@ __device__ __forceinline__ void stage_segment(const Batch& b, int i, Segment* ds
 // `mlp` and its per-feature table in LDS.
 template <class E, class L, int NW>
 __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, char* smem,
-                                           char* extra, const float*& staged, int tid, int wave,
-                                           int lane) {
+                                           char* extra, char* draws, const float*& staged,
+                                           int tid, int wave, int lane) {
     using HO = HeadOf<E>;
     constexpr int DT = L::DTYPE;
     constexpr int R = L::R;
@@ -694,6 +694,16 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
     constexpr int C = B::C;
     static_assert(R * G <= NTHR, "G lanes per tile row");
     const int rr = tid / G, sub = tid % G;   // tile row and lane within its group
+    // The action draw of a step depends only on the key, the step and the row,
+    // so when whole waves are left over after the R G row lanes, R of their
+    // lanes (draw lanes, starting at the next wave) compute the next step's
+    // draws while the row lanes run this step's sampling and dynamics; the
+    // draws pass through LDS, double-buffered by step parity. The market
+    // keeps its draws on the row lanes.
+    constexpr int DOFF = (R * G + 63) / 64 * 64;
+    constexpr bool kDrawLanes = E::KIND != Market::KIND && DOFF + R <= NTHR;
+    Pre<E>* const pbuf = reinterpret_cast<Pre<E>*>(draws);   // [2][R]
+    const int dr = tid - DOFF;                               // a draw lane's tile row
     const PolicyArgs& pol = sg.pol;
     const float inv_q0 = DT == DT_FP8 ? 1.0f / pol.act_scale[0] : 1.0f;
     const float log_std = (E::NACT == 0 && pol.log_std) ? pol.log_std[0] : 0.0f;
@@ -723,6 +733,8 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
     const bool mine = rr < R;
     const bool valid = mine && row < tl.row1;
     const bool lead = valid && sub == 0;   // writes the row's scalar records
+    const int drow = tl.row0 + dr;
+    const bool dvalid = kDrawLanes && dr >= 0 && dr < R && drow < tl.row1;
     float s[E::SR];
 #pragma unroll
     for (int i = 0; i < E::SR; ++i) s[i] = 0.0f;
@@ -739,7 +751,12 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
         if (valid && horizon > 0) store_obs<E::OD, G>(tr.obs + (size_t)row * E::OD, o, sub);
     }
     const float sigma = expf(log_std);
-    Pre<E> pre = prepare<E>(key, t0, (uint32_t)row, log_std);   // step 0's draw
+    Pre<E> pre{0.0f, 0.0f};   // step 0's draw
+    if constexpr (kDrawLanes) {
+        if (dvalid) pbuf[dr] = prepare<E>(key, t0, (uint32_t)drow, log_std);
+    } else {
+        pre = prepare<E>(key, t0, (uint32_t)row, log_std);
+    }
     __syncthreads();
 
     const int passes = horizon + (__builtin_amdgcn_readfirstlane(sg.last) ? 1 : 0);   // + V(s_T)
@@ -748,6 +765,10 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
         __syncthreads();
         const uint32_t t = t0 + (uint32_t)step;
         const size_t idx = (size_t)step * env.n_rows + row;
+        if constexpr (kDrawLanes) {   // the next step's draws, beside this step's row work
+            if (dvalid && step + 1 < horizon)
+                pbuf[((step + 1) & 1) * R + dr] = prepare<E>(key, t + 1, (uint32_t)drow, log_std);
+        }
         Act<E> act{0, 0.0f};
         if (valid) {
             float hb[C], hv;
@@ -756,6 +777,7 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
                 if (lead) tr.last_value[row] = hv;
             } else {
                 float logp;
+                if constexpr (kDrawLanes) pre = pbuf[(step & 1) * R + rr];
                 act = decide<E, G, C>(hb, sub, pre, sigma, logp);
                 if (lead) {
                     tr.value[idx] = hv;
@@ -793,12 +815,13 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
         } else {
             if (valid && step < horizon) {
                 // the next step's draw, independent of this step's dynamics
-                const Pre<E> nxt = prepare<E>(key, t + 1, (uint32_t)row, log_std);
+                Pre<E> nxt{0.0f, 0.0f};
+                if constexpr (!kDrawLanes) nxt = prepare<E>(key, t + 1, (uint32_t)row, log_std);
                 float reward;
                 bool done;
                 E::template step<G>(s, act.index, act.value, t, (uint32_t)row, key, ctx, sub,
                                     reward, done);
-                pre = nxt;
+                if constexpr (!kDrawLanes) pre = nxt;
                 if (done) E::reset(s, key, t + 1, (uint32_t)row, ctx);
                 if (lead) {
                     tr.reward[idx] = reward;
@@ -835,8 +858,11 @@ k_fused(Batch batch) {
     constexpr int NTHR = NW * 64;
     constexpr int EXTRA = extra_lds_bytes<E>(R) > extra_lds_bytes<E2>(R) ? extra_lds_bytes<E>(R)
                                                                          : extra_lds_bytes<E2>(R);
-    __shared__ __attribute__((aligned(16))) char smem[L::BYTES + EXTRA];
+    constexpr int DRAWS = 2 * R * (int)sizeof(Pre<E>);   // the draw lanes' buffer
+    static_assert(sizeof(Pre<E>) == sizeof(Pre<E2>), "one draw buffer for both kinds");
+    __shared__ __attribute__((aligned(16))) char smem[L::BYTES + EXTRA + DRAWS];
     char* extra = smem + L::BYTES;
+    char* draws = extra + EXTRA;
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     L mlp;
@@ -860,11 +886,11 @@ k_fused(Batch batch) {
         }
         if constexpr (!std::is_same<E, E2>::value) {
             if (sg.env.kind == E2::KIND) {
-                fused_tile<E2, L, NW>(sg, tile, mlp, smem, extra, staged, tid, wave, lane);
+                fused_tile<E2, L, NW>(sg, tile, mlp, smem, extra, draws, staged, tid, wave, lane);
                 continue;
             }
         }
-        fused_tile<E, L, NW>(sg, tile, mlp, smem, extra, staged, tid, wave, lane);
+        fused_tile<E, L, NW>(sg, tile, mlp, smem, extra, draws, staged, tid, wave, lane);
     }
 }
 
