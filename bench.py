@@ -360,18 +360,34 @@ def serving(args, wsx, inputs, torch):
             "launches": st["launches"], "arena_peak_gb": round(st["arena_peak"] / 2**30, 2)}
 
 
-def traffic_for(kernel_name, launches_bytes_key):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources."""
+def counters_for(kernel_name):
+    """The committed rocprofv3 counter figures of a kernel, if they were taken
+    on the current kernel sources (else an empty dict)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
-        return None
+        return {}
     with open(path) as f:
         data = json.load(f)
     ent = data.get(kernel_name)
     if not ent or ent.get("source_hash") != kernel_source_hash():
+        return {}
+    return ent
+
+
+def traffic_for(kernel_name, launches_bytes_key):
+    """HBM bytes per launch from the committed rocprofv3 counter summary."""
+    return counters_for(kernel_name).get(launches_bytes_key)
+
+
+def unit_busy_for(kernel_name):
+    """Share of the dispatch's cycles the MFMA and vector ALUs were busy
+    (rocprofv3 SQ_VALU_MFMA_BUSY_CYCLES and SQ_ACTIVE_INST_VALU over
+    GRBM_GUI_ACTIVE), or None."""
+    ent = counters_for(kernel_name)
+    if "mfma_busy" not in ent:
         return None
-    return ent.get(launches_bytes_key)
+    return {"mfma": ent["mfma_busy"], "valu": ent["valu_busy"],
+            "from": "rocprofv3 PMC: SQ_VALU_MFMA_BUSY_CYCLES, SQ_ACTIVE_INST_VALU / GRBM_GUI_ACTIVE"}
 
 
 def main():
@@ -498,6 +514,7 @@ def main():
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_TFLOPS[dtype],
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[dtype], 4),
                 "traffic": traffic_for(kname, "hbm_bytes_per_launch"),
+                "unit_busy": unit_busy_for(kname),
                 "kernel": kname, "avg_launch_ms": round(avg_ms, 4),
                 "flop_per_launch": flop}
     out = {
