@@ -153,9 +153,13 @@ def sweep(kind_key, counts, steps, wsx, inputs, torch):
 
 
 def kernel_source_hash():
+    """Hash of the device-code sources (.hip and .h under csrc/): counter
+    figures taken on other kernel code are not reported."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2408_00930_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
+        if not name.endswith((".hip", ".h")):
+            continue
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode() + f.read())
     return h.hexdigest()[:16]

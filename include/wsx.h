@@ -286,8 +286,10 @@ int wsx_adam_step(float* param, const float* grad, float* m, float* v, int64_t n
 /* WSX_MODE_FUSED_GRAPH, wsx_rollout_batch of sets of this kind, and the     */
 /* returns and update calls. Policies: FP32 width 64 with <= 16 head         */
 /* outputs, or BF16 width 256. A source that does not compile returns        */
-/* WSX_EINVAL with the compiler's log in wsx_last_error(). Kinds stay        */
-/* registered until the process ends.                                        */
+/* WSX_EINVAL with the compiler's log in wsx_last_error(). The kernels are  */
+/* loaded on the device current at registration; launching a kind while     */
+/* another device is current returns WSX_EHIP. Kinds stay registered until  */
+/* the process ends.                                                         */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int32_t state_dim;       /* SD                                                */

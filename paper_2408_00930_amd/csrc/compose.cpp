@@ -64,6 +64,12 @@ const UserKind* find_kind(int kind) {
     return i >= 0 && i < (int)g_kinds.size() ? &g_kinds[i] : nullptr;
 }
 
+// The kernels of a kind are loaded on the device current at registration.
+bool on_device(int device) {
+    int cur = -1;
+    return hipGetDevice(&cur) == hipSuccess && cur == device;
+}
+
 }  // namespace
 
 bool user_kind_info(int kind, KindInfo& k) {
@@ -88,6 +94,7 @@ hipError_t launch_user_fused(const Variant& v, const Batch& batch, int grid, hip
         std::lock_guard<std::mutex> lk(g_mu);
         const UserKind* u = find_kind(v.kind);
         if (!u) return hipErrorInvalidValue;
+        if (!on_device(u->device)) return hipErrorInvalidDevice;
         f = u->fused;
     }
     void* args[] = {const_cast<Batch*>(&batch)};
@@ -100,6 +107,7 @@ hipError_t launch_user_reset(int kind, const EnvArgs& env, hipStream_t s) {
         std::lock_guard<std::mutex> lk(g_mu);
         const UserKind* u = find_kind(kind);
         if (!u) return hipErrorInvalidValue;
+        if (!on_device(u->device)) return hipErrorInvalidDevice;
         f = u->reset;
     }
     const int threads = 256;
