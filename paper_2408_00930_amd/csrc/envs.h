@@ -235,6 +235,35 @@ struct Market {
 #pragma unroll
         for (int i = 5; i < 32; ++i) s[i] = 0.99f * s[i];
     }
+    // The same update on a slice: the lanes of a row's group of G hold the
+    // state entries i = sub + j G (j < 32 / G), each updated as above.
+    template <int G>
+    __device__ static void settle_slice(float (&s)[32 / G], int sub, int a, int demand_half_sum,
+                                        int supply_18th_sum, float& reward) {
+        const int k = a % 10, j = a / 10;
+        const float labour = (float)k / 9.0f;
+        const float trade = (float)(j - 2) * 0.5f;
+        const float eps = 1e-3f;
+        const float demand = (float)demand_half_sum * 0.5f;
+        const float supply = (float)supply_18th_sum / 18.0f;
+        const float price = (demand + eps) / (supply + eps);
+        const float sold = trade < 0.0f ? -trade : 0.0f;
+        const float bought = trade > 0.0f ? trade : 0.0f;
+        const float cons = fmaxf(0.0f, labour - sold + bought / price);
+        reward = log1pf(cons) - 0.1f * labour * labour;
+        const float lp = logf(price);
+#pragma unroll
+        for (int q = 0; q < 32 / G; ++q) {
+            const int i = sub + q * G;
+            const float v = s[q];
+            s[q] = i == 0   ? 0.9f * v + 0.1f * (cons - 0.5f)
+                   : i == 1 ? lp
+                   : i == 2 ? labour
+                   : i == 3 ? trade
+                   : i == 4 ? cons
+                            : 0.99f * v;
+        }
+    }
 };
 
 // ------------------------------------------------------------ Reaction --

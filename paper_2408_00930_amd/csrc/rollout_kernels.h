@@ -437,6 +437,14 @@ struct Mlp {
         for (int k = 0; k < OD; ++k)
             if (k % G == sub) store1<DT>(p + k * EB, o[k], inv_q0);
     }
+    // The same from a lane's slice: entries k = sub + j G of the row.
+    template <int OD, int G>
+    __device__ static void put_obs_slice(char* smem, int r, const float (&o)[OD / G], float inv_q0,
+                                         int sub) {
+        char* p = smem + OFF_IN + r * P_IN;
+#pragma unroll
+        for (int j = 0; j < OD / G; ++j) store1<DT>(p + (sub + j * G) * EB, o[j], inv_q0);
+    }
 };
 
 // ------------------------------------------------------------- sampling --
@@ -580,6 +588,27 @@ __device__ __forceinline__ void store_obs(float* dst, const float (&o)[OD], int 
 #pragma unroll
     for (int k = 0; k < OD; ++k)
         if (k % G == sub) dst[k] = o[k];
+}
+
+// State and observation slices: lane `sub` of a row's group of G holds the
+// entries i = sub + j G (the market's state is its observation, and every
+// entry evolves on its own, so no lane needs the others').
+template <class E, int G>
+__device__ __forceinline__ void load_slice(const EnvArgs& env, int64_t row, float (&s)[E::SD / G],
+                                           int sub) {
+#pragma unroll
+    for (int j = 0; j < E::SD / G; ++j) s[j] = env.state[(size_t)(sub + j * G) * env.n_rows + row];
+}
+template <class E, int G>
+__device__ __forceinline__ void save_slice(const EnvArgs& env, int64_t row,
+                                           const float (&s)[E::SD / G], int sub) {
+#pragma unroll
+    for (int j = 0; j < E::SD / G; ++j) env.state[(size_t)(sub + j * G) * env.n_rows + row] = s[j];
+}
+template <int OD, int G>
+__device__ __forceinline__ void store_obs_slice(float* dst, const float (&o)[OD / G], int sub) {
+#pragma unroll
+    for (int j = 0; j < OD / G; ++j) dst[sub + j * G] = o[j];
 }
 
 // Stage the reaction potential in LDS: A, centres, -1/(2 w^2), amplitudes.
@@ -735,20 +764,33 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
     const bool lead = valid && sub == 0;   // writes the row's scalar records
     const int drow = tl.row0 + dr;
     const bool dvalid = kDrawLanes && dr >= 0 && dr < R && drow < tl.row1;
-    float s[E::SR];
+    // the market's lanes hold slices of the row's state (its observation is
+    // the state itself); the other kinds hold the whole state on every lane
+    constexpr bool kSlice = E::KIND == Market::KIND;
+    static_assert(!kSlice || (E::SD % G == 0 && E::OD == E::SD), "state slices");
+    constexpr int NS = kSlice ? E::SD / G : E::SR;
+    float s[NS];
 #pragma unroll
-    for (int i = 0; i < E::SR; ++i) s[i] = 0.0f;
-    if (valid) load_state<E>(env, row, s);
+    for (int i = 0; i < NS; ++i) s[i] = 0.0f;
+    if (valid) {
+        if constexpr (kSlice) load_slice<E, G>(env, row, s, sub);
+        else load_state<E>(env, row, s);
+    }
     int slot = 0;
     if constexpr (E::KIND == Market::KIND) {
         if (valid) slot = env_slot(env, tl, row);
         for (int i = tid; i < 4 * R; i += NTHR) sums[i] = 0;
     }
     if (mine) {
-        float o[E::OD];
-        E::observe(s, o);
-        L::template put_obs<E::OD, G>(smem, rr, o, inv_q0, sub);
-        if (valid && horizon > 0) store_obs<E::OD, G>(tr.obs + (size_t)row * E::OD, o, sub);
+        if constexpr (kSlice) {
+            L::template put_obs_slice<E::OD, G>(smem, rr, s, inv_q0, sub);
+            if (valid && horizon > 0) store_obs_slice<E::OD, G>(tr.obs + (size_t)row * E::OD, s, sub);
+        } else {
+            float o[E::OD];
+            E::observe(s, o);
+            L::template put_obs<E::OD, G>(smem, rr, o, inv_q0, sub);
+            if (valid && horizon > 0) store_obs<E::OD, G>(tr.obs + (size_t)row * E::OD, o, sub);
+        }
     }
     const float sigma = expf(log_std);
     Pre<E> pre{0.0f, 0.0f};   // step 0's draw
@@ -802,7 +844,7 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
                     const Pre<E> nxt = prepare<E>(key, t + 1, (uint32_t)row, log_std);
                     const int* sl = sums + ((step & 1) * R + slot) * 2;
                     float reward;
-                    Market::settle(s, act.index, sl[0], sl[1], reward);
+                    Market::settle_slice<G>(s, sub, act.index, sl[0], sl[1], reward);
                     pre = nxt;
                     if (lead) {
                         tr.reward[idx] = reward;
@@ -812,7 +854,7 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
                 // the other parity's sums were last read in the previous step
                 for (int i = tid; i < 2 * R; i += NTHR) sums[((step + 1) & 1) * 2 * R + i] = 0;
             }
-        } else {
+        } else if constexpr (!kSlice) {
             if (valid && step < horizon) {
                 // the next step's draw, independent of this step's dynamics
                 Pre<E> nxt{0.0f, 0.0f};
@@ -830,16 +872,23 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
             }
         }
         if (valid && step < horizon) {
-            float o[E::OD];
-            E::observe(s, o);
-            L::template put_obs<E::OD, G>(smem, rr, o, inv_q0, sub);
-            if (step + 1 < horizon)
-                store_obs<E::OD, G>(tr.obs + ((size_t)(step + 1) * env.n_rows + row) * E::OD, o,
-                                    sub);
+            float* dst = tr.obs + ((size_t)(step + 1) * env.n_rows + row) * E::OD;
+            if constexpr (kSlice) {
+                L::template put_obs_slice<E::OD, G>(smem, rr, s, inv_q0, sub);
+                if (step + 1 < horizon) store_obs_slice<E::OD, G>(dst, s, sub);
+            } else {
+                float o[E::OD];
+                E::observe(s, o);
+                L::template put_obs<E::OD, G>(smem, rr, o, inv_q0, sub);
+                if (step + 1 < horizon) store_obs<E::OD, G>(dst, o, sub);
+            }
         }
         __syncthreads();
     }
-    if (valid) save_state<E, G>(env, row, s, sub);
+    if (valid) {
+        if constexpr (kSlice) save_slice<E, G>(env, row, s, sub);
+        else save_state<E, G>(env, row, s, sub);
+    }
 }
 
 // Persistent fused roll-out: each workgroup walks tiles of the launch's
