@@ -51,7 +51,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 // multiplies its own h2 features by its K-slice of the head for every head
 // row, leaving NW partial sums per row (no extra barrier). HS = 1 (split-M):
 // after a barrier, wave w computes head row tiles w, w + NW, ... over the whole
-// K (one result per row; for wide heads whose partials would not fit in LDS).
+// K (one result per row; for wide heads whose partials would not fit in LDS);
+// when the waves are a multiple of the head row tiles, the RS waves of one
+// head row tile each take NT / RS of the row tiles instead.
 template <int DT, int H, int NW, int NT, int KIN, int NHP, int HS, int OCC>
 struct Mlp {
     using M = Mma<DT>;
@@ -63,6 +65,13 @@ struct Mlp {
     static constexpr int NHW = HS ? (NHT + NW - 1) / NW : NHT;   // head tiles held by a wave
     static constexpr int KHS = HS ? K2S : K3S;                   // head K-steps of a wave
     static constexpr int NPART = HS ? 1 : NW;                    // head results per row
+    static constexpr int RS = (HS && NW % NHT == 0 && NT % (NW / NHT) == 0) ? NW / NHT : 1;
+    static constexpr int NTR = NT / RS;                          // row tiles of a head job
+    // the head row tile of a wave's job hw, and the first row tile of its job
+    __device__ static int head_tile(int wave, int hw) {
+        return HS ? (RS > 1 ? wave % NHT : wave + hw * NW) : hw;
+    }
+    __device__ static int head_row0(int wave) { return RS > 1 ? (wave / NHT) * NTR : 0; }
     static constexpr int R = 16 * NT;
     static constexpr int P_IN = KIN * EB + 16;   // LDS row pitches (bytes)
     static constexpr int P_H = H * EB + 16;
@@ -151,7 +160,7 @@ struct Mlp {
         }
 #pragma unroll
         for (int hw = 0; hw < NHW; ++hw) {
-            const int ht = HS ? wave + hw * NW : hw;   // head row tile
+            const int ht = head_tile(wave, hw);   // head row tile
             const int m = ht * 16 + lr;
 #pragma unroll
             for (int ks = 0; ks < KHS; ++ks) {
@@ -351,31 +360,32 @@ struct Mlp {
             dense_tanh<K2S, false>(w2, tab + 2 * H, smem + OFF_H1, P_H, smem + OFF_H2, inv_q2, wave,
                                    lane, acc);
             __syncthreads();   // every wave reads all of h2
-            const char* h2 = smem + OFF_H2;
+            const char* h2 = smem + OFF_H2 + head_row0(wave) * 16 * P_H;
 #pragma unroll
             for (int ks = 0; ks < KHS; ++ks) {
-                Frag b[NT];
+                Frag b[NTR];
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
-                    b[nt] = M::lds(h2 + (nt * 16 + lr) * P_H + (ks * K + kq) * EB);
+                for (int i = 0; i < NTR; ++i)
+                    b[i] = M::lds(h2 + (i * 16 + lr) * P_H + (ks * K + kq) * EB);
 #pragma unroll
                 for (int hw = 0; hw < NHW; ++hw) {
-                    if (wave + hw * NW >= NHT) break;
+                    if (head_tile(wave, hw) >= NHT) break;
 #pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) acc[hw][nt] = M::mma(w3[hw][ks], b[nt], acc[hw][nt]);
+                    for (int i = 0; i < NTR; ++i) acc[hw][i] = M::mma(w3[hw][ks], b[i], acc[hw][i]);
                 }
             }
         }
-        float* part = reinterpret_cast<float*>(smem + OFF_PART) + (HS ? 0 : wave * R * P_PART);
+        float* part = reinterpret_cast<float*>(smem + OFF_PART) + (HS ? 0 : wave * R * P_PART) +
+                      (HS ? head_row0(wave) * 16 * P_PART : 0);
 #pragma unroll
         for (int hw = 0; hw < NHW; ++hw) {
-            const int ht = HS ? wave + hw * NW : hw;
+            const int ht = head_tile(wave, hw);
             if (HS && ht >= NHT) break;
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const f32x4 a = acc[hw][nt];
+            for (int i = 0; i < (HS ? NTR : NT); ++i) {
+                const f32x4 a = acc[hw][i];
                 const int j = ht * 16 + 4 * (lane >> 4);
-                *reinterpret_cast<float4*>(part + (nt * 16 + lr) * P_PART + j) =
+                *reinterpret_cast<float4*>(part + (i * 16 + lr) * P_PART + j) =
                     make_float4(a[0] * o3[hw][0], a[1] * o3[hw][1], a[2] * o3[hw][2], a[3] * o3[hw][3]);
             }
         }
