@@ -445,9 +445,11 @@ k_ac_bwd1(AcArgs a) {
     using M = typename S::M;
     using Frag = typename S::Frag;
     constexpr int R = S::R, MT = S::MT, K = S::K, KC = S::KC, EB = S::EB;
-    __shared__ __attribute__((aligned(16))) char x0[R * S::P_IN];
-    __shared__ __attribute__((aligned(16))) char x0T[S::KT * 16 * S::P_T];
-    __shared__ __attribute__((aligned(16))) char dz[R * S::P_H];
+    // by tile parity: a tile's inputs go to the buffers its predecessor's
+    // predecessor read, so one barrier per tile remains
+    __shared__ __attribute__((aligned(16))) char x0b[2][R * S::P_IN];
+    __shared__ __attribute__((aligned(16))) char x0Tb[2][S::KT * 16 * S::P_T];
+    __shared__ __attribute__((aligned(16))) char dzs[2][R * S::P_H];
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lr = lane & 15, q = lane >> 4;
     const int kq = q * KC;
@@ -474,8 +476,10 @@ k_ac_bwd1(AcArgs a) {
         for (int it = 0; it < S::KT; ++it) dw1[mt][it] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
     // transposed-input rows >= KIN stay zero
-    for (int e = tid; e < (S::KT * 16 - KIN) * R; e += S::NTHR)
-        put<DT>(x0T + (KIN + e / R) * S::P_T + (e % R) * EB, 0.0f);
+    for (int e = tid; e < (S::KT * 16 - KIN) * R; e += S::NTHR) {
+        put<DT>(x0Tb[0] + (KIN + e / R) * S::P_T + (e % R) * EB, 0.0f);
+        put<DT>(x0Tb[1] + (KIN + e / R) * S::P_T + (e % R) * EB, 0.0f);
+    }
 
     const int64_t n_tiles = (a.n + R - 1) / R;
     // the next tile's observations and dz2 rows are loaded while this tile runs
@@ -497,8 +501,11 @@ k_ac_bwd1(AcArgs a) {
     ObsPrefetch<S> obs;
     obs.load(a, blockIdx.x, tid);
     load_dz(blockIdx.x);
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        lds_barrier();
+    int pb = 0;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x, pb ^= 1) {
+        char* x0 = x0b[pb];
+        char* x0T = x0Tb[pb];
+        char* dz = dzs[pb];
         obs.template store<DT>(x0, x0T, tid);
 #pragma unroll
         for (int u = 0; u < DPER; ++u) {
@@ -576,7 +583,7 @@ k_ac_dw2(AcArgs a) {
     using Frag = typename S::Frag;
     constexpr int R = S::R, MT = S::MT, K = S::K, KC = S::KC, EB = S::EB, NKT = H / 16;
     constexpr int RB = R * EB;   // bytes of one block row
-    __shared__ __attribute__((aligned(16))) char h1T[H * S::P_T];
+    __shared__ __attribute__((aligned(16))) char h1Tb[2][H * S::P_T];   // by tile parity
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lr = lane & 15, q = lane >> 4;
     const int kq = q * KC;
     f32x4 acc[MT][NKT];
@@ -585,28 +592,56 @@ k_ac_dw2(AcArgs a) {
 #pragma unroll
         for (int kt = 0; kt < NKT; ++kt) acc[mt][kt] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int64_t n_tiles = (a.n + R - 1) / R;
-    constexpr int CPR = RB / 16;   // 16-byte chunks per block row
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const char* hb = a.h1_blk + (size_t)tile * H * RB;
-        const char* db = a.dz2_blk + (size_t)tile * H * RB;
-        // this wave's A fragments, issued before the block copy
-        Frag A_[MT][R / K];
+    constexpr int CPR = RB / 16;                                 // 16-byte chunks per block row
+    constexpr int HPER = (H * CPR + S::NTHR - 1) / S::NTHR;     // chunks per thread
+    // A tile's operands are loaded one tile ahead: this wave's A fragments
+    // (dz2 block) and this thread's chunks of the h1 block, which go to the
+    // LDS buffer of the tile's parity (read two tiles earlier, before the
+    // previous tile's barrier), so one barrier per tile remains.
+    Frag A_[MT][R / K];
+    uint4 hv[HPER];
+    auto load_tile = [&](int64_t tile) {
+        const bool ok = tile < n_tiles;   // past the last tile: nothing is loaded
+        const char* hb = a.h1_blk + (size_t)(ok ? tile : 0) * H * RB;
+        const char* db = a.dz2_blk + (size_t)(ok ? tile : 0) * H * RB;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int ks = 0; ks < R / K; ++ks) {
                 const char* src = db + (size_t)(wave * S::FPW + mt * 16 + lr) * RB + (ks * K + kq) * EB;
-                if constexpr (EB == 2)
-                    A_[mt][ks] = __builtin_bit_cast(Frag, *reinterpret_cast<const uint4*>(src));
-                else
-                    A_[mt][ks] = *reinterpret_cast<const float*>(src);
+                Frag f{};
+                if (ok) {
+                    if constexpr (EB == 2)
+                        f = __builtin_bit_cast(Frag, *reinterpret_cast<const uint4*>(src));
+                    else
+                        f = *reinterpret_cast<const float*>(src);
+                }
+                A_[mt][ks] = f;
             }
-        lds_barrier();   // the previous tile's reads of h1T are done
-        for (int e = tid; e < H * CPR; e += S::NTHR) {
-            const int row = e / CPR, c = e % CPR;
-            *reinterpret_cast<uint4*>(h1T + row * S::P_T + c * 16) =
-                *reinterpret_cast<const uint4*>(hb + (size_t)row * RB + c * 16);
+#pragma unroll
+        for (int u = 0; u < HPER; ++u) {
+            const int e = tid + u * S::NTHR;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (ok && e < H * CPR)
+                v = *reinterpret_cast<const uint4*>(hb + (size_t)(e / CPR) * RB + (e % CPR) * 16);
+            hv[u] = v;
         }
+    };
+    load_tile(blockIdx.x);
+    int pb = 0;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x, pb ^= 1) {
+        char* h1T = h1Tb[pb];
+#pragma unroll
+        for (int u = 0; u < HPER; ++u) {
+            const int e = tid + u * S::NTHR;
+            if (e < H * CPR) *reinterpret_cast<uint4*>(h1T + (e / CPR) * S::P_T + (e % CPR) * 16) = hv[u];
+        }
+        Frag A_cur[MT][R / K];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int ks = 0; ks < R / K; ++ks) A_cur[mt][ks] = A_[mt][ks];
+        load_tile(tile + gridDim.x);   // in flight during this tile's products
         lds_barrier();
 #pragma unroll
         for (int ks = 0; ks < R / K; ++ks)
@@ -614,7 +649,7 @@ k_ac_dw2(AcArgs a) {
             for (int kt = 0; kt < NKT; ++kt) {
                 const Frag B_ = M::lds(h1T + (kt * 16 + lr) * S::P_T + (ks * K + kq) * EB);
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt) acc[mt][kt] = M::mma(A_[mt][ks], B_, acc[mt][kt]);
+                for (int mt = 0; mt < MT; ++mt) acc[mt][kt] = M::mma(A_cur[mt][ks], B_, acc[mt][kt]);
             }
     }
     float* out = a.part_w2 + (size_t)blockIdx.x * H * H;
