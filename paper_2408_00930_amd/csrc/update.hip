@@ -181,7 +181,7 @@ k_ac_fwd(AcArgs a) {
     using M = typename S::M;
     using Frag = typename S::Frag;
     constexpr int R = S::R, MT = S::MT, K = S::K, KC = S::KC, EB = S::EB;
-    __shared__ __attribute__((aligned(16))) char x0b[2][R * S::P_IN];   // by tile parity
+    __shared__ __attribute__((aligned(16))) char x0[R * S::P_IN];
     __shared__ __attribute__((aligned(16))) char h1[R * S::P_H];
     __shared__ __attribute__((aligned(16))) char h2[R * S::P_H];
     __shared__ __attribute__((aligned(16))) char dz[R * S::P_H];
@@ -235,35 +235,26 @@ k_ac_fwd(AcArgs a) {
     for (int e = tid; e < NHP * R; e += S::NTHR) put<DT>(dhT + (e / R) * S::P_T + (e % R) * EB, 0.0f);
 
     const int64_t n_tiles = (a.n + R - 1) / R;
-    // A head of one row tile is computed by two waves (16 samples each), which
-    // then take its gradient for their own samples: only a wave-local wait
-    // separates the two. Wider heads spread a sample's outputs over waves.
-    constexpr bool kFuseHead = S::NHT == 1;
-    const int gr = kFuseHead ? (wave & 1) * 16 + lane : tid;   // sample of this lane's gradient
-    const bool gl = kFuseHead ? (wave < 2 && lane < 16) : tid < R;
-    // The observation tile is double-buffered: tile i + 1's observations are
-    // stored during tile i's layer 2, and tile i + 2's loaded into registers.
     ObsPrefetch<S> obs;
     obs.load(a, blockIdx.x, tid);
-    obs.template store<DT>(x0b[0], nullptr, tid);
-    obs.load(a, (int64_t)blockIdx.x + gridDim.x, tid);
-    lds_barrier();
-    int pb = 0;
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x, pb ^= 1) {
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t base = tile * R;
         char* h1b = a.h1_blk + (size_t)tile * H * R * EB;    // this tile's blocks
         char* dzb = a.dz2_blk + (size_t)tile * H * R * EB;
-        const char* x0 = x0b[pb];
-        // this tile's per-sample inputs (used by the head gradient), in
-        // flight while the layers run
+        lds_barrier();   // the previous tile's LDS reads are done
+        obs.template store<DT>(x0, nullptr, tid);
+        lds_barrier();
+        // this tile's per-sample inputs (used after the head) and the next
+        // tile's observations, in flight while the layers run
         float s_adv = 0.0f, s_ret = 0.0f, s_act = 0.0f;
-        if (gl && base + gr < a.n) {
-            const int64_t n = base + gr;
+        if (tid < R && base + tid < a.n) {
+            const int64_t n = base + tid;
             s_adv = a.adv[n];
             s_ret = a.ret[n];
             s_act = a.n_act == 0 ? static_cast<const float*>(a.action)[n]
                                  : (float)static_cast<const uint8_t*>(a.action)[n];
         }
+        obs.load(a, tile + gridDim.x, tid);
         // layer 1
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
@@ -284,10 +275,6 @@ k_ac_fwd(AcArgs a) {
             }
         }
         lds_barrier();
-        // the next tile's observations into the other buffer (last read by the
-        // previous tile's layer 1), the one after into registers
-        obs.template store<DT>(x0b[pb ^ 1], nullptr, tid);
-        obs.load(a, tile + 2 * (int64_t)gridDim.x, tid);
         // layer 2, keeping the unrounded activations
         f32x4 t2[MT][2];
 #pragma unroll
@@ -316,13 +303,10 @@ k_ac_fwd(AcArgs a) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) hd[jnt * 16 + 4 * q + i][jht * 16 + lr] = acc[i];
         }
-        if constexpr (kFuseHead)
-            __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // this wave's head rows
-        else
-            lds_barrier();
-        // gradient of the loss at the head, one lane per sample
-        if (gl) {
-            const int r = gr;
+        lds_barrier();
+        // gradient of the loss at the head, one thread per sample
+        if (tid < R) {
+            const int r = tid;
             const int64_t n = base + r;
             const bool ok = n < a.n;
             const float A = s_adv;
