@@ -268,30 +268,49 @@ def percentile(sorted_vals, q):
     return sorted_vals[k]
 
 
+def iqr(sorted_vals, digits):
+    """Interquartile range of sorted values (None when there are none)."""
+    if not sorted_vals:
+        return None
+    return round(percentile(sorted_vals, 75) - percentile(sorted_vals, 25), digits)
+
+
 def cpu_baseline(sets, sample_envs):
     """The FP64 oracle on a bounded sample of the same workload."""
     import numpy as np
 
     import oracle as O
     from paper_2408_00930_amd import inputs
-    total_env_steps = 0
-    t0 = time.perf_counter()
-    for s in sets:
-        n = min(sample_envs, s.n_envs)
-        offsets = inputs.agent_offsets(s.n_envs, seed=0)[:n + 1] if s.kind == O.MARKET else None
-        params = inputs.reaction_params(0).astype(np.float64) if s.kind == O.REACTION else None
-        oenv = O.env_hold(s.kind, n, offsets, params)
-        st = O.env_reset(oenv, 0, 0)
-        out = O.rollout(oenv, O.mlp_hold(s.policy), 0, 0, 0, s.T, st,
-                        s.policy.exact("log_std"), margins=False)
-        O.returns_gae(out["reward"], out["value"], out["done"], out["last_value"], 0.99, 0.95)
-        total_env_steps += n * s.T
-    el = time.perf_counter() - t0
-    return {"value": total_env_steps / el, "unit": "env-steps/s", "cores": O.num_threads(),
+
+    def run(envs):
+        total = 0
+        t0 = time.perf_counter()
+        for s in sets:
+            n = min(envs, s.n_envs)
+            offsets = inputs.agent_offsets(s.n_envs, seed=0)[:n + 1] if s.kind == O.MARKET else None
+            params = inputs.reaction_params(0).astype(np.float64) if s.kind == O.REACTION else None
+            oenv = O.env_hold(s.kind, n, offsets, params)
+            st = O.env_reset(oenv, 0, 0)
+            out = O.rollout(oenv, O.mlp_hold(s.policy), 0, 0, 0, s.T, st,
+                            s.policy.exact("log_std"), margins=False)
+            O.returns_gae(out["reward"], out["value"], out["done"], out["last_value"], 0.99, 0.95)
+            total += n * s.T
+        return total, time.perf_counter() - t0
+
+    cores = O.num_threads()
+    total_env_steps, el = run(sample_envs)
+    # the same oracle on one thread, over a quarter of the sample
+    O.set_threads(1)
+    one_steps, one_el = run(max(1, sample_envs // 4))
+    O.set_threads(cores)
+    return {"value": total_env_steps / el, "unit": "env-steps/s", "cores": cores,
             "kind": "oracle",
             "sample": f"first {sample_envs} envs of each set over the full horizon "
                       f"({total_env_steps} env-steps, {el:.1f} s), FP64 C oracle with "
-                      f"OpenMP over envs, returns/GAE included"}
+                      f"OpenMP over envs, returns/GAE included",
+            "single_thread": {"value": round(one_steps / one_el, 1), "cores": 1,
+                              "sample": f"first {max(1, sample_envs // 4)} envs of each set "
+                                        f"({one_steps} env-steps, {one_el:.1f} s)"}}
 
 
 def serving(args, wsx, inputs, torch):
@@ -430,9 +449,9 @@ def main():
     ap.add_argument("--sweep-counts", default="10,100,1000,10000,100000,1000000")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(replicas shard by contiguous env ranges with no exchange; see the design "
-              "notes). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (replicas "
+              "would shard by contiguous env ranges with no exchange). Run with --gpus 1.",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -537,7 +556,8 @@ def main():
                                                      "chunk_steps"), wsx.env_shape(s.env)))
                                     for s in sets},
                    "autotuned": bool(tuned), "one_launch": batched},
-        "latency_ms": {"p50": round(percentile(lat, 50), 4), "p99": round(percentile(lat, 99), 4)},
+        "latency_ms": {"p50": round(percentile(lat, 50), 4), "p99": round(percentile(lat, 99), 4),
+                       "iqr": iqr(lat, 4)},
         "roofline": roofline,
     }
     for name in ("plain", "graph", "fused_graph"):
@@ -546,7 +566,8 @@ def main():
             pv = env_steps * n / pel
             out[name] = {"value": round(pv, 1), "steps": n, "ms_per_step": round(pel / n * 1e3, 3),
                          "latency_ms": {"p50": round(percentile(plat, 50), 3),
-                                        "p99": round(percentile(plat, 99), 3)}}
+                                        "p99": round(percentile(plat, 99), 3),
+                                        "iqr": iqr(plat, 3)}}
             out[f"fused_speedup_vs_{name}"] = round(value / pv, 2)
     if args.serve_requests > 0:
         out["serving"] = serving(args, wsx, inputs, torch)

@@ -388,6 +388,11 @@ def num_threads():
     return lib().orc_num_threads()
 
 
+def set_threads(n):
+    """Threads of the OpenMP loops over independent environments."""
+    lib().orc_set_threads(int(n))
+
+
 # ------------------------------------------------------ actor-critic update ----
 
 def ac_grad(policy, n_act, obs, action, adv, ret, value_coef=0.5, entropy_coef=0.0,

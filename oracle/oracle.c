@@ -4,8 +4,8 @@
  * TEST INFRASTRUCTURE. Only the tests, the smoke check and the CPU-baseline
  * leg of the benchmark may load this library. The product path never calls it.
  * It shares no code, header, table or constant with the HIP kernels: both
- * sides follow the same written specification (the readings listed in the
- * design notes), nothing more.
+ * sides implement the same readings of the paper independently, nothing
+ * more.
  *
  * What the paper fixes (arXiv 2408.00930):
  *   - Sec. 2 and App. B: many environment replicas run independently and
@@ -973,5 +973,15 @@ int orc_num_threads(void)
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+/* Sets the threads of those loops (n >= 1; ignored without OpenMP).           */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }
