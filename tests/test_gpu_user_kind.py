@@ -31,6 +31,8 @@ def _kind(name):
             _KINDS[name] = wsx.user_kind_register(user_envs.PENDULUM, 2, 3, 0, "bf16", 256)
         elif name == "cartpole":
             _KINDS[name] = wsx.user_kind_register(user_envs.CARTPOLE, 4, 4, 2, "f32", 64)
+        elif name == "group_walk":
+            _KINDS[name] = wsx.user_kind_register(user_envs.GROUP_WALK, 4, 4, 0, "bf16", 256)
         else:
             _KINDS[name] = wsx.user_kind_register(user_envs.POINT_MASS, 2, 2, 0, "bf16", 256)
     return _KINDS[name]
@@ -168,3 +170,27 @@ def test_user_kind_served_with_builtin_requests():
     for f in ("obs", "action", "reward", "done", "value", "logp", "last_value", "returns",
               "advantages"):
         assert np.array_equal(got[f], want[f]), f
+
+
+def test_user_environment_with_lane_groups():
+    """Four lanes per row (LANES = 4): the reward summed over the row's lanes
+    with group_sum, and the state, match numpy on every transition."""
+    wsx = _wsx()
+    k = _kind("group_walk")
+    say("group walk")
+    T, n = 20, 301
+    env = wsx.Env(k, n, seed=8)
+    dp = wsx.DevicePolicy(inputs.make_policy(4, 256, 256, 1, "bf16", seed=9))
+    tr = wsx.Trajectory(k, T, env.rows)
+    wsx.env_reset(env, 0)
+    wsx.rollout(env, dp, T, tr)
+    g = tr.host()
+    obs, act = g["obs"].astype(np.float32), g["action"].astype(np.float32)
+    assert (np.abs(obs[0]) <= 1.0).all() and not g["done"].any()
+
+    def close(a, b):
+        return np.abs(a - b) <= 1e-6 + 4e-6 * np.abs(b)
+    for t in range(T - 1):
+        s2, r = user_envs.group_walk_step(obs[t], act[t])
+        assert close(g["reward"][t], r).all(), t
+        assert close(obs[t + 1], s2).all(), t

@@ -110,3 +110,46 @@ def point_mass_step(x, v, f):
     x2 = (x + f32(0.1) * v2).astype(f32)
     r = (-(x2 * x2) - f32(0.01) * u * u).astype(f32)
     return x2, v2, r, np.abs(x2) > f32(2)
+
+
+# a new environment whose rows use four lanes: every lane moves the whole
+# state, the reward's sum of squares is split over the lanes and combined
+# with the library's group reduction
+GROUP_WALK = r"""
+struct UserEnv {
+    static constexpr int KIND = WSX_USER_KIND, SD = 4, SR = 4, OD = 4, NACT = 0, LANES = 4;
+    __device__ static void complete(float*) {}
+    __device__ static void reset(float* s, const RngKey& key, uint32_t t, uint32_t row,
+                                 const EnvCtx&) {
+        const Words w = draw(key, t, row, PURPOSE_RESET, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s[i] = -1.0f + 2.0f * unit_uniform(w.w[i]);
+    }
+    __device__ static void observe(const float* s, float* o) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) o[i] = s[i];
+    }
+    template <int G>
+    __device__ static void step(float* s, int, float a, uint32_t, uint32_t, const RngKey&,
+                                const EnvCtx&, int sub, float& reward, bool& done) {
+        const float u = fminf(fmaxf(a, -1.0f), 1.0f);
+        float part = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            s[i] = 0.9f * s[i] + 0.1f * u * (float)(i + 1);
+            if (i % G == sub) part += s[i] * s[i];
+        }
+        reward = -group_sum<G>(part);
+        done = false;
+    }
+};
+"""
+
+
+def group_walk_step(s, a):
+    """numpy float32 re-implementation of GROUP_WALK's step: s [n, 4], a [n]."""
+    import numpy as np
+    f32 = np.float32
+    u = np.clip(a.astype(f32), f32(-1), f32(1))
+    s2 = (f32(0.9) * s.astype(f32) + (f32(0.1) * u)[:, None] * np.arange(1, 5, dtype=f32)).astype(f32)
+    return s2, -(s2 * s2).sum(axis=1)
