@@ -297,20 +297,38 @@ def cpu_baseline(sets, sample_envs):
             total += n * s.T
         return total, time.perf_counter() - t0
 
+    def median_of_3(envs):
+        runs = sorted((run(envs) for _ in range(3)), key=lambda r: r[1])
+        return runs[1]
+
     cores = O.num_threads()
-    total_env_steps, el = run(sample_envs)
+    total_env_steps, el = median_of_3(sample_envs)
     # the same oracle on one thread, over a quarter of the sample
     O.set_threads(1)
-    one_steps, one_el = run(max(1, sample_envs // 4))
+    one_steps, one_el = median_of_3(max(1, sample_envs // 4))
     O.set_threads(cores)
     return {"value": total_env_steps / el, "unit": "env-steps/s", "cores": cores,
             "kind": "oracle",
             "sample": f"first {sample_envs} envs of each set over the full horizon "
-                      f"({total_env_steps} env-steps, {el:.1f} s), FP64 C oracle with "
-                      f"OpenMP over envs, returns/GAE included",
+                      f"({total_env_steps} env-steps, median of 3 runs: {el:.1f} s), FP64 C "
+                      f"oracle with OpenMP over envs, returns/GAE included",
+            "cpu": cpu_model(),
             "single_thread": {"value": round(one_steps / one_el, 1), "cores": 1,
                               "sample": f"first {max(1, sample_envs // 4)} envs of each set "
-                                        f"({one_steps} env-steps, {one_el:.1f} s)"}}
+                                        f"({one_steps} env-steps, median of 3 runs: "
+                                        f"{one_el:.1f} s)"}}
+
+
+def cpu_model():
+    """The host CPU's model name, from /proc/cpuinfo (None if unreadable)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def serving(args, wsx, inputs, torch):

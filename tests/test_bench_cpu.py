@@ -35,6 +35,7 @@ def test_cpu_baseline_reports_all_threads_and_one():
     assert out["value"] > 0 and out["cores"] == before
     assert out["single_thread"]["cores"] == 1 and out["single_thread"]["value"] > 0
     assert "160 env-steps" in out["sample"] and "40 env-steps" in out["single_thread"]["sample"]
+    assert out["cpu"] is None or isinstance(out["cpu"], str)
 
 
 def test_more_than_one_gpu_is_refused():
