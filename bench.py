@@ -221,6 +221,33 @@ def batch_step(sets, i, wsx, torch, timed, k_events):
             wsx.compute_returns(s.traj, s.T, 0.99, 0.95, True, torch.float32, s.ret, s.adv)
 
 
+def plain_vs_fused(sets, wsx, torch, batched, epoch):
+    """One roll-out of every set in the plain per-step form and one in the
+    fused form (batched when the benchmark batches), from the same reset: the
+    trajectories must be equal bit for bit."""
+    fields = ("obs", "action", "reward", "done", "value", "logp", "last_value")
+
+    def run(mode):
+        for s in sets:
+            wsx.env_reset(s.env, epoch=epoch)
+        if batched and mode == wsx.MODE_FUSED:
+            wsx.rollout_batch([s.env for s in sets], [s.dp for s in sets], sets[0].T,
+                              [s.traj for s in sets])
+        else:
+            for s in sets:
+                wsx.rollout(s.env, s.dp, s.T, s.traj, mode)
+        torch.cuda.synchronize()
+        return [[getattr(s.traj, f).clone() for f in fields] for s in sets]
+
+    a, b = run(wsx.MODE_FUSED), run(wsx.MODE_PLAIN)
+    equal = all(torch.equal(x, y) for sa, sb in zip(a, b) for x, y in zip(sa, sb))
+    # the sets' returns again match their (last written) trajectories
+    for s in sets:
+        wsx.compute_returns(s.traj, s.T, 0.99, 0.95, True, torch.float32, s.ret, s.adv)
+    torch.cuda.synchronize()
+    return {"plain_equals_fused": bool(equal), "epoch": epoch, "fields": list(fields)}
+
+
 def run_form(sets, mode, steps, warmup, wsx, torch, first_epoch, batched=False):
     main = torch.cuda.current_stream()
     k_events = []
@@ -536,6 +563,12 @@ def main():
             result[name] = r + (n,)
             print(f"[bench] {name}: {n} steps in {r[0]:.3f} s", file=sys.stderr, flush=True)
 
+    # plain and fused forms on identical inputs, compared in the same run
+    parity = None
+    if "plain" in forms and args.plain_steps > 0:
+        parity = plain_vs_fused(sets, wsx, torch, batched, epoch=4321)
+        print(f"[bench] parity: {parity}", file=sys.stderr, flush=True)
+
     el, lat, kern = result["fused"]
     value = env_steps * args.steps / el
     # dominant kernel: the fused roll-out launch (the batched one, or the set's
@@ -587,6 +620,8 @@ def main():
                                         "p99": round(percentile(plat, 99), 3),
                                         "iqr": iqr(plat, 3)}}
             out[f"fused_speedup_vs_{name}"] = round(value / pv, 2)
+    if parity is not None:
+        out["parity"] = parity
     if args.serve_requests > 0:
         out["serving"] = serving(args, wsx, inputs, torch)
     if not args.no_cpu_baseline:
