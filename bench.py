@@ -248,6 +248,40 @@ def plain_vs_fused(sets, wsx, torch, batched, epoch):
     return {"plain_equals_fused": bool(equal), "epoch": epoch, "fields": list(fields)}
 
 
+def peak_probe(torch):
+    """Achievable rates on this GPU, for reading the roofline fractions: a
+    device-to-device copy of 4 GiB (HBM read + write) and 8192^3 matrix products
+    in BF16 and FP32 through torch (hipBLASLt / rocBLAS)."""
+    out = {}
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps * 1e-3
+
+    n = 4 << 30
+    src = torch.empty(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    t = timed(lambda: dst.copy_(src), 5)
+    out["hbm_copy_gb_s"] = round(2 * n / t / 1e9, 1)
+    del src, dst
+    m = 8192
+    for name, dt in (("bf16_gemm_tflops", torch.bfloat16), ("fp32_gemm_tflops", torch.float32)):
+        x = torch.randn(m, m, device="cuda").to(dt)
+        y = torch.randn(m, m, device="cuda").to(dt)
+        t = timed(lambda: torch.matmul(x, y), 10)
+        out[name] = round(2 * m ** 3 / t / 1e12, 1)
+        del x, y
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_form(sets, mode, steps, warmup, wsx, torch, first_epoch, batched=False):
     main = torch.cuda.current_stream()
     k_events = []
@@ -492,6 +526,9 @@ def main():
                     help="instead of the benchmark: env-count sweep of this workload key "
                          "(e.g. pendulum_10k), one JSON line per count")
     ap.add_argument("--sweep-counts", default="10,100,1000,10000,100000,1000000")
+    ap.add_argument("--peak-probe", action="store_true",
+                    help="instead of the benchmark: achievable HBM copy bandwidth and BF16 / "
+                         "FP32 GEMM rates on this GPU, one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (replicas "
@@ -517,6 +554,11 @@ def main():
     if args.sweep:
         sweep(args.sweep, [int(x) for x in args.sweep_counts.split(",")], args.steps, wsx, inputs,
               torch)
+        return
+    if args.peak_probe:
+        print(json.dumps({"peak_probe": peak_probe(torch),
+                          "published": {"hbm_gb_s": 8000, "bf16_tflops": 2500,
+                                        "fp32_tflops": 157.3}}), flush=True)
         return
     keys = WORKLOADS[args.workload]
     batched = len(keys) > 1 and not args.no_batch
