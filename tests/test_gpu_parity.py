@@ -105,8 +105,10 @@ def test_policy_forward_matches_oracle(kind, rows):
 
 @pytest.mark.parametrize("T,rows", [(1, 1), (63, 31), (64, 33), (65, 32), (200, 100),
                                     (1000, 7), (129, 257),
-                                    # row-parallel kernel (>= 24 rows per CU)
-                                    (3, 10000), (70, 12001), (200, 10000)])
+                                    # row-parallel kernel (>= 24 rows per CU), including
+                                    # horizons just past one and sixteen 16-step blocks
+                                    (3, 10000), (70, 12001), (200, 10000), (33, 8000),
+                                    (256, 6500), (257, 7000)])
 @pytest.mark.parametrize("boot", [True, False])
 def test_returns_match_oracle(T, rows, boot):
     import torch
