@@ -199,6 +199,93 @@ k_returns_rows(const float* __restrict__ reward, const float* __restrict__ value
     }
 }
 
+// Segmented row-parallel form for many rows and horizons of 33 to 8 x 32
+// steps: a workgroup owns 64 rows (lane = row) and one wave per 32-step
+// segment of the horizon. Each wave loads its segment into registers once
+// (branch-free: indices past the set are clamped and their values unused),
+// composes its steps' affine maps backwards (G_start = bg + cg G_end,
+// A_start = ba + ca A_end; the A map's last step takes V at the next
+// segment's first step), publishes (cg, bg, ca, ba) in LDS, forms its carry
+// from the later segments' maps, and runs the same recursion as
+// k_returns_rows from its registers to write the outputs. A row's chain of
+// dependent loads is one segment long instead of the whole horizon.
+constexpr int kSeg = 32;
+constexpr int kSegMax = 8;   // segments (waves) per workgroup: two waves per SIMD
+
+template <int OUT_F64>
+__global__ void __attribute__((amdgpu_flat_work_group_size(64, 64 * kSegMax),
+                               amdgpu_waves_per_eu(2)))
+k_returns_seg(const float* __restrict__ reward, const float* __restrict__ value,
+              const uint8_t* __restrict__ done, const float* __restrict__ last_value, int T,
+              int64_t rows, double gamma, double lambda, int bootstrap, void* __restrict__ ret,
+              void* __restrict__ adv) {
+    __shared__ double maps[4][kSegMax][64];   // cg, bg, ca, ba per segment and row
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nseg = blockDim.x >> 6;
+    const int64_t r = (int64_t)blockIdx.x * 64 + lane;
+    const bool ok = r < rows;
+    const int64_t rl = ok ? r : rows - 1;   // a row inside the set, for the loads
+    const double gl = gamma * lambda;
+    const int t0 = w * kSeg;   // this wave's steps t0 .. t0 + kSeg - 1 (below T)
+    float rw[kSeg], vv[kSeg];
+    uint32_t dmask = 0;   // bit j: step t0 + j terminated
+#pragma unroll
+    for (int j = 0; j < kSeg; ++j) {
+        const size_t i = (size_t)min(t0 + j, T - 1) * rows + rl;
+        rw[j] = reward[i];
+        vv[j] = value[i];
+        dmask |= (uint32_t)(done[i] != 0) << j;
+    }
+    const int t_end = min(t0 + kSeg, T);   // first step after the segment
+    const double v_T = bootstrap ? (double)last_value[rl] : 0.0;
+    // V at the segment's end: the next segment's first value, or V(s_T)
+    const double v_end = t_end < T ? (double)value[(size_t)t_end * rows + rl] : v_T;
+    double cg = 1.0, bg = 0.0, ca = 1.0, ba = 0.0, v_next = v_end;
+#pragma unroll
+    for (int j = kSeg - 1; j >= 0; --j) {
+        if (t0 + j < T) {
+            const double rt = rw[j], v = vv[j];
+            const double keep = (dmask >> j) & 1u ? 0.0 : 1.0;
+            ba = (rt + gamma * keep * v_next - v) + gl * keep * ba;
+            ca = gl * keep * ca;
+            bg = rt + gamma * keep * bg;
+            cg = gamma * keep * cg;
+            v_next = v;
+        }
+    }
+    maps[0][w][lane] = cg;
+    maps[1][w][lane] = bg;
+    maps[2][w][lane] = ca;
+    maps[3][w][lane] = ba;
+    __syncthreads();
+    // carry into this segment: the later segments' maps applied to (G_T, A_T)
+    double g = v_T, a = 0.0;
+    for (int k = nseg - 1; k > w; --k) {
+        g = maps[1][k][lane] + maps[0][k][lane] * g;
+        a = maps[3][k][lane] + maps[2][k][lane] * a;
+    }
+    if (!ok) return;
+    v_next = v_end;
+#pragma unroll
+    for (int j = kSeg - 1; j >= 0; --j) {
+        const int t = t0 + j;
+        if (t < T) {
+            const size_t i = (size_t)t * rows + r;
+            const double rt = rw[j], v = vv[j];
+            const double keep = (dmask >> j) & 1u ? 0.0 : 1.0;
+            a = (rt + gamma * keep * v_next - v) + gl * keep * a;
+            g = rt + gamma * keep * g;
+            v_next = v;
+            if (OUT_F64) {
+                static_cast<double*>(ret)[i] = g;
+                static_cast<double*>(adv)[i] = a;
+            } else {
+                static_cast<float*>(ret)[i] = (float)g;
+                static_cast<float*>(adv)[i] = (float)a;
+            }
+        }
+    }
+}
+
 hipError_t launch_returns(const float* reward, const float* value, const uint8_t* done,
                           const float* last_value, int horizon, int64_t rows, double gamma,
                           double lambda, int bootstrap, void* ret, void* adv, int out_f64,
@@ -206,6 +293,20 @@ hipError_t launch_returns(const float* reward, const float* value, const uint8_t
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    // the segmented form while one chain per row leaves the set latency-bound
+    // (below one 64-row wave per CU); with more rows the row form streams faster
+    if (rows >= (int64_t)kRowsPerLaneMin * cus && rows < (int64_t)64 * cus && horizon > kSeg &&
+        horizon <= kSeg * kSegMax) {
+        const unsigned blocks = (unsigned)((rows + 63) / 64);
+        const int nseg = (horizon + kSeg - 1) / kSeg;
+        if (out_f64)
+            hipLaunchKernelGGL(k_returns_seg<1>, dim3(blocks), dim3(64 * nseg), 0, s, reward, value,
+                               done, last_value, horizon, rows, gamma, lambda, bootstrap, ret, adv);
+        else
+            hipLaunchKernelGGL(k_returns_seg<0>, dim3(blocks), dim3(64 * nseg), 0, s, reward, value,
+                               done, last_value, horizon, rows, gamma, lambda, bootstrap, ret, adv);
+        return hipGetLastError();
+    }
     if (rows >= (int64_t)kRowsPerLaneMin * cus) {
         const unsigned blocks = (unsigned)((rows + 63) / 64);
         if (out_f64)
