@@ -649,7 +649,9 @@ k_ac_dw2(AcArgs a) {
 
 // Reduction of the per-workgroup partial sums, one launch for every
 // gradient tensor: segment y sums, for r < rows and c < cols,
-// out[r][c] = sum over parts g (in order) of part[g * stride + off + r * cols_in + c].
+// out[r][c] = sum over parts g of part[g * stride + off + r * cols_in + c], in a
+// fixed order (eight contiguous groups of parts, each summed in order, then
+// the groups in order).
 struct SumSeg {
     const float* part;
     float* out;
@@ -661,23 +663,42 @@ struct SumTable {
     SumSeg seg[kMaxSeg];
 };
 
+// A workgroup takes 32 elements of a segment; the eight lanes of an element
+// (one per 32-lane group) each sum a contiguous eighth of the parts in order,
+// and the eight partial sums are added in group order: a fixed order, with
+// eight times the loads in flight of one chain per element.
+constexpr int kSumSplit = 8;
 __global__ void __launch_bounds__(256) k_ac_sum(SumTable t) {
+    __shared__ float red[kSumSplit][32];
     const SumSeg& sg = t.seg[blockIdx.y];
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= (int64_t)sg.rows * sg.cols) return;
-    const int r = (int)(e / sg.cols), c = (int)(e % sg.cols);
-    const float* src = sg.part + sg.off + (int64_t)r * sg.cols_in + c;
+    const int el = threadIdx.x & 31, sub = threadIdx.x >> 5;
+    const int64_t e = (int64_t)blockIdx.x * 32 + el;
+    const bool ok = e < (int64_t)sg.rows * sg.cols;
     float s = 0.0f;
-    int g = 0;
-    for (; g + 8 <= sg.nparts; g += 8) {   // eight loads in flight, summed in order
-        float v[8];
+    if (ok) {
+        const int r = (int)(e / sg.cols), c = (int)(e % sg.cols);
+        const float* src = sg.part + sg.off + (int64_t)r * sg.cols_in + c;
+        const int per = (sg.nparts + kSumSplit - 1) / kSumSplit;
+        const int g0 = sub * per, g1 = min(sg.nparts, g0 + per);
+        int g = g0;
+        constexpr int kInFlight = 32;
+        for (; g + kInFlight <= g1; g += kInFlight) {
+            float v[kInFlight];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = src[(size_t)(g + u) * sg.stride];
+            for (int u = 0; u < kInFlight; ++u) v[u] = src[(size_t)(g + u) * sg.stride];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) s += v[u];
+            for (int u = 0; u < kInFlight; ++u) s += v[u];
+        }
+        for (; g < g1; ++g) s += src[(size_t)g * sg.stride];
     }
-    for (; g < sg.nparts; ++g) s += src[(size_t)g * sg.stride];
-    sg.out[e] = s;
+    red[sub][el] = s;
+    __syncthreads();
+    if (ok && sub == 0) {
+        float total = red[0][el];
+#pragma unroll
+        for (int k = 1; k < kSumSplit; ++k) total += red[k][el];
+        sg.out[e] = total;
+    }
 }
 
 // Adam (Kingma and Ba 2015, Algorithm 1), one element per thread; c1 and c2
@@ -732,7 +753,7 @@ struct AcVariant {
         seg(a.part_bwd, B, grid1, 0, H, p.d_in, KIN, o.w1);
         seg(a.part_bwd, B, grid1, (int64_t)H * KIN, 1, H, H, o.b1);
         seg(a.part_w2, (int64_t)H * H, grid2, 0, H, H, H, o.w2);
-        hipLaunchKernelGGL(k_ac_sum, dim3((unsigned)((most + 255) / 256), ns), dim3(256), 0, s, t);
+        hipLaunchKernelGGL(k_ac_sum, dim3((unsigned)((most + 31) / 32), ns), dim3(256), 0, s, t);
         return hipGetLastError();
     }
     static size_t part_floats(int grid1, int grid2) {
