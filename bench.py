@@ -68,12 +68,14 @@ def update_leg(sets, steps, wsx, torch):
         legs.append((s, obs, act, r, a, g, ws, names, master, mom, store))
 
     def one(t):
+        items = []
         for s, obs, act, r, a, g, ws, names, master, mom, store in legs:
             wsx.ac_grad(s.dp, wsx.N_ACTIONS[s.kind], obs, act, r, a, 0.5, 0.01, grads=g,
                         workspace=ws)
-            for k in names:
-                wsx.adam_step(master[k], g[k].reshape(-1)[:master[k].numel()], mom[k][0],
-                              mom[k][1], t, 3e-4, store=store[k])
+            items += [(master[k], g[k].reshape(-1)[:master[k].numel()], mom[k][0], mom[k][1],
+                       store[k]) for k in names]
+        for i in range(0, len(items), 16):   # every tensor of the sets in one Adam launch
+            wsx.adam_step_many(items[i:i + 16], t, 3e-4)
     if not legs:
         return None
     one(1)

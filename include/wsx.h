@@ -260,6 +260,26 @@ int wsx_adam_step(float* param, const float* grad, float* m, float* v, int64_t n
                   float lr, float beta1, float beta2, float eps, void* store,
                   int32_t store_dtype, void* stream);
 
+/* The same Adam step on several tensors in one launch (one step t and one set
+ * of hyper-parameters): exactly wsx_adam_step on each tensor, for callers
+ * that update a policy's weight tensors together. n_tensors in
+ * 1..WSX_ADAM_MAX_TENSORS; each entry as wsx_adam_step's arguments (n >= 0;
+ * entries with n == 0 are skipped; pointers of the others non-NULL). The
+ * tensors must not overlap. */
+#define WSX_ADAM_MAX_TENSORS 16
+typedef struct {
+    float* param;            /* n FP32 masters, updated in place                  */
+    const float* grad;       /* n FP32 gradients                                  */
+    float* m;                /* n FP32 first moments                              */
+    float* v;                /* n FP32 second moments                             */
+    int64_t n;
+    void* store;             /* NULL, or n values in store_dtype                  */
+    int32_t store_dtype;     /* WSX_F32 or WSX_BF16                               */
+} wsx_adam_tensor;
+
+int wsx_adam_step_many(const wsx_adam_tensor* tensors, int32_t n_tensors, int32_t step, float lr,
+                       float beta1, float beta2, float eps, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* User environment kinds (Sec. 2: the framework is environment-agnostic;    */
 /* App. B: user environments are compiled for the device and run in the same */

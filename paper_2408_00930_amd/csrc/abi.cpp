@@ -700,4 +700,38 @@ int wsx_adam_step(float* param, const float* grad, float* m, float* v, int64_t n
     return WSX_OK;
 }
 
+int wsx_adam_step_many(const wsx_adam_tensor* tensors, int32_t n_tensors, int32_t step, float lr,
+                       float beta1, float beta2, float eps, void* stream) {
+    if (!tensors) return fail(WSX_EINVAL, "tensors is NULL");
+    if (n_tensors < 1 || n_tensors > WSX_ADAM_MAX_TENSORS)
+        return fail(WSX_EINVAL, "n_tensors must lie in 1..%d", WSX_ADAM_MAX_TENSORS);
+    if (step < 1) return fail(WSX_EINVAL, "step must be >= 1");
+    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f))
+        return fail(WSX_EINVAL, "betas must lie in [0, 1)");
+    if (!std::isfinite(lr) || !(eps >= 0.0f) || !std::isfinite(eps))
+        return fail(WSX_EINVAL, "lr must be finite and eps finite and >= 0");
+    AdamTable t{};
+    int used = 0;
+    int64_t most = 0;
+    for (int i = 0; i < n_tensors; ++i) {
+        const wsx_adam_tensor& a = tensors[i];
+        if (a.n < 0) return fail(WSX_EINVAL, "tensor %d: n < 0", i);
+        if (a.store && a.store_dtype != WSX_F32 && a.store_dtype != WSX_BF16)
+            return fail(WSX_EINVAL, "tensor %d: store_dtype must be WSX_F32 or WSX_BF16", i);
+        if (a.n == 0) continue;
+        if (!a.param || !a.grad || !a.m || !a.v)
+            return fail(WSX_EINVAL, "tensor %d: param, grad, m or v is NULL", i);
+        // the ABI's WSX_F32 / WSX_BF16 codes are the kernels' format codes
+        t.seg[used++] = AdamSeg{a.param, a.grad, a.m, a.v, a.n, a.store, a.store_dtype};
+        most = std::max(most, a.n);
+    }
+    if (used == 0) return WSX_OK;
+    const float c1 = (float)(1.0 - std::pow((double)beta1, step));
+    const float c2 = (float)(1.0 - std::pow((double)beta2, step));
+    const hipError_t e = launch_adam_many(t, used, most, lr, beta1, beta2, eps, c1, c2,
+                                          static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "wsx_adam_step_many");
+    return WSX_OK;
+}
+
 }  // extern "C"

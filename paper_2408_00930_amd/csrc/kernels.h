@@ -116,6 +116,19 @@ struct AcLaunch {
     int grid1, grid2;        // workgroups of the per-tile kernels and of dW2
     AcOut out;
 };
+// Adam on several tensors in one launch (the same step and hyper-parameters).
+constexpr int kAdamMaxTensors = 16;
+struct AdamSeg {
+    float* param;
+    const float* grad;
+    float *m, *v;
+    int64_t n;
+    void* store;   // NULL, or the parameter in store_dtype
+    int store_dtype;
+};
+struct AdamTable {
+    AdamSeg seg[kAdamMaxTensors];
+};
 #ifndef __HIPCC_RTC__   // host-side launchers
 bool ac_supported(int dtype, int hidden, int d_in, int n_head);
 int64_t ac_chunk_samples(int64_t n);   // samples per chunk of a call over n
@@ -124,6 +137,8 @@ hipError_t launch_ac_grad(const AcLaunch& l, hipStream_t s);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
                        float b1, float b2, float eps, float c1, float c2, void* store,
                        int store_dtype, hipStream_t s);
+hipError_t launch_adam_many(const AdamTable& t, int n_tensors, int64_t most, float lr, float b1,
+                            float b2, float eps, float c1, float c2, hipStream_t s);
 
 // User environment kinds compiled at run time (compose.cpp): kinds
 // kUserKindBase, kUserKindBase + 1, ...

@@ -701,15 +701,13 @@ __global__ void __launch_bounds__(256) k_ac_sum(SumTable t) {
     }
 }
 
-// Adam (Kingma and Ba 2015, Algorithm 1), one element per thread; c1 and c2
-// are the bias corrections 1 - beta^t. The updated parameter is also stored
-// in the policy's format (`store`, NULL to skip).
-__global__ void __launch_bounds__(256)
-k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
-       float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float c1,
-       float c2, void* __restrict__ store, int store_dtype) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
+// Adam (Kingma and Ba 2015, Algorithm 1) on element i; c1 and c2 are the bias
+// corrections 1 - beta^t. The updated parameter is also stored in the
+// policy's format (`store`, NULL to skip).
+__device__ __forceinline__ void adam_elem(float* __restrict__ p, const float* __restrict__ g,
+                                          float* __restrict__ m, float* __restrict__ v, int64_t i,
+                                          float lr, float b1, float b2, float eps, float c1,
+                                          float c2, void* __restrict__ store, int store_dtype) {
     const float gi = g[i];
     const float mi = b1 * m[i] + (1.0f - b1) * gi;
     const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
@@ -723,6 +721,24 @@ k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m
         else
             static_cast<float*>(store)[i] = pi;
     }
+}
+
+// One element per thread.
+__global__ void __launch_bounds__(256)
+k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+       float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float c1,
+       float c2, void* __restrict__ store, int store_dtype) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) adam_elem(p, g, m, v, i, lr, b1, b2, eps, c1, c2, store, store_dtype);
+}
+
+// Several tensors in one launch: tensor blockIdx.y, the same element update.
+__global__ void __launch_bounds__(256) k_adam_many(AdamTable t, float lr, float b1, float b2,
+                                                   float eps, float c1, float c2) {
+    const AdamSeg& a = t.seg[blockIdx.y];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < a.n)
+        adam_elem(a.param, a.grad, a.m, a.v, i, lr, b1, b2, eps, c1, c2, a.store, a.store_dtype);
 }
 
 template <int DT, int H, int KIN, int NHP>
@@ -835,6 +851,13 @@ hipError_t launch_ac_grad(const AcLaunch& l, hipStream_t s) {
         }
         return V::sum(a, l.grid1, l.grid2, l.out, s);
     });
+}
+
+hipError_t launch_adam_many(const AdamTable& t, int n_tensors, int64_t most, float lr, float b1,
+                            float b2, float eps, float c1, float c2, hipStream_t s) {
+    hipLaunchKernelGGL(k_adam_many, dim3((unsigned)((most + 255) / 256), (unsigned)n_tensors),
+                       dim3(256), 0, s, t, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
 }
 
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,

@@ -513,7 +513,7 @@ class _Grads(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("w1", "b1", "w2", "b2", "w3", "b3", "log_std")]
 
 
-EXPORTS += ["wsx_ac_grad_workspace_bytes", "wsx_ac_grad", "wsx_adam_step"]
+EXPORTS += ["wsx_ac_grad_workspace_bytes", "wsx_ac_grad", "wsx_adam_step", "wsx_adam_step_many"]
 
 
 def _update_sigs(L):
@@ -526,7 +526,15 @@ def _update_sigs(L):
                               C.c_float, C.c_float, C.POINTER(_Grads), vp, C.c_size_t, vp]
     L.wsx_adam_step.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int32, C.c_float, C.c_float,
                                 C.c_float, C.c_float, vp, C.c_int32, vp]
+    L.wsx_adam_step_many.argtypes = [C.POINTER(_AdamTensor), C.c_int32, C.c_int32, C.c_float,
+                                     C.c_float, C.c_float, C.c_float, vp]
     L._update_sigs = True
+
+
+class _AdamTensor(C.Structure):
+    _fields_ = [("param", C.c_void_p), ("grad", C.c_void_p), ("m", C.c_void_p),
+                ("v", C.c_void_p), ("n", C.c_int64), ("store", C.c_void_p),
+                ("store_dtype", C.c_int32)]
 
 
 class Grads:
@@ -595,6 +603,27 @@ def adam_step(param, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, sto
     _check(L.wsx_adam_step(param.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(), n,
                            int(step), float(lr), float(beta1), float(beta2), float(eps),
                            None if store is None else store.data_ptr(), sd, _stream(stream)))
+
+
+def adam_step_many(tensors, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    """The same Adam step on several tensors in one launch: `tensors` is a
+    list of (param, grad, m, v, store) with store None or a tensor as in
+    adam_step."""
+    L = lib()
+    _update_sigs(L)
+    arr = (_AdamTensor * max(1, len(tensors)))()
+    for i, (param, grad, m, v, store) in enumerate(tensors):
+        n = param.numel()
+        for t in (param, grad, m, v):
+            assert t.is_cuda and t.is_contiguous() and t.dtype == torch.float32 and t.numel() == n
+        sd = F32
+        if store is not None:
+            assert store.numel() == n and store.is_contiguous()
+            sd = BF16 if store.dtype in (torch.bfloat16, torch.int16, torch.uint16) else F32
+        arr[i] = _AdamTensor(param.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(), n,
+                             None if store is None else store.data_ptr(), sd)
+    _check(L.wsx_adam_step_many(arr, len(tensors), int(step), float(lr), float(beta1),
+                                float(beta2), float(eps), _stream(stream)))
 
 
 # ----------------------------------------------------------- user kinds ----

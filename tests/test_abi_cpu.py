@@ -182,6 +182,25 @@ def test_update_validation_without_gpu():
     assert L.wsx_adam_step(p, p, p, p, 10, 1, 1e-3, 0.9, 0.999, 1e-8, p, 2, None) == -1
     assert L.wsx_adam_step(None, None, None, None, 0, 1, 1e-3, 0.9, 0.999, 1e-8, None, 0,
                            None) == 0
+    # Adam on several tensors in one launch
+    T = wsx._AdamTensor
+    good = (T * 2)(T(p, p, p, p, 10, None, 0), T(p, p, p, p, 0, None, 0))
+    assert L.wsx_adam_step_many(None, 1, 1, 1e-3, 0.9, 0.999, 1e-8, None) == -1
+    assert L.wsx_adam_step_many(good, 0, 1, 1e-3, 0.9, 0.999, 1e-8, None) == -1
+    assert L.wsx_adam_step_many(good, 17, 1, 1e-3, 0.9, 0.999, 1e-8, None) == -1
+    assert b"n_tensors" in L.wsx_last_error()
+    assert L.wsx_adam_step_many(good, 2, 0, 1e-3, 0.9, 0.999, 1e-8, None) == -1
+    assert L.wsx_adam_step_many(good, 2, 1, 1e-3, 0.9, 1.0, 1e-8, None) == -1
+    bad = (T * 2)(T(p, p, p, p, 10, p, 2), T(p, p, p, p, 5, None, 0))
+    assert L.wsx_adam_step_many(bad, 2, 1, 1e-3, 0.9, 0.999, 1e-8, None) == -1
+    assert b"tensor 0" in L.wsx_last_error()
+    null = (T * 2)(T(p, p, p, p, 10, None, 0), T(p, None, p, p, 5, None, 0))
+    assert L.wsx_adam_step_many(null, 2, 1, 1e-3, 0.9, 0.999, 1e-8, None) == -1
+    assert b"tensor 1" in L.wsx_last_error()
+    neg = (T * 1)(T(p, p, p, p, -1, None, 0))
+    assert L.wsx_adam_step_many(neg, 1, 1, 1e-3, 0.9, 0.999, 1e-8, None) == -1
+    empty = (T * 2)(T(None, None, None, None, 0, None, 0), T(None, None, None, None, 0, None, 0))
+    assert L.wsx_adam_step_many(empty, 2, 1, 1e-3, 0.9, 0.999, 1e-8, None) == 0
 
 
 def test_user_kind_validation_and_compile_errors_without_gpu():

@@ -178,6 +178,40 @@ def test_adam_matches_oracle_and_stores_bf16():
         assert torch.equal(store, p_d.to(torch.bfloat16))
 
 
+def test_adam_step_many_equals_one_call_per_tensor():
+    """One launch over several tensors (sizes 1 to 70,001; BF16, FP32 and no
+    store) gives bit for bit what one wsx_adam_step per tensor gives."""
+    import torch
+    wsx = _wsx()
+    say("adam many")
+    rng = np.random.default_rng(5)
+    sizes = (1, 300, 70001, 257)
+    stores = ("bf16", "f32", None, "bf16")
+
+    def make():
+        ts = []
+        for n, st in zip(sizes, stores):
+            p = torch.from_numpy(rng.normal(0, 0.1, n).astype(np.float32)).cuda()
+            g = torch.from_numpy(rng.normal(0, 1e-3, n).astype(np.float32)).cuda()
+            m = torch.from_numpy(rng.normal(0, 1e-4, n).astype(np.float32)).cuda()
+            v = torch.from_numpy(np.abs(rng.normal(0, 1e-6, n)).astype(np.float32)).cuda()
+            s = None if st is None else torch.zeros(n, dtype=torch.bfloat16 if st == "bf16" else
+                                                    torch.float32, device="cuda")
+            ts.append([p, g, m, v, s])
+        return ts
+    a = make()
+    b = [[t.clone() if t is not None else None for t in row] for row in a]
+    for step in (1, 2, 7):
+        for p, g, m, v, s in a:
+            wsx.adam_step(p, g, m, v, step, 1e-3, store=s)
+        wsx.adam_step_many([tuple(row) for row in b], step, 1e-3)
+        torch.cuda.synchronize()
+        for ra, rb in zip(a, b):
+            for x, y in zip(ra, rb):
+                if x is not None:
+                    assert torch.equal(x, y), step
+
+
 def test_update_step_changes_the_policy_the_rollout_uses():
     """Gradient, Adam into the policy's own BF16 weights, and a new roll-out
     that sees them: the next policy's forward equals the oracle's forward with
