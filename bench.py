@@ -97,7 +97,7 @@ def update_leg(sets, steps, wsx, torch):
             "achieved_tflops": round(tflops, 2), "peak_tflops": PEAK_TFLOPS[dtype],
             "frac": round(tflops / PEAK_TFLOPS[dtype], 4),
             "what": "gradient of the actor-critic loss over every sample of the sets' "
-                    "trajectories plus one Adam step per tensor into the policy weights"}
+                    "trajectories plus one batched Adam launch over every policy tensor"}
 
 
 def sweep(kind_key, counts, steps, wsx, inputs, torch):
