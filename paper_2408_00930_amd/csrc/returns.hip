@@ -2,7 +2,8 @@
 // (arXiv 2408.00930, Sec. 3: actor-critic training consumes them; GAE of
 // Schulman et al. 2016).
 //
-// Two kernels. For sets with few rows and long horizons, a time-parallel
+// Three kernels, chosen by the set's shape in launch_returns. For sets with
+// few rows and horizons past 512 steps (or of at most 32), a time-parallel
 // scan: both recursions are affine maps run backwards in time,
 //   A_t = delta_t + gamma lambda (1 - d_t) A_{t+1},  G_t = r_t + gamma (1 - d_t) G_{t+1},
 // so a block of consecutive steps composes into one map x -> b + c x with
@@ -199,9 +200,9 @@ k_returns_rows(const float* __restrict__ reward, const float* __restrict__ value
     }
 }
 
-// Segmented row-parallel form for many rows and horizons of 33 to 8 x 32
-// steps: a workgroup owns 64 rows (lane = row) and one wave per 32-step
-// segment of the horizon. Each wave loads its segment into registers once
+// Segmented row-parallel form for horizons of 33 to 16 x 32 steps: a
+// workgroup owns 64 rows (lane = row) and one wave per 32-step segment of
+// the horizon. Each wave loads its segment into registers once
 // (branch-free: indices past the set are clamped and their values unused),
 // composes its steps' affine maps backwards (G_start = bg + cg G_end,
 // A_start = ba + ca A_end; the A map's last step takes V at the next
@@ -209,36 +210,44 @@ k_returns_rows(const float* __restrict__ reward, const float* __restrict__ value
 // from the later segments' maps, and runs the same recursion as
 // k_returns_rows from its registers to write the outputs. A row's chain of
 // dependent loads is one segment long instead of the whole horizon.
+// Up to 16 segments (1024 threads, four waves per SIMD within 128 VGPRs).
 constexpr int kSeg = 32;
-constexpr int kSegMax = 8;   // segments (waves) per workgroup: two waves per SIMD
+constexpr int kSegMax = 16;
 
 template <int OUT_F64>
-__global__ void __attribute__((amdgpu_flat_work_group_size(64, 64 * kSegMax),
-                               amdgpu_waves_per_eu(2)))
+__global__ void __attribute__((amdgpu_flat_work_group_size(64, 64 * kSegMax)))
 k_returns_seg(const float* __restrict__ reward, const float* __restrict__ value,
               const uint8_t* __restrict__ done, const float* __restrict__ last_value, int T,
               int64_t rows, double gamma, double lambda, int bootstrap, void* __restrict__ ret,
               void* __restrict__ adv) {
     __shared__ double maps[4][kSegMax][64];   // cg, bg, ca, ba per segment and row
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nseg = blockDim.x >> 6;
-    const int64_t r = (int64_t)blockIdx.x * 64 + lane;
-    const bool ok = r < rows;
-    const int64_t rl = ok ? r : rows - 1;   // a row inside the set, for the loads
+    // Element offsets fit 32 bits (the launcher takes this form only while
+    // rows x T < 2^31). The segment index is wave-uniform: held in a scalar
+    // register it keeps each step's offset scalar, so a lane holds one vector
+    // offset (its row) instead of one per step.
+    const int lane = threadIdx.x & 63, nseg = blockDim.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t nrows = (uint32_t)rows;
+    const uint32_t r = blockIdx.x * 64u + (uint32_t)lane;
+    const bool ok = r < nrows;
+    const uint32_t rl = ok ? r : nrows - 1;   // a row inside the set, for the loads
     const double gl = gamma * lambda;
     const int t0 = w * kSeg;   // this wave's steps t0 .. t0 + kSeg - 1 (below T)
     float rw[kSeg], vv[kSeg];
     uint32_t dmask = 0;   // bit j: step t0 + j terminated
 #pragma unroll
+    for (int j = 0; j < kSeg; ++j)
+        dmask |= (uint32_t)(done[(uint32_t)min(t0 + j, T - 1) * nrows + rl] != 0) << j;
+#pragma unroll
     for (int j = 0; j < kSeg; ++j) {
-        const size_t i = (size_t)min(t0 + j, T - 1) * rows + rl;
+        const uint32_t i = (uint32_t)min(t0 + j, T - 1) * nrows + rl;
         rw[j] = reward[i];
         vv[j] = value[i];
-        dmask |= (uint32_t)(done[i] != 0) << j;
     }
     const int t_end = min(t0 + kSeg, T);   // first step after the segment
     const double v_T = bootstrap ? (double)last_value[rl] : 0.0;
     // V at the segment's end: the next segment's first value, or V(s_T)
-    const double v_end = t_end < T ? (double)value[(size_t)t_end * rows + rl] : v_T;
+    const double v_end = t_end < T ? (double)value[(uint32_t)t_end * nrows + rl] : v_T;
     double cg = 1.0, bg = 0.0, ca = 1.0, ba = 0.0, v_next = v_end;
 #pragma unroll
     for (int j = kSeg - 1; j >= 0; --j) {
@@ -269,7 +278,7 @@ k_returns_seg(const float* __restrict__ reward, const float* __restrict__ value,
     for (int j = kSeg - 1; j >= 0; --j) {
         const int t = t0 + j;
         if (t < T) {
-            const size_t i = (size_t)t * rows + r;
+            const uint32_t i = (uint32_t)t * nrows + r;
             const double rt = rw[j], v = vv[j];
             const double keep = (dmask >> j) & 1u ? 0.0 : 1.0;
             a = (rt + gamma * keep * v_next - v) + gl * keep * a;
@@ -294,17 +303,22 @@ hipError_t launch_returns(const float* reward, const float* value, const uint8_t
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     // the segmented form while one chain per row leaves the set latency-bound
-    // (below one 64-row wave per CU); with more rows the row form streams faster
-    if (rows >= (int64_t)kRowsPerLaneMin * cus && rows < (int64_t)64 * cus && horizon > kSeg &&
-        horizon <= kSeg * kSegMax) {
+    // (below one 64-row wave per CU), for horizons of 33 to 512 steps (to 256
+    // from 24 rows per CU up, where the row form is as fast beyond); with more
+    // rows the row form streams faster, and the time-parallel scan takes the
+    // rest (short or very long horizons on few rows)
+    const bool seg_rows = rows < (int64_t)64 * cus;
+    const int nseg = (horizon + kSeg - 1) / kSeg;
+    if (seg_rows && horizon > kSeg && nseg <= kSegMax && rows * horizon < ((int64_t)1 << 31) &&
+        (rows >= (int64_t)kRowsPerLaneMin * cus ? nseg <= 8 : true)) {
         const unsigned blocks = (unsigned)((rows + 63) / 64);
-        const int nseg = (horizon + kSeg - 1) / kSeg;
+        const dim3 grid(blocks), block(64 * nseg);
         if (out_f64)
-            hipLaunchKernelGGL(k_returns_seg<1>, dim3(blocks), dim3(64 * nseg), 0, s, reward, value,
-                               done, last_value, horizon, rows, gamma, lambda, bootstrap, ret, adv);
+            hipLaunchKernelGGL(k_returns_seg<1>, grid, block, 0, s, reward, value, done,
+                               last_value, horizon, rows, gamma, lambda, bootstrap, ret, adv);
         else
-            hipLaunchKernelGGL(k_returns_seg<0>, dim3(blocks), dim3(64 * nseg), 0, s, reward, value,
-                               done, last_value, horizon, rows, gamma, lambda, bootstrap, ret, adv);
+            hipLaunchKernelGGL(k_returns_seg<0>, grid, block, 0, s, reward, value, done,
+                               last_value, horizon, rows, gamma, lambda, bootstrap, ret, adv);
         return hipGetLastError();
     }
     if (rows >= (int64_t)kRowsPerLaneMin * cus) {

@@ -108,7 +108,10 @@ def test_policy_forward_matches_oracle(kind, rows):
                                     # row-parallel kernel (>= 24 rows per CU), including
                                     # horizons just past one and sixteen 16-step blocks
                                     (3, 10000), (70, 12001), (200, 10000), (33, 8000),
-                                    (256, 6500), (257, 7000)])
+                                    (256, 6500), (257, 7000),
+                                    # segmented kernel on few rows: up to sixteen
+                                    # 32-step segments, then the scan past 512 steps
+                                    (500, 1000), (512, 65), (513, 70), (300, 6200)])
 @pytest.mark.parametrize("boot", [True, False])
 def test_returns_match_oracle(T, rows, boot):
     import torch
