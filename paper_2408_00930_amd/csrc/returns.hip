@@ -2,9 +2,9 @@
 // (arXiv 2408.00930, Sec. 3: actor-critic training consumes them; GAE of
 // Schulman et al. 2016).
 //
-// Three kernels, chosen by the set's shape in launch_returns. For sets with
-// few rows and horizons past 512 steps (or of at most 32), a time-parallel
-// scan: both recursions are affine maps run backwards in time,
+// Four kernels, chosen by the set's shape in launch_returns. For sets with
+// few rows and horizons of at most 32 steps, a time-parallel scan: both
+// recursions are affine maps run backwards in time,
 //   A_t = delta_t + gamma lambda (1 - d_t) A_{t+1},  G_t = r_t + gamma (1 - d_t) G_{t+1},
 // so a block of consecutive steps composes into one map x -> b + c x with
 // (c1, b1) o (c2, b2) = (c1 c2, b1 + c1 b2). A workgroup owns 32 rows and
@@ -295,6 +295,110 @@ k_returns_seg(const float* __restrict__ reward, const float* __restrict__ value,
     }
 }
 
+// Long horizons (past 512 steps): the same with segments of nsub blocks of
+// kSegL steps. Each block is loaded into registers in the first pass and
+// again (from L2) in the second, so a lane's registers hold one block
+// whatever the segment's length (half the short form's block, as the running
+// maps stay live across the loads).
+constexpr int kSegL = 16;   // steps per block of the long form
+
+template <int OUT_F64>
+__global__ void __attribute__((amdgpu_flat_work_group_size(64, 64 * kSegMax)))
+k_returns_seg_long(const float* __restrict__ reward, const float* __restrict__ value,
+                   const uint8_t* __restrict__ done, const float* __restrict__ last_value, int T,
+                   int nsub, int64_t rows, double gamma, double lambda, int bootstrap,
+                   void* __restrict__ ret, void* __restrict__ adv) {
+    __shared__ double maps[4][kSegMax][64];   // cg, bg, ca, ba per segment and row
+    // Element offsets fit 32 bits (the launcher takes this form only while
+    // rows x T < 2^31). The segment index is wave-uniform: held in a scalar
+    // register it keeps each step's offset scalar, so a lane holds one vector
+    // offset (its row) instead of one per step.
+    const int lane = threadIdx.x & 63, nseg = blockDim.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t nrows = (uint32_t)rows;
+    const uint32_t r = blockIdx.x * 64u + (uint32_t)lane;
+    const bool ok = r < nrows;
+    const uint32_t rl = ok ? r : nrows - 1;   // a row inside the set, for the loads
+    const double gl = gamma * lambda;
+    // this wave's steps ts .. te - 1: nsub blocks of kSegL steps (ts below T)
+    const int ts = w * kSegL * nsub, te = min(ts + kSegL * nsub, T);
+    float rw[kSegL], vv[kSegL];
+    uint32_t dmask = 0;   // bit j: step t0 + j terminated (j < 16)
+    auto load = [&](int t0) {
+        dmask = 0;
+#pragma unroll
+        for (int j = 0; j < kSegL; ++j)
+            dmask |= (uint32_t)(done[(uint32_t)min(t0 + j, T - 1) * nrows + rl] != 0) << j;
+#pragma unroll
+        for (int j = 0; j < kSegL; ++j) {
+            const uint32_t i = (uint32_t)min(t0 + j, T - 1) * nrows + rl;
+            rw[j] = reward[i];
+            vv[j] = value[i];
+        }
+    };
+    const double v_T = bootstrap ? (double)last_value[rl] : 0.0;
+    // V at the segment's end: the next segment's first value, or V(s_T)
+    const double v_end = te < T ? (double)value[(uint32_t)te * nrows + rl] : v_T;
+    double cg = 1.0, bg = 0.0, ca = 1.0, ba = 0.0, v_next = v_end;
+    // the segment's map, composed backwards block by block
+#pragma nounroll
+    for (int b = nsub - 1; b >= 0; --b) {
+        const int t0 = ts + b * kSegL;
+        if (t0 >= te) continue;
+        load(t0);
+#pragma unroll
+        for (int j = kSegL - 1; j >= 0; --j) {
+            if (t0 + j < te) {
+                const double rt = rw[j], v = vv[j];
+                const double keep = (dmask >> j) & 1u ? 0.0 : 1.0;
+                ba = (rt + gamma * keep * v_next - v) + gl * keep * ba;
+                ca = gl * keep * ca;
+                bg = rt + gamma * keep * bg;
+                cg = gamma * keep * cg;
+                v_next = v;
+            }
+        }
+    }
+    maps[0][w][lane] = cg;
+    maps[1][w][lane] = bg;
+    maps[2][w][lane] = ca;
+    maps[3][w][lane] = ba;
+    __syncthreads();
+    // carry into this segment: the later segments' maps applied to (G_T, A_T)
+    double g = v_T, a = 0.0;
+    for (int k = nseg - 1; k > w; --k) {
+        g = maps[1][k][lane] + maps[0][k][lane] * g;
+        a = maps[3][k][lane] + maps[2][k][lane] * a;
+    }
+    if (!ok) return;
+    v_next = v_end;
+#pragma nounroll
+    for (int b = nsub - 1; b >= 0; --b) {
+        const int t0 = ts + b * kSegL;
+        if (t0 >= te) continue;
+        load(t0);   // again: an L2 hit
+#pragma unroll
+        for (int j = kSegL - 1; j >= 0; --j) {
+            const int t = t0 + j;
+            if (t < te) {
+                const uint32_t i = (uint32_t)t * nrows + r;
+                const double rt = rw[j], v = vv[j];
+                const double keep = (dmask >> j) & 1u ? 0.0 : 1.0;
+                a = (rt + gamma * keep * v_next - v) + gl * keep * a;
+                g = rt + gamma * keep * g;
+                v_next = v;
+                if (OUT_F64) {
+                    static_cast<double*>(ret)[i] = g;
+                    static_cast<double*>(adv)[i] = a;
+                } else {
+                    static_cast<float*>(ret)[i] = (float)g;
+                    static_cast<float*>(adv)[i] = (float)a;
+                }
+            }
+        }
+    }
+}
+
 hipError_t launch_returns(const float* reward, const float* value, const uint8_t* done,
                           const float* last_value, int horizon, int64_t rows, double gamma,
                           double lambda, int bootstrap, void* ret, void* adv, int out_f64,
@@ -302,23 +406,31 @@ hipError_t launch_returns(const float* reward, const float* value, const uint8_t
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    // the segmented form while one chain per row leaves the set latency-bound
-    // (below one 64-row wave per CU), for horizons of 33 to 512 steps (to 256
-    // from 24 rows per CU up, where the row form is as fast beyond); with more
-    // rows the row form streams faster, and the time-parallel scan takes the
-    // rest (short or very long horizons on few rows)
-    const bool seg_rows = rows < (int64_t)64 * cus;
-    const int nseg = (horizon + kSeg - 1) / kSeg;
-    if (seg_rows && horizon > kSeg && nseg <= kSegMax && rows * horizon < ((int64_t)1 << 31) &&
-        (rows >= (int64_t)kRowsPerLaneMin * cus ? nseg <= 8 : true)) {
-        const unsigned blocks = (unsigned)((rows + 63) / 64);
-        const dim3 grid(blocks), block(64 * nseg);
-        if (out_f64)
-            hipLaunchKernelGGL(k_returns_seg<1>, grid, block, 0, s, reward, value, done,
-                               last_value, horizon, rows, gamma, lambda, bootstrap, ret, adv);
-        else
-            hipLaunchKernelGGL(k_returns_seg<0>, grid, block, 0, s, reward, value, done,
-                               last_value, horizon, rows, gamma, lambda, bootstrap, ret, adv);
+    // the segmented forms while one chain per row leaves the set latency-bound
+    // (below one 64-row wave per CU): up to 16 segments of one 32-step block,
+    // past 512 steps up to 16 segments of nsub 16-step blocks. From 24 rows
+    // per CU up they are kept to horizons of 8 segments, past which the row
+    // form is as fast; with more rows the row form streams faster, and the
+    // time-parallel scan takes the rest (horizons within one block, or
+    // offsets past 32 bits)
+    const int64_t nblk = ((int64_t)horizon + kSeg - 1) / kSeg;
+    const bool many = rows >= (int64_t)kRowsPerLaneMin * cus;
+    if (rows < (int64_t)64 * cus && horizon > kSeg && rows * horizon < ((int64_t)1 << 31) &&
+        (!many || nblk <= 8)) {
+        const dim3 grid((unsigned)((rows + 63) / 64));
+        if (nblk > kSegMax) {
+            const int64_t nb16 = ((int64_t)horizon + kSegL - 1) / kSegL;
+            const int nsub = (int)((nb16 + kSegMax - 1) / kSegMax);
+            const dim3 block(64 * (int)((nb16 + nsub - 1) / nsub));
+            auto* k = out_f64 ? k_returns_seg_long<1> : k_returns_seg_long<0>;
+            hipLaunchKernelGGL(k, grid, block, 0, s, reward, value, done, last_value, horizon,
+                               nsub, rows, gamma, lambda, bootstrap, ret, adv);
+        } else {
+            const dim3 block(64 * (int)nblk);
+            auto* k = out_f64 ? k_returns_seg<1> : k_returns_seg<0>;
+            hipLaunchKernelGGL(k, grid, block, 0, s, reward, value, done, last_value, horizon,
+                               rows, gamma, lambda, bootstrap, ret, adv);
+        }
         return hipGetLastError();
     }
     if (rows >= (int64_t)kRowsPerLaneMin * cus) {

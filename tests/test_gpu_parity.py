@@ -110,8 +110,10 @@ def test_policy_forward_matches_oracle(kind, rows):
                                     (3, 10000), (70, 12001), (200, 10000), (33, 8000),
                                     (256, 6500), (257, 7000),
                                     # segmented kernel on few rows: up to sixteen
-                                    # 32-step segments, then the scan past 512 steps
-                                    (500, 1000), (512, 65), (513, 70), (300, 6200)])
+                                    # one-block segments, then segments of several
+                                    # 32-step blocks past 512 steps
+                                    (500, 1000), (512, 65), (513, 70), (300, 6200),
+                                    (1000, 4096), (4000, 130)])
 @pytest.mark.parametrize("boot", [True, False])
 def test_returns_match_oracle(T, rows, boot):
     import torch
