@@ -11,6 +11,7 @@ with the kernel shape chosen by the library's autotuner. Prints one JSON line.
 """
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -154,16 +155,24 @@ def sweep(kind_key, counts, steps, wsx, inputs, torch):
         del env, tr, ret, adv, ws, g
 
 
-def kernel_source_hash():
-    """Hash of the device-code sources (.hip and .h under csrc/): counter
-    figures taken on other kernel code are not reported."""
+def strip_comments(text):
+    """C/C++ source without its comments and with whitespace runs collapsed,
+    so that a change to comments alone keeps the hash below."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def kernel_source_hash(csrc=None):
+    """Hash of the device-code sources (.hip and .h under csrc/, comments
+    left out): counter figures taken on other kernel code are not reported."""
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2408_00930_amd", "csrc")
+    csrc = csrc or os.path.join(ROOT, "paper_2408_00930_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
         if not name.endswith((".hip", ".h")):
             continue
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode() + f.read())
+        with open(os.path.join(csrc, name), encoding="utf-8") as f:
+            h.update(name.encode() + strip_comments(f.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -24,6 +24,7 @@ namespace wsx {
 constexpr int kRetRows = 32;   // rows per workgroup (128-byte rows of float)
 constexpr int kRetSteps = 64;  // steps per tile = lanes of a wave
 // sets with at least this many rows per CU take the row-parallel kernel
+// unless their horizon fits eight one-block segments
 constexpr int kRowsPerLaneMin = 24;
 
 __global__ void __launch_bounds__(256)

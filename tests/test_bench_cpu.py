@@ -43,3 +43,15 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=300)
     assert r.returncode != 0
     assert "--gpus 1" in r.stderr
+
+
+def test_source_hash_ignores_comments_only(tmp_path):
+    """Profile figures stay valid across comment edits, not code edits."""
+    assert bench.strip_comments("a = 1; // x\n/* y\n z */ b  =\n2;") == "a = 1; b = 2;"
+    (tmp_path / "k.hip").write_text("int f() { return 1; } // one\n")
+    (tmp_path / "notes.txt").write_text("not device code")
+    h0 = bench.kernel_source_hash(str(tmp_path))
+    (tmp_path / "k.hip").write_text("/* the first */\nint f() {\n  return 1;  // still one\n}\n")
+    assert bench.kernel_source_hash(str(tmp_path)) == h0
+    (tmp_path / "k.hip").write_text("int f() { return 2; }\n")
+    assert bench.kernel_source_hash(str(tmp_path)) != h0
