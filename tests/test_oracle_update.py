@@ -159,3 +159,16 @@ def test_adam_first_step_closed_form():
     want = theta - 1e-3 * (m_w / (1 - 0.9 ** 2)) / (np.sqrt(v_w / (1 - 0.999 ** 2)) + 1e-8)
     O.adam(theta, g2, m, v, 2, 1e-3, 0.9, 0.999, 1e-8)
     assert np.allclose(theta, want, rtol=1e-14, atol=1e-16)
+
+
+def test_adam_constant_gradient_steps_by_lr():
+    """With a constant gradient the bias-corrected moments are g and g^2 at
+    every step, so (eps = 0) each step moves every weight by lr * sign(g)."""
+    rng = np.random.default_rng(12)
+    g = rng.normal(0, 1, 40)
+    theta = rng.normal(0, 1, 40)
+    m, v = np.zeros(40), np.zeros(40)
+    t0 = theta.copy()
+    for t in range(1, 26):
+        O.adam(theta, g, m, v, t, 2e-3, 0.8, 0.99, 0.0)
+        assert np.allclose(theta, t0 - 2e-3 * t * np.sign(g), rtol=0, atol=1e-12), t
