@@ -506,8 +506,10 @@ def unit_busy_for(kernel_name):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    # 20 untimed steps bring the GPU to its sustained clock (after 3, launches
+    # still ran ~6 % slower); 50 timed steps are ~55 ms of GPU work
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--workload", default="pendulum_acrobot_10k", choices=sorted(WORKLOADS))
     ap.add_argument("--tile-rows", type=int, default=0)
