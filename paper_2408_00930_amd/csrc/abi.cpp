@@ -67,8 +67,8 @@ Layout layout_of(const KindInfo& k, int64_t n_envs, int64_t n_rows, bool market)
     if (market) at = align256(at + (size_t)(n_envs + 1) * 4);
     L.tiles = at;
     if (market) at = align256(at + (size_t)n_envs * sizeof(Tile));
-    L.step = at;
-    at = align256(at + 4);
+    L.step = at;   // [step counter, epoch] for graph replays
+    at = align256(at + 8);
     L.total = at;
     return L;
 }
@@ -421,8 +421,9 @@ int wsx_rollout(wsx_env* env, const wsx_policy* policy, int32_t horizon, const w
     } else if (mode == WSX_MODE_PLAIN) {
         e = launch_plain(v, ea, pa, ta, horizon, false, s);
     } else if (mode == WSX_MODE_GRAPH || mode == WSX_MODE_FUSED_GRAPH) {
-        // the launches read the step counter from the state block, so one
-        // captured graph serves every call with the same buffers and horizon
+        // the launches read the step counter and the epoch from the state
+        // block, so one captured graph serves every call with the same
+        // buffers and horizon
         EnvArgs ga = ea;
         ga.step_ptr = reinterpret_cast<const uint32_t*>(env->block + env->lay.step);
         ga.t0 = 0;
@@ -464,7 +465,7 @@ int wsx_rollout(wsx_env* env, const wsx_policy* policy, int32_t horizon, const w
             if (e != hipSuccess) return hip_fail(e, "wsx_rollout (capture)");
             env->graph_key = key;
         }
-        e = launch_set_step(const_cast<uint32_t*>(ga.step_ptr), (int)env->step, s);
+        e = launch_set_step(const_cast<uint32_t*>(ga.step_ptr), env->step, env->epoch, s);
         if (e == hipSuccess) e = hipGraphLaunch(env->graph, s);
     } else {
         return fail(WSX_EINVAL, "unknown mode %d", mode);

@@ -48,7 +48,7 @@ struct EnvArgs {
     const float* params;      // reaction potential block (global)
     const int32_t* offsets;   // market CSR offsets [n_envs + 1]
     const Tile* tiles;        // tile table [n_tiles]
-    const uint32_t* step_ptr; // graph mode: device copy of the step counter
+    const uint32_t* step_ptr; // graph mode: device copy of [step counter, epoch]
     int64_t n_rows;
     int32_t n_envs;
     int32_t n_tiles;
@@ -156,7 +156,7 @@ hipError_t launch_fused(const Variant& v, const Batch& batch, int grid, hipStrea
 hipError_t launch_plain(const Variant& v, const EnvArgs& env, const PolicyArgs& pol,
                         const TrajArgs& tr, int horizon, bool counter_from_device,
                         hipStream_t s);
-hipError_t launch_set_step(uint32_t* step_ptr, int value, hipStream_t s);
+hipError_t launch_set_step(uint32_t* step_ptr, uint32_t step, uint32_t epoch, hipStream_t s);
 hipError_t launch_policy_forward(const Variant& v, const PolicyArgs& pol, const float* obs,
                                  int64_t rows, float* head, hipStream_t s);
 hipError_t launch_quantize(int dtype, float scale, const float* x, float* y, int64_t n,

@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(256) k_plain_sample(EnvArgs env, PolicyArgs po
     for (int c = 0; c < C; ++c)
         hb[c] = j0 + c < HO::NOUT ? env.head_scratch[row * HO::NH + j0 + c] : 0.0f;
     const float hv = env.head_scratch[row * HO::NH + HO::NOUT];
-    const RngKey key{env.k0, env.k1, env.epoch};
+    const RngKey key = rng_key(env);
     const uint32_t t = step_base(env) + (uint32_t)step;
     const float log_std = (E::NACT == 0 && pol.log_std) ? pol.log_std[0] : 0.0f;
     float logp;
@@ -116,7 +116,7 @@ __global__ void __launch_bounds__(256) k_plain_step(EnvArgs env, TrajArgs tr, in
     const int sub = threadIdx.x % G;
     const int64_t row = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
     if (row >= env.n_rows) return;
-    const RngKey key{env.k0, env.k1, env.epoch};
+    const RngKey key = rng_key(env);
     const uint32_t t = step_base(env) + (uint32_t)step;
     float s[E::SR];
     load_state<E>(env, row, s);
@@ -177,7 +177,12 @@ __global__ void k_plain_last(EnvArgs env, TrajArgs tr) {
     tr.last_value[row] = env.head_scratch[row * HO::NH + HO::NOUT];
 }
 
-__global__ void k_set_step(uint32_t* p, uint32_t v) { *p = v; }
+// The device copy of the step counter and the reset epoch that graph-captured
+// launches read.
+__global__ void k_set_step(uint32_t* p, uint32_t step, uint32_t epoch) {
+    p[0] = step;
+    p[1] = epoch;
+}
 
 // -------------------------------------------------------- small kernels --
 __global__ void k_quantize(int dtype, float scale, const float* x, float* y, int64_t n) {
@@ -342,8 +347,8 @@ hipError_t launch_plain(const Variant& v, const EnvArgs& env, const PolicyArgs& 
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_set_step(uint32_t* step_ptr, int value, hipStream_t s) {
-    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, s, step_ptr, (uint32_t)value);
+hipError_t launch_set_step(uint32_t* step_ptr, uint32_t step, uint32_t epoch, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, s, step_ptr, step, epoch);
     return hipGetLastError();
 }
 

@@ -639,7 +639,14 @@ constexpr int extra_lds_bytes(int R) {
 }
 
 __device__ __forceinline__ uint32_t step_base(const EnvArgs& env) {
-    return env.step_ptr ? *env.step_ptr + env.t0 : env.t0;
+    return env.step_ptr ? env.step_ptr[0] + env.t0 : env.t0;
+}
+
+// The random-stream key of a launch; a graph-captured launch reads the reset
+// epoch from the device copy beside the step counter, so one captured graph
+// serves every epoch.
+__device__ __forceinline__ RngKey rng_key(const EnvArgs& env) {
+    return RngKey{env.k0, env.k1, env.step_ptr ? env.step_ptr[1] : env.epoch};
 }
 
 __device__ __forceinline__ Tile tile_of(const EnvArgs& env, int tile) {
@@ -758,7 +765,7 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
     const EnvArgs env = uniform(sg.env);
     const TrajArgs tr = uniform(sg.tr);
     const int horizon = __builtin_amdgcn_readfirstlane(sg.steps);
-    const RngKey key{env.k0, env.k1, env.epoch};
+    const RngKey key = rng_key(env);
     const uint32_t t0 = step_base(env);
     if constexpr (E::KIND == Reaction::KIND) {
         if (env.params != staged) {   // uniform over the workgroup

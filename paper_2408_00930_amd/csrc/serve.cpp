@@ -220,6 +220,11 @@ bool try_admit(wsx_server* S, Request* r) {
     if (fresh) {
         wsx_env_desc d{};
         d.kind = r->req.kind;
+        // every session of a kind runs the kind's built-in kernel shape (not
+        // an autotuner entry for its size), so that one launch covers them all
+        d.tile_rows = k.tile_rows;
+        d.waves = k.waves;
+        d.occupancy = k.occupancy;
         d.n_envs = r->req.n_envs;
         d.seed = r->req.seed;
         d.state = S->arena.at(soff);
@@ -297,12 +302,14 @@ bool admit(wsx_server* S) {
     return any;
 }
 
+void fail_request(wsx_server* S, Request* r, int code) {
+    r->status = code;
+    r->t_done = Clock::now();
+    S->sessions[r->session].busy = false;
+}
+
 void fail_group(wsx_server* S, Group& g, int code) {
-    for (auto& m : g.members) {
-        Request* r = S->requests[m.first].get();
-        r->status = code;
-        S->sessions[r->session].busy = false;
-    }
+    for (auto& m : g.members) fail_request(S, S->requests[m.first].get(), code);
     g.members.clear();
     g.inflight = false;
     S->cv_done.notify_all();
@@ -321,14 +328,22 @@ bool launch_rounds(wsx_server* S) {
             if ((int)batch.size() == S->desc.max_batch) break;
         }
         if (batch.empty()) continue;
-        int32_t tiles = 0;
+        // one kernel for the round: the waves and occupancy the sessions share
+        // and the row capacity of the tallest tile among them
+        const wsx_env* first = S->sessions[batch[0]->session].env;
+        int tile_max = 0;
+        for (Request* r : batch) tile_max = std::max(tile_max, S->sessions[r->session].env->tile_rows);
         Variant v{};
+        if (!find_variant(first->kind, batch[0]->policy.dtype, batch[0]->policy.h1, first->waves,
+                          tile_max, first->occupancy, v)) {
+            for (Request* r : batch) fail_request(S, r, WSX_EUNSUPPORTED);
+            S->cv_done.notify_all();
+            continue;
+        }
+        int32_t tiles = 0;
         for (size_t i = 0; i < batch.size(); ++i) {
             Request* r = batch[i];
             wsx_env* env = S->sessions[r->session].env;
-            if (i == 0)
-                find_variant(env->kind, r->policy.dtype, r->policy.h1, env->waves, env->tile_rows,
-                             env->occupancy, v);
             const int32_t steps = std::min(S->desc.chunk_steps, r->req.horizon - r->issued);
             const size_t base = (size_t)r->issued * (size_t)r->rows;
             Segment sg{};
@@ -391,8 +406,11 @@ bool poll(wsx_server* S) {
                                               g.stream);
                 if (e == hipSuccess) e = hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming);
                 if (e == hipSuccess) e = hipEventRecord(r->done_ev, g.stream);
-                if (e != hipSuccess) r->status = WSX_EHIP;
                 r->returns_issued = true;
+                if (e != hipSuccess) {
+                    fail_request(S, r, WSX_EHIP);
+                    S->cv_done.notify_all();
+                }
             }
         }
         g.members.clear();

@@ -370,6 +370,30 @@ def test_fused_graph_chunks_equal_fused_bitwise(kind, n, chunk):
         torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("kind,n", [(O.CARTPOLE, 70), (O.PENDULUM, 90), (O.MARKET, 7)])
+@pytest.mark.parametrize("mode_name", ["MODE_GRAPH", "MODE_FUSED_GRAPH"])
+def test_graph_replays_follow_the_reset_epoch(kind, n, mode_name):
+    """A graph captured after a reset with one epoch and replayed into the same
+    buffers after resets with other epochs draws from the new epoch's streams:
+    every replay equals the fused launch of that epoch."""
+    wsx = _wsx()
+    c = Case(kind, n, seed=12)
+    mode = getattr(wsx, mode_name)
+    T = 7
+    want = {e: _run(c, wsx.MODE_FUSED, T, epoch=e) for e in (1, 2, 5)}
+    assert not np.array_equal(want[1]["obs"], want[2]["obs"])
+    c.env.set_chunk(3)
+    traj = wsx.Trajectory(kind, T, c.rows)
+    for epoch in (1, 2, 5, 1):
+        say("graph replay epoch", kind, mode_name, epoch)
+        wsx.env_reset(c.env, epoch)
+        wsx.rollout(c.env, c.dpol, T, traj, mode)
+        g = traj.host()
+        g["state"] = c.gpu_state()
+        for k in want[epoch]:
+            assert np.array_equal(want[epoch][k], g[k]), (epoch, k)
+
+
 def test_fused_graph_horizon_zero_and_rejects_negative_chunk():
     wsx = _wsx()
     c = Case(O.PENDULUM, 40, seed=2)

@@ -40,13 +40,21 @@ def _host(view):
     return {k: v.cpu().numpy() for k, v in view.items()}
 
 
+# the built-in kernel shape (tile rows, waves, occupancy) every server
+# session of a kind runs with
+DEFAULT_SHAPE = {2: (80, 8, 2), 3: (80, 8, 2), 4: (128, 4, 1), 5: (16, 8, 2)}
+
+
 def _direct(fx, spec):
-    """The same roll-out through wsx_rollout and wsx_compute_returns."""
+    """The same roll-out through wsx_rollout and wsx_compute_returns, on the
+    kernel shape the server runs."""
     import torch
     wsx = _wsx()
     kind = spec["kind"]
+    rows, waves, occ = DEFAULT_SHAPE[kind]
     env = wsx.Env(kind, spec["n_envs"], seed=spec["seed"], agent_offsets=spec.get("agent_offsets"),
-                  params=None if kind != 5 else inputs.reaction_params(1))
+                  params=None if kind != 5 else inputs.reaction_params(1), tile_rows=rows,
+                  waves=waves, occupancy=occ)
     traj = wsx.Trajectory(kind, spec["horizon"], env.rows)
     wsx.env_reset(env, spec["epoch"])
     wsx.rollout(env, spec["policy"], spec["horizon"], traj)
@@ -163,4 +171,26 @@ def test_request_larger_than_arena_is_rejected():
     srv = wsx.Server(1 << 22, chunk_steps=20)
     with pytest.raises(wsx.WsxError):
         srv.submit(**fx.spec(2, 100000, 500, seed=1))
+    srv.close()
+
+
+def test_sizes_with_an_autotuner_entry_mix_with_others():
+    """A request whose size has an autotuner entry (a tile shape other than
+    the default) shares rounds with requests of other sizes; every result
+    still equals its direct roll-out on the kind's built-in shape."""
+    wsx = _wsx()
+    fx = Fixture()
+    kind, n_tuned = 2, 333
+    say("serve tuned size in a mix")
+    best = wsx.autotune(kind, n_tuned, fx.pol[kind], horizon=8, reps=1, seed=3)
+    print("tuned", best, flush=True)
+    specs = [fx.spec(kind, n_tuned, 40, seed=21), fx.spec(kind, 70, 30, seed=22),
+             fx.spec(kind, 1000, 35, seed=23), fx.spec(kind, n_tuned, 20, seed=24)]
+    srv = wsx.Server(1 << 30, chunk_steps=10, max_batch=16)
+    ids = [srv.submit(**x) for x in specs]
+    for x, rid in zip(specs, ids):
+        r = srv.wait(rid, 60000)
+        got = _host(srv.view(r, kind))
+        _equal(got, _direct(fx, x))
+        srv.release(rid)
     srv.close()

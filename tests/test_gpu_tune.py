@@ -61,16 +61,12 @@ def test_autotune_batch_records_one_shape_for_the_mix():
     T = 10
     trs = [wsx.Trajectory(e.kind, T, e.rows) for e in envs]
     for e in envs:
-        wsx.env_reset(e, 2)
+        wsx.env_reset(e, 1)
     wsx.rollout_batch(envs, [pols[2], pols[3]], T, trs)
     for e, tr, d in zip(envs, trs, spec):
+        # the batched launch equals each set's own launch on the same shape
         ref = _roll(wsx, wsx.Env(d["kind"], d["n_envs"], seed=d["seed"]), pols[d["kind"]],
                     d["kind"], T)
-        # _roll resets with epoch 1; redo ours with the same epoch for the comparison
-        wsx.env_reset(e, 1)
-        mine = wsx.Trajectory(e.kind, T, e.rows)
-        wsx.rollout(e, pols[d["kind"]], T, mine)
-        got = mine.host()
+        got = tr.host()
         for k in got:
             assert np.array_equal(got[k], ref[k]), k
-        assert np.isfinite(tr.host()["value"]).all()
