@@ -195,6 +195,22 @@ int wsx_compute_returns(const float* reward, const float* value, const uint8_t* 
 int wsx_policy_forward(const wsx_policy* policy, const float* obs, int64_t rows,
                        float* head, void* stream);
 
+/* Policy forward with the kernel of an environment set's roll-out (the same
+ * weight split over waves and the same FP32 accumulation order as that set's
+ * fused and plain launches, App. B's action inference), for `rows`
+ * observations [rows][d_in] float: head outputs [rows][n_head] float, and the
+ * quantised outputs of both hidden layers -- the inputs of the second and
+ * third products -- as codes of the policy format, [rows][hidden] each:
+ * bfloat16 (2 bytes), OCP E4M3 (1 byte; the value is code x act_scale[1] or
+ * act_scale[2]) or float (FP32 policies). Lets a checker adopt the rounding
+ * decisions the FP32 accumulation took next to a rounding midpoint and test
+ * every other result tightly. act1 / act2 / head: caller-owned device
+ * buffers. Built-in kinds only. Errors: WSX_EINVAL (NULL pointers, rows out
+ * of range, policy shape not the set's), WSX_EUNSUPPORTED (user kinds),
+ * WSX_EHIP. */
+int wsx_policy_trace(const wsx_env* env, const wsx_policy* policy, const float* obs,
+                     int64_t rows, float* head, void* act1, void* act2, void* stream);
+
 /* Rounds n floats to `dtype` (WSX_BF16: RNE; WSX_FP8_E4M3: s * fp8(x / s),
  * RNE, saturating) with the device conversion the kernels use and returns
  * the real values as float. */

@@ -86,9 +86,13 @@ def _declare(L):
         getattr(L, name).argtypes = [C.c_double]
         getattr(L, name).restype = C.c_double
     L.orc_mlp_forward.argtypes = [C.POINTER(_Mlp), dp, dp]
+    L.orc_mlp_adopt.argtypes = [C.POINTER(_Mlp), C.c_int64, dp, dp, dp, dp, dp,
+                                C.POINTER(C.c_int32), dp]
     L.orc_sample_categorical.argtypes = [dp, C.c_int, C.c_double, dp, dp]
     L.orc_sample_categorical.restype = C.c_int
     L.orc_sample_gaussian.argtypes = [dp, dp, dp, C.c_int, dp, dp]
+    L.orc_sample_rows.argtypes = [C.c_int64, C.c_int, C.c_int, dp, dp, C.c_uint64, C.c_uint32,
+                                  u32p, C.c_uint32, dp, dp, dp]
     for name in ("orc_state_dim", "orc_obs_dim", "orc_n_actions"):
         getattr(L, name).argtypes = [C.c_int]
         getattr(L, name).restype = C.c_int
@@ -114,6 +118,9 @@ def _declare(L):
     L.orc_rollout.argtypes = [C.POINTER(_Env), C.POINTER(_Mlp), dp, C.c_uint64, C.c_uint32,
                               C.c_uint32, C.c_int32, dp, C.POINTER(_Traj)]
     L.orc_rollout.restype = C.c_int
+    L.orc_cartpole_rollout_f32.argtypes = [C.POINTER(_Mlp), C.c_int64, C.c_uint64, C.c_uint32,
+                                           C.c_uint32, C.c_int32, dp, dp, dp]
+    L.orc_cartpole_rollout_f32.restype = C.c_int
     for name in ("orc_returns_gae", "orc_gae_bruteforce"):
         getattr(L, name).argtypes = [C.c_int32, C.c_int64, dp, dp, C.c_void_p, dp,
                                      C.c_double, C.c_double, C.c_int32, dp, dp]
@@ -209,11 +216,58 @@ def mlp_forward(policy, obs):
     return out
 
 
+U32 = 2.0 ** -24
+
+
+def fp32_sum_bound(n_terms, abs_sum):
+    """gamma_n * S: the bound of an FP32 sum of n terms whose magnitudes add
+    up to S, in any order (Higham, Sec. 3.1)."""
+    g = n_terms * U32 / (1.0 - n_terms * U32)
+    return g * np.asarray(abs_sum)
+
+
+def mlp_adopt(policy, obs, codes1, codes2):
+    """Evaluate the policy from a device run's hidden-layer codes.
+
+    obs [n, d_in] (the device's FP32 observations), codes1 [n, h1] and
+    codes2 [n, h2] (real values of its quantised hidden outputs). Returns a
+    dict: head [n, n_head] (FP64 from codes2), head_bound [n, n_head] (the
+    error bound of the device's FP32 head), flips [n, 2] (codes that differ
+    from the oracle's rounding, per layer) and ratio [n, 2] (the largest
+    distance to the deciding midpoint in units of the activation's error
+    bound; <= 1 for a legitimate flip)."""
+    h = mlp_hold(policy) if not isinstance(policy, _MlpHold) else policy
+    s = h.s
+    obs = _f64(np.atleast_2d(obs))
+    n = obs.shape[0]
+    c1, c2 = _f64(codes1).reshape(n, s.h1), _f64(codes2).reshape(n, s.h2)
+    out = {"head": np.zeros((n, s.n_head)), "head_bound": np.zeros((n, s.n_head)),
+           "flips": np.zeros((n, 2), np.int32), "ratio": np.zeros((n, 2))}
+    lib().orc_mlp_adopt(C.byref(s), n, _ptr(obs), _ptr(c1), _ptr(c2), _ptr(out["head"]),
+                        _ptr(out["head_bound"]), _ptr(out["flips"], C.c_int32),
+                        _ptr(out["ratio"]))
+    return out
+
+
 def sample_categorical(logits, u):
     lg = _f64(logits)
     lp, mg = C.c_double(), C.c_double()
     a = lib().orc_sample_categorical(_ptr(lg), lg.size, float(u), C.byref(lp), C.byref(mg))
     return a, lp.value, mg.value
+
+
+def sample_rows(head, n_act, log_std, seed, t, rows, epoch):
+    """Draws of the given rows at step t from their heads [n, n_head]:
+    (action, logp, margin) arrays, margin = distance to the nearest CDF
+    boundary (inf for Gaussian heads)."""
+    h = _f64(np.atleast_2d(head))
+    n, nh = h.shape
+    r = np.ascontiguousarray(rows, dtype=np.uint32)
+    ls = _f64(log_std if log_std is not None else np.zeros(1))
+    a, lp, mg = np.zeros(n), np.zeros(n), np.zeros(n)
+    lib().orc_sample_rows(n, nh, int(n_act), _ptr(h), _ptr(ls), seed, t,
+                          _ptr(r, C.c_uint32), epoch, _ptr(a), _ptr(lp), _ptr(mg))
+    return a, lp, mg
 
 
 def sample_gaussian(mu, log_std, z):
@@ -357,6 +411,21 @@ def rollout(env, policy, seed, epoch, t0, T, states, log_std=None, margins=True)
         raise ValueError(f"orc_rollout rejected its arguments (code {rc})")
     out["states"] = st
     return out
+
+
+def cartpole_rollout_f32(policy, seed, epoch, t0, T, states):
+    """The CartPole roll-out computed in FP32 throughout (the divergence
+    envelope beside the FP64 oracle): obs [T, n, 4] and action [T, n]."""
+    h = mlp_hold(policy) if not isinstance(policy, _MlpHold) else policy
+    st = _f64(states)
+    n = st.shape[0]
+    obs = np.zeros((T, n, 4))
+    act = np.zeros((T, n))
+    rc = lib().orc_cartpole_rollout_f32(C.byref(h.s), n, seed, epoch, t0, T, _ptr(st), _ptr(obs),
+                                        _ptr(act))
+    if rc != 0:
+        raise ValueError("not a CartPole FP32 policy")
+    return {"obs": obs, "action": act}
 
 
 # ------------------------------------------------------------ returns ----

@@ -583,6 +583,26 @@ int wsx_policy_forward(const wsx_policy* policy, const float* obs, int64_t rows,
     return WSX_OK;
 }
 
+int wsx_policy_trace(const wsx_env* env, const wsx_policy* policy, const float* obs,
+                     int64_t rows, float* head, void* act1, void* act2, void* stream) {
+    if (!env || !policy) return fail(WSX_EINVAL, "env or policy is NULL");
+    if (rows < 0 || rows > 0x7FFFFFFF) return fail(WSX_EINVAL, "rows out of range");
+    if (env->kind >= kUserKindBase)
+        return fail(WSX_EUNSUPPORTED, "no policy trace for user environment kinds");
+    int rc = check_policy(policy, env->info, env->kind);
+    if (rc) return rc;
+    if (rows == 0) return WSX_OK;
+    if (!obs || !head || !act1 || !act2) return fail(WSX_EINVAL, "a buffer pointer is NULL");
+    Variant v;
+    if (!find_variant(env->kind, env->info.dtype, env->info.hidden, env->waves, env->tile_rows,
+                      env->occupancy, v))
+        return fail(WSX_EUNSUPPORTED, "no compiled kernel for the set's shape");
+    const hipError_t e = launch_policy_trace(v, policy_args(policy), obs, rows, head, act1, act2,
+                                             static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "wsx_policy_trace");
+    return WSX_OK;
+}
+
 int wsx_quantize(int32_t dtype, float scale, const float* x, float* y, int64_t n, void* stream) {
     if (dtype != WSX_F32 && dtype != WSX_BF16 && dtype != WSX_FP8_E4M3)
         return fail(WSX_EINVAL, "unknown dtype %d", dtype);

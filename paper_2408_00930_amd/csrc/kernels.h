@@ -159,6 +159,8 @@ hipError_t launch_plain(const Variant& v, const EnvArgs& env, const PolicyArgs& 
 hipError_t launch_set_step(uint32_t* step_ptr, uint32_t step, uint32_t epoch, hipStream_t s);
 hipError_t launch_policy_forward(const Variant& v, const PolicyArgs& pol, const float* obs,
                                  int64_t rows, float* head, hipStream_t s);
+hipError_t launch_policy_trace(const Variant& v, const PolicyArgs& pol, const float* obs,
+                               int64_t rows, float* head, void* act1, void* act2, hipStream_t s);
 hipError_t launch_quantize(int dtype, float scale, const float* x, float* y, int64_t n,
                            hipStream_t s);
 hipError_t launch_returns(const float* reward, const float* value, const uint8_t* done,

@@ -23,12 +23,13 @@ __global__ void k_plain_observe(EnvArgs env, TrajArgs tr, int horizon) {
 }
 
 // Policy over one tile of rows per workgroup: obs_scratch -> head_scratch.
-template <class E, int DT, int H, int NW, int NT, int HS, int OCC>
-__global__ void __attribute__((amdgpu_flat_work_group_size(NW * 64, NW * 64),
-                               amdgpu_waves_per_eu(OCC)))
-k_plain_policy(EnvArgs env, PolicyArgs pol) {
+// TRACE also writes the quantised hidden-layer outputs ([rows][H] codes of the
+// policy format) to act1 / act2; the arithmetic is the fused kernel's.
+template <class E, int DT, int H, int NW, int NT, int HS, int OCC, bool TRACE>
+__device__ __forceinline__ void policy_tile(const EnvArgs& env, const PolicyArgs& pol, char* act1,
+                                            char* act2) {
     using HO = HeadOf<E>;
-    using L = Mlp<DT, H, NW, NT, kin_of<E, DT>(), HO::NHP, HS, OCC>;
+    using L = Mlp<DT, H, NW, NT, kin_of<E, DT>(), HO::NHP, HS, OCC, TRACE>;
     constexpr int R = L::R;
     __shared__ __attribute__((aligned(16))) char smem[L::BYTES];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -39,6 +40,11 @@ k_plain_policy(EnvArgs env, PolicyArgs pol) {
         reinterpret_cast<uint32_t*>(smem + L::OFF_IN)[i] = 0u;
     __syncthreads();
     const Tile tl = tile_of(env, blockIdx.x);
+    if constexpr (TRACE) {
+        mlp.tr_act[0] = act1 + (size_t)tl.row0 * H * L::EB;
+        mlp.tr_act[1] = act2 + (size_t)tl.row0 * H * L::EB;
+        mlp.tr_rows = tl.row1 - tl.row0;
+    }
     const int row = tl.row0 + tid;
     const bool valid = tid < R && row < tl.row1;
     if (valid) {
@@ -59,6 +65,20 @@ k_plain_policy(EnvArgs env, PolicyArgs pol) {
 #pragma unroll
         for (int j = 0; j < HO::NH; ++j) env.head_scratch[(size_t)row * HO::NH + j] = h[j];
     }
+}
+
+template <class E, int DT, int H, int NW, int NT, int HS, int OCC>
+__global__ void __attribute__((amdgpu_flat_work_group_size(NW * 64, NW * 64),
+                               amdgpu_waves_per_eu(OCC)))
+k_plain_policy(EnvArgs env, PolicyArgs pol) {
+    policy_tile<E, DT, H, NW, NT, HS, OCC, false>(env, pol, nullptr, nullptr);
+}
+
+template <class E, int DT, int H, int NW, int NT, int HS, int OCC>
+__global__ void __attribute__((amdgpu_flat_work_group_size(NW * 64, NW * 64),
+                               amdgpu_waves_per_eu(OCC)))
+k_policy_trace(EnvArgs env, PolicyArgs pol, char* act1, char* act2) {
+    policy_tile<E, DT, H, NW, NT, HS, OCC, true>(env, pol, act1, act2);
 }
 
 // Plain sampling: G lanes per row, the same group code as the fused kernel.
@@ -234,6 +254,7 @@ struct VariantEntry {
     Variant v;
     const void* fused;
     const void* policy;
+    const void* trace;    // the policy kernel that also writes its hidden-layer codes
     const void* sample;   // plain-form sampling and step kernels with the same
     const void* step;     // lanes per row as the fused kernel
     int lanes;
@@ -252,6 +273,7 @@ const void* step_entry() {
     {{E::KIND, DT, H, NW, 16 * NT, OCC, 0},                                           \
      reinterpret_cast<const void*>(&k_fused<E, E, DT, H, NW, NT, HS, OCC>),           \
      reinterpret_cast<const void*>(&k_plain_policy<E, DT, H, NW, NT, HS, OCC>),       \
+     reinterpret_cast<const void*>(&k_policy_trace<E, DT, H, NW, NT, HS, OCC>),       \
      reinterpret_cast<const void*>(&k_plain_sample<E, WSX_G(E, NW, NT)>),             \
      step_entry<E, WSX_G(E, NW, NT)>(), WSX_G(E, NW, NT)},
 
@@ -268,7 +290,7 @@ const void* step_entry() {
 #define WSX_PAIR_ENTRY(E, E2, DT, H, NW, NT, HS, OCC)                                 \
     {{E::KIND, DT, H, NW, 16 * NT, OCC, E2::KIND},                                    \
      reinterpret_cast<const void*>(&k_fused<E, E2, DT, H, NW, NT, HS, OCC>), nullptr,  \
-     nullptr, nullptr, 0},
+     nullptr, nullptr, nullptr, 0},
 
 static const VariantEntry kVariants[] = {WSX_VARIANTS(WSX_ENTRY)
                                              WSX_PAIR_VARIANTS(WSX_PAIR_ENTRY)};
@@ -378,6 +400,22 @@ hipError_t launch_policy_forward(const Variant& v, const PolicyArgs& pol, const 
     env.n_tiles = (int)((rows + v.tile_rows - 1) / v.tile_rows);
     void* args[] = {(void*)&env, (void*)&pol};
     return hipLaunchKernel(e->policy, dim3(env.n_tiles), dim3(v.waves * 64), args, 0, s);
+}
+
+hipError_t launch_policy_trace(const Variant& v, const PolicyArgs& pol, const float* obs,
+                               int64_t rows, float* head, void* act1, void* act2, hipStream_t s) {
+    const VariantEntry* e = find_entry(v);
+    if (!e || !e->trace) return hipErrorInvalidValue;
+    EnvArgs env{};
+    env.obs_scratch = const_cast<float*>(obs);
+    env.head_scratch = head;
+    env.n_rows = rows;
+    env.tile_rows = v.tile_rows;
+    env.n_tiles = (int)((rows + v.tile_rows - 1) / v.tile_rows);
+    char* a1 = static_cast<char*>(act1);
+    char* a2 = static_cast<char*>(act2);
+    void* args[] = {(void*)&env, (void*)&pol, (void*)&a1, (void*)&a2};
+    return hipLaunchKernel(e->trace, dim3(env.n_tiles), dim3(v.waves * 64), args, 0, s);
 }
 
 hipError_t launch_quantize(int dtype, float scale, const float* x, float* y, int64_t n,

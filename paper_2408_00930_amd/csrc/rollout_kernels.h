@@ -54,7 +54,11 @@ __device__ __forceinline__ void wave_lds_sync() {
 // K (one result per row; for wide heads whose partials would not fit in LDS);
 // when the waves are a multiple of the head row tiles, the RS waves of one
 // head row tile each take NT / RS of the row tiles instead.
-template <int DT, int H, int NW, int NT, int KIN, int NHP, int HS, int OCC>
+// TRACE (a separate instantiation, used only by the policy-trace kernel): the
+// quantised outputs of both hidden layers are also written to global memory,
+// [row][H] codes of the policy format, so a checker can adopt the rounding
+// decisions of the FP32 accumulation; the arithmetic is the same code.
+template <int DT, int H, int NW, int NT, int KIN, int NHP, int HS, int OCC, bool TRACE = false>
 struct Mlp {
     using M = Mma<DT>;
     using Frag = typename M::frag;
@@ -115,6 +119,8 @@ struct Mlp {
     Frag w3[NHW][KHS];
     float o3[NHW][4];                  // head output scale
     float inv_q1, inv_q2;              // 1 / scale of the h1 and h2 quantisation
+    char* tr_act[2];                   // TRACE: the tile's first row of each layer's codes
+    int tr_rows;                       // TRACE: valid rows of the tile
 
     __device__ static Frag& w1_lds(char* base, int wave, int mt, int ks, int lane) {
         return reinterpret_cast<Frag*>(base)[((wave * MT + mt) * K1S + ks) * 64 + lane];
@@ -238,7 +244,7 @@ struct Mlp {
     // tanh of row tile `nt`'s accumulators: quantised into `out` ([R][H]) for
     // the next layer (layer 1, split-M layer 2), or fed to the split-K head
     // MFMAs of this row tile (HEAD: layer 2 of a split-K head).
-    template <bool HEAD>
+    template <bool HEAD, int LAYER>
     __device__ __forceinline__ void tanh_rows(const f32x4 (&acc)[MT], const float4 (&kx)[MT],
                                               char* out, float q, int nt, int wave, int lane,
                                               f32x4 (&acc3)[NHW][NT]) {
@@ -246,6 +252,16 @@ struct Mlp {
         Packed pk[MT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) pk[mt] = tanh_pack(acc[mt], kx[mt], DT == DT_FP8 ? q : 1.0f);
+        if constexpr (TRACE) {
+            if (nt * 16 + lr < tr_rows) {
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const int feat = wave * FPW + mt * 16 + 4 * (lane >> 4);
+                    *reinterpret_cast<Packed*>(tr_act[LAYER] +
+                                               ((size_t)(nt * 16 + lr) * H + feat) * EB) = pk[mt];
+                }
+            }
+        }
         if constexpr (HEAD) {
 #pragma unroll
             for (int ks = 0; ks < KHS; ++ks) {
@@ -272,7 +288,7 @@ struct Mlp {
     // whose layer-2 weights take more than 64 registers per lane -- each row
     // tile is multiplied, then activated). `tab` holds the layer's
     // accumulator starts and tanh factors.
-    template <int KS, bool HEAD>
+    template <int KS, bool HEAD, int LAYER>
     __device__ __forceinline__ void dense_tanh(const Frag (&w)[MT][KS], const float* tab,
                                                const char* in, int p_in, char* out, float inv_q,
                                                int wave, int lane, f32x4 (&acc3)[NHW][NT]) {
@@ -294,7 +310,7 @@ struct Mlp {
                 f32x4 acc[MT];
                 per_feature();   // re-read per row tile: fewer live registers
                 mma_rows<KS>(acc, w, ini, in, p_in, nt, lane);
-                tanh_rows<HEAD>(acc, kx, out, inv_q, nt, wave, lane, acc3);
+                tanh_rows<HEAD, LAYER>(acc, kx, out, inv_q, nt, wave, lane, acc3);
             }
             return;
         }
@@ -304,7 +320,7 @@ struct Mlp {
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             if (nt + 1 < NT) mma_rows<KS>(acc[(nt + 1) & 1], w, ini, in, p_in, nt + 1, lane);
-            tanh_rows<HEAD>(acc[nt & 1], kx, out, inv_q, nt, wave, lane, acc3);
+            tanh_rows<HEAD, LAYER>(acc[nt & 1], kx, out, inv_q, nt, wave, lane, acc3);
             if (nt + 1 < NT) {
                 // all LDS reads of the next row tile first, a few vector
                 // instructions while they land, then one MFMA at a time, each
@@ -339,10 +355,10 @@ struct Mlp {
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int ks = 0; ks < K1S; ++ks) w1r[mt][ks] = w1_lds(smem + OFF_W1, wave, mt, ks, lane);
-            dense_tanh<K1S, false>(w1r, tab, smem + OFF_IN, P_IN, smem + OFF_H1, inv_q1, wave, lane,
+            dense_tanh<K1S, false, 0>(w1r, tab, smem + OFF_IN, P_IN, smem + OFF_H1, inv_q1, wave, lane,
                                    acc);
         } else {
-            dense_tanh<K1S, false>(w1, tab, smem + OFF_IN, P_IN, smem + OFF_H1, inv_q1, wave, lane,
+            dense_tanh<K1S, false, 0>(w1, tab, smem + OFF_IN, P_IN, smem + OFF_H1, inv_q1, wave, lane,
                                    acc);
         }
         __syncthreads();
@@ -354,10 +370,10 @@ struct Mlp {
                     for (int ks = 0; ks < KHS; ++ks) w3[hw][ks] = w3_lds(smem + OFF_W3, wave, hw, ks, lane);
             }
             // split-K: the head consumes each wave's own h2 from its registers
-            dense_tanh<K2S, true>(w2, tab + 2 * H, smem + OFF_H1, P_H, nullptr, inv_q2, wave, lane,
+            dense_tanh<K2S, true, 1>(w2, tab + 2 * H, smem + OFF_H1, P_H, nullptr, inv_q2, wave, lane,
                                   acc);
         } else {
-            dense_tanh<K2S, false>(w2, tab + 2 * H, smem + OFF_H1, P_H, smem + OFF_H2, inv_q2, wave,
+            dense_tanh<K2S, false, 1>(w2, tab + 2 * H, smem + OFF_H1, P_H, smem + OFF_H2, inv_q2, wave,
                                    lane, acc);
             __syncthreads();   // every wave reads all of h2
             const char* h2 = smem + OFF_H2 + head_row0(wave) * 16 * P_H;

@@ -57,7 +57,7 @@ EXPORTS = ["wsx_env_state_bytes", "wsx_env_create", "wsx_env_reset", "wsx_rollou
            "wsx_rollout_batch",
            "wsx_env_info", "wsx_env_set_step", "wsx_env_set_chunk", "wsx_env_destroy",
            "wsx_compute_returns",
-           "wsx_policy_forward", "wsx_quantize", "wsx_last_error"]
+           "wsx_policy_forward", "wsx_policy_trace", "wsx_quantize", "wsx_last_error"]
 
 _lib = None
 
@@ -81,6 +81,7 @@ def lib():
         L.wsx_env_destroy.argtypes = [vp]
         L.wsx_compute_returns.argtypes = [vp, vp, vp, vp, i32, i64, f64, f64, i32, vp, vp, i32, vp]
         L.wsx_policy_forward.argtypes = [C.POINTER(_Policy), vp, i64, vp, vp]
+        L.wsx_policy_trace.argtypes = [vp, C.POINTER(_Policy), vp, i64, vp, vp, vp, vp]
         L.wsx_quantize.argtypes = [i32, C.c_float, vp, vp, i64, vp]
         L.wsx_last_error.restype = C.c_char_p
         _lib = L
@@ -262,6 +263,23 @@ def policy_forward(policy, obs, stream=None):
     _check(lib().wsx_policy_forward(C.byref(policy.c), _ptr(obs), rows, _ptr(head),
                                     _stream(stream)))
     return head
+
+
+def policy_trace(env, policy, obs, stream=None):
+    """Head outputs [rows, n_head] and the quantised hidden-layer outputs
+    h1, h2 [rows, hidden] (their real values, float64 on the host) from the
+    kernel of env's roll-out."""
+    rows = obs.shape[0]
+    p = policy.host
+    head = torch.empty((rows, p.n_head), dtype=torch.float32, device=obs.device)
+    cdt = {"f32": torch.float32, "bf16": torch.bfloat16, "fp8": torch.float8_e4m3fn}[p.dtype]
+    a1 = torch.empty((rows, p.h1), dtype=cdt, device=obs.device)
+    a2 = torch.empty((rows, p.h2), dtype=cdt, device=obs.device)
+    _check(lib().wsx_policy_trace(env.handle, C.byref(policy.c), _ptr(obs), rows, _ptr(head),
+                                  _ptr(a1), _ptr(a2), _stream(stream)))
+    h1 = a1.float().cpu().numpy().astype(np.float64) * p.act_scale[1]
+    h2 = a2.float().cpu().numpy().astype(np.float64) * p.act_scale[2]
+    return head, h1, h2
 
 
 def quantize(dtype, x, scale=1.0, stream=None):

@@ -158,3 +158,22 @@ def test_gaussian_zero_noise_returns_mean():
     a, lp = O.sample_gaussian([0.25], [-0.5], [0.0])
     assert a[0] == 0.25
     assert lp == pytest.approx(0.5 - 0.5 * np.log(2 * np.pi), abs=1e-15)
+
+
+def test_sample_rows_is_the_per_row_draw_and_sample():
+    """The batched draw equals the per-row composition of the pinned parts."""
+    rng = np.random.default_rng(12)
+    head = rng.normal(size=(30, 6))
+    rows = rng.integers(0, 2 ** 31, 30)
+    a, lp, mg = O.sample_rows(head, 5, None, 9, 17, rows, 3)
+    for i, r in enumerate(rows):
+        w = O.draw(9, 17, int(r), O.ACTION, 0, 3)
+        want = O.sample_categorical(head[i, :5], O.u01(w[0]))
+        assert (a[i], lp[i], mg[i]) == want
+    ls = np.array([-0.5])
+    a, lp, mg = O.sample_rows(head[:, :2], 0, ls, 9, 17, rows, 3)
+    for i, r in enumerate(rows):
+        w = O.draw(9, 17, int(r), O.ACTION, 0, 3)
+        z0, _ = O.box_muller(O.u01(w[0]), O.u01(w[1]))
+        ga, glp = O.sample_gaussian(head[i, :1], ls, [z0])
+        assert a[i] == ga[0] and lp[i] == glp and np.isinf(mg[i])

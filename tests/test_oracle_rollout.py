@@ -102,3 +102,24 @@ def test_market_rows_follow_offsets():
     assert env.rows == env.offsets[-1]
     counts = np.diff(env.offsets)
     assert counts.min() >= 5 and counts.max() <= 100
+
+
+def test_cartpole_fp32_twin_follows_the_fp64_oracle():
+    """The FP32 twin takes the FP64 oracle's decisions and stays within FP32
+    rounding of its states over a short horizon (its first observation is the
+    reset state rounded to float)."""
+    pol = inputs.policy_for(O.CARTPOLE, "f32", 64, seed=1)
+    hold = O.env_hold(O.CARTPOLE, 300)
+    s0 = O.env_reset(hold, 4, 2)
+    T = 25
+    ref = O.rollout(hold, O.mlp_hold(pol), 4, 2, 0, T, s0, None)
+    tw = O.cartpole_rollout_f32(pol, 4, 2, 0, T, s0)
+    assert np.array_equal(tw["obs"][0], s0.astype(np.float32).astype(np.float64))
+    same = (tw["action"] == ref["action"]).mean()
+    assert same > 0.99
+    first = np.nonzero((tw["action"] != ref["action"]).any(axis=0) |
+                       (ref["done"] != 0).any(axis=0))[0]
+    keep = np.setdiff1d(np.arange(300), first)
+    assert len(keep) > 50
+    err = np.abs(tw["obs"][:, keep] - ref["obs"][:, keep])
+    assert err.max() < 1e-5 and err.max() > 0
