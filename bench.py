@@ -24,6 +24,11 @@ METRIC = "env-steps/s fused vs per-step-launch at tolerance; p50/p99 rollout lat
 PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
 
 # name -> list of (config key in inputs.CONFIGS)
+# oracle sample of each workload's CPU baseline when it is a sub-record (about
+# 1-5 s of the FP64 oracle on 16 host threads)
+CPU_SAMPLE_ENVS = {"cartpole_1k": 1000, "market_2k": 32, "reaction_4k": 64,
+                   "pendulum_acrobot_10k": 256}
+
 WORKLOADS = {
     "pendulum_acrobot_10k": ["pendulum_10k", "acrobot_10k"],
     "cartpole_1k": ["cartpole_1k"],
@@ -347,8 +352,10 @@ def iqr(sorted_vals, digits):
     return round(percentile(sorted_vals, 75) - percentile(sorted_vals, 25), digits)
 
 
-def cpu_baseline(sets, sample_envs):
-    """The FP64 oracle on a bounded sample of the same workload."""
+def cpu_baseline(sets, sample_envs, single_thread=True):
+    """The FP64 oracle on a bounded sample of the same workload (the first
+    `sample_envs` envs of each set over the full horizon); with single_thread
+    also on one thread over a quarter of that sample."""
     import numpy as np
 
     import oracle as O
@@ -375,20 +382,22 @@ def cpu_baseline(sets, sample_envs):
 
     cores = O.num_threads()
     total_env_steps, el = median_of_3(sample_envs)
-    # the same oracle on one thread, over a quarter of the sample
-    O.set_threads(1)
-    one_steps, one_el = median_of_3(max(1, sample_envs // 4))
-    O.set_threads(cores)
-    return {"value": total_env_steps / el, "unit": "env-steps/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"first {sample_envs} envs of each set over the full horizon "
-                      f"({total_env_steps} env-steps, median of 3 runs: {el:.1f} s), FP64 C "
-                      f"oracle with OpenMP over envs, returns/GAE included",
-            "cpu": cpu_model(),
-            "single_thread": {"value": round(one_steps / one_el, 1), "cores": 1,
-                              "sample": f"first {max(1, sample_envs // 4)} envs of each set "
-                                        f"({one_steps} env-steps, median of 3 runs: "
-                                        f"{one_el:.1f} s)"}}
+    out = {"value": total_env_steps / el, "unit": "env-steps/s", "cores": cores,
+           "kind": "oracle",
+           "sample": f"first {sample_envs} envs of each set over the full horizon "
+                     f"({total_env_steps} env-steps, median of 3 runs: {el:.1f} s), FP64 C "
+                     f"oracle with OpenMP over envs, returns/GAE included",
+           "cpu": cpu_model()}
+    if single_thread:
+        # the same oracle on one thread, over a quarter of the sample
+        O.set_threads(1)
+        one_steps, one_el = median_of_3(max(1, sample_envs // 4))
+        O.set_threads(cores)
+        out["single_thread"] = {"value": round(one_steps / one_el, 1), "cores": 1,
+                                "sample": f"first {max(1, sample_envs // 4)} envs of each set "
+                                          f"({one_steps} env-steps, median of 3 runs: "
+                                          f"{one_el:.1f} s)"}
+    return out
 
 
 def cpu_model():
@@ -503,6 +512,124 @@ def unit_busy_for(kernel_name):
             "from": "rocprofv3 PMC: SQ_VALU_MFMA_BUSY_CYCLES, SQ_ACTIVE_INST_VALU / GRBM_GUI_ACTIVE"}
 
 
+def measure(workload, args, wsx, inputs, torch, plain_steps, cpu_envs, single_thread):
+    """One workload: the autotuner's shape (untimed), then the fused form
+    timed over args.steps steps after args.warmup, the plain / graph / fused
+    graph forms, plain = fused bit for bit on the same inputs, the roofline
+    of the fused launch and the oracle on a bounded sample. Returns the
+    record and the sets."""
+    keys = WORKLOADS[workload]
+    batched = len(keys) > 1 and not args.no_batch
+    tuned = {}
+    shape = dict(zip(("tile_rows", "waves", "occupancy"),
+                     (int(x) for x in args.shape.split(",")))) if args.shape else None
+    if args.autotune and not args.tile_rows and not shape:
+        # the library's autotuner picks the kernel shape (untimed here): for a
+        # batched workload one shape for the whole single launch
+        spec = []
+        for key in keys:
+            cfg = inputs.CONFIGS[key]
+            kind = cfg["kind"]
+            spec.append(dict(
+                kind=kind, n_envs=cfg["n_envs"], seed=0, horizon=cfg["horizon"],
+                policy=wsx.DevicePolicy(inputs.policy_for(kind, cfg["dtype"], cfg["hidden"], seed=0)),
+                agent_offsets=inputs.agent_offsets(cfg["n_envs"], seed=0)
+                if kind == wsx.MARKET else None,
+                params=inputs.reaction_params(0) if kind == wsx.REACTION else None))
+        t0 = time.perf_counter()
+        if batched:
+            tuned["batch"] = wsx.autotune_batch(spec, spec[0]["horizon"], reps=2)
+        else:
+            for key, d in zip(keys, spec):
+                tuned[key] = wsx.autotune(d["kind"], d["n_envs"], d["policy"], d["horizon"], reps=2,
+                                          seed=0, agent_offsets=d["agent_offsets"],
+                                          params=d["params"])
+        print(f"[bench] {workload} autotune: {tuned} in {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
+    sets = [EnvSet(k, 0, args.tile_rows, wsx, inputs, torch, shape) for k in keys]
+    env_steps = sum(s.n_envs * s.T for s in sets)
+    forms = args.forms.split(",")
+
+    result = {}
+    el, lat, kern = run_form(sets, wsx.MODE_FUSED, args.steps, args.warmup, wsx, torch, 0,
+                             batched=batched)
+    result["fused"] = (el, lat, kern)
+    print(f"[bench] {workload} fused: {args.steps} steps in {el:.3f} s", file=sys.stderr,
+          flush=True)
+    for name, mode in (("plain", wsx.MODE_PLAIN), ("graph", wsx.MODE_GRAPH),
+                       ("fused_graph", wsx.MODE_FUSED_GRAPH)):
+        n = args.steps if name == "fused_graph" else plain_steps
+        if name in forms and n > 0:
+            r = run_form(sets, mode, n, 1, wsx, torch, 1000)
+            result[name] = r + (n,)
+            print(f"[bench] {workload} {name}: {n} steps in {r[0]:.3f} s", file=sys.stderr,
+                  flush=True)
+
+    # plain and fused forms on identical inputs, compared in the same run
+    parity = None
+    if "plain" in forms and plain_steps > 0:
+        parity = plain_vs_fused(sets, wsx, torch, batched, epoch=4321)
+        print(f"[bench] {workload} parity: {parity}", file=sys.stderr, flush=True)
+
+    el, lat, kern = result["fused"]
+    value = env_steps * args.steps / el
+    # dominant kernel: the fused roll-out launch (the batched one, or the set's
+    # launch with the most total time)
+    if batched:
+        avg_ms = sum(kern["batch"]) / len(kern["batch"])
+        flop = sum(s.flop_per_launch for s in sets)
+        dtype = sets[0].policy.dtype
+        kname = f"k_fused/{workload}"
+    else:
+        dom = max(sets, key=lambda s: sum(kern[s.key]))
+        avg_ms = sum(kern[dom.key]) / len(kern[dom.key])
+        flop = dom.flop_per_launch
+        dtype = dom.policy.dtype
+        kname = f"k_fused/{dom.key}"
+    achieved = flop / (avg_ms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_TFLOPS[dtype],
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[dtype], 4),
+                "traffic": traffic_for(kname, "hbm_bytes_per_launch"),
+                "unit_busy": unit_busy_for(kname),
+                "kernel": kname, "avg_launch_ms": round(avg_ms, 4),
+                "flop_per_launch": flop}
+    out = {
+        "value": round(value, 1), "unit": "env-steps/s",
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(el / args.steps * 1e3, 4),
+        "dtype": "bf16" if any(s.policy.dtype == "bf16" for s in sets) else dtype,
+        "config": {"workload": workload, "envs": sum(s.n_envs for s in sets),
+                   "rows": sum(s.rows for s in sets),
+                   "horizon": max(s.T for s in sets), "sets": [s.key for s in sets],
+                   "policy": {s.key: f"{s.policy.dtype} {s.policy.d_in}-{s.policy.h1}-"
+                                     f"{s.policy.h2}-{s.policy.n_head}" for s in sets},
+                   "returns": "FP64 scan, FP32 outputs", "streams": 1 if batched else len(sets),
+                   "kernel_shape": {s.key: dict(zip(("tile_rows", "waves", "occupancy",
+                                                     "chunk_steps"), wsx.env_shape(s.env)))
+                                    for s in sets},
+                   "autotuned": bool(tuned), "one_launch": batched},
+        "latency_ms": {"p50": round(percentile(lat, 50), 4), "p99": round(percentile(lat, 99), 4),
+                       "iqr": iqr(lat, 4)},
+        "roofline": roofline,
+    }
+    if any(s.kind == wsx.MARKET for s in sets):
+        agent_steps = sum(s.rows * s.T for s in sets)
+        out["agent_steps_per_s"] = round(agent_steps * args.steps / el, 1)
+    for name in ("plain", "graph", "fused_graph"):
+        if name in result:
+            pel, plat, _, n = result[name]
+            pv = env_steps * n / pel
+            out[name] = {"value": round(pv, 1), "steps": n, "ms_per_step": round(pel / n * 1e3, 3),
+                         "latency_ms": {"p50": round(percentile(plat, 50), 3),
+                                        "p99": round(percentile(plat, 99), 3),
+                                        "iqr": iqr(plat, 3)}}
+            out[f"fused_speedup_vs_{name}"] = round(value / pv, 2)
+    if parity is not None:
+        out["parity"] = parity
+    if cpu_envs > 0 and not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sets, cpu_envs, single_thread)
+    return out, sets
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -510,12 +637,15 @@ def main():
     # still ran ~6 % slower); 50 timed steps are ~55 ms of GPU work
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--plain-steps", type=int, default=10)
     ap.add_argument("--workload", default="pendulum_acrobot_10k", choices=sorted(WORKLOADS))
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--shape", default="",
                     help="ROWS,WAVES,OCCUPANCY kernel shape for every set (skips the autotuner)")
     ap.add_argument("--cpu-sample-envs", type=int, default=1024)
+    ap.add_argument("--also", default="cartpole_1k,market_2k,reaction_4k",
+                    help="other workloads measured the same way, reported as sub-records "
+                         "under 'workloads' ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="fused,plain,graph,fused_graph")
     ap.add_argument("--no-batch", action="store_true",
@@ -525,9 +655,9 @@ def main():
     ap.add_argument("--update-steps", type=int, default=5,
                     help="timed passes of the actor-critic update after the roll-out legs "
                          "(0: skip)")
-    ap.add_argument("--serve-requests", type=int, default=400,
+    ap.add_argument("--serve-requests", type=int, default=2000,
                     help="measured requests of the serving load (0: skip serving)")
-    ap.add_argument("--serve-warmup", type=int, default=50)
+    ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-arena-gb", type=float, default=200.0)
     ap.add_argument("--serve-chunk", type=int, default=25)
@@ -573,114 +703,25 @@ def main():
                           "published": {"hbm_gb_s": 8000, "bf16_tflops": 2500,
                                         "fp32_tflops": 157.3}}), flush=True)
         return
-    keys = WORKLOADS[args.workload]
-    batched = len(keys) > 1 and not args.no_batch
-    tuned = {}
-    shape = dict(zip(("tile_rows", "waves", "occupancy"),
-                     (int(x) for x in args.shape.split(",")))) if args.shape else None
-    if args.autotune and not args.tile_rows and not shape:
-        # the library's autotuner picks the kernel shape (untimed here): for a
-        # batched workload one shape for the whole single launch
-        spec = []
-        for key in keys:
-            cfg = inputs.CONFIGS[key]
-            kind = cfg["kind"]
-            spec.append(dict(
-                kind=kind, n_envs=cfg["n_envs"], seed=0, horizon=cfg["horizon"],
-                policy=wsx.DevicePolicy(inputs.policy_for(kind, cfg["dtype"], cfg["hidden"], seed=0)),
-                agent_offsets=inputs.agent_offsets(cfg["n_envs"], seed=0)
-                if kind == wsx.MARKET else None,
-                params=inputs.reaction_params(0) if kind == wsx.REACTION else None))
-        t0 = time.perf_counter()
-        if batched:
-            tuned["batch"] = wsx.autotune_batch(spec, spec[0]["horizon"], reps=2)
-        else:
-            for key, d in zip(keys, spec):
-                tuned[key] = wsx.autotune(d["kind"], d["n_envs"], d["policy"], d["horizon"], reps=2,
-                                          seed=0, agent_offsets=d["agent_offsets"],
-                                          params=d["params"])
-        print(f"[bench] autotune: {tuned} in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
-              flush=True)
-    sets = [EnvSet(k, 0, args.tile_rows, wsx, inputs, torch, shape) for k in keys]
-    env_steps = sum(s.n_envs * s.T for s in sets)
-    forms = args.forms.split(",")
-
-    result = {}
-    el, lat, kern = run_form(sets, wsx.MODE_FUSED, args.steps, args.warmup, wsx, torch, 0,
-                             batched=batched)
-    result["fused"] = (el, lat, kern)
-    print(f"[bench] fused: {args.steps} steps in {el:.3f} s", file=sys.stderr, flush=True)
-    for name, mode in (("plain", wsx.MODE_PLAIN), ("graph", wsx.MODE_GRAPH),
-                       ("fused_graph", wsx.MODE_FUSED_GRAPH)):
-        n = args.steps if name == "fused_graph" else args.plain_steps
-        if name in forms and n > 0:
-            r = run_form(sets, mode, n, 1, wsx, torch, 1000)
-            result[name] = r + (n,)
-            print(f"[bench] {name}: {n} steps in {r[0]:.3f} s", file=sys.stderr, flush=True)
-
-    # plain and fused forms on identical inputs, compared in the same run
-    parity = None
-    if "plain" in forms and args.plain_steps > 0:
-        parity = plain_vs_fused(sets, wsx, torch, batched, epoch=4321)
-        print(f"[bench] parity: {parity}", file=sys.stderr, flush=True)
-
-    el, lat, kern = result["fused"]
-    value = env_steps * args.steps / el
-    # dominant kernel: the fused roll-out launch (the batched one, or the set's
-    # launch with the most total time)
-    if batched:
-        avg_ms = sum(kern["batch"]) / len(kern["batch"])
-        flop = sum(s.flop_per_launch for s in sets)
-        dtype = sets[0].policy.dtype
-        kname = f"k_fused/{args.workload}"
-    else:
-        dom = max(sets, key=lambda s: sum(kern[s.key]))
-        avg_ms = sum(kern[dom.key]) / len(kern[dom.key])
-        flop = dom.flop_per_launch
-        dtype = dom.policy.dtype
-        kname = f"k_fused/{dom.key}"
-    achieved = flop / (avg_ms * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_TFLOPS[dtype],
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[dtype], 4),
-                "traffic": traffic_for(kname, "hbm_bytes_per_launch"),
-                "unit_busy": unit_busy_for(kname),
-                "kernel": kname, "avg_launch_ms": round(avg_ms, 4),
-                "flop_per_launch": flop}
-    out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "env-steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(el / args.steps * 1e3, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16" if any(s.policy.dtype == "bf16" for s in sets) else dtype,
-        "data": "synthetic (seeded inputs; random-init policies)",
-        "config": {"workload": args.workload, "envs": sum(s.n_envs for s in sets),
-                   "rows": sum(s.rows for s in sets),
-                   "horizon": max(s.T for s in sets), "sets": [s.key for s in sets],
-                   "policy": {s.key: f"{s.policy.dtype} {s.policy.d_in}-{s.policy.h1}-"
-                                     f"{s.policy.h2}-{s.policy.n_head}" for s in sets},
-                   "returns": "FP64 scan, FP32 outputs", "streams": 1 if batched else len(sets),
-                   "kernel_shape": {s.key: dict(zip(("tile_rows", "waves", "occupancy",
-                                                     "chunk_steps"), wsx.env_shape(s.env)))
-                                    for s in sets},
-                   "autotuned": bool(tuned), "one_launch": batched},
-        "latency_ms": {"p50": round(percentile(lat, 50), 4), "p99": round(percentile(lat, 99), 4),
-                       "iqr": iqr(lat, 4)},
-        "roofline": roofline,
-    }
-    for name in ("plain", "graph", "fused_graph"):
-        if name in result:
-            pel, plat, _, n = result[name]
-            pv = env_steps * n / pel
-            out[name] = {"value": round(pv, 1), "steps": n, "ms_per_step": round(pel / n * 1e3, 3),
-                         "latency_ms": {"p50": round(percentile(plat, 50), 3),
-                                        "p99": round(percentile(plat, 99), 3),
-                                        "iqr": iqr(plat, 3)}}
-            out[f"fused_speedup_vs_{name}"] = round(value / pv, 2)
-    if parity is not None:
-        out["parity"] = parity
+    headline, sets = measure(args.workload, args, wsx, inputs, torch, args.plain_steps,
+                             args.cpu_sample_envs, True)
+    out = {"metric": METRIC, "value": headline["value"], "unit": "env-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": headline["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": headline["dtype"], "data": "synthetic (seeded inputs; random-init policies)"}
+    for k, v in headline.items():
+        if k not in out:
+            out[k] = v
+    # the other workloads, each timed the same way, as sub-records
+    others = [w for w in args.also.split(",") if w and w != args.workload]
+    if others:
+        out["workloads"] = {}
+    for w in others:
+        rec, _ = measure(w, args, wsx, inputs, torch, args.plain_steps,
+                         CPU_SAMPLE_ENVS.get(w, 64), False)
+        out["workloads"][w] = rec
     if args.serve_requests > 0:
         out["serving"] = serving(args, wsx, inputs, torch)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sets, args.cpu_sample_envs)
     if args.update_steps > 0:   # last: it writes new weights into the policies
         upd = update_leg(sets, args.update_steps, wsx, torch)
         if upd:

