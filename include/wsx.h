@@ -265,6 +265,22 @@ int wsx_ac_grad(const wsx_policy* policy, int32_t n_actions, const float* obs,
                 int64_t samples, float value_coef, float entropy_coef,
                 const wsx_grads* grads, void* workspace, size_t workspace_bytes, void* stream);
 
+/* wsx_ac_grad without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving or training loops, harnesses that forbid hipMalloc). The
+ * workspace is a file-scope device array of the library (about 25 MiB, one
+ * per GPU, held until the process ends), which bounds `samples` to
+ * WSX_AC_STATIC_MAX_SAMPLES; larger counts return WSX_EINVAL, other errors
+ * as wsx_ac_grad. Same arguments and results as wsx_ac_grad (the same kernels
+ * and the same partial-sum layout, so the gradients are equal bit for bit).
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (other streams, other threads) race; order them on one stream. */
+#define WSX_AC_STATIC_MAX_SAMPLES 2048
+int wsx_ac_grad_static(const wsx_policy* policy, int32_t n_actions, const float* obs,
+                       const void* action, const float* returns, const float* advantages,
+                       int64_t samples, float value_coef, float entropy_coef,
+                       const wsx_grads* grads, void* stream);
+
 /* One Adam step (Kingma and Ba, ICLR 2015, Algorithm 1) on n FP32 master
  * parameters in place, step t >= 1 (bias corrections 1 - beta^t):
  *   m <- b1 m + (1 - b1) g,  v <- b2 v + (1 - b2) g^2,

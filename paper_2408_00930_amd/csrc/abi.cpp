@@ -700,6 +700,28 @@ int wsx_ac_grad(const wsx_policy* policy, int32_t n_actions, const float* obs,
     return WSX_OK;
 }
 
+static_assert(kAcStaticSamples == WSX_AC_STATIC_MAX_SAMPLES, "one sample bound");
+
+int wsx_ac_grad_static(const wsx_policy* policy, int32_t n_actions, const float* obs,
+                       const void* action, const float* returns, const float* advantages,
+                       int64_t samples, float value_coef, float entropy_coef,
+                       const wsx_grads* grads, void* stream) {
+    if (samples > WSX_AC_STATIC_MAX_SAMPLES)
+        return fail(WSX_EINVAL, "wsx_ac_grad_static takes at most %d samples (got %lld)",
+                    WSX_AC_STATIC_MAX_SAMPLES, (long long)samples);
+    if (const int rc = check_ac_policy(policy)) return rc;
+    if (samples >= 1) {
+        const int g = ac_grid(samples);
+        if (ac_workspace_bytes(policy->dtype, policy->h1, samples, g, g) > ac_static_capacity())
+            return fail(WSX_EUNSUPPORTED, "the static workspace does not hold this policy shape");
+    }
+    hipError_t err;
+    void* ws = ac_static_workspace(&err);
+    if (!ws) return hip_fail(err, "wsx_ac_grad_static: address of the static workspace");
+    return wsx_ac_grad(policy, n_actions, obs, action, returns, advantages, samples, value_coef,
+                       entropy_coef, grads, ws, ac_static_capacity(), stream);
+}
+
 int wsx_adam_step(float* param, const float* grad, float* m, float* v, int64_t n, int32_t step,
                   float lr, float beta1, float beta2, float eps, void* store, int32_t store_dtype,
                   void* stream) {

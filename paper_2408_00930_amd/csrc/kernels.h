@@ -131,6 +131,11 @@ struct AdamTable {
 };
 #ifndef __HIPCC_RTC__   // host-side launchers
 bool ac_supported(int dtype, int hidden, int d_in, int n_head);
+// The allocation-free gradient: at most kAcStaticSamples samples, workspace in
+// a file-scope device array (its per-device address, or nullptr and *err).
+constexpr int64_t kAcStaticSamples = 2048;
+size_t ac_static_capacity();
+void* ac_static_workspace(hipError_t* err);
 int64_t ac_chunk_samples(int64_t n);   // samples per chunk of a call over n
 size_t ac_workspace_bytes(int dtype, int hidden, int64_t n, int grid1, int grid2);
 hipError_t launch_ac_grad(const AcLaunch& l, hipStream_t s);

@@ -31,6 +31,7 @@
 // weight-gradient products (K = samples) directly, taking the K elements in
 // accumulator order; the other operand is read from LDS in the same order.
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "device.h"
@@ -803,6 +804,54 @@ bool ac_supported(int dtype, int hidden, int d_in, int n_head) {
 static size_t ac_round_up(size_t b) { return (b + 255) / 256 * 256; }
 
 int64_t ac_chunk_samples(int64_t n) { return std::min<int64_t>(n, kAcChunk); }
+
+// ------------------------------------------- allocation-free workspace --
+// For callers that cannot allocate (graph capture, serving loops): the
+// workspace of a gradient over at most kAcStaticSamples samples lives in a
+// file-scope device array, one per GPU, for the life of the process. Its size
+// is the largest workspace of the compiled update variants at that count
+// (BF16 width 256 with the 64-wide head; every tile its own workgroup).
+namespace {
+constexpr size_t ac_round_up_c(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t ac_static_bytes() {
+    constexpr size_t n = kAcStaticSamples, h = 256, eb = 2;
+    constexpr size_t tiles = (n + kAcRows - 1) / kAcRows;
+    constexpr size_t grid = tiles;   // ac_grid: min(tiles, CUs)
+    constexpr size_t nhp = 64, kin = 32;
+    constexpr size_t part = grid * ((nhp * h + h + nhp + 1) + (h * kin + h)) + grid * h * h;
+    return 256 + ac_round_up_c(n * h * eb) + 2 * ac_round_up_c(tiles * kAcRows * h * eb) +
+           part * sizeof(float);
+}
+}  // namespace
+
+static __device__ __align__(256) char scratch[ac_static_bytes()];
+
+constexpr int kMaxDevices = 64;
+static void* g_scratch_ptr[kMaxDevices];
+static bool g_scratch_done[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+size_t ac_static_capacity() { return ac_static_bytes(); }
+
+// The current device's copy of the array (looked up once per device, with
+// that device current); nullptr with the HIP error in *err on failure.
+void* ac_static_workspace(hipError_t* err) {
+    *err = hipSuccess;
+    int dev = 0;
+    if ((*err = hipGetDevice(&dev)) != hipSuccess) return nullptr;
+    if (dev < 0 || dev >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_done[dev]) {
+        void* ptr = nullptr;
+        if ((*err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch))) != hipSuccess) return nullptr;
+        g_scratch_ptr[dev] = ptr;
+        g_scratch_done[dev] = true;
+    }
+    return g_scratch_ptr[dev];
+}
 
 size_t ac_workspace_bytes(int dtype, int hidden, int64_t n, int grid1, int grid2) {
     n = ac_chunk_samples(n);

@@ -531,7 +531,8 @@ class _Grads(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("w1", "b1", "w2", "b2", "w3", "b3", "log_std")]
 
 
-EXPORTS += ["wsx_ac_grad_workspace_bytes", "wsx_ac_grad", "wsx_adam_step", "wsx_adam_step_many"]
+EXPORTS += ["wsx_ac_grad_workspace_bytes", "wsx_ac_grad", "wsx_ac_grad_static", "wsx_adam_step",
+            "wsx_adam_step_many"]
 
 
 def _update_sigs(L):
@@ -542,6 +543,8 @@ def _update_sigs(L):
                                               C.POINTER(C.c_size_t)]
     L.wsx_ac_grad.argtypes = [C.POINTER(_Policy), C.c_int32, vp, vp, vp, vp, C.c_int64,
                               C.c_float, C.c_float, C.POINTER(_Grads), vp, C.c_size_t, vp]
+    L.wsx_ac_grad_static.argtypes = [C.POINTER(_Policy), C.c_int32, vp, vp, vp, vp, C.c_int64,
+                                     C.c_float, C.c_float, C.POINTER(_Grads), vp]
     L.wsx_adam_step.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int32, C.c_float, C.c_float,
                                 C.c_float, C.c_float, vp, C.c_int32, vp]
     L.wsx_adam_step_many.argtypes = [C.POINTER(_AdamTensor), C.c_int32, C.c_int32, C.c_float,
@@ -601,6 +604,24 @@ def ac_grad(policy, n_actions, obs, action, returns, advantages, value_coef=0.5,
                          returns.data_ptr(), advantages.data_ptr(), n, float(value_coef),
                          float(entropy_coef), C.byref(grads.c), workspace.data_ptr(),
                          workspace.numel(), _stream(stream)))
+    return grads
+
+
+AC_STATIC_MAX_SAMPLES = 2048
+
+
+def ac_grad_static(policy, n_actions, obs, action, returns, advantages, value_coef=0.5,
+                   entropy_coef=0.0, grads=None, stream=None):
+    """ac_grad through wsx_ac_grad_static: no workspace argument and no
+    allocation in the library (at most AC_STATIC_MAX_SAMPLES samples)."""
+    L = lib()
+    _update_sigs(L)
+    n = int(returns.numel())
+    grads = grads or Grads(policy)
+    _check(L.wsx_ac_grad_static(C.byref(policy.c), int(n_actions), obs.data_ptr(),
+                                action.data_ptr(), returns.data_ptr(), advantages.data_ptr(), n,
+                                float(value_coef), float(entropy_coef), C.byref(grads.c),
+                                _stream(stream)))
     return grads
 
 
