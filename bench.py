@@ -27,7 +27,7 @@ PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
 # oracle sample of each workload's CPU baseline when it is a sub-record (about
 # 1-5 s of the FP64 oracle on 16 host threads)
 CPU_SAMPLE_ENVS = {"cartpole_1k": 1000, "market_2k": 32, "reaction_4k": 64,
-                   "pendulum_acrobot_10k": 256}
+                   "pendulum_acrobot_10k": 1024}
 
 WORKLOADS = {
     "pendulum_acrobot_10k": ["pendulum_10k", "acrobot_10k"],
@@ -606,7 +606,11 @@ def measure(workload, args, wsx, inputs, torch, plain_steps, cpu_envs, single_th
                    "kernel_shape": {s.key: dict(zip(("tile_rows", "waves", "occupancy",
                                                      "chunk_steps"), wsx.env_shape(s.env)))
                                     for s in sets},
-                   "autotuned": bool(tuned), "one_launch": batched},
+                   "autotuned": bool(tuned), "one_launch": batched,
+                   "tiles": {s.key: dict(zip(("tiles", "rows_per_tile"), s.env.tiles()),
+                                         fill=round(s.rows / (s.env.tiles()[0] *
+                                                              s.env.tiles()[1]), 4))
+                             for s in sets}},
         "latency_ms": {"p50": round(percentile(lat, 50), 4), "p99": round(percentile(lat, 99), 4),
                        "iqr": iqr(lat, 4)},
         "roofline": roofline,
@@ -626,7 +630,11 @@ def measure(workload, args, wsx, inputs, torch, plain_steps, cpu_envs, single_th
     if parity is not None:
         out["parity"] = parity
     if cpu_envs > 0 and not args.no_cpu_baseline:
+        print(f"[bench] {workload} cpu baseline: the oracle on {cpu_envs} envs of each set",
+              file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sets, cpu_envs, single_thread)
+        print(f"[bench] {workload} cpu baseline: {out['cpu_baseline']['value']:.4g} env-steps/s",
+              file=sys.stderr, flush=True)
     return out, sets
 
 
@@ -642,7 +650,9 @@ def main():
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--shape", default="",
                     help="ROWS,WAVES,OCCUPANCY kernel shape for every set (skips the autotuner)")
-    ap.add_argument("--cpu-sample-envs", type=int, default=1024)
+    ap.add_argument("--cpu-sample-envs", type=int, default=0,
+                    help="envs of each set the oracle runs for the CPU baseline (0: the "
+                         "workload's default, about 1-5 s of oracle work)")
     ap.add_argument("--also", default="cartpole_1k,market_2k,reaction_4k",
                     help="other workloads measured the same way, reported as sub-records "
                          "under 'workloads' ('' for none)")
@@ -704,7 +714,7 @@ def main():
                                         "fp32_tflops": 157.3}}), flush=True)
         return
     headline, sets = measure(args.workload, args, wsx, inputs, torch, args.plain_steps,
-                             args.cpu_sample_envs, True)
+                             args.cpu_sample_envs or CPU_SAMPLE_ENVS[args.workload], True)
     out = {"metric": METRIC, "value": headline["value"], "unit": "env-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": headline["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,

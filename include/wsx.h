@@ -166,6 +166,14 @@ int wsx_env_info(const wsx_env* env, int64_t* n_rows, uint32_t* step, uint32_t* 
 int wsx_rollout_batch(wsx_env* const* envs, const wsx_policy* const* policies,
                       const wsx_traj* const* trajs, int32_t n, int32_t horizon, void* stream);
 
+/* Workgroup tiles of an environment set's fused launch and the rows one tile
+ * holds. Single-agent kinds: ceil(n_rows / tile_rows) tiles of consecutive
+ * replicas. The market (App. B: the agents of one environment interact, so
+ * they share one block): whole environments packed by first-fit decreasing
+ * into tiles of at most `capacity` agents, so n_rows / (n_tiles * capacity)
+ * is the tiles' fill. */
+int wsx_env_tiles(const wsx_env* env, int32_t* n_tiles, int32_t* capacity);
+
 /* Sets the step counter (resuming from a saved state block). */
 int wsx_env_set_step(wsx_env* env, uint32_t step);
 

@@ -67,6 +67,10 @@ Layout layout_of(const KindInfo& k, int64_t n_envs, int64_t n_rows, bool market)
     if (market) at = align256(at + (size_t)(n_envs + 1) * 4);
     L.tiles = at;
     if (market) at = align256(at + (size_t)n_envs * sizeof(Tile));
+    L.row_map = at;
+    if (market) at = align256(at + (size_t)n_rows * 4);
+    L.slot_map = at;
+    if (market) at = align256(at + (size_t)n_rows);
     L.step = at;   // [step counter, epoch] for graph replays
     at = align256(at + 8);
     L.total = at;
@@ -127,6 +131,12 @@ EnvArgs wsx::env_args(const wsx_env* env) {
                                         : nullptr;
     a.tiles = env->kind == WSX_MARKET ? reinterpret_cast<const Tile*>(env->block + env->lay.tiles)
                                       : nullptr;
+    a.row_map = env->kind == WSX_MARKET
+                    ? reinterpret_cast<const int32_t*>(env->block + env->lay.row_map)
+                    : nullptr;
+    a.slot_map = env->kind == WSX_MARKET
+                     ? reinterpret_cast<const uint8_t*>(env->block + env->lay.slot_map)
+                     : nullptr;
     a.step_ptr = nullptr;
     a.n_rows = env->n_rows;
     a.n_envs = (int32_t)env->n_envs;
@@ -219,6 +229,51 @@ PolicyArgs wsx::policy_args(const wsx_policy* p) {
     return a;
 }
 
+// Whole market envs into tiles of at most `cap` agents by first-fit
+// decreasing (envs by agent count, largest first, each into the first tile
+// with room; ties in env order), so the tiles are nearly full: the kernel's
+// time per tile does not depend on its fill, only the number of tiles does.
+// Within a tile the envs keep ascending env order and each env's agents stay
+// together; the row map lists the tiles' rows in tile order, the slot map
+// each row's env index within its tile.
+void wsx::pack_market_tiles(const int32_t* off, int64_t n_envs, int cap, std::vector<Tile>& tiles,
+                            std::vector<int32_t>& row_map, std::vector<uint8_t>& slot_map) {
+    std::vector<int32_t> order((size_t)n_envs);
+    for (int64_t e = 0; e < n_envs; ++e) order[(size_t)e] = (int32_t)e;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return off[a + 1] - off[a] > off[b + 1] - off[b];
+    });
+    std::vector<int> room;                        // free agent slots of each tile
+    std::vector<std::vector<int32_t>> members;    // envs of each tile
+    for (const int32_t e : order) {
+        const int c = off[e + 1] - off[e];
+        size_t t = 0;
+        while (t < room.size() && room[t] < c) ++t;
+        if (t == room.size()) {
+            room.push_back(cap);
+            members.emplace_back();
+        }
+        room[t] -= c;
+        members[t].push_back(e);
+    }
+    tiles.clear();
+    row_map.clear();
+    slot_map.clear();
+    row_map.reserve((size_t)off[n_envs]);
+    slot_map.reserve((size_t)off[n_envs]);
+    for (auto& m : members) {
+        std::sort(m.begin(), m.end());
+        Tile tl{(int32_t)row_map.size(), 0, 0, (int32_t)m.size()};
+        for (size_t i = 0; i < m.size(); ++i)
+            for (int32_t r = off[m[i]]; r < off[m[i] + 1]; ++r) {
+                row_map.push_back(r);
+                slot_map.push_back((uint8_t)i);
+            }
+        tl.row1 = (int32_t)row_map.size();
+        tiles.push_back(tl);
+    }
+}
+
 extern "C" {
 
 const char* wsx_last_error(void) { return g_last_error.c_str(); }
@@ -271,6 +326,8 @@ int wsx_env_create(const wsx_env_desc* d, wsx_env** out) {
 
     int64_t n_rows = d->n_envs;
     std::vector<Tile> tiles;
+    std::vector<int32_t> row_map;
+    std::vector<uint8_t> slot_map;
     if (market) {
         const int32_t* off = d->agent_offsets;
         for (int64_t e = 0; e < d->n_envs; ++e) {
@@ -280,17 +337,7 @@ int wsx_env_create(const wsx_env_desc* d, wsx_env** out) {
                             (long long)c, tile_rows);
         }
         n_rows = off[d->n_envs];
-        // contiguous greedy packing of whole envs into tiles of <= tile_rows agents
-        Tile cur{0, 0, 0, 0};
-        for (int32_t e = 0; e < (int32_t)d->n_envs; ++e) {
-            if (off[e + 1] - cur.row0 > tile_rows) {
-                tiles.push_back(cur);
-                cur = Tile{off[e], off[e], e, e};
-            }
-            cur.row1 = off[e + 1];
-            cur.env1 = e + 1;
-        }
-        tiles.push_back(cur);
+        pack_market_tiles(off, d->n_envs, tile_rows, tiles, row_map, slot_map);
     }
     wsx_env* env = new (std::nothrow) wsx_env();
     if (!env) return fail(WSX_EINVAL, "out of host memory");
@@ -320,6 +367,12 @@ int wsx_env_create(const wsx_env_desc* d, wsx_env** out) {
         if (e == hipSuccess)
             e = hipMemcpy(env->block + env->lay.tiles, tiles.data(), tiles.size() * sizeof(Tile),
                           hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(env->block + env->lay.row_map, row_map.data(), row_map.size() * 4,
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(env->block + env->lay.slot_map, slot_map.data(), slot_map.size(),
+                          hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) {
         delete env;
@@ -334,6 +387,13 @@ int wsx_env_destroy(wsx_env* env) {
     if (env->graph) (void)hipGraphExecDestroy(env->graph);
     if (env->capture_stream) (void)hipStreamDestroy(env->capture_stream);
     delete env;
+    return WSX_OK;
+}
+
+int wsx_env_tiles(const wsx_env* env, int32_t* n_tiles, int32_t* capacity) {
+    if (!env) return fail(WSX_EINVAL, "env is NULL");
+    if (n_tiles) *n_tiles = env->n_tiles;
+    if (capacity) *capacity = env->tile_rows;
     return WSX_OK;
 }
 

@@ -28,7 +28,7 @@ size_t align256(size_t x);
 
 // Byte offsets of the parts of an environment set's device state block.
 struct Layout {
-    size_t state, obs, head, offsets, tiles, step, total;
+    size_t state, obs, head, offsets, tiles, row_map, slot_map, step, total;
 };
 Layout layout_of(const KindInfo& k, int64_t n_envs, int64_t n_rows, bool market);
 
@@ -40,6 +40,11 @@ bool find_variant(int kind, int dtype, int hidden, int waves, int tile_rows, int
 // The fused kernel over tiles of two kinds (either order), same rules.
 bool find_pair_variant(int kind, int kind2, int dtype, int hidden, int waves, int tile_rows,
                        int occupancy, Variant& out);
+
+// Packing of whole market envs into tiles (first-fit decreasing): the tile
+// table, the row map and the slot map of the state block.
+void pack_market_tiles(const int32_t* offsets, int64_t n_envs, int cap, std::vector<Tile>& tiles,
+                       std::vector<int32_t>& row_map, std::vector<uint8_t>& slot_map);
 
 // The autotuner's entry for an environment set, if there is one.
 bool tune_lookup(int32_t kind, int64_t n_envs, int64_t n_rows, int32_t cus, wsx_tune_entry& out);

@@ -35,7 +35,10 @@ struct TrajArgs {
     float* last_value;
 };
 
-// Tile of a workgroup: rows [row0, row1) of envs [env0, env1).
+// Tile of a workgroup: rows [row0, row1) of envs [env0, env1). For the market
+// (tiles packed from whole envs in any order) [row0, row1) is a range of the
+// row map: entry i holds the global row of tile slot i - row0, and the slot
+// map the index of that row's env among the tile's env1 - env0 envs.
 struct Tile {
     int32_t row0, row1, env0, env1;
 };
@@ -48,6 +51,8 @@ struct EnvArgs {
     const float* params;      // reaction potential block (global)
     const int32_t* offsets;   // market CSR offsets [n_envs + 1]
     const Tile* tiles;        // tile table [n_tiles]
+    const int32_t* row_map;   // market: global row of each tile slot [n_rows]
+    const uint8_t* slot_map;  // market: the row's env among its tile's envs [n_rows]
     const uint32_t* step_ptr; // graph mode: device copy of [step counter, epoch]
     int64_t n_rows;
     int32_t n_envs;

@@ -45,8 +45,8 @@ __device__ __forceinline__ void policy_tile(const EnvArgs& env, const PolicyArgs
         mlp.tr_act[1] = act2 + (size_t)tl.row0 * H * L::EB;
         mlp.tr_rows = tl.row1 - tl.row0;
     }
-    const int row = tl.row0 + tid;
-    const bool valid = tid < R && row < tl.row1;
+    const bool valid = tid < R && tl.row0 + tid < tl.row1;
+    const int row = valid ? tile_row(env, tl.row0 + tid) : 0;
     if (valid) {
         float o[E::OD];
 #pragma unroll
@@ -165,8 +165,8 @@ __global__ void __launch_bounds__(256) k_plain_step_market(EnvArgs env, TrajArgs
     for (int r = threadIdx.x, q = 0; q < 2; r += blockDim.x, ++q) {
         slot[q] = -1;
         if (r < n) {
-            const int row = tl.row0 + r;
-            slot[q] = env_slot(env, tl, row);
+            const int row = env.row_map[tl.row0 + r];
+            slot[q] = env.slot_map[tl.row0 + r];
             act[q] = static_cast<const uint8_t*>(tr.action)[(size_t)step * env.n_rows + row];
             int dh, s18;
             Market::decide(act[q], dh, s18);
@@ -177,7 +177,7 @@ __global__ void __launch_bounds__(256) k_plain_step_market(EnvArgs env, TrajArgs
     __syncthreads();
     for (int r = threadIdx.x, q = 0; q < 2; r += blockDim.x, ++q) {
         if (slot[q] < 0) continue;
-        const int64_t row = tl.row0 + r;
+        const int64_t row = env.row_map[tl.row0 + r];
         float s[Market::SD];
         load_state<Market>(env, row, s);
         float reward;

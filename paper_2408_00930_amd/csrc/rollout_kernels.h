@@ -676,14 +676,10 @@ __device__ __forceinline__ Tile tile_of(const EnvArgs& env, int tile) {
     return t;
 }
 
-// Market: slot of row r (global) among the tile's envs (binary search).
-__device__ __forceinline__ int env_slot(const EnvArgs& env, const Tile& tl, int r) {
-    int lo = tl.env0, hi = tl.env1 - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (env.offsets[mid] <= r) lo = mid; else hi = mid - 1;
-    }
-    return lo - tl.env0;
+// Global row of tile entry i (row0 <= i < row1): the market's tiles list their
+// rows in the row map, the other kinds' tiles are row ranges.
+__device__ __forceinline__ int tile_row(const EnvArgs& env, int i) {
+    return env.row_map ? env.row_map[i] : i;
 }
 
 // ---------------------------------------------------------- fused form --
@@ -791,9 +787,9 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
         }
     }
     const Tile tl = tile_of(env, tile - __builtin_amdgcn_readfirstlane(sg.tile_begin));
-    const int row = tl.row0 + rr;
     const bool mine = rr < R;
-    const bool valid = mine && row < tl.row1;
+    const bool valid = mine && tl.row0 + rr < tl.row1;
+    const int row = valid ? tile_row(env, tl.row0 + rr) : tl.row0 + rr;
     const bool lead = valid && sub == 0;   // writes the row's scalar records
     const int drow = tl.row0 + dr;
     const bool dvalid = kDrawLanes && dr >= 0 && dr < R && drow < tl.row1;
@@ -811,7 +807,7 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
     }
     int slot = 0;
     if constexpr (E::KIND == Market::KIND) {
-        if (valid) slot = env_slot(env, tl, row);
+        if (valid) slot = env.slot_map[tl.row0 + rr];
         for (int i = tid; i < 4 * R; i += NTHR) sums[i] = 0;
     }
     if (mine) {

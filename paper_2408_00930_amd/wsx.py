@@ -55,7 +55,8 @@ class _EnvDesc(C.Structure):
 
 EXPORTS = ["wsx_env_state_bytes", "wsx_env_create", "wsx_env_reset", "wsx_rollout",
            "wsx_rollout_batch",
-           "wsx_env_info", "wsx_env_set_step", "wsx_env_set_chunk", "wsx_env_destroy",
+           "wsx_env_info", "wsx_env_tiles", "wsx_env_set_step", "wsx_env_set_chunk",
+           "wsx_env_destroy",
            "wsx_compute_returns",
            "wsx_policy_forward", "wsx_policy_trace", "wsx_quantize", "wsx_last_error"]
 
@@ -76,6 +77,7 @@ def lib():
         L.wsx_env_reset.argtypes = [vp, u32, vp]
         L.wsx_rollout.argtypes = [vp, C.POINTER(_Policy), i32, C.POINTER(_Traj), i32, vp]
         L.wsx_env_info.argtypes = [vp, C.POINTER(i64), C.POINTER(u32), C.POINTER(u32)]
+        L.wsx_env_tiles.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
         L.wsx_env_set_step.argtypes = [vp, u32]
         L.wsx_env_set_chunk.argtypes = [vp, i32]
         L.wsx_env_destroy.argtypes = [vp]
@@ -192,6 +194,12 @@ class Env:
         """The state as a [state_dim, rows] float32 view (structure of arrays)."""
         sd = STATE_DIM[self.kind]
         return self.block[: sd * self.rows * 4].view(torch.float32).view(sd, self.rows)
+
+    def tiles(self):
+        """(tiles of the fused launch, rows one tile holds)."""
+        n, cap = C.c_int32(), C.c_int32()
+        _check(lib().wsx_env_tiles(self.handle, C.byref(n), C.byref(cap)))
+        return n.value, cap.value
 
     def info(self):
         rows, step, epoch = C.c_int64(), C.c_uint32(), C.c_uint32()
