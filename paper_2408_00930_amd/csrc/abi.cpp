@@ -54,7 +54,7 @@ int n_head_of(const KindInfo& k) { return (k.nact ? k.nact : 1) + 1; }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-Layout layout_of(const KindInfo& k, int64_t n_envs, int64_t n_rows, bool market) {
+Layout layout_of(const KindInfo& k, int64_t n_envs, int64_t n_rows, bool market, bool reaction) {
     Layout L{};
     size_t at = 0;
     L.state = at;
@@ -71,6 +71,8 @@ Layout layout_of(const KindInfo& k, int64_t n_envs, int64_t n_rows, bool market)
     if (market) at = align256(at + (size_t)n_rows * 4);
     L.slot_map = at;
     if (market) at = align256(at + (size_t)n_rows);
+    L.cache = at;   // the reaction's FP64 energy terms [NCACHE][n_rows]
+    if (reaction) at = align256(at + (size_t)kReactionCache * n_rows * 8);
     L.step = at;   // [step counter, epoch] for graph replays
     at = align256(at + 8);
     L.total = at;
@@ -137,6 +139,8 @@ EnvArgs wsx::env_args(const wsx_env* env) {
     a.slot_map = env->kind == WSX_MARKET
                      ? reinterpret_cast<const uint8_t*>(env->block + env->lay.slot_map)
                      : nullptr;
+    a.cache = env->kind == WSX_REACTION ? reinterpret_cast<double*>(env->block + env->lay.cache)
+                                        : nullptr;
     a.step_ptr = nullptr;
     a.n_rows = env->n_rows;
     a.n_envs = (int32_t)env->n_envs;
@@ -286,7 +290,7 @@ int wsx_env_state_bytes(int32_t kind, int64_t n_envs, int64_t n_rows, size_t* by
         return fail(WSX_EINVAL, "single-agent kinds have n_rows == n_envs");
     if (n_rows > 0x7FFFFFFF) return fail(WSX_EUNSUPPORTED, "at most 2^31-1 rows");
     if (!bytes) return fail(WSX_EINVAL, "bytes is NULL");
-    *bytes = layout_of(k, n_envs, n_rows, kind == WSX_MARKET).total;
+    *bytes = layout_of(k, n_envs, n_rows, kind == WSX_MARKET, kind == WSX_REACTION).total;
     return WSX_OK;
 }
 
@@ -350,7 +354,7 @@ int wsx_env_create(const wsx_env_desc* d, wsx_env** out) {
     env->epoch = 0;
     env->block = static_cast<char*>(d->state);
     env->params = d->params;
-    env->lay = layout_of(k, d->n_envs, n_rows, market);
+    env->lay = layout_of(k, d->n_envs, n_rows, market, d->kind == WSX_REACTION);
     env->tile_rows = tile_rows;
     env->waves = probe.waves;
     env->occupancy = probe.occupancy;

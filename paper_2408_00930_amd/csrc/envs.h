@@ -18,6 +18,8 @@ namespace wsx {
 
 struct EnvCtx {
     const float* lds_params;  // reaction: potential block staged in LDS
+    double* cache;            // reaction: this row's FP64 energy terms, entry j at
+    int cache_stride;         //   cache[j * cache_stride]
 };
 
 // ------------------------------------------------------------ CartPole --
@@ -274,39 +276,85 @@ struct Reaction {
     static constexpr int KIND = 5, SD = 21, SR = 21, OD = 20, NACT = 40, NDIM = 20, NG = 64, LANES = 16;
     __device__ static void complete(float*) {}
     static constexpr int PARAM_FLOATS = NDIM * NDIM + NG * NDIM + NG + NG;
-    // E(x) with its quadratic rows and its Gaussians dealt over the G lanes of
-    // the row's group (lane `sub` takes those congruent to sub mod G); every
-    // lane returns the same total.
+    // Per row, the energy's terms in FP64 (the row's cache): y = A x (NDIM
+    // entries), then d_k = |x - c_k|^2 (NG entries). A move of coordinate c by
+    // dl (the exact difference of the FP32 coordinates) updates them by
+    // y_i += dl A_ic and d_k += dl (2 (x_c - c_kc) + dl), which are exact
+    // identities: the cache stays the FP64 value of its definition (rounding
+    // of order 1e-16 per step), and a step costs O(NDIM + NG) instead of
+    // O(NDIM^2 + NG NDIM). Lane `sub` of the row's G lanes owns entries
+    // i = sub + m G of y and k = sub + m G of d.
+    static constexpr int NCACHE = NDIM + NG;
     template <int G>
-    __device__ static float energy(const float* x, const float* p, int sub) {
+    __device__ static void cache_init(const float* x, const float* p, const EnvCtx& c, int sub) {
         const float* A = p;
         const float* cen = p + NDIM * NDIM;
-        const float* nhw = cen + NG * NDIM;
+#pragma unroll
+        for (int m = 0; m < (NDIM + G - 1) / G; ++m) {
+            const int i = sub + m * G;
+            if (i < NDIM) {
+                double y = 0.0;
+#pragma unroll
+                for (int j = 0; j < NDIM; ++j) y = __builtin_fma((double)A[i * NDIM + j], (double)x[j], y);
+                c.cache[i * c.cache_stride] = y;
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < NG / G; ++m) {
+            const int k = sub + m * G;
+            double d2 = 0.0;
+#pragma unroll
+            for (int i = 0; i < NDIM; ++i) {
+                const double d = (double)x[i] - (double)cen[k * NDIM + i];
+                d2 = __builtin_fma(d, d, d2);
+            }
+            c.cache[(NDIM + k) * c.cache_stride] = d2;
+        }
+    }
+    template <int G>
+    __device__ static void cache_move(int coord, float x_old, float x_new, const float* p,
+                                      const EnvCtx& c, int sub) {
+        const float* A = p;
+        const float* cen = p + NDIM * NDIM;
+        const double dl = (double)x_new - (double)x_old;   // exact
+#pragma unroll
+        for (int m = 0; m < (NDIM + G - 1) / G; ++m) {
+            const int i = sub + m * G;
+            if (i < NDIM) {
+                double& y = c.cache[i * c.cache_stride];
+                y = __builtin_fma(dl, (double)A[i * NDIM + coord], y);
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < NG / G; ++m) {
+            const int k = sub + m * G;
+            double& d2 = c.cache[(NDIM + k) * c.cache_stride];
+            const double two_off = 2.0 * ((double)x_old - (double)cen[k * NDIM + coord]) + dl;
+            d2 = __builtin_fma(dl, two_off, d2);
+        }
+    }
+    // E(x) = x^T y / 2 + sum_k a_k exp(-d_k / (2 w_k^2)) from the cache, the
+    // lane's terms in FP32, summed over the row's lanes; every lane returns
+    // the same total.
+    template <int G>
+    __device__ static float energy(const float* x, const float* p, const EnvCtx& c, int sub) {
+        const float* nhw = p + NDIM * NDIM + NG * NDIM;
         const float* amp = nhw + NG;
         float part = 0.0f;
 #pragma unroll
         for (int m = 0; m < (NDIM + G - 1) / G; ++m) {
             const int i = sub + m * G;
             if (i < NDIM) {
-                float row = 0.0f, xi = 0.0f;
+                float xi = 0.0f;
 #pragma unroll
-                for (int j = 0; j < NDIM; ++j) {
-                    row += A[i * NDIM + j] * x[j];
-                    xi = j == i ? x[j] : xi;
-                }
-                part += 0.5f * xi * row;
+                for (int j = 0; j < NDIM; ++j) xi = j == i ? x[j] : xi;
+                part += 0.5f * xi * (float)c.cache[i * c.cache_stride];
             }
         }
 #pragma unroll
         for (int m = 0; m < NG / G; ++m) {
             const int k = sub + m * G;
-            float d2 = 0.0f;
-#pragma unroll
-            for (int i = 0; i < NDIM; ++i) {
-                const float d = x[i] - cen[k * NDIM + i];
-                d2 += d * d;
-            }
-            part += amp[k] * expf(d2 * nhw[k]);
+            part += amp[k] * expf((float)c.cache[(NDIM + k) * c.cache_stride] * nhw[k]);
         }
         return group_sum<G>(part);
     }
@@ -316,7 +364,7 @@ struct Reaction {
         const Words w = draw(key, t, row, PURPOSE_NOISE, 0);
         float zc, zs;
         gauss_pair(unit_uniform(w.w[0]), unit_uniform(w.w[1]), zc, zs);
-        return energy<G>(x, c.lds_params, sub) + 0.05f * zc;
+        return energy<G>(x, c.lds_params, c, sub) + 0.05f * zc;
     }
     __device__ static void reset(float* s, const RngKey& key, uint32_t t, uint32_t row,
                                  const EnvCtx& c) {
@@ -326,6 +374,7 @@ struct Reaction {
 #pragma unroll
             for (int i = 0; i < 4; ++i) s[4 * sub + i] = -3.0f + 6.0f * unit_uniform(w.w[i]);
         }
+        cache_init<1>(s, c.lds_params, c, 0);
         s[20] = noisy_energy<1>(s, key, t, row, c, 0);
     }
     __device__ static void observe(const float* s, float* o) {
@@ -339,11 +388,15 @@ struct Reaction {
         const float delta = (a & 1) ? -0.05f : 0.05f;
         // a select per coordinate keeps the state in registers (a branch on
         // the coordinate would index the array dynamically)
+        float x_old = 0.0f, x_new = 0.0f;
 #pragma unroll
         for (int i = 0; i < 20; ++i) {
             const float moved = s[i] + delta;
+            x_old = i == coord ? s[i] : x_old;
+            x_new = i == coord ? moved : x_new;
             s[i] = i == coord ? moved : s[i];
         }
+        cache_move<G>(coord, x_old, x_new, c.lds_params, c, sub);
         const float e_new = noisy_energy<G>(s, key, t + 1, row, c, sub);
         reward = -(e_new - s[20]);
         s[20] = e_new;

@@ -28,9 +28,10 @@ size_t align256(size_t x);
 
 // Byte offsets of the parts of an environment set's device state block.
 struct Layout {
-    size_t state, obs, head, offsets, tiles, row_map, slot_map, step, total;
+    size_t state, obs, head, offsets, tiles, row_map, slot_map, cache, step, total;
 };
-Layout layout_of(const KindInfo& k, int64_t n_envs, int64_t n_rows, bool market);
+Layout layout_of(const KindInfo& k, int64_t n_envs, int64_t n_rows, bool market,
+                 bool reaction = false);
 
 // The compiled kernel with the fewest row slots >= tile_rows; waves /
 // occupancy 0 match any compiled value.

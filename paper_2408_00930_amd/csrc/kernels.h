@@ -53,6 +53,7 @@ struct EnvArgs {
     const Tile* tiles;        // tile table [n_tiles]
     const int32_t* row_map;   // market: global row of each tile slot [n_rows]
     const uint8_t* slot_map;  // market: the row's env among its tile's envs [n_rows]
+    double* cache;            // reaction: FP64 energy terms [Reaction::NCACHE][n_rows]
     const uint32_t* step_ptr; // graph mode: device copy of [step counter, epoch]
     int64_t n_rows;
     int32_t n_envs;
@@ -62,6 +63,10 @@ struct EnvArgs {
     uint32_t t0;              // step counter at the start of the launch; with
                               // step_ptr, its offset from the device counter
 };
+
+// Entries of the reaction's per-row FP64 energy cache (A x, then the squared
+// distances to the Gaussians' centres).
+constexpr int kReactionCache = 20 + 64;
 
 // One roll-out request inside a fused launch: its environment set, its policy,
 // its trajectory pointers (offset to the launch's first slot) and its steps.

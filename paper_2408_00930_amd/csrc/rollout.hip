@@ -126,7 +126,7 @@ template <class E, int G>
 __global__ void __launch_bounds__(256) k_plain_step(EnvArgs env, TrajArgs tr, int step,
                                                     int horizon) {
     __shared__ float params[E::KIND == Reaction::KIND ? Reaction::PARAM_FLOATS : 1];
-    EnvCtx ctx{nullptr};
+    EnvCtx ctx{nullptr, nullptr, 0};
     if constexpr (E::KIND == Reaction::KIND) {
         // every block stages the potential (the plain form re-reads it per launch)
         stage_params(params, env.params, threadIdx.x, blockDim.x);
@@ -136,6 +136,11 @@ __global__ void __launch_bounds__(256) k_plain_step(EnvArgs env, TrajArgs tr, in
     const int sub = threadIdx.x % G;
     const int64_t row = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
     if (row >= env.n_rows) return;
+    if constexpr (E::KIND == Reaction::KIND) {
+        // the row's cache in place in the state block (each lane its own entries)
+        ctx.cache = env.cache + row;
+        ctx.cache_stride = (int)env.n_rows;
+    }
     const RngKey key = rng_key(env);
     const uint32_t t = step_base(env) + (uint32_t)step;
     float s[E::SR];

@@ -28,6 +28,8 @@
 
 namespace wsx {
 
+static_assert(Reaction::NCACHE == kReactionCache, "one reaction cache size");
+
 // ------------------------------------------------------ per-kind shapes --
 template <class E>
 struct HeadOf {
@@ -647,9 +649,15 @@ __device__ __forceinline__ void stage_params(float* dst, const float* src, int t
     }
 }
 
+// The reaction's LDS: the potential block, then the cache of the tile's rows,
+// row-major with an odd pitch of doubles so that the lanes of a row (entries
+// sub + m G) and the rows of a wave fall on different banks.
+constexpr int kRxCacheOff = (Reaction::PARAM_FLOATS * 4 + 15) / 16 * 16;
+constexpr int kRxCachePitch = Reaction::NCACHE + 1;
+
 template <class E>
 constexpr int extra_lds_bytes(int R) {
-    if constexpr (E::KIND == Reaction::KIND) return Reaction::PARAM_FLOATS * 4;
+    if constexpr (E::KIND == Reaction::KIND) return kRxCacheOff + kRxCachePitch * R * 8;
     if constexpr (E::KIND == Market::KIND) return 2 * R * 2 * 4;   // [parity][slot][D, S]
     return 0;
 }
@@ -770,7 +778,8 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
 #pragma unroll
     for (int c = 0; c < C; ++c) b3b[c] = j0 + c < HO::NOUT ? pol.b3[j0 + c] : 0.0f;
     const float b3v = pol.b3[HO::NOUT];
-    EnvCtx ctx{reinterpret_cast<const float*>(extra)};
+    EnvCtx ctx{reinterpret_cast<const float*>(extra), nullptr, 1};
+    double* const lds_cache = reinterpret_cast<double*>(extra + kRxCacheOff);   // reaction
     int* sums = reinterpret_cast<int*>(extra);   // market: [2][R][2]
     // the segment's fields the steps use, read once from LDS into scalar
     // registers (they are uniform over the workgroup)
@@ -804,6 +813,15 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
     if (valid) {
         if constexpr (kSlice) load_slice<E, G>(env, row, s, sub);
         else load_state<E>(env, row, s);
+    }
+    if constexpr (E::KIND == Reaction::KIND) {
+        // the tile's cache into LDS (rows are consecutive for this kind)
+        for (int i = tid; i < Reaction::NCACHE * R; i += NTHR) {
+            const int r = i % R, j = i / R;
+            if (tl.row0 + r < tl.row1)
+                lds_cache[r * kRxCachePitch + j] = env.cache[(size_t)j * env.n_rows + tl.row0 + r];
+        }
+        ctx.cache = lds_cache + (mine ? rr : 0) * kRxCachePitch;
     }
     int slot = 0;
     if constexpr (E::KIND == Market::KIND) {
@@ -918,6 +936,14 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
         if constexpr (kSlice) save_slice<E, G>(env, row, s, sub);
         else save_state<E, G>(env, row, s, sub);
     }
+    if constexpr (E::KIND == Reaction::KIND) {
+        __syncthreads();   // every lane's last cache update is in LDS
+        for (int i = tid; i < Reaction::NCACHE * R; i += NTHR) {
+            const int r = i % R, j = i / R;
+            if (tl.row0 + r < tl.row1)
+                env.cache[(size_t)j * env.n_rows + tl.row0 + r] = lds_cache[r * kRxCachePitch + j];
+        }
+    }
 }
 
 // Persistent fused roll-out: each workgroup walks tiles of the launch's
@@ -976,7 +1002,7 @@ k_fused(Batch batch) {
 template <class E>
 __global__ void k_reset(EnvArgs env) {
     __shared__ float params[E::KIND == Reaction::KIND ? Reaction::PARAM_FLOATS : 1];
-    EnvCtx ctx{nullptr};
+    EnvCtx ctx{nullptr, nullptr, 0};
     if constexpr (E::KIND == Reaction::KIND) {
         stage_params(params, env.params, threadIdx.x, blockDim.x);
         ctx.lds_params = params;
@@ -984,6 +1010,10 @@ __global__ void k_reset(EnvArgs env) {
     __syncthreads();
     const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= env.n_rows) return;
+    if constexpr (E::KIND == Reaction::KIND) {
+        ctx.cache = env.cache + row;
+        ctx.cache_stride = (int)env.n_rows;
+    }
     const RngKey key{env.k0, env.k1, env.epoch};
     float s[E::SR];
     E::reset(s, key, 0u, (uint32_t)row, ctx);

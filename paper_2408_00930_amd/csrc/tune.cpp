@@ -53,7 +53,7 @@ struct Trial {
 
 Trial trial_layout(const KindInfo& k, int kind, int64_t n_envs, int64_t n_rows, int32_t horizon) {
     Trial t;
-    t.state_bytes = layout_of(k, n_envs, n_rows, kind == WSX_MARKET).total;
+    t.state_bytes = layout_of(k, n_envs, n_rows, kind == WSX_MARKET, kind == WSX_REACTION).total;
     size_t at = align256(t.state_bytes);
     const size_t slots = (size_t)horizon * (size_t)n_rows;
     const size_t sizes[7] = {slots * (size_t)k.od * 4, slots * (k.nact ? 1 : 4), slots * 4, slots,
