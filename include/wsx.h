@@ -103,9 +103,13 @@ typedef struct {
     float* last_value;       /* [rows] V(s_T) of the state after the last step    */
 } wsx_traj;
 
-/* Size in bytes of the device state block an environment set needs
- * (state, per-step scratch for the PLAIN mode, and for the market the CSR
- * offsets and the tile table). n_rows: agents (market) or n_envs. */
+/* Size in bytes of the device state block an environment set needs (Sec. 2
+ * and App. B: every replica's state lives in device memory for the whole
+ * run): the state, per-step scratch for the PLAIN mode, for the market the
+ * CSR offsets, the tile table and its row and slot maps, for the reaction
+ * walk its FP64 energy terms. n_rows: agents (market) or n_envs. Errors:
+ * WSX_EINVAL (unknown kind, n_envs <= 0, n_rows < n_envs, single-agent kinds
+ * with n_rows != n_envs, NULL bytes), WSX_EUNSUPPORTED (n_rows >= 2^31). */
 int wsx_env_state_bytes(int32_t kind, int64_t n_envs, int64_t n_rows, size_t* bytes);
 
 typedef struct {
@@ -149,7 +153,9 @@ int wsx_env_reset(wsx_env* env, uint32_t epoch, void* stream);
 int wsx_rollout(wsx_env* env, const wsx_policy* policy, int32_t horizon,
                 const wsx_traj* traj, int32_t mode, void* stream);
 
-/* Number of rows, current step counter and epoch of an environment set. */
+/* Number of rows, current step counter and epoch of an environment set
+ * (App. B: the step counter and the reset epoch key each replica's random
+ * streams). Any pointer may be NULL. Errors: WSX_EINVAL (env NULL). */
 int wsx_env_info(const wsx_env* env, int64_t* n_rows, uint32_t* step, uint32_t* epoch);
 
 /* Several environment sets in ONE persistent fused launch (App. B: many
@@ -174,7 +180,8 @@ int wsx_rollout_batch(wsx_env* const* envs, const wsx_policy* const* policies,
  * is the tiles' fill. */
 int wsx_env_tiles(const wsx_env* env, int32_t* n_tiles, int32_t* capacity);
 
-/* Sets the step counter (resuming from a saved state block). */
+/* Sets the step counter (resuming from a saved state block: App. B, the
+ * roll-out continues in place). Errors: WSX_EINVAL (env NULL). */
 int wsx_env_set_step(wsx_env* env, uint32_t step);
 
 /* Steps per fused launch in WSX_MODE_FUSED_GRAPH (0 = the whole horizon in
@@ -182,8 +189,9 @@ int wsx_env_set_step(wsx_env* env, uint32_t step);
  * depend on it. */
 int wsx_env_set_chunk(wsx_env* env, int32_t chunk_steps);
 
-/* Releases the host handle (and cached graphs); the state block is the
- * caller's. */
+/* Releases the host handle and its cached graphs (App. B: the state stays in
+ * device memory, owned by the caller, who frees the state block after this
+ * call). Errors: WSX_EINVAL (env NULL). */
 int wsx_env_destroy(wsx_env* env);
 
 /* Discounted returns and GAE advantages (Sec. 3, actor-critic), FP64:
@@ -221,7 +229,11 @@ int wsx_policy_trace(const wsx_env* env, const wsx_policy* policy, const float* 
 
 /* Rounds n floats to `dtype` (WSX_BF16: RNE; WSX_FP8_E4M3: s * fp8(x / s),
  * RNE, saturating) with the device conversion the kernels use and returns
- * the real values as float. */
+ * the real values as float: the quantisation points of the policy forward
+ * (the paper runs policy inference on the device, App. B, and fixes no
+ * precision; these formats are this library's). x, y: device [n] float,
+ * caller-owned. Errors: WSX_EINVAL (unknown dtype, scale not a positive power
+ * of two, n < 0, NULL pointers), WSX_EHIP. */
 int wsx_quantize(int32_t dtype, float scale, const float* x, float* y, int64_t n, void* stream);
 
 /* ------------------------------------------------------------------------ */
@@ -421,12 +433,17 @@ int wsx_tune_lookup(int32_t kind, int64_t n_envs, int64_t n_rows, int32_t cus,
 int wsx_tune_save(const char* path);
 int wsx_tune_load(const char* path);
 
-/* The kernel shape and chunk length an environment set runs with. */
+/* The kernel shape and chunk length an environment set runs with (App. B: a
+ * block per environment instance; here rows per workgroup tile, waves per
+ * workgroup, occupancy). Any pointer may be NULL. Errors: WSX_EINVAL. */
 int wsx_env_shape(const wsx_env* env, int32_t* tile_rows, int32_t* waves, int32_t* occupancy,
                   int32_t* chunk_steps);
 
 /* ------------------------------------------------------------------------ */
 /* Roll-out server: continuous batching of roll-out requests.                */
+/* The paper has no serving layer: it keeps thousands of replicas and their  */
+/* roll-out data resident on one GPU (Sec. 2, App. B). The server applies    */
+/* that to a stream of independent requests.                                 */
 /*                                                                          */
 /* Requests (an environment kind, a number of replicas, a horizon, a policy) */
 /* are submitted from any thread and run by a scheduler thread inside the    */
@@ -488,7 +505,10 @@ typedef struct {
 } wsx_server_stats;
 
 /* Creates the server and starts its scheduler thread (streams at default
- * priority are created on the current device). */
+ * priority are created on the current device). desc->arena: caller-owned
+ * device memory, kept until wsx_server_destroy. Errors: WSX_EINVAL (NULL
+ * arguments, empty arena, arena smaller than the launch tables,
+ * chunk_steps or max_batch <= 0), WSX_EHIP. */
 int wsx_server_create(const wsx_server_desc* desc, wsx_server** out);
 
 /* Queues a request; returns its id. Fails with WSX_EINVAL if its memory can
@@ -500,19 +520,23 @@ int wsx_server_submit(wsx_server* srv, const wsx_request* req, int64_t* id);
 int wsx_server_wait(wsx_server* srv, int64_t id, int32_t timeout_ms, wsx_result* out);
 
 /* Frees a completed request's trajectory and returns (and its session unless
- * it was kept). */
+ * it was kept). Errors: WSX_EINVAL (unknown id), WSX_ESTATE (not completed). */
 int wsx_server_release(wsx_server* srv, int64_t id);
 
-/* Frees a kept session that no request is using. */
+/* Frees a kept session that no request is using. Errors: WSX_EINVAL (unknown
+ * session), WSX_ESTATE (a request is using it). */
 int wsx_server_close_session(wsx_server* srv, int64_t session);
 
+/* Counters of the server since its creation (requests, launches, replica
+ * steps, arena use). Errors: WSX_EINVAL (NULL arguments). */
 int wsx_server_get_stats(wsx_server* srv, wsx_server_stats* out);
 
 /* Stops the scheduler after the device work in flight ends and frees the
  * server (the arena is the caller's). */
 int wsx_server_destroy(wsx_server* srv);
 
-/* Human-readable description of the last error on the calling thread. */
+/* Human-readable description of the last error on the calling thread
+ * (thread-local, valid until the thread's next call into the library). */
 const char* wsx_last_error(void);
 
 #ifdef __cplusplus

@@ -24,6 +24,7 @@
 #include <thread>
 #include <vector>
 
+#include "admission.h"
 #include "internal.h"
 #include "kernels.h"
 
@@ -33,57 +34,6 @@ using Clock = std::chrono::steady_clock;
 namespace {
 
 constexpr int kMaxGroups = 8;
-
-// First-fit sub-allocator over the arena (256-byte granules, neighbours merge).
-class Arena {
-public:
-    void init(char* base, size_t size) {
-        base_ = base;
-        size_ = size;
-        free_.clear();
-        if (size) free_[0] = size;
-    }
-    bool alloc(size_t bytes, size_t* off) {
-        bytes = align256(bytes);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second < bytes) continue;
-            *off = it->first;
-            const size_t rest = it->second - bytes, next = it->first + bytes;
-            free_.erase(it);
-            if (rest) free_[next] = rest;
-            in_use_ += bytes;
-            peak_ = std::max(peak_, in_use_);
-            return true;
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes) {
-        bytes = align256(bytes);
-        in_use_ -= bytes;
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-    char* at(size_t off) const { return base_ + off; }
-    size_t in_use() const { return in_use_; }
-    size_t peak() const { return peak_; }
-
-private:
-    char* base_ = nullptr;
-    size_t size_ = 0;
-    std::map<size_t, size_t> free_;
-    size_t in_use_ = 0, peak_ = 0;
-};
 
 struct Session {
     wsx_env* env = nullptr;
@@ -142,7 +92,8 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
 
 struct wsx_server {
     wsx_server_desc desc{};
-    Arena arena;
+    Arena arena;          // offsets into [arena_base, arena_base + arena_bytes)
+    char* arena_base = nullptr;
     std::mutex mu;
     std::condition_variable cv_done, cv_work;
     std::thread worker;
@@ -172,7 +123,7 @@ int group_of(wsx_server* S, int kind, const wsx_policy& p) {
         return -1;
     // launch tables sit at the start of the arena, reserved at creation
     g.dev_table = reinterpret_cast<Segment*>(
-        S->arena.at(align256(sizeof(Segment) * S->desc.max_batch) * S->groups.size()));
+        S->arena_base + align256(sizeof(Segment) * S->desc.max_batch) * S->groups.size());
     S->groups.push_back(g);
     return (int)S->groups.size() - 1;
 }
@@ -227,7 +178,7 @@ bool try_admit(wsx_server* S, Request* r) {
         d.occupancy = k.occupancy;
         d.n_envs = r->req.n_envs;
         d.seed = r->req.seed;
-        d.state = S->arena.at(soff);
+        d.state = S->arena_base + soff;
         d.agent_offsets = r->req.kind == WSX_MARKET ? r->offsets.data() : nullptr;
         d.params = r->req.params;
         wsx_env* env = nullptr;
@@ -257,7 +208,7 @@ bool try_admit(wsx_server* S, Request* r) {
     r->bytes = tb;
     // carve the trajectory and the returns out of the block
     const size_t n = (size_t)r->rows * (size_t)r->req.horizon;
-    char* p = S->arena.at(toff);
+    char* p = S->arena_base + toff;
     auto take = [&p](size_t bytes) {
         char* q = p;
         p += align256(bytes);
@@ -280,26 +231,19 @@ bool try_admit(wsx_server* S, Request* r) {
 }
 
 bool admit(wsx_server* S) {
-    bool any = false;
     const auto now = Clock::now();
-    for (auto it = S->queue.begin(); it != S->queue.end();) {
-        Request* r = S->requests[*it].get();
-        const bool head = it == S->queue.begin();
-        if (try_admit(S, r)) {
+    return admit_in_order(
+        S->queue, 100.0,
+        [&](int64_t id) {
+            Request* r = S->requests[id].get();
+            if (!try_admit(S, r)) return false;
             if (r->status < 0) {
                 r->t_done = Clock::now();
                 S->cv_done.notify_all();
             }
-            it = S->queue.erase(it);
-            any = true;
-        } else {
-            // a request waiting long at the head of the queue stops later ones
-            // from overtaking it, so large requests are not starved
-            if (head && ms_between(r->t_submit, now) > 100.0) break;
-            ++it;
-        }
-    }
-    return any;
+            return true;
+        },
+        [&](int64_t id) { return ms_between(S->requests[id]->t_submit, now); });
 }
 
 void fail_request(wsx_server* S, Request* r, int code) {
@@ -508,7 +452,8 @@ int wsx_server_create(const wsx_server_desc* desc, wsx_server** out) {
     wsx_server* S = new (std::nothrow) wsx_server();
     if (!S) return fail(WSX_EINVAL, "out of host memory");
     S->desc = *desc;
-    S->arena.init(static_cast<char*>(desc->arena), desc->arena_bytes);
+    S->arena_base = static_cast<char*>(desc->arena);
+    S->arena.init(desc->arena_bytes);
     size_t off;
     S->arena.alloc(reserve, &off);   // the launch tables of up to kMaxGroups groups
     const hipError_t e = hipGetDevice(&S->device);
