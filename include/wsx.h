@@ -40,6 +40,7 @@ extern "C" {
 #define WSX_EHIP (-3)          /* the HIP runtime reported an error                */
 #define WSX_ESTATE (-4)        /* object used in a state that does not allow it    */
 #define WSX_ETIMEOUT (-5)      /* a wait ended before the request completed        */
+#define WSX_ECANCELED (-6)     /* the request was cancelled                        */
 
 /* Environment kinds (App. C example families; dynamics are the project's
  * readings, see the design notes). */
@@ -522,6 +523,22 @@ int wsx_server_wait(wsx_server* srv, int64_t id, int32_t timeout_ms, wsx_result*
 /* Frees a completed request's trajectory and returns (and its session unless
  * it was kept). Errors: WSX_EINVAL (unknown id), WSX_ESTATE (not completed). */
 int wsx_server_release(wsx_server* srv, int64_t id);
+
+/* Cancels a request: a queued one leaves the queue, a running one gets no
+ * further rounds and ends once its rounds on the device have ended; either
+ * way its status becomes WSX_ECANCELED (wsx_server_wait returns it) and its
+ * memory is freed by wsx_server_release. Other requests are unaffected.
+ * Errors: WSX_EINVAL (unknown id), WSX_ESTATE (already ended, or its last
+ * round and returns are already on the device). */
+int wsx_server_cancel(wsx_server* srv, int64_t id);
+
+/* Test support for failure isolation (not an operation of the method):
+ * marks request `id` so that its next launch is reported as failed. The
+ * round's shared launch is then replaced by one launch per request, and
+ * only the marked request ends, with WSX_EHIP, once its earlier rounds have
+ * ended; the others run on. Errors: WSX_EINVAL (unknown id), WSX_ESTATE
+ * (already ended). */
+int wsx_server_inject_launch_failure(wsx_server* srv, int64_t id);
 
 /* Frees a kept session that no request is using. Errors: WSX_EINVAL (unknown
  * session), WSX_ESTATE (a request is using it). */

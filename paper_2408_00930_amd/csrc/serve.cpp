@@ -56,20 +56,34 @@ struct Request {
     float* adv = nullptr;
     int32_t issued = 0, finished = 0;   // steps launched / completed on the device
     bool returns_issued = false;
+    int32_t end_status = 0;      // nonzero: no further rounds; the request ends with
+                                 // this status once its rounds in flight end
+                                 // (WSX_ECANCELED, or WSX_EHIP after a failed launch)
+    bool inject_fail = false;    // test hook: its next launch is reported failed
     hipEvent_t done_ev = nullptr;
     int group = -1;
     Clock::time_point t_submit, t_admit, t_done;
+};
+
+// One issued round of a group: its launch table and the (request, steps) it
+// covers. A group keeps up to kSlots rounds queued on its stream, so the next
+// round is on the device before the current one ends.
+constexpr int kSlots = 2;
+struct Round {
+    hipEvent_t ev = nullptr;
+    bool inflight = false;
+    std::vector<std::pair<int64_t, int32_t>> members;
+    Segment* host_table = nullptr;   // pinned
+    Segment* dev_table = nullptr;    // in the arena
 };
 
 struct Group {
     int kind = 0;
     wsx_policy policy{};
     hipStream_t stream = nullptr;
-    hipEvent_t ev = nullptr;
-    bool inflight = false;
-    std::vector<std::pair<int64_t, int32_t>> members;   // (request, steps) in flight
-    Segment* host_table = nullptr;   // pinned
-    Segment* dev_table = nullptr;    // in the arena
+    Round round[kSlots];
+    std::deque<int> order;   // slots in flight, oldest first (stream order)
+    int next = 0;            // the slot the next round uses
 };
 
 size_t traj_bytes(const KindInfo& k, int64_t rows, int32_t T) {
@@ -118,12 +132,17 @@ int group_of(wsx_server* S, int kind, const wsx_policy& p) {
     g.kind = kind;
     g.policy = p;
     if (hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking) != hipSuccess) return -1;
-    if (hipEventCreateWithFlags(&g.ev, hipEventDisableTiming) != hipSuccess) return -1;
-    if (hipHostMalloc((void**)&g.host_table, sizeof(Segment) * S->desc.max_batch) != hipSuccess)
-        return -1;
-    // launch tables sit at the start of the arena, reserved at creation
-    g.dev_table = reinterpret_cast<Segment*>(
-        S->arena_base + align256(sizeof(Segment) * S->desc.max_batch) * S->groups.size());
+    for (int k = 0; k < kSlots; ++k) {
+        Round& rd = g.round[k];
+        if (hipEventCreateWithFlags(&rd.ev, hipEventDisableTiming) != hipSuccess) return -1;
+        if (hipHostMalloc((void**)&rd.host_table, sizeof(Segment) * S->desc.max_batch) !=
+            hipSuccess)
+            return -1;
+        // launch tables sit at the start of the arena, reserved at creation
+        rd.dev_table = reinterpret_cast<Segment*>(
+            S->arena_base +
+            align256(sizeof(Segment) * S->desc.max_batch) * (S->groups.size() * kSlots + k));
+    }
     S->groups.push_back(g);
     return (int)S->groups.size() - 1;
 }
@@ -252,22 +271,75 @@ void fail_request(wsx_server* S, Request* r, int code) {
     S->sessions[r->session].busy = false;
 }
 
-void fail_group(wsx_server* S, Group& g, int code) {
-    for (auto& m : g.members) fail_request(S, S->requests[m.first].get(), code);
-    g.members.clear();
-    g.inflight = false;
+// A round's member, or nullptr if the caller has released it: a request that
+// completed in a round is marked done by its own event, recorded before the
+// round's, so it can be released while the round's event is still pending.
+Request* member(wsx_server* S, int64_t id) {
+    auto it = S->requests.find(id);
+    return it == S->requests.end() ? nullptr : it->second.get();
+}
+
+void fail_round(wsx_server* S, Round& rd, int code) {
+    for (auto& m : rd.members) {
+        Request* r = member(S, m.first);
+        if (r && r->status == 1) fail_request(S, r, code);
+    }
+    rd.members.clear();
+    rd.inflight = false;
     S->cv_done.notify_all();
 }
 
+// The returns of a request whose last round was just enqueued, right behind
+// it on the group's stream, and the event that marks the request complete.
+void issue_returns(wsx_server* S, Request* r, hipStream_t stream) {
+    hipError_t e = launch_returns(r->traj.reward, r->traj.value, r->traj.done,
+                                  r->traj.last_value, r->req.horizon, r->rows, r->req.gamma,
+                                  r->req.lambda, 1, r->ret, r->adv, 0, stream);
+    if (e == hipSuccess && !r->done_ev) e = hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(r->done_ev, stream);
+    r->returns_issued = true;
+    if (e != hipSuccess) {
+        fail_request(S, r, WSX_EHIP);
+        S->cv_done.notify_all();
+    }
+}
+
+// The segment of request r's next `steps` steps (advances its counters).
+Segment next_segment(wsx_server* S, Request* r, int32_t steps, int32_t tile_begin) {
+    wsx_env* env = S->sessions[r->session].env;
+    const size_t base = (size_t)r->issued * (size_t)r->rows;
+    Segment sg{};
+    sg.env = env_args(env);
+    sg.tr.obs = r->traj.obs + base * env->info.od;
+    sg.tr.action = static_cast<char*>(r->traj.action) + base * (env->info.nact ? 1 : 4);
+    sg.tr.reward = r->traj.reward + base;
+    sg.tr.done = r->traj.done + base;
+    sg.tr.value = r->traj.value + base;
+    sg.tr.logp = r->traj.logp + base;
+    sg.tr.last_value = r->traj.last_value;
+    sg.pol = policy_args(&r->policy);
+    sg.steps = steps;
+    sg.tile_begin = tile_begin;
+    sg.last = r->issued + steps == r->req.horizon ? 1 : 0;   // V(s_T) once, at the end
+    env->step += (uint32_t)steps;
+    r->issued += steps;
+    return sg;
+}
+
+// Issues, per group with a free slot, one round covering the next chunk of
+// every admitted request of the group (up to max_batch), as one fused launch.
+// If that launch fails, each member is launched on its own so that only the
+// request whose launch fails is failed.
 bool launch_rounds(wsx_server* S) {
     bool any = false;
     for (size_t gi = 0; gi < S->groups.size(); ++gi) {
         Group& g = S->groups[gi];
-        if (g.inflight) continue;
+        if ((int)g.order.size() >= kSlots) continue;
         std::vector<Request*> batch;
         for (auto& kv : S->requests) {
             Request* r = kv.second.get();
-            if (r->status == 1 && r->group == (int)gi && r->issued < r->req.horizon)
+            if (r->status == 1 && r->group == (int)gi && r->issued < r->req.horizon &&
+                r->end_status == 0)
                 batch.push_back(r);
             if ((int)batch.size() == S->desc.max_batch) break;
         }
@@ -284,47 +356,76 @@ bool launch_rounds(wsx_server* S) {
             S->cv_done.notify_all();
             continue;
         }
+        const int slot = g.next;
+        Round& rd = g.round[slot];
         int32_t tiles = 0;
+        bool injected = false;
+        std::vector<std::pair<Request*, int32_t>> plan;
         for (size_t i = 0; i < batch.size(); ++i) {
             Request* r = batch[i];
-            wsx_env* env = S->sessions[r->session].env;
             const int32_t steps = std::min(S->desc.chunk_steps, r->req.horizon - r->issued);
-            const size_t base = (size_t)r->issued * (size_t)r->rows;
-            Segment sg{};
-            sg.env = env_args(env);
-            sg.tr.obs = r->traj.obs + base * env->info.od;
-            sg.tr.action = static_cast<char*>(r->traj.action) + base * (env->info.nact ? 1 : 4);
-            sg.tr.reward = r->traj.reward + base;
-            sg.tr.done = r->traj.done + base;
-            sg.tr.value = r->traj.value + base;
-            sg.tr.logp = r->traj.logp + base;
-            sg.tr.last_value = r->traj.last_value;
-            sg.pol = policy_args(&r->policy);
-            sg.steps = steps;
-            sg.tile_begin = tiles;
-            sg.last = r->issued + steps == r->req.horizon ? 1 : 0;   // V(s_T) once, at the end
-            tiles += env->n_tiles;
-            g.host_table[i] = sg;
-            env->step += (uint32_t)steps;
-            r->issued += steps;
-            g.members.push_back({r->id, steps});
+            plan.push_back({r, steps});
+            injected |= r->inject_fail;
+            rd.host_table[i] = next_segment(S, r, steps, tiles);
+            tiles += S->sessions[r->session].env->n_tiles;
         }
-        hipError_t e = hipMemcpyAsync(g.dev_table, g.host_table, sizeof(Segment) * batch.size(),
-                                      hipMemcpyHostToDevice, g.stream);
-        Batch b{};
-        b.table = g.dev_table;
-        b.n_segs = (int32_t)batch.size();
-        b.n_tiles = tiles;
         const wsx_env* env0 = S->sessions[batch[0]->session].env;
-        const int grid = std::max(1, std::min(tiles, env0->cus * fused_blocks_per_cu(v)));
-        if (e == hipSuccess) e = launch_fused(v, b, grid, g.stream);
-        if (e == hipSuccess) e = hipEventRecord(g.ev, g.stream);
-        g.inflight = true;
-        if (e != hipSuccess) {
-            fail_group(S, g, WSX_EHIP);
-            continue;
+        const int per_cu = fused_blocks_per_cu(v);
+        hipError_t e = hipMemcpyAsync(rd.dev_table, rd.host_table, sizeof(Segment) * batch.size(),
+                                      hipMemcpyHostToDevice, g.stream);
+        if (e == hipSuccess && !injected) {
+            Batch b{};
+            b.table = rd.dev_table;
+            b.n_segs = (int32_t)batch.size();
+            b.n_tiles = tiles;
+            e = launch_fused(v, b, std::max(1, std::min(tiles, env0->cus * per_cu)), g.stream);
+            if (e == hipSuccess) S->st.launches++;
         }
-        S->st.launches++;
+        rd.members.clear();
+        if (e != hipSuccess || injected) {
+            // one launch per member (inline segment): only a member whose own
+            // launch fails is failed
+            for (size_t i = 0; i < plan.size(); ++i) {
+                Request* r = plan[i].first;
+                Segment sg = rd.host_table[i];
+                sg.tile_begin = 0;
+                const int32_t n_tiles = S->sessions[r->session].env->n_tiles;
+                hipError_t ei = hipSuccess;
+                if (r->inject_fail) {
+                    r->inject_fail = false;
+                    ei = hipErrorLaunchFailure;
+                } else {
+                    Batch b{};
+                    b.inl[0] = sg;
+                    b.n_segs = 1;
+                    b.n_tiles = n_tiles;
+                    ei = launch_fused(v, b, std::max(1, std::min(n_tiles, env0->cus * per_cu)),
+                                      g.stream);
+                }
+                if (ei != hipSuccess) {
+                    // its earlier rounds may still be writing its memory: it
+                    // ends when they have (poll), without these steps
+                    r->issued -= plan[i].second;
+                    S->sessions[r->session].env->step -= (uint32_t)plan[i].second;
+                    r->end_status = WSX_EHIP;
+                    continue;
+                }
+                S->st.launches++;
+                rd.members.push_back({r->id, plan[i].second});
+            }
+        } else {
+            for (auto& [r, steps] : plan) rd.members.push_back({r->id, steps});
+        }
+        // the returns of the requests this round completes, right behind it
+        for (auto& m : rd.members) {
+            Request* r = member(S, m.first);
+            if (r && r->status == 1 && r->issued == r->req.horizon) issue_returns(S, r, g.stream);
+        }
+        e = hipEventRecord(rd.ev, g.stream);
+        rd.inflight = true;
+        g.order.push_back(slot);
+        g.next = (slot + 1) % kSlots;
+        if (e != hipSuccess) fail_round(S, rd, WSX_EHIP);
         any = true;
     }
     return any;
@@ -333,37 +434,37 @@ bool launch_rounds(wsx_server* S) {
 bool poll(wsx_server* S) {
     bool any = false;
     for (auto& g : S->groups) {
-        if (!g.inflight) continue;
-        const hipError_t q = hipEventQuery(g.ev);
-        if (q == hipErrorNotReady) continue;
-        if (q != hipSuccess) {
-            fail_group(S, g, WSX_EHIP);
-            continue;
-        }
-        for (auto& m : g.members) {
-            Request* r = S->requests[m.first].get();
-            r->finished += m.second;
-            if (r->finished == r->req.horizon && !r->returns_issued) {
-                hipError_t e = launch_returns(r->traj.reward, r->traj.value, r->traj.done,
-                                              r->traj.last_value, r->req.horizon, r->rows,
-                                              r->req.gamma, r->req.lambda, 1, r->ret, r->adv, 0,
-                                              g.stream);
-                if (e == hipSuccess) e = hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming);
-                if (e == hipSuccess) e = hipEventRecord(r->done_ev, g.stream);
-                r->returns_issued = true;
-                if (e != hipSuccess) {
-                    fail_request(S, r, WSX_EHIP);
-                    S->cv_done.notify_all();
-                }
+        // rounds complete in stream order: look at the oldest first
+        while (!g.order.empty()) {
+            Round& rd = g.round[g.order.front()];
+            const hipError_t q = hipEventQuery(rd.ev);
+            if (q == hipErrorNotReady) break;
+            g.order.pop_front();
+            any = true;
+            if (q != hipSuccess) {
+                fail_round(S, rd, WSX_EHIP);
+                continue;
             }
+            for (auto& m : rd.members)
+                if (Request* r = member(S, m.first)) r->finished += m.second;
+            rd.members.clear();
+            rd.inflight = false;
         }
-        g.members.clear();
-        g.inflight = false;
-        any = true;
     }
     for (auto& kv : S->requests) {
         Request* r = kv.second.get();
-        if (r->status != 1 || !r->returns_issued || !r->done_ev) continue;
+        if (r->status != 1) continue;
+        if (r->end_status != 0 && !r->returns_issued && r->finished == r->issued) {
+            // a cancelled (or failed) request ends once its rounds in flight
+            // have ended
+            r->status = r->end_status;
+            r->t_done = Clock::now();
+            S->sessions[r->session].busy = false;
+            any = true;
+            S->cv_done.notify_all();
+            continue;
+        }
+        if (!r->returns_issued || !r->done_ev) continue;
         const hipError_t q = hipEventQuery(r->done_ev);
         if (q == hipErrorNotReady) continue;
         r->status = q == hipSuccess ? 2 : WSX_EHIP;
@@ -381,7 +482,7 @@ bool poll(wsx_server* S) {
 
 bool busy(const wsx_server* S) {
     for (const auto& g : S->groups)
-        if (g.inflight) return true;
+        if (!g.order.empty()) return true;
     for (const auto& kv : S->requests)
         if (kv.second->status == 1) return true;
     return false;
@@ -401,7 +502,7 @@ void worker_loop(wsx_server* S) {
                     kv.second->status = WSX_ESTATE;
             S->cv_done.notify_all();
             bool inflight = false;
-            for (auto& g : S->groups) inflight |= g.inflight;
+            for (auto& g : S->groups) inflight |= !g.order.empty();
             for (auto& kv : S->requests)
                 inflight |= kv.second->status == 1 && kv.second->returns_issued;
             if (!inflight) break;
@@ -412,8 +513,11 @@ void worker_loop(wsx_server* S) {
         progressed |= poll(S);
         if (!progressed) {
             if (busy(S)) {
+                // device work in flight: poll again at once (a sleep of a few
+                // microseconds lasts tens on a loaded host); the next round of
+                // every group is already queued behind the current one
                 lk.unlock();
-                std::this_thread::sleep_for(std::chrono::microseconds(20));
+                std::this_thread::yield();
                 lk.lock();
             } else {
                 S->cv_work.wait_for(lk, std::chrono::milliseconds(2));
@@ -447,7 +551,7 @@ int wsx_server_create(const wsx_server_desc* desc, wsx_server** out) {
     if (!desc->arena || desc->arena_bytes == 0) return fail(WSX_EINVAL, "arena is empty");
     if (desc->chunk_steps <= 0 || desc->max_batch <= 0 || desc->max_batch > 4096)
         return fail(WSX_EINVAL, "chunk_steps and max_batch must be positive (max_batch <= 4096)");
-    const size_t reserve = align256(sizeof(Segment) * desc->max_batch) * kMaxGroups;
+    const size_t reserve = align256(sizeof(Segment) * desc->max_batch) * kMaxGroups * kSlots;
     if (desc->arena_bytes <= reserve) return fail(WSX_EINVAL, "arena smaller than the launch tables");
     wsx_server* S = new (std::nothrow) wsx_server();
     if (!S) return fail(WSX_EINVAL, "out of host memory");
@@ -502,7 +606,7 @@ int wsx_server_submit(wsx_server* S, const wsx_request* q, int64_t* id) {
         rc = wsx_env_state_bytes(q->kind, q->n_envs, rows, &sbytes);
         if (rc) return rc;
         const size_t need = align256(sbytes) + traj_bytes(k, rows, q->horizon) +
-                            align256(sizeof(Segment) * S->desc.max_batch) * kMaxGroups;
+                            align256(sizeof(Segment) * S->desc.max_batch) * kMaxGroups * kSlots;
         if (need > S->desc.arena_bytes)
             return fail(WSX_EINVAL, "request needs %zu bytes, more than the arena", need);
     } else {
@@ -556,6 +660,37 @@ int wsx_server_release(wsx_server* S, int64_t id) {
     return WSX_OK;
 }
 
+int wsx_server_cancel(wsx_server* S, int64_t id) {
+    if (!S) return fail(WSX_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->requests.find(id);
+    if (it == S->requests.end()) return fail(WSX_EINVAL, "no request %lld", (long long)id);
+    Request* r = it->second.get();
+    if (r->status == 0) {
+        S->queue.erase(std::remove(S->queue.begin(), S->queue.end(), id), S->queue.end());
+        r->status = WSX_ECANCELED;
+        r->t_done = Clock::now();
+        S->cv_done.notify_all();
+        return WSX_OK;
+    }
+    if (r->status != 1 || r->returns_issued)
+        return fail(WSX_ESTATE, "request %lld has already ended or is completing", (long long)id);
+    if (r->end_status == 0) r->end_status = WSX_ECANCELED;
+    S->cv_work.notify_one();
+    return WSX_OK;
+}
+
+int wsx_server_inject_launch_failure(wsx_server* S, int64_t id) {
+    if (!S) return fail(WSX_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->requests.find(id);
+    if (it == S->requests.end()) return fail(WSX_EINVAL, "no request %lld", (long long)id);
+    if (it->second->status > 1 || it->second->status < 0)
+        return fail(WSX_ESTATE, "request %lld has ended", (long long)id);
+    it->second->inject_fail = true;
+    return WSX_OK;
+}
+
 int wsx_server_close_session(wsx_server* S, int64_t session) {
     if (!S) return fail(WSX_EINVAL, "server is NULL");
     std::lock_guard<std::mutex> lk(S->mu);
@@ -590,8 +725,10 @@ int wsx_server_destroy(wsx_server* S) {
     for (auto& g : S->groups) {
         (void)hipStreamSynchronize(g.stream);
         (void)hipStreamDestroy(g.stream);
-        (void)hipEventDestroy(g.ev);
-        (void)hipHostFree(g.host_table);
+        for (auto& rd : g.round) {
+            (void)hipEventDestroy(rd.ev);
+            (void)hipHostFree(rd.host_table);
+        }
     }
     for (auto& kv : S->requests)
         if (kv.second->done_ev) (void)hipEventDestroy(kv.second->done_ev);

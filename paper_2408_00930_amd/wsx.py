@@ -324,6 +324,7 @@ class _ServerStats(C.Structure):
 
 
 EXPORTS += ["wsx_server_create", "wsx_server_submit", "wsx_server_wait", "wsx_server_release",
+            "wsx_server_cancel", "wsx_server_inject_launch_failure",
             "wsx_server_close_session", "wsx_server_get_stats", "wsx_server_destroy"]
 
 
@@ -335,6 +336,8 @@ def _server_sigs(L):
     L.wsx_server_submit.argtypes = [vp, C.POINTER(_Request), C.POINTER(C.c_int64)]
     L.wsx_server_wait.argtypes = [vp, C.c_int64, C.c_int32, C.POINTER(_Result)]
     L.wsx_server_release.argtypes = [vp, C.c_int64]
+    L.wsx_server_cancel.argtypes = [vp, C.c_int64]
+    L.wsx_server_inject_launch_failure.argtypes = [vp, C.c_int64]
     L.wsx_server_close_session.argtypes = [vp, C.c_int64]
     L.wsx_server_get_stats.argtypes = [vp, C.POINTER(_ServerStats)]
     L.wsx_server_destroy.argtypes = [vp]
@@ -401,6 +404,13 @@ class Server:
 
     def close_session(self, sid):
         _check(lib().wsx_server_close_session(self.handle, sid))
+
+    def cancel(self, rid):
+        _check(lib().wsx_server_cancel(self.handle, rid))
+
+    def inject_launch_failure(self, rid):
+        """Test support: the request's next launch is reported as failed."""
+        _check(lib().wsx_server_inject_launch_failure(self.handle, rid))
 
     def stats(self):
         s = _ServerStats()

@@ -194,3 +194,64 @@ def test_sizes_with_an_autotuner_entry_mix_with_others():
         _equal(got, _direct(fx, x))
         srv.release(rid)
     srv.close()
+
+
+def test_cancel_queued_and_running_requests():
+    """A cancelled request ends with WSX_ECANCELED, queued or running; the
+    requests beside it complete and equal their direct roll-outs."""
+    wsx = _wsx()
+    fx = Fixture()
+    say("serve cancel")
+    srv = wsx.Server(1 << 30, chunk_steps=5, max_batch=16)
+    # 1,000 rounds of 5 steps: tens of milliseconds on the device
+    long_run = srv.submit(**fx.spec(2, 2000, 5000, seed=31))
+    keep = [fx.spec(3, 120, 30, seed=32), fx.spec(2, 64, 25, seed=33)]
+    ids = [srv.submit(**x) for x in keep]
+    time.sleep(0.002)
+    srv.cancel(long_run)
+    with pytest.raises(wsx.WsxError, match="-6"):
+        srv.wait(long_run, 60000)
+    for x, rid in zip(keep, ids):
+        r = srv.wait(rid, 60000)
+        _equal(_host(srv.view(r, x["kind"])), _direct(fx, x))
+        srv.release(rid)
+    srv.release(long_run)
+    srv.close()
+    # queued: an arena that holds one of these at a time
+    one = 3 * 1024 * 1024
+    srv = wsx.Server(one + (1 << 21), chunk_steps=20)
+    a = srv.submit(**fx.spec(2, 1500, 60, seed=41))
+    b = srv.submit(**fx.spec(2, 1500, 60, seed=42))
+    srv.cancel(b)
+    with pytest.raises(wsx.WsxError, match="-6"):
+        srv.wait(b, 60000)
+    srv.wait(a, 60000)
+    srv.release(a)
+    srv.release(b)
+    with pytest.raises(wsx.WsxError):
+        srv.cancel(a)            # released: unknown
+    srv.close()
+
+
+def test_a_failed_launch_fails_only_its_request():
+    """With one request's launch failing (forced from the host), the round is
+    relaunched per request: only that request ends with WSX_EHIP, the others
+    of the same rounds complete and equal their direct roll-outs."""
+    wsx = _wsx()
+    fx = Fixture()
+    say("serve launch failure isolation")
+    srv = wsx.Server(1 << 30, chunk_steps=8, max_batch=16)
+    specs = [fx.spec(2, 100 + 10 * i, 40, seed=50 + i) for i in range(5)]
+    ids = [srv.submit(**x) for x in specs]
+    srv.inject_launch_failure(ids[2])
+    for i, (x, rid) in enumerate(zip(specs, ids)):
+        if i == 2:
+            with pytest.raises(wsx.WsxError, match="-3"):
+                srv.wait(rid, 60000)
+        else:
+            r = srv.wait(rid, 60000)
+            _equal(_host(srv.view(r, 2)), _direct(fx, x))
+        srv.release(rid)
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == 4
