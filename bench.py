@@ -1,11 +1,14 @@
 #!/usr/bin/env python3
 """Roll-out throughput on one MI355X: fused vs per-step-launch forms.
 
-One step = the whole hot path over one batch: env_reset, rollout(horizon)
-and compute_returns for every environment set of the workload. The default
-workload is 10,000 Pendulum + 10,000 Acrobot replicas, horizon 200, BF16
-policies obs-256-256-(1+1), both sets in one fused launch (rollout_batch)
-with the kernel shape chosen by the library's autotuner. Prints one JSON line.
+One step = the whole hot path over one batch: reset, roll-out over the
+horizon and returns/GAE for every environment set of the workload. The
+fused form runs all of it in one persistent launch (rollout_batch_ext); the
+comparison forms run it as separate calls (fused_calls: reset and returns
+kernels around the fused roll-out; plain / graph: per-step launches). The
+default workload is 10,000 Pendulum + 10,000 Acrobot replicas, horizon 200,
+BF16 policies obs-256-256-(1+1), both sets in the one launch, with the kernel
+shape chosen by the library's autotuner. Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME]
 """
@@ -218,23 +221,33 @@ class EnvSet:
                                 self.ret, self.adv)
 
 
-def batch_step(sets, i, wsx, torch, timed, k_events):
-    """All sets in ONE fused launch on the first set's stream (reset, batched
-    roll-out, returns per set)."""
+def batch_step(sets, i, wsx, torch, timed, k_events, one_launch=True):
+    """All sets in ONE fused launch on the first set's stream. one_launch: the
+    reset, the roll-out and the returns/GAE of every set in that launch
+    (wsx_rollout_batch_ext); else the separate calls (reset per set, the
+    batched roll-out, returns per set), the launch alone timed as the kernel."""
     st = sets[0].stream
     with torch.cuda.stream(st):
-        for s in sets:
-            wsx.env_reset(s.env, epoch=i)
+        if not one_launch:
+            for s in sets:
+                wsx.env_reset(s.env, epoch=i)
         if timed:
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record(st)
-        wsx.rollout_batch([s.env for s in sets], [s.dp for s in sets], sets[0].T,
-                          [s.traj for s in sets])
+        if one_launch:
+            wsx.rollout_batch_ext([s.env for s in sets], [s.dp for s in sets], sets[0].T,
+                                  [s.traj for s in sets], epoch=i,
+                                  returns=[s.ret for s in sets], advantages=[s.adv for s in sets],
+                                  gamma=0.99, lam=0.95, bootstrap=True)
+        else:
+            wsx.rollout_batch([s.env for s in sets], [s.dp for s in sets], sets[0].T,
+                              [s.traj for s in sets])
         if timed:
             b.record(st)
             k_events.append((a, b))
-        for s in sets:
-            wsx.compute_returns(s.traj, s.T, 0.99, 0.95, True, torch.float32, s.ret, s.adv)
+        if not one_launch:
+            for s in sets:
+                wsx.compute_returns(s.traj, s.T, 0.99, 0.95, True, torch.float32, s.ret, s.adv)
 
 
 def plain_vs_fused(sets, wsx, torch, batched, epoch):
@@ -244,12 +257,14 @@ def plain_vs_fused(sets, wsx, torch, batched, epoch):
     fields = ("obs", "action", "reward", "done", "value", "logp", "last_value")
 
     def run(mode):
-        for s in sets:
-            wsx.env_reset(s.env, epoch=epoch)
-        if batched and mode == wsx.MODE_FUSED:
-            wsx.rollout_batch([s.env for s in sets], [s.dp for s in sets], sets[0].T,
-                              [s.traj for s in sets])
+        if batched and mode == wsx.MODE_FUSED:   # the timed form: one launch
+            wsx.rollout_batch_ext([s.env for s in sets], [s.dp for s in sets], sets[0].T,
+                                  [s.traj for s in sets], epoch=epoch,
+                                  returns=[s.ret for s in sets], advantages=[s.adv for s in sets],
+                                  gamma=0.99, lam=0.95, bootstrap=True)
         else:
+            for s in sets:
+                wsx.env_reset(s.env, epoch=epoch)
             for s in sets:
                 wsx.rollout(s.env, s.dp, s.T, s.traj, mode)
         torch.cuda.synchronize()
@@ -298,14 +313,14 @@ def peak_probe(torch):
     return out
 
 
-def run_form(sets, mode, steps, warmup, wsx, torch, first_epoch, batched=False):
+def run_form(sets, mode, steps, warmup, wsx, torch, first_epoch, batched=False, one_launch=True):
     main = torch.cuda.current_stream()
     k_events = []
 
     def one(i, timed):
         if batched:
             sets[0].stream.wait_stream(main)
-            batch_step(sets, i, wsx, torch, timed, k_events)
+            batch_step(sets, i, wsx, torch, timed, k_events, one_launch)
             main.wait_stream(sets[0].stream)
             return
         for s in sets:
@@ -519,7 +534,8 @@ def measure(workload, args, wsx, inputs, torch, plain_steps, cpu_envs, single_th
     of the fused launch and the oracle on a bounded sample. Returns the
     record and the sets."""
     keys = WORKLOADS[workload]
-    batched = len(keys) > 1 and not args.no_batch
+    # one fused launch per step for all sets (a single set is a batch of one)
+    batched = len(keys) == 1 or not args.no_batch
     tuned = {}
     shape = dict(zip(("tile_rows", "waves", "occupancy"),
                      (int(x) for x in args.shape.split(",")))) if args.shape else None
@@ -556,6 +572,14 @@ def measure(workload, args, wsx, inputs, torch, plain_steps, cpu_envs, single_th
     result["fused"] = (el, lat, kern)
     print(f"[bench] {workload} fused: {args.steps} steps in {el:.3f} s", file=sys.stderr,
           flush=True)
+    if batched and "fused_calls" in forms:
+        # the same launch without the reset and returns in it: reset and
+        # returns as separate kernels around it
+        r = run_form(sets, wsx.MODE_FUSED, args.steps, 5, wsx, torch, 2000, batched=True,
+                     one_launch=False)
+        result["fused_calls"] = r + (args.steps,)
+        print(f"[bench] {workload} fused_calls: {args.steps} steps in {r[0]:.3f} s",
+              file=sys.stderr, flush=True)
     for name, mode in (("plain", wsx.MODE_PLAIN), ("graph", wsx.MODE_GRAPH),
                        ("fused_graph", wsx.MODE_FUSED_GRAPH)):
         n = args.steps if name == "fused_graph" else plain_steps
@@ -602,7 +626,10 @@ def measure(workload, args, wsx, inputs, torch, plain_steps, cpu_envs, single_th
                    "horizon": max(s.T for s in sets), "sets": [s.key for s in sets],
                    "policy": {s.key: f"{s.policy.dtype} {s.policy.d_in}-{s.policy.h1}-"
                                      f"{s.policy.h2}-{s.policy.n_head}" for s in sets},
-                   "returns": "FP64 scan, FP32 outputs", "streams": 1 if batched else len(sets),
+                   "returns": "FP64, FP32 outputs" + (", in the roll-out launch" if batched
+                                                         else ", separate kernel"),
+                   "reset": "in the roll-out launch" if batched else "separate kernel",
+                   "streams": 1 if batched else len(sets),
                    "kernel_shape": {s.key: dict(zip(("tile_rows", "waves", "occupancy",
                                                      "chunk_steps"), wsx.env_shape(s.env)))
                                     for s in sets},
@@ -618,15 +645,17 @@ def measure(workload, args, wsx, inputs, torch, plain_steps, cpu_envs, single_th
     if any(s.kind == wsx.MARKET for s in sets):
         agent_steps = sum(s.rows * s.T for s in sets)
         out["agent_steps_per_s"] = round(agent_steps * args.steps / el, 1)
-    for name in ("plain", "graph", "fused_graph"):
+    for name in ("fused_calls", "plain", "graph", "fused_graph"):
         if name in result:
-            pel, plat, _, n = result[name]
+            pel, plat, pk, n = result[name]
             pv = env_steps * n / pel
             out[name] = {"value": round(pv, 1), "steps": n, "ms_per_step": round(pel / n * 1e3, 3),
                          "latency_ms": {"p50": round(percentile(plat, 50), 3),
                                         "p99": round(percentile(plat, 99), 3),
                                         "iqr": iqr(plat, 3)}}
-            out[f"fused_speedup_vs_{name}"] = round(value / pv, 2)
+            if name == "fused_calls":
+                out[name]["avg_launch_ms"] = round(sum(pk["batch"]) / len(pk["batch"]), 4)
+            out[f"fused_speedup_vs_{name}"] = round(value / pv, 3 if name == "fused_calls" else 2)
     if parity is not None:
         out["parity"] = parity
     if cpu_envs > 0 and not args.no_cpu_baseline:
@@ -657,7 +686,7 @@ def main():
                     help="other workloads measured the same way, reported as sub-records "
                          "under 'workloads' ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="fused,plain,graph,fused_graph")
+    ap.add_argument("--forms", default="fused,fused_calls,plain,graph,fused_graph")
     ap.add_argument("--no-batch", action="store_true",
                     help="run a multi-set workload as one launch per set on its own stream")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",

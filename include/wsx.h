@@ -173,6 +173,40 @@ int wsx_env_info(const wsx_env* env, int64_t* n_rows, uint32_t* step, uint32_t* 
 int wsx_rollout_batch(wsx_env* const* envs, const wsx_policy* const* policies,
                       const wsx_traj* const* trajs, int32_t n, int32_t horizon, void* stream);
 
+/* What a fused batch launch does besides the roll-out (wsx_rollout_batch_ext):
+ * a reset before the first step and the returns/GAE after the last, in the
+ * same kernel, so one launch runs a whole iteration of the hot path (Sec. 2:
+ * simulation and data preparation for training stay on the device; Sec. 3:
+ * actor-critic consumes returns and advantages). */
+typedef struct {
+    int32_t reset;           /* 1: every row first takes its initial state, as   */
+                             /* wsx_env_reset(env, epoch) would draw it, and the */
+                             /* step counter restarts at 0                       */
+    uint32_t epoch;
+    int32_t returns;         /* 1: returns and GAE of each set over the horizon,  */
+                             /* the recursions of wsx_compute_returns (FP64)     */
+    int32_t bootstrap;       /* as in wsx_compute_returns                         */
+    int32_t out_dtype;       /* WSX_F32 or WSX_F64                                */
+    double gamma, lambda;    /* in [0, 1]                                         */
+    void* const* ret;        /* [n] device buffers [horizon][rows] of out_dtype   */
+    void* const* adv;        /* [n] device buffers [horizon][rows]                */
+} wsx_rollout_ext;
+
+/* wsx_rollout_batch with a reset before and returns/GAE after the roll-out,
+ * all in the one persistent launch: each workgroup resets its tile's rows
+ * from the RESET stream (when ext->reset), rolls them out, and then computes
+ * their returns and advantages from the records it has just written (FP64,
+ * segments of the horizon composed as affine maps; equal to
+ * wsx_compute_returns within FP64 rounding of the association order). The
+ * trajectories and final states equal those of wsx_env_reset +
+ * wsx_rollout_batch bit for bit. ext == NULL is wsx_rollout_batch. Buffers
+ * are caller-owned; ret/adv must not overlap the trajectories. Errors:
+ * WSX_EINVAL (as wsx_rollout_batch; NULL ret/adv when returns is set,
+ * gamma/lambda outside [0, 1]), WSX_EUNSUPPORTED (out_dtype), WSX_EHIP. */
+int wsx_rollout_batch_ext(wsx_env* const* envs, const wsx_policy* const* policies,
+                          const wsx_traj* const* trajs, int32_t n, int32_t horizon,
+                          const wsx_rollout_ext* ext, void* stream);
+
 /* Workgroup tiles of an environment set's fused launch and the rows one tile
  * holds. Single-agent kinds: ceil(n_rows / tile_rows) tiles of consecutive
  * replicas. The market (App. B: the agents of one environment interact, so

@@ -541,7 +541,21 @@ int wsx_rollout(wsx_env* env, const wsx_policy* policy, int32_t horizon, const w
 
 int wsx_rollout_batch(wsx_env* const* envs, const wsx_policy* const* policies,
                       const wsx_traj* const* trajs, int32_t n, int32_t horizon, void* stream) {
+    return wsx_rollout_batch_ext(envs, policies, trajs, n, horizon, nullptr, stream);
+}
+
+int wsx_rollout_batch_ext(wsx_env* const* envs, const wsx_policy* const* policies,
+                          const wsx_traj* const* trajs, int32_t n, int32_t horizon,
+                          const wsx_rollout_ext* ext, void* stream) {
     if (!envs || !policies || !trajs) return fail(WSX_EINVAL, "envs, policies, trajs must not be NULL");
+    const bool gae = ext && ext->returns;
+    if (gae) {
+        if (!ext->ret || !ext->adv) return fail(WSX_EINVAL, "ext->ret and ext->adv must not be NULL");
+        if (ext->out_dtype != WSX_F32 && ext->out_dtype != WSX_F64)
+            return fail(WSX_EUNSUPPORTED, "returns are written as WSX_F32 or WSX_F64");
+        if (!(ext->gamma >= 0.0 && ext->gamma <= 1.0) || !(ext->lambda >= 0.0 && ext->lambda <= 1.0))
+            return fail(WSX_EINVAL, "gamma and lambda must lie in [0, 1]");
+    }
     if (n < 1 || n > kInlineSegments)
         return fail(WSX_EINVAL, "a batch holds 1 to %d environment sets (got %d)", kInlineSegments, n);
     int kinds[2] = {0, 0}, n_kinds = 0, tile_max = 0;
@@ -575,25 +589,52 @@ int wsx_rollout_batch(wsx_env* const* envs, const wsx_policy* const* policies,
         return fail(WSX_EUNSUPPORTED,
                     "no fused kernel for kinds %d/%d with %d waves, occupancy %d, %d-row tiles",
                     kinds[0], kinds[1], envs[0]->waves, envs[0]->occupancy, tile_max);
+    if (gae)
+        for (int i = 0; i < n; ++i)
+            if (horizon > 0 && (!ext->ret[i] || !ext->adv[i]))
+                return fail(WSX_EINVAL, "ext->ret[%d] / ext->adv[%d] is NULL", i, i);
+    const bool reset = ext && ext->reset;
     Batch b{};
     b.table = nullptr;
     int tiles = 0;
     for (int i = 0; i < n; ++i) {
         Segment& sg = b.inl[i];
         sg.env = env_args(envs[i]);
+        if (reset) {   // the state the reset kernel would leave: step 0 of the epoch
+            sg.env.epoch = ext->epoch;
+            sg.env.t0 = 0;
+        }
         sg.tr = traj_args(trajs[i]);
         sg.pol = policy_args(policies[i]);
+        sg.gae = GaeArgs{};
+        if (gae && horizon > 0) {
+            sg.gae.ret = ext->ret[i];
+            sg.gae.adv = ext->adv[i];
+            sg.gae.gamma = ext->gamma;
+            sg.gae.lambda = ext->lambda;
+            sg.gae.bootstrap = ext->bootstrap ? 1 : 0;
+            sg.gae.out_f64 = ext->out_dtype == WSX_F64 ? 1 : 0;
+        }
         sg.steps = horizon;
         sg.tile_begin = tiles;
         sg.last = 1;
+        sg.reset = reset ? 1 : 0;
         tiles += envs[i]->n_tiles;
     }
     b.n_segs = n;
     b.n_tiles = tiles;
+    b.any_reset = reset ? 1 : 0;
+    b.any_gae = gae && horizon > 0 ? 1 : 0;
     const int grid = std::max(1, std::min(tiles, envs[0]->cus * fused_blocks_per_cu(v)));
     const hipError_t e = launch_fused(v, b, grid, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "wsx_rollout_batch");
-    for (int i = 0; i < n; ++i) envs[i]->step += (uint32_t)horizon;
+    for (int i = 0; i < n; ++i) {
+        if (reset) {
+            envs[i]->epoch = ext->epoch;
+            envs[i]->step = 0;
+        }
+        envs[i]->step += (uint32_t)horizon;
+    }
     return WSX_OK;
 }
 

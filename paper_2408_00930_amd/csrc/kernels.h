@@ -68,15 +68,29 @@ struct EnvArgs {
 // distances to the Gaussians' centres).
 constexpr int kReactionCache = 20 + 64;
 
+// Returns and GAE of a segment's rows, computed by the tiles of a fused
+// launch after their steps ([steps][rows] outputs, offset like the
+// trajectory); ret == NULL: none.
+struct GaeArgs {
+    void* ret;
+    void* adv;
+    double gamma, lambda;
+    int32_t bootstrap;
+    int32_t out_f64;
+};
+
 // One roll-out request inside a fused launch: its environment set, its policy,
 // its trajectory pointers (offset to the launch's first slot) and its steps.
 struct Segment {
     EnvArgs env;
     TrajArgs tr;
     PolicyArgs pol;
+    GaeArgs gae;
     int32_t steps;
     int32_t tile_begin;   // first tile of this segment in the launch
     int32_t last;         // 1: also evaluate V(s_T) into tr.last_value after the steps
+    int32_t reset;        // 1: rows start from the RESET draw of step t0 (the epoch's
+                          // initial state), not from the state block
 };
 
 // The tiles of a fused launch: up to kInlineSegments segments passed with the
@@ -87,6 +101,8 @@ struct Batch {
     Segment inl[kInlineSegments];
     int32_t n_segs;
     int32_t n_tiles;
+    int32_t any_reset;   // some segment has `reset` set
+    int32_t any_gae;     // some segment has gae.ret set
 };
 
 // One compiled variant of the fused / plain kernels for an environment kind

@@ -744,6 +744,106 @@ __device__ __forceinline__ void stage_segment(const Batch& b, int i, Segment* ds
     }
 }
 
+// Returns and GAE of a tile's rows after its steps, FP64 (the recursions of
+// the returns kernels): thread tid takes row tid % n of the tile's n rows and
+// time segment tid / n of the horizon. Each segment composes its steps' affine
+// maps backwards (x -> b + c x, for G and for A), the compositions meet in
+// `buf` (LDS, 32 bytes per row and segment), and each segment then reruns its
+// recursion from the carry of the later segments and writes its outputs. A
+// segment's records are loaded GB steps at a time with every load in flight
+// (one chain of dependent loads per step would cost a memory round trip
+// each), and kept in registers for the second pass when the segment is one
+// block. The records are the workgroup's own stores, visible after the
+// barrier that precedes the call; `buf` is reused by the caller afterwards.
+template <int NTHR, int GB>
+__device__ void tile_gae(const EnvArgs& env, const TrajArgs& tr, const GaeArgs& g, const Tile& tl,
+                         int horizon, double* buf, int buf_bytes, int tid) {
+    const int n = tl.row1 - tl.row0;
+    if (n <= 0 || horizon <= 0) return;
+    int nseg = min(min(NTHR / n, buf_bytes / (32 * n)), horizon);
+    const int len = (horizon + nseg - 1) / nseg;
+    nseg = (horizon + len - 1) / len;   // every segment non-empty
+    const int r = tid % n, q = tid / n;
+    const bool live = q < nseg;
+    const size_t rows = (size_t)env.n_rows;
+    const int row = live ? tile_row(env, tl.row0 + r) : 0;
+    const int lo = q * len, hi = min(horizon, lo + len);
+    const double gam = g.gamma, gl = g.gamma * g.lambda;
+    const double v_end = (live && g.bootstrap) ? (double)tr.last_value[row] : 0.0;
+    const double v_hi = !live ? 0.0 : hi == horizon ? v_end : (double)tr.value[(size_t)hi * rows + row];
+    double* mine = buf + ((size_t)q * n + r) * 4;
+    float br[GB], bv[GB], bk[GB];   // a block of records
+    // steps tb - 1, tb - 2, ..., down to max(lo, tb - GB)
+    auto load_block = [&](int tb) {
+#pragma unroll
+        for (int u = 0; u < GB; ++u) {
+            const int t = tb - 1 - u;
+            const size_t i = (size_t)(t >= lo ? t : lo) * rows + row;
+            br[u] = tr.reward[i];
+            bv[u] = tr.value[i];
+            bk[u] = tr.done[i] ? 0.0f : 1.0f;
+        }
+    };
+    if (live) {
+        double cg = 1.0, bg = 0.0, ca = 1.0, ba = 0.0, v_next = v_hi;
+        for (int tb = hi; tb > lo; tb -= GB) {
+            load_block(tb);
+#pragma unroll
+            for (int u = 0; u < GB; ++u) {
+                if (tb - 1 - u >= lo) {
+                    const double rw = br[u], v = bv[u], keep = bk[u];
+                    const double c = gam * keep, e = gl * keep;
+                    const double delta = rw + c * v_next - v;
+                    bg = rw + c * bg;
+                    cg = c * cg;
+                    ba = delta + e * ba;
+                    ca = e * ca;
+                    v_next = v;
+                }
+            }
+        }
+        mine[0] = cg;
+        mine[1] = bg;
+        mine[2] = ca;
+        mine[3] = ba;
+    }
+    __syncthreads();
+    if (live) {
+        double G = v_end, A = 0.0;
+        for (int p = nseg - 1; p > q; --p) {
+            const double* m = buf + ((size_t)p * n + r) * 4;
+            G = m[1] + m[0] * G;
+            A = m[3] + m[2] * A;
+        }
+        double v_next = v_hi;
+        const bool kept = hi - lo <= GB;   // the one block is still in registers
+        for (int tb = hi; tb > lo; tb -= GB) {
+            if (!kept) load_block(tb);
+#pragma unroll
+            for (int u = 0; u < GB; ++u) {
+                const int t = tb - 1 - u;
+                if (t >= lo) {
+                    const double rw = br[u], v = bv[u], keep = bk[u];
+                    const double c = gam * keep, e = gl * keep;
+                    const double delta = rw + c * v_next - v;
+                    G = rw + c * G;
+                    A = delta + e * A;
+                    v_next = v;
+                    const size_t i = (size_t)t * rows + row;
+                    if (g.out_f64) {
+                        static_cast<double*>(g.ret)[i] = G;
+                        static_cast<double*>(g.adv)[i] = A;
+                    } else {
+                        static_cast<float*>(g.ret)[i] = (float)G;
+                        static_cast<float*>(g.adv)[i] = (float)A;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();   // `buf` is free again
+}
+
 // One tile of a fused launch: rows [row0, row1) of segment `sg` for its
 // steps (plus the value pass), with the policy already in the registers of
 // `mlp` and its per-feature table in LDS.
@@ -946,6 +1046,35 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
     }
 }
 
+// The reset kernel's work for the rows of one tile (segments with `reset`),
+// run by a fused launch before its first tile: the same draws and stores, so
+// the state block ends up as the reset kernel leaves it, bit for bit.
+template <class E, int NTHR>
+__device__ void reset_tile(const Segment& sg, int tile, char* extra, const float*& staged,
+                           int tid) {
+    const EnvArgs env = uniform(sg.env);
+    EnvCtx ctx{nullptr, nullptr, 0};
+    if constexpr (E::KIND == Reaction::KIND) {
+        if (env.params != staged) {   // uniform over the workgroup
+            __syncthreads();          // earlier readers of the staged block are done
+            stage_params(reinterpret_cast<float*>(extra), env.params, tid, NTHR);
+            staged = env.params;
+            __syncthreads();
+        }
+        ctx.lds_params = reinterpret_cast<const float*>(extra);
+        ctx.cache_stride = (int)env.n_rows;
+    }
+    const Tile tl = tile_of(env, tile - __builtin_amdgcn_readfirstlane(sg.tile_begin));
+    const RngKey key{env.k0, env.k1, env.epoch};
+    for (int i = tl.row0 + tid; i < tl.row1; i += NTHR) {
+        const int row = tile_row(env, i);
+        if constexpr (E::KIND == Reaction::KIND) ctx.cache = env.cache + row;
+        float s[E::SR];
+        E::reset(s, key, 0u, (uint32_t)row, ctx);
+        save_state<E, 1>(env, row, s, 0);
+    }
+}
+
 // Persistent fused roll-out: each workgroup walks tiles of the launch's
 // segments; E2 (if not E) is a second environment kind whose tiles share the
 // policy shape. The weights are (re)loaded when a tile's policy differs from
@@ -977,6 +1106,26 @@ k_fused(Batch batch) {
         reinterpret_cast<uint32_t*>(smem + L::OFF_IN)[i] = 0u;
 
     __shared__ Segment seg;          // the current tile's segment
+    if (batch.any_reset) {
+        // reset the rows of this workgroup's tiles before any weights occupy
+        // registers; the tiles below read the state back (the workgroup's own
+        // stores, visible after a barrier)
+        for (int tile = blockIdx.x; tile < batch.n_tiles; tile += gridDim.x) {
+            const int si = segment_index(batch, tile);
+            __syncthreads();
+            stage_segment(batch, si, &seg, tid, NTHR);
+            __syncthreads();
+            if (__builtin_amdgcn_readfirstlane(seg.reset)) {
+                if constexpr (!std::is_same<E, E2>::value) {
+                    if (seg.env.kind == E2::KIND) {
+                        reset_tile<E2, NTHR>(seg, tile, extra, staged, tid);
+                        continue;
+                    }
+                }
+                reset_tile<E, NTHR>(seg, tile, extra, staged, tid);
+            }
+        }
+    }
     for (int tile = blockIdx.x; tile < batch.n_tiles; tile += gridDim.x) {
         const int si = segment_index(batch, tile);   // uniform over the workgroup
         __syncthreads();   // the previous tile's last reads of `seg` and the table are done
@@ -995,6 +1144,29 @@ k_fused(Batch batch) {
             }
         }
         fused_tile<E, L, NW>(sg, tile, mlp, smem, extra, draws, staged, tid, wave, lane);
+    }
+    if (batch.any_gae) {
+        // returns and GAE of every tile this workgroup rolled out, after all of
+        // them (the weights are no longer needed, so this pass takes no
+        // registers from the roll-out), with the whole LDS as its buffer
+        static_assert(L::BYTES >= 32 * R, "one segment per row fits");
+        for (int tile = blockIdx.x; tile < batch.n_tiles; tile += gridDim.x) {
+            const int si = segment_index(batch, tile);
+            __syncthreads();   // the previous pass over `seg` and the buffer is done
+            stage_segment(batch, si, &seg, tid, NTHR);
+            __syncthreads();   // also: this workgroup's records are visible to every wave
+            const GaeArgs gae = uniform(seg.gae);
+            if (gae.ret == nullptr) continue;
+            const EnvArgs env = uniform(seg.env);
+            const TrajArgs tr = uniform(seg.tr);
+            const Tile tl = tile_of(env, tile - __builtin_amdgcn_readfirstlane(seg.tile_begin));
+            // blocks of 36 steps hold a 200-step horizon's segments over
+            // six row groups; kernels that keep fewer registers free for
+            // this pass (their occupancy is set by the roll-out) take 16
+            constexpr int GB = DT == DT_BF16 ? 36 : 16;
+            tile_gae<NTHR, GB>(env, tr, gae, tl, __builtin_amdgcn_readfirstlane(seg.steps),
+                               reinterpret_cast<double*>(smem), L::BYTES, tid);
+        }
     }
 }
 

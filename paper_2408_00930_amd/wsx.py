@@ -54,7 +54,7 @@ class _EnvDesc(C.Structure):
 
 
 EXPORTS = ["wsx_env_state_bytes", "wsx_env_create", "wsx_env_reset", "wsx_rollout",
-           "wsx_rollout_batch",
+           "wsx_rollout_batch", "wsx_rollout_batch_ext",
            "wsx_env_info", "wsx_env_tiles", "wsx_env_set_step", "wsx_env_set_chunk",
            "wsx_env_destroy",
            "wsx_compute_returns",
@@ -235,6 +235,42 @@ def rollout_batch(envs, policies, horizon, trajs, stream=None):
     p = (C.POINTER(_Policy) * n)(*[C.pointer(x.c) for x in policies])
     t = (C.POINTER(_Traj) * n)(*[C.pointer(x.c) for x in trajs])
     _check(L.wsx_rollout_batch(e, p, t, n, horizon, _stream(stream)))
+
+
+class _RolloutExt(C.Structure):
+    _fields_ = [("reset", C.c_int32), ("epoch", C.c_uint32), ("returns", C.c_int32),
+                ("bootstrap", C.c_int32), ("out_dtype", C.c_int32), ("gamma", C.c_double),
+                ("lam", C.c_double), ("ret", C.c_void_p), ("adv", C.c_void_p)]
+
+
+def rollout_batch_ext(envs, policies, horizon, trajs, epoch=None, returns=None, advantages=None,
+                      gamma=0.99, lam=0.95, bootstrap=True, stream=None):
+    """One fused launch: reset (if epoch is not None), roll-out of every set,
+    then returns/GAE into the [horizon, rows] tensors `returns[i]`,
+    `advantages[i]` (if given; float32 or float64)."""
+    n = len(envs)
+    L = lib()
+    if not getattr(L, "_batch_ext_sigs", False):
+        L.wsx_rollout_batch_ext.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                            C.c_int32, C.POINTER(_RolloutExt), C.c_void_p]
+        L._batch_ext_sigs = True
+    e = (C.c_void_p * n)(*[x.handle.value for x in envs])
+    p = (C.POINTER(_Policy) * n)(*[C.pointer(x.c) for x in policies])
+    t = (C.POINTER(_Traj) * n)(*[C.pointer(x.c) for x in trajs])
+    x = _RolloutExt()
+    x.reset = 0 if epoch is None else 1
+    x.epoch = 0 if epoch is None else int(epoch)
+    keep = []
+    if returns is not None:
+        code = {torch.float64: F64, torch.float32: F32}.get(returns[0].dtype, -1)
+        r = (C.c_void_p * n)(*[_ptr(a) for a in returns])
+        a = (C.c_void_p * n)(*[_ptr(a) for a in advantages])
+        keep += [r, a]
+        x.returns, x.bootstrap, x.out_dtype = 1, int(bootstrap), code
+        x.gamma, x.lam = gamma, lam
+        x.ret = C.cast(r, C.c_void_p).value
+        x.adv = C.cast(a, C.c_void_p).value
+    _check(L.wsx_rollout_batch_ext(e, p, t, n, horizon, C.byref(x), _stream(stream)))
 
 
 def compute_returns(traj, horizon, gamma, lam, bootstrap=True, out_dtype=torch.float64,

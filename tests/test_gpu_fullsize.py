@@ -10,6 +10,10 @@ bench.py times them (the autotuner's kernel shape, the same launch form):
 - the reaction walk: 4,096 replicas, horizon 1,000, FP8 policy;
 - CartPole: 1,000 replicas, horizon 500, free-running against the oracle.
 
+Each runs as the benchmark runs it: reset, roll-out and returns/GAE in one
+fused launch, itself checked against the separate calls (bitwise
+trajectories and state, returns within 1e-12).
+
 The oracle cannot replay the larger ones in FP64 within a test, so for those
 it checks sampled steps for every row: the state at step t comes from the
 recorded observation, the policy results are checked with the device's
@@ -66,6 +70,46 @@ def _returns_on_sampled_rows(tr, ret, adv, rows, seed, prec):
     assert T > 0
 
 
+def _one_launch(envs, dps, kinds, T, epoch, prec_list):
+    """The benchmark's form: reset, roll-out and returns/GAE of every set in one
+    fused launch (wsx_rollout_batch_ext). Checked against the separate calls
+    (reset, batched roll-out, returns kernel) on the same inputs: every
+    trajectory field and the state block bit for bit, the returns and
+    advantages within 1e-12 relative. Returns the one launch's trajectories
+    and (returns, advantages)."""
+    import torch
+    from paper_2408_00930_amd import wsx
+    rows = [e.rows for e in envs]
+    say("full size: one launch (reset, roll-out, returns)", kinds, T)
+    trs = [wsx.Trajectory(k, T, r) for k, r in zip(kinds, rows)]
+    ret = [torch.empty((T, r), dtype=torch.float64, device="cuda") for r in rows]
+    adv = [torch.empty((T, r), dtype=torch.float64, device="cuda") for r in rows]
+    wsx.rollout_batch_ext(envs, dps, T, trs, epoch=epoch, returns=ret, advantages=adv,
+                          gamma=inputs.GAMMA, lam=inputs.LAMBDA, bootstrap=True)
+    torch.cuda.synchronize()
+    blocks = [e.block.clone() for e in envs]
+    say("full size: separate calls")
+    sep = [wsx.Trajectory(k, T, r) for k, r in zip(kinds, rows)]
+    for e in envs:
+        wsx.env_reset(e, epoch)
+    wsx.rollout_batch(envs, dps, T, sep)
+    sret = [wsx.compute_returns(tr, T, inputs.GAMMA, inputs.LAMBDA, True, torch.float64)
+            for tr in sep]
+    torch.cuda.synchronize()
+    for i in range(len(envs)):
+        for f in ("obs", "action", "reward", "done", "value", "logp", "last_value"):
+            assert torch.equal(getattr(trs[i], f), getattr(sep[i], f)), (kinds[i], f)
+        assert torch.equal(blocks[i], envs[i].block), (kinds[i], "state block")
+        worst = 0.0
+        for got, want in ((ret[i], sret[i][0]), (adv[i], sret[i][1])):
+            e = ((got - want).abs() / want.abs().clamp(min=1.0)).max().item()
+            assert e <= 1e-12, (kinds[i], e)
+            worst = max(worst, e)
+        prec_list[i]["one_launch_vs_separate"] = \
+            f"trajectories and state bitwise; returns/GAE {worst:.1e} relative"
+    return trs, list(zip(ret, adv))
+
+
 def _worst(prec, key, v):
     prec[key] = max(prec.get(key, 0.0), float(np.max(v, initial=0.0)))
 
@@ -84,21 +128,14 @@ def test_bench_configuration_matches_oracle_on_sampled_steps():
                               reps=1)
     envs = [wsx.Env(k, N, seed=0) for k in kinds]
     print("shape", best, [wsx.env_shape(e) for e in envs], flush=True)
-    trs = [wsx.Trajectory(k, T, N) for k in kinds]
-    for e in envs:
-        wsx.env_reset(e, EPOCH)
-    say("full size: batched roll-out")
-    wsx.rollout_batch(envs, [dps[k] for k in kinds], T, trs)
-    rets = [wsx.compute_returns(tr, T, inputs.GAMMA, inputs.LAMBDA, True, torch.float64)
-            for tr in trs]
-    torch.cuda.synchronize()
-    for k, env, tr, (ret, adv) in zip(kinds, envs, trs, rets):
+    precs = [{"kind": k, "rows": N, "steps_checked": list(STEPS),
+              "shape": list(wsx.env_shape(e))} for k, e in zip(kinds, envs)]
+    trs, rets = _one_launch(envs, [dps[k] for k in kinds], list(kinds), T, EPOCH, precs)
+    for k, env, tr, (ret, adv), prec in zip(kinds, envs, trs, rets, precs):
         g = _steps(tr, STEPS + tuple(t + 1 for t in STEPS))
         hold = O.env_hold(k, N)
         log_std = pols[k].exact("log_std")
         flips = 0
-        prec = {"kind": k, "rows": N, "steps_checked": list(STEPS),
-                "shape": list(wsx.env_shape(env))}
         for t in STEPS:
             say("full size: oracle", k, "step", t)
             obs = g["obs"][t].astype(np.float64)
@@ -148,15 +185,10 @@ def test_market_full_size_matches_oracle_on_sampled_steps():
     rows = env.rows
     shape = wsx.env_shape(env)
     print("shape", best, shape, "rows", rows, flush=True)
-    tr = wsx.Trajectory(O.MARKET, T, rows)
-    wsx.env_reset(env, EPOCH)
-    say("full size market: roll-out", rows, T)
-    wsx.rollout(env, dp, T, tr, wsx.MODE_FUSED)
-    ret, adv = wsx.compute_returns(tr, T, inputs.GAMMA, inputs.LAMBDA, True, torch.float64)
-    torch.cuda.synchronize()
-    g = _steps(tr, STEPS + tuple(t + 1 for t in STEPS))
     prec = {"kind": O.MARKET, "envs": n, "rows": rows, "steps_checked": list(STEPS),
             "shape": list(shape)}
+    (tr,), ((ret, adv),) = _one_launch([env], [dp], [O.MARKET], T, EPOCH, [prec])
+    g = _steps(tr, STEPS + tuple(t + 1 for t in STEPS))
     for t in STEPS:
         say("full size market: oracle step", t)
         obs = g["obs"][t]
@@ -198,15 +230,10 @@ def test_reaction_full_size_matches_oracle_on_sampled_steps():
     env = wsx.Env(O.REACTION, n, seed=0, params=params)
     shape = wsx.env_shape(env)
     print("shape", best, shape, flush=True)
-    tr = wsx.Trajectory(O.REACTION, T, n)
-    wsx.env_reset(env, EPOCH)
-    say("full size reaction: roll-out", n, T)
-    wsx.rollout(env, dp, T, tr, wsx.MODE_FUSED)
-    ret, adv = wsx.compute_returns(tr, T, inputs.GAMMA, inputs.LAMBDA, True, torch.float64)
-    torch.cuda.synchronize()
+    prec = {"kind": O.REACTION, "rows": n, "steps_checked": list(STEPS), "shape": list(shape)}
+    (tr,), ((ret, adv),) = _one_launch([env], [dp], [O.REACTION], T, EPOCH, [prec])
     g = _steps(tr, STEPS + tuple(t + 1 for t in STEPS))
     hold = O.env_hold(O.REACTION, n, None, params.astype(np.float64))
-    prec = {"kind": O.REACTION, "rows": n, "steps_checked": list(STEPS), "shape": list(shape)}
     for t in STEPS:
         say("full size reaction: oracle step", t)
         obs = g["obs"][t]
@@ -261,11 +288,8 @@ def test_cartpole_full_size_free_running_matches_oracle():
     env = wsx.Env(O.CARTPOLE, n, seed=0)
     shape = wsx.env_shape(env)
     print("shape", best, shape, flush=True)
-    tr = wsx.Trajectory(O.CARTPOLE, T, n)
-    wsx.env_reset(env, EPOCH)
-    say("full size cartpole: roll-out")
-    wsx.rollout(env, dp, T, tr, wsx.MODE_FUSED)
-    torch.cuda.synchronize()
+    prec = {}
+    (tr,), ((ret, adv),) = _one_launch([env], [dp], [O.CARTPOLE], T, EPOCH, [prec])
     g = tr.host()
     hold = O.env_hold(O.CARTPOLE, n)
     say("full size cartpole: oracle")
@@ -309,11 +333,12 @@ def test_cartpole_full_size_free_running_matches_oracle():
     assert np.all(gq[:3] <= 2.0 * tq[:3] + 1e-7), (gq, tq)
     assert beyond <= n // 100 and gq[-1] <= 1e-3, (beyond, gq[-1])
     worst = float(gerr.max())
-    prec = {"kind": O.CARTPOLE, "envs": n, "steps": T, "shape": list(shape),
+    _returns_on_sampled_rows(tr, ret, adv, n, 17, prec)
+    prec.update({"kind": O.CARTPOLE, "envs": n, "steps": T, "shape": list(shape),
             "envs_with_excused_decision": excused, "terminations": episodes,
             "state_rel_until_excused": worst, "envs_beyond_1e-4": beyond,
             "state_rel_quantiles_50_90_99_999_100": [float(v) for v in gq],
             "fp32_twin_quantiles_50_90_99_999_100": [float(v) for v in tq],
-            "fp32_twin_envs_beyond_1e-4": t_beyond}
+            "fp32_twin_envs_beyond_1e-4": t_beyond})
     print("PRECISION " + json.dumps(prec), flush=True)
     assert excused <= n // 50
