@@ -358,13 +358,18 @@ struct Reaction {
         }
         return group_sum<G>(part);
     }
-    template <int G>
-    __device__ static float noisy_energy(const float* x, const RngKey& key, uint32_t t, uint32_t row,
-                                         const EnvCtx& c, int sub) {
+    // The standard normal of the energy noise of the state reached at step t
+    // (the cosine branch of the NOISE block (t, row)).
+    __device__ static float noise_normal(const RngKey& key, uint32_t t, uint32_t row) {
         const Words w = draw(key, t, row, PURPOSE_NOISE, 0);
         float zc, zs;
         gauss_pair(unit_uniform(w.w[0]), unit_uniform(w.w[1]), zc, zs);
-        return energy<G>(x, c.lds_params, c, sub) + 0.05f * zc;
+        return zc;
+    }
+    template <int G>
+    __device__ static float noisy_energy(const float* x, const RngKey& key, uint32_t t, uint32_t row,
+                                         const EnvCtx& c, int sub) {
+        return energy<G>(x, c.lds_params, c, sub) + 0.05f * noise_normal(key, t, row);
     }
     __device__ static void reset(float* s, const RngKey& key, uint32_t t, uint32_t row,
                                  const EnvCtx& c) {
@@ -384,6 +389,14 @@ struct Reaction {
     template <int G>
     __device__ static void step(float* s, int a, float, uint32_t t, uint32_t row, const RngKey& key,
                                 const EnvCtx& c, int sub, float& reward, bool& done) {
+        step_noise<G>(s, a, noise_normal(key, t + 1, row), c, sub, reward);
+        done = false;
+    }
+    // The step with its noise normal z already drawn (noise_normal(key, t + 1,
+    // row)); never terminates.
+    template <int G>
+    __device__ static void step_noise(float* s, int a, float z, const EnvCtx& c, int sub,
+                                      float& reward) {
         const int coord = a >> 1;
         const float delta = (a & 1) ? -0.05f : 0.05f;
         // a select per coordinate keeps the state in registers (a branch on
@@ -397,10 +410,9 @@ struct Reaction {
             s[i] = i == coord ? moved : s[i];
         }
         cache_move<G>(coord, x_old, x_new, c.lds_params, c, sub);
-        const float e_new = noisy_energy<G>(s, key, t + 1, row, c, sub);
+        const float e_new = energy<G>(s, c.lds_params, c, sub) + 0.05f * z;
         reward = -(e_new - s[20]);
         s[20] = e_new;
-        done = false;
     }
 };
 

@@ -126,8 +126,6 @@ struct AcArgs {
     float value_coef, entropy_coef, inv_n;   // inv_n: 1 / all samples of the call
     bool accumulate;         // add to the workgroups' partial sums (later chunks)
     char* dz2_rows;          // workspace [n][H] in the policy format
-    char* h1_blk;            // workspace: per 32-sample tile a [H][32] block
-    char* dz2_blk;           // (feature-major) of h1 and of dz2
     float* part_fwd;         // per-workgroup partial sums of the kernels
     float* part_bwd;
     float* part_w2;

@@ -867,7 +867,18 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
     // draws pass through LDS, double-buffered by step parity. The market
     // keeps its draws on the row lanes.
     constexpr int DOFF = (R * G + 63) / 64 * 64;
-    constexpr bool kDrawLanes = E::KIND != Market::KIND && DOFF + R <= NTHR;
+    constexpr bool kDrawLanes = E::KIND != Market::KIND && E::KIND != Reaction::KIND &&
+                                DOFF + R <= NTHR;
+    // The reaction walk (16 lanes per row, one wave per SIMD, two Philox
+    // blocks and a Box-Muller pair per step) draws ahead instead: every G
+    // steps, lane `sub` of a row's group draws for step t + sub (the action's
+    // uniform and the energy noise), and each step takes its draws from that
+    // lane, so a step pays for 1 / G of the draws on its critical path. The
+    // values are the same draws. (The market, four lanes per row and one
+    // Philox block per step, measured no gain.)
+    constexpr bool kAhead = E::KIND == Reaction::KIND && G > 1;
+    float ahead_u = 0.0f, ahead_z = 0.0f, noise_z = 0.0f;
+    const int ahead_base = (tid & 63) & ~(G - 1);   // the group's first lane in the wave
     Pre<E>* const pbuf = reinterpret_cast<Pre<E>*>(draws);   // [2][R]
     const int dr = tid - DOFF;                               // a draw lane's tile row
     const PolicyArgs& pol = sg.pol;
@@ -943,7 +954,7 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
     Pre<E> pre{0.0f, 0.0f};   // step 0's draw
     if constexpr (kDrawLanes) {
         if (dvalid) pbuf[dr] = prepare<E>(key, t0, (uint32_t)drow, log_std);
-    } else {
+    } else if constexpr (!kAhead) {
         pre = prepare<E>(key, t0, (uint32_t)row, log_std);
     }
     __syncthreads();
@@ -957,6 +968,17 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
         if constexpr (kDrawLanes) {   // the next step's draws, beside this step's row work
             if (dvalid && step + 1 < horizon)
                 pbuf[((step + 1) & 1) * R + dr] = prepare<E>(key, t + 1, (uint32_t)drow, log_std);
+        }
+        if constexpr (kAhead) {   // every lane, so each source lane holds its value
+            if (step % G == 0) {
+                const uint32_t ts = t + (uint32_t)sub;
+                ahead_u = prepare<E>(key, ts, (uint32_t)row, log_std).u;
+                if constexpr (E::KIND == Reaction::KIND)
+                    ahead_z = Reaction::noise_normal(key, ts + 1, (uint32_t)row);
+            }
+            const int src = ahead_base | (step % G);
+            pre.u = __shfl(ahead_u, src);
+            if constexpr (E::KIND == Reaction::KIND) noise_z = __shfl(ahead_z, src);
         }
         Act<E> act{0, 0.0f};
         if (valid) {
@@ -988,11 +1010,12 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
             __syncthreads();
             if (step < horizon) {
                 if (valid) {
-                    const Pre<E> nxt = prepare<E>(key, t + 1, (uint32_t)row, log_std);
+                    Pre<E> nxt{0.0f, 0.0f};
+                    if constexpr (!kAhead) nxt = prepare<E>(key, t + 1, (uint32_t)row, log_std);
                     const int* sl = sums + ((step & 1) * R + slot) * 2;
                     float reward;
                     Market::settle_slice<G>(s, sub, act.index, sl[0], sl[1], reward);
-                    pre = nxt;
+                    if constexpr (!kAhead) pre = nxt;
                     if (lead) {
                         tr.reward[idx] = reward;
                         tr.done[idx] = 0;
@@ -1005,12 +1028,16 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
             if (valid && step < horizon) {
                 // the next step's draw, independent of this step's dynamics
                 Pre<E> nxt{0.0f, 0.0f};
-                if constexpr (!kDrawLanes) nxt = prepare<E>(key, t + 1, (uint32_t)row, log_std);
+                if constexpr (!kDrawLanes && !kAhead)
+                    nxt = prepare<E>(key, t + 1, (uint32_t)row, log_std);
                 float reward;
-                bool done;
-                E::template step<G>(s, act.index, act.value, t, (uint32_t)row, key, ctx, sub,
-                                    reward, done);
-                if constexpr (!kDrawLanes) pre = nxt;
+                bool done = false;
+                if constexpr (E::KIND == Reaction::KIND && kAhead)
+                    Reaction::step_noise<G>(s, act.index, noise_z, ctx, sub, reward);
+                else
+                    E::template step<G>(s, act.index, act.value, t, (uint32_t)row, key, ctx, sub,
+                                        reward, done);
+                if constexpr (!kDrawLanes && !kAhead) pre = nxt;
                 if (done) E::reset(s, key, t + 1, (uint32_t)row, ctx);
                 if (lead) {
                     tr.reward[idx] = reward;

@@ -17,12 +17,13 @@
 // Four kernels:
 //  k_ac_fwd   per 32-sample tile: forward (layer 1, layer 2, head), head
 //             gradient, dz2 = (dhead W3) (1 - t2^2); accumulates dW3, db3,
-//             db2 and the log-std gradient; writes dz2 rows, and h1 and dz2
-//             as feature-major [H][32] blocks per tile, to the workspace.
+//             db2 and the log-std gradient; writes the dz2 rows to the
+//             workspace (the only per-sample staging).
 //  k_ac_bwd1  per tile: layer 1 again, dz1 = (dz2 W2) (1 - t1^2); accumulates
 //             dW1 and db1.
-//  k_ac_dw2   dW2 = sum_i dz2_i h1_i^T from the blocks, split over the samples
-//             (split-K).
+//  k_ac_dw2   per tile: layer 1 again, dW2 = sum_i dz2_i h1_i^T with h1 from
+//             the accumulators and dz2 transposed into LDS, split over the
+//             samples (split-K).
 //  k_ac_sum   per-workgroup partial sums -> the gradients, one launch.
 // The products run with samples as the MFMA rows (the weight fragments the
 // roll-out loads as A operands serve unchanged as B operands), so the
@@ -43,7 +44,7 @@ namespace {
 
 constexpr int kAcRows = 32;   // samples per tile (two row tiles of 16)
 // samples per pass over the workspace: larger sets run in chunks, so the
-// workspace stays bounded (3 GiB for BF16 hidden 256)
+// workspace stays bounded (1 GiB for BF16 hidden 256)
 constexpr int64_t kAcChunk = int64_t(1) << 21;
 
 // KC elements of a B fragment down column `col` of a row-major [k][ld]
@@ -110,16 +111,6 @@ __device__ __forceinline__ void lds_barrier() {
 // A workgroup's partial sum: written by the first chunk of samples, added to
 // by later chunks (each workgroup owns its slot; chunks run in stream order).
 __device__ __forceinline__ void part_out(float* p, float v, bool acc) { *p = acc ? *p + v : v; }
-
-// Four consecutive samples of one feature (an accumulator's four values) into
-// a feature-major block, rounded to the policy format.
-template <int DT>
-__device__ __forceinline__ void put4(char* p, float a0, float a1, float a2, float a3) {
-    if constexpr (DT == DT_BF16)
-        *reinterpret_cast<uint2*>(p) = make_uint2(pack_bf16x2(a0, a1), pack_bf16x2(a2, a3));
-    else
-        *reinterpret_cast<float4*>(p) = make_float4(a0, a1, a2, a3);
-}
 
 template <int DT, int H, int KIN, int NHP>
 struct AcShape {
@@ -240,8 +231,6 @@ k_ac_fwd(AcArgs a) {
     obs.load(a, blockIdx.x, tid);
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t base = tile * R;
-        char* h1b = a.h1_blk + (size_t)tile * H * R * EB;    // this tile's blocks
-        char* dzb = a.dz2_blk + (size_t)tile * H * R * EB;
         lds_barrier();   // the previous tile's LDS reads are done
         obs.template store<DT>(x0, nullptr, tid);
         lds_barrier();
@@ -266,13 +255,9 @@ k_ac_fwd(AcArgs a) {
 #pragma unroll
                 for (int ks = 0; ks < S::K1S; ++ks)
                     acc = M::mma(M::lds(x0 + (nt * 16 + lr) * S::P_IN + (ks * K + kq) * EB), w1[mt][ks], acc);
-                float t[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    t[i] = act_tanh(acc[i]);
-                    put<DT>(h1 + (nt * 16 + 4 * q + i) * S::P_H + f * EB, t[i]);
-                }
-                put4<DT>(h1b + (size_t)(f * R + nt * 16 + 4 * q) * EB, t[0], t[1], t[2], t[3]);
+                for (int i = 0; i < 4; ++i)
+                    put<DT>(h1 + (nt * 16 + 4 * q + i) * S::P_H + f * EB, act_tanh(acc[i]));
             }
         }
         lds_barrier();
@@ -357,15 +342,13 @@ k_ac_fwd(AcArgs a) {
 #pragma unroll
                 for (int ks = 0; ks < S::KO; ++ks)
                     acc = M::mma(M::lds(dh + (nt * 16 + lr) * S::P_DH + (ks * K + kq) * EB), w3t[mt][ks], acc);
-                float g[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const float t = t2[mt][nt][i];
-                    g[i] = acc[i] * (1.0f - t * t);
-                    db2a[mt] += g[i];
-                    put<DT>(dz + (nt * 16 + 4 * q + i) * S::P_H + f * EB, g[i]);
+                    const float g = acc[i] * (1.0f - t * t);
+                    db2a[mt] += g;
+                    put<DT>(dz + (nt * 16 + 4 * q + i) * S::P_H + f * EB, g);
                 }
-                put4<DT>(dzb + (size_t)(f * R + nt * 16 + 4 * q) * EB, g[0], g[1], g[2], g[3]);
             }
 #pragma unroll
             for (int ht = 0; ht < S::NHT; ++ht) {
@@ -556,96 +539,133 @@ k_ac_bwd1(AcArgs a) {
     }
 }
 
-// dW2[j][k] = sum_i dz2[i][j] h1[i][k] over this workgroup's tiles, from the
-// feature-major blocks: the A fragments (rows j, K = samples) come straight
-// from the dz2 block, the B fragments from the h1 block copied to LDS (every
-// wave reads all of it).
+// dW2[j][k] = sum_i dz2[i][j] h1[i][k] over this workgroup's tiles. Each wave
+// recomputes layer 1 for its own features k (the forward's code, so h1 is
+// the forward's, rounded as the forward rounded it) and takes h1 straight
+// from the accumulators as the B fragments (K = the tile's samples in
+// accumulator order). The dz2 rows are transposed into LDS ([feature]
+// [sample]), from which the A fragments of every feature j are read in the
+// same sample order. A tile's observations and dz2 rows are loaded one tile
+// ahead and stored into the LDS buffers of the tile's parity, so one barrier
+// per tile remains.
 template <int DT, int H, int KIN, int NHP>
 __global__ void __launch_bounds__((AcShape<DT, H, KIN, NHP>::NTHR))
 k_ac_dw2(AcArgs a) {
     using S = AcShape<DT, H, KIN, NHP>;
     using M = typename S::M;
     using Frag = typename S::Frag;
-    constexpr int R = S::R, MT = S::MT, K = S::K, KC = S::KC, EB = S::EB, NKT = H / 16;
-    constexpr int RB = R * EB;   // bytes of one block row
-    __shared__ __attribute__((aligned(16))) char h1Tb[2][H * S::P_T];   // by tile parity
+    constexpr int R = S::R, MT = S::MT, K = S::K, KC = S::KC, EB = S::EB, NJT = H / 16;
+    __shared__ __attribute__((aligned(16))) char x0b[2][R * S::P_IN];
+    __shared__ __attribute__((aligned(16))) char dzTb[2][H * S::P_T];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lr = lane & 15, q = lane >> 4;
     const int kq = q * KC;
-    f32x4 acc[MT][NKT];
+    const PolicyArgs& p = a.pol;
+    Frag w1[MT][S::K1S];
+    float b1v[MT];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < MT; ++mt) {
+        const int f = wave * S::FPW + mt * 16 + lr;
 #pragma unroll
-        for (int kt = 0; kt < NKT; ++kt) acc[mt][kt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int ks = 0; ks < S::K1S; ++ks) load_a(w1[mt][ks], p.w1, p.d_in, f, H, ks * K + kq, p.d_in);
+        b1v[mt] = p.b1[f];
+    }
+    f32x4 acc[NJT][MT];
+#pragma unroll
+    for (int jt = 0; jt < NJT; ++jt)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[jt][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+
     const int64_t n_tiles = (a.n + R - 1) / R;
-    constexpr int CPR = RB / 16;                                 // 16-byte chunks per block row
-    constexpr int HPER = (H * CPR + S::NTHR - 1) / S::NTHR;     // chunks per thread
-    // A tile's operands are loaded one tile ahead: this wave's A fragments
-    // (dz2 block) and this thread's chunks of the h1 block, which go to the
-    // LDS buffer of the tile's parity (read two tiles earlier, before the
-    // previous tile's barrier), so one barrier per tile remains.
-    Frag A_[MT][R / K];
-    uint4 hv[HPER];
-    auto load_tile = [&](int64_t tile) {
-        const bool ok = tile < n_tiles;   // past the last tile: nothing is loaded
-        const char* hb = a.h1_blk + (size_t)(ok ? tile : 0) * H * RB;
-        const char* db = a.dz2_blk + (size_t)(ok ? tile : 0) * H * RB;
+    // dz2 chunks of 16 bytes (KC = 16 / EB features of one sample), sample
+    // fastest over the threads, so the transposed LDS stores of a wave fall
+    // on distinct banks
+    constexpr int CH = H * EB / 16, FPC = 16 / EB;
+    constexpr int DPER = (R * CH + S::NTHR - 1) / S::NTHR;
+    uint4 dzv[DPER];
+    auto load_dz = [&](int64_t tile) {
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-            for (int ks = 0; ks < R / K; ++ks) {
-                const char* src = db + (size_t)(wave * S::FPW + mt * 16 + lr) * RB + (ks * K + kq) * EB;
-                Frag f{};
-                if (ok) {
-                    if constexpr (EB == 2)
-                        f = __builtin_bit_cast(Frag, *reinterpret_cast<const uint4*>(src));
-                    else
-                        f = *reinterpret_cast<const float*>(src);
-                }
-                A_[mt][ks] = f;
-            }
-#pragma unroll
-        for (int u = 0; u < HPER; ++u) {
+        for (int u = 0; u < DPER; ++u) {
             const int e = tid + u * S::NTHR;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (ok && e < H * CPR)
-                v = *reinterpret_cast<const uint4*>(hb + (size_t)(e / CPR) * RB + (e % CPR) * 16);
-            hv[u] = v;
+            const int r = e % R, c = e / R;
+            const int64_t n = tile * R + r;
+            dzv[u] = make_uint4(0u, 0u, 0u, 0u);
+            if (e < R * CH && n < a.n)
+                dzv[u] = *reinterpret_cast<const uint4*>(a.dz2_rows + (size_t)n * (H * EB) +
+                                                         (size_t)c * 16);
         }
     };
-    load_tile(blockIdx.x);
+    ObsPrefetch<S> obs;
+    obs.load(a, blockIdx.x, tid);
+    load_dz(blockIdx.x);
     int pb = 0;
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x, pb ^= 1) {
-        char* h1T = h1Tb[pb];
+        char* x0 = x0b[pb];
+        char* dzT = dzTb[pb];
+        obs.template store<DT>(x0, nullptr, tid);
 #pragma unroll
-        for (int u = 0; u < HPER; ++u) {
+        for (int u = 0; u < DPER; ++u) {
             const int e = tid + u * S::NTHR;
-            if (e < H * CPR) *reinterpret_cast<uint4*>(h1T + (e / CPR) * S::P_T + (e % CPR) * 16) = hv[u];
+            if (e >= R * CH) break;
+            const int r = e % R, c = e / R;
+            const uint32_t wd[4] = {dzv[u].x, dzv[u].y, dzv[u].z, dzv[u].w};
+#pragma unroll
+            for (int k = 0; k < FPC; ++k) {
+                char* dst = dzT + (c * FPC + k) * S::P_T + r * EB;
+                if constexpr (EB == 2)
+                    *reinterpret_cast<uint16_t*>(dst) = (uint16_t)(wd[k >> 1] >> (16 * (k & 1)));
+                else
+                    *reinterpret_cast<uint32_t*>(dst) = wd[k];
+            }
         }
-        Frag A_cur[MT][R / K];
+        obs.load(a, tile + gridDim.x, tid);
+        load_dz(tile + gridDim.x);
+        lds_barrier();
+        f32x4 t[MT][2];   // h1 of this wave's features, unrounded
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int ks = 0; ks < R / K; ++ks) A_cur[mt][ks] = A_[mt][ks];
-        load_tile(tile + gridDim.x);   // in flight during this tile's products
-        lds_barrier();
+            for (int nt = 0; nt < 2; ++nt) {
+                f32x4 z = {b1v[mt], b1v[mt], b1v[mt], b1v[mt]};
 #pragma unroll
-        for (int ks = 0; ks < R / K; ++ks)
+                for (int ks = 0; ks < S::K1S; ++ks)
+                    z = M::mma(M::lds(x0 + (nt * 16 + lr) * S::P_IN + (ks * K + kq) * EB), w1[mt][ks], z);
 #pragma unroll
-            for (int kt = 0; kt < NKT; ++kt) {
-                const Frag B_ = M::lds(h1T + (kt * 16 + lr) * S::P_T + (ks * K + kq) * EB);
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt) acc[mt][kt] = M::mma(A_cur[mt][ks], B_, acc[mt][kt]);
+                for (int i = 0; i < 4; ++i) t[mt][nt][i] = act_tanh(z[i]);
             }
+        if constexpr (DT == DT_BF16) {
+            Frag B_[MT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) B_[mt] = pack_acc_k(t[mt][0], t[mt][1]);
+#pragma unroll
+            for (int jt = 0; jt < NJT; ++jt) {
+                const Frag A_ = lds_k_perm(dzT, S::P_T, jt * 16 + lr, q);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) acc[jt][mt] = M::mma(A_, B_[mt], acc[jt][mt]);
+            }
+        } else {
+#pragma unroll
+            for (int jt = 0; jt < NJT; ++jt)
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const float A_ = *reinterpret_cast<const float*>(
+                            dzT + (jt * 16 + lr) * S::P_T + (16 * nt + 4 * q + i) * EB);
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt)
+                            acc[jt][mt] = M::mma(A_, t[mt][nt][i], acc[jt][mt]);
+                    }
+        }
     }
     float* out = a.part_w2 + (size_t)blockIdx.x * H * H;
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int jt = 0; jt < NJT; ++jt)
 #pragma unroll
-        for (int kt = 0; kt < NKT; ++kt)
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                part_out(&out[(size_t)(wave * S::FPW + mt * 16 + 4 * q + i) * H + kt * 16 + lr],
-                         acc[mt][kt][i], a.accumulate);
+                part_out(&out[(size_t)(jt * 16 + 4 * q + i) * H + wave * S::FPW + mt * 16 + lr],
+                         acc[jt][mt][i], a.accumulate);
 }
 
 // Reduction of the per-workgroup partial sums, one launch for every
@@ -799,8 +819,8 @@ bool ac_supported(int dtype, int hidden, int d_in, int n_head) {
            hipSuccess;
 }
 
-// Workspace: dz2 rows [n][H], the h1 and dz2 blocks (whole tiles), the
-// partial sums; each part 256-byte aligned.
+// Workspace: dz2 rows [n][H] and the partial sums; each part 256-byte
+// aligned.
 static size_t ac_round_up(size_t b) { return (b + 255) / 256 * 256; }
 
 int64_t ac_chunk_samples(int64_t n) { return std::min<int64_t>(n, kAcChunk); }
@@ -819,8 +839,7 @@ constexpr size_t ac_static_bytes() {
     constexpr size_t grid = tiles;   // ac_grid: min(tiles, CUs)
     constexpr size_t nhp = 64, kin = 32;
     constexpr size_t part = grid * ((nhp * h + h + nhp + 1) + (h * kin + h)) + grid * h * h;
-    return 256 + ac_round_up_c(n * h * eb) + 2 * ac_round_up_c(tiles * kAcRows * h * eb) +
-           part * sizeof(float);
+    return 256 + ac_round_up_c(n * h * eb) + part * sizeof(float);
 }
 }  // namespace
 
@@ -857,14 +876,13 @@ size_t ac_workspace_bytes(int dtype, int hidden, int64_t n, int grid1, int grid2
     n = ac_chunk_samples(n);
     const size_t eb = dtype == DT_BF16 ? 2 : 4;
     const size_t rows = (size_t)n * hidden * eb;
-    const size_t blk = (size_t)((n + kAcRows - 1) / kAcRows) * kAcRows * hidden * eb;
     // partial sums of the widest head compiled for this format and width
     size_t part = 0;
     if (dtype == DT_F32 && hidden == 64)
         part = AcVariant<DT_F32, 64, 4, 16>::part_floats(grid1, grid2);
     else if (dtype == DT_BF16 && hidden == 256)
         part = AcVariant<DT_BF16, 256, 32, 64>::part_floats(grid1, grid2);
-    return 256 + ac_round_up(rows) + 2 * ac_round_up(blk) + part * sizeof(float);
+    return 256 + ac_round_up(rows) + part * sizeof(float);
 }
 
 hipError_t launch_ac_grad(const AcLaunch& l, hipStream_t s) {
@@ -875,15 +893,10 @@ hipError_t launch_ac_grad(const AcLaunch& l, hipStream_t s) {
         const int64_t chunk = std::min<int64_t>(l.args.n, kAcChunk);
         const size_t eb = S::EB;
         const size_t rows = (size_t)chunk * p.hidden * eb;
-        const size_t blk = (size_t)((chunk + kAcRows - 1) / kAcRows) * kAcRows * p.hidden * eb;
         AcArgs a = l.args;
         char* w = reinterpret_cast<char*>(((uintptr_t)l.workspace + 255) / 256 * 256);
         a.dz2_rows = w;
         w += ac_round_up(rows);
-        a.h1_blk = w;
-        w += ac_round_up(blk);
-        a.dz2_blk = w;
-        w += ac_round_up(blk);
         a.part_fwd = reinterpret_cast<float*>(w);
         a.part_bwd = a.part_fwd + (size_t)l.grid1 * S::FWD_FLOATS;
         a.part_w2 = a.part_bwd + (size_t)l.grid1 * S::BWD_FLOATS;
