@@ -67,9 +67,20 @@ struct Mlp {
     static constexpr int K = M::K, KC = M::KC, EB = M::EB;
     static constexpr int FPW = H / NW;   // hidden features owned by a wave
     static constexpr int MT = FPW / 16;
-    static constexpr int K1S = KIN / K, K2S = H / K, K3S = FPW / K, NHT = NHP / 16;
+    // FP8 products over K = 128 (layer 2; the head when a wave's K-slice, or
+    // the split-M head's whole K, is a multiple of 128) take the 16x16x128
+    // form, twice the matrix-core rate of the 16x16x32 one; layer 1 keeps
+    // the narrow form (its K is the observation, padded to 32)
+    using M2 = typename std::conditional<DT == DT_FP8 && H % 128 == 0, MmaF8K128, M>::type;
+    using M3 = typename std::conditional<HS ? (DT == DT_FP8 && H % 128 == 0)
+                                            : (DT == DT_FP8 && FPW % 128 == 0),
+                                         MmaF8K128, M>::type;
+    using Frag2 = typename M2::frag;
+    using Frag3 = typename M3::frag;
+    static constexpr int K2 = M2::K, KC2 = M2::KC, K3 = M3::K, KC3 = M3::KC;
+    static constexpr int K1S = KIN / K, K2S = H / K2, K3S = FPW / K3, NHT = NHP / 16;
     static constexpr int NHW = HS ? (NHT + NW - 1) / NW : NHT;   // head tiles held by a wave
-    static constexpr int KHS = HS ? K2S : K3S;                   // head K-steps of a wave
+    static constexpr int KHS = HS ? H / K3 : K3S;                // head K-steps of a wave
     static constexpr int NPART = HS ? 1 : NW;                    // head results per row
     static constexpr int RS = (HS && NW % NHT == 0 && NT % (NW / NHT) == 0) ? NW / NHT : 1;
     static constexpr int NTR = NT / RS;                          // row tiles of a head job
@@ -102,23 +113,24 @@ struct Mlp {
     // the same for the head weights of the split-K head ([wave][hw][ks][lane])
     static constexpr bool W3_LDS = W1_LDS && !HS;
     static constexpr int OFF_W3 = OFF_W1 + W1_BYTES;
-    static constexpr int W3_BYTES = W3_LDS ? NW * NHW * KHS * 64 * (int)sizeof(Frag) : 0;
+    static constexpr int W3_BYTES = W3_LDS ? NW * NHW * KHS * 64 * (int)sizeof(Frag3) : 0;
     static constexpr int BYTES = OFF_W3 + W3_BYTES;
     static_assert(!HS || P_PART * 4 <= P_H, "head results fit in the h1 tile");
-    static_assert(FPW % 16 == 0 && FPW % K == 0 && KIN % K == 0 && H % K == 0, "tile shape");
+    static_assert(FPW % 16 == 0 && (HS || FPW % K3 == 0) && KIN % K == 0 && H % K2 == 0 && H % K3 == 0,
+                  "tile shape");
     static_assert(BYTES <= 160 * 1024, "LDS budget");
 
     static constexpr int DTYPE = DT;
     // software pipelining of the dense layers (see dense_tanh): with at most
     // two waves per SIMD and at most 64 registers of layer-2 weights per lane,
     // or with one wave per SIMD and at most four output tiles per wave
-    static constexpr int W2_REGS = MT * K2S * (int)sizeof(Frag) / 4;
+    static constexpr int W2_REGS = MT * K2S * (int)sizeof(Frag2) / 4;
     static constexpr bool PIPE_ON =
         (WPS <= 2 && W2_REGS <= 64) || (WPS == 1 && MT <= 4);
 
     Frag w1[MT][K1S];
-    Frag w2[MT][K2S];
-    Frag w3[NHW][KHS];
+    Frag2 w2[MT][K2S];
+    Frag3 w3[NHW][KHS];
     float o3[NHW][4];                  // head output scale
     float inv_q1, inv_q2;              // 1 / scale of the h1 and h2 quantisation
     char* tr_act[2];                   // TRACE: the tile's first row of each layer's codes
@@ -127,8 +139,8 @@ struct Mlp {
     __device__ static Frag& w1_lds(char* base, int wave, int mt, int ks, int lane) {
         return reinterpret_cast<Frag*>(base)[((wave * MT + mt) * K1S + ks) * 64 + lane];
     }
-    __device__ static Frag& w3_lds(char* base, int wave, int hw, int ks, int lane) {
-        return reinterpret_cast<Frag*>(base)[((wave * NHW + hw) * KHS + ks) * 64 + lane];
+    __device__ static Frag3& w3_lds(char* base, int wave, int hw, int ks, int lane) {
+        return reinterpret_cast<Frag3*>(base)[((wave * NHW + hw) * KHS + ks) * 64 + lane];
     }
 
     __device__ static float row_scale(const float* s, int m, int m_valid) {
@@ -164,7 +176,8 @@ struct Mlp {
                         w1[mt][ks];
             }
 #pragma unroll
-            for (int ks = 0; ks < K2S; ++ks) load_a(w2[mt][ks], p.w2, H, m, H, ks * K + kq, H);
+            for (int ks = 0; ks < K2S; ++ks)
+                load_a(w2[mt][ks], p.w2, H, m, H, ks * K2 + (lane >> 4) * KC2, H);
         }
 #pragma unroll
         for (int hw = 0; hw < NHW; ++hw) {
@@ -173,13 +186,13 @@ struct Mlp {
 #pragma unroll
             for (int ks = 0; ks < KHS; ++ks) {
                 if constexpr (HS) {
-                    load_a(w3[hw][ks], p.w3, H, m, p.n_head, ks * K + kq, H);
+                    load_a(w3[hw][ks], p.w3, H, m, p.n_head, ks * K3 + (lane >> 4) * KC3, H);
                 } else {
                     // K element e of lane group q is this wave's layer-2 output
-                    // (tile mt, accumulator row i): idx = ks KC + e, mt = idx / 4
+                    // (tile mt, accumulator row i): idx = ks KC3 + e, mt = idx / 4
                     const int q = lane >> 4;
                     load_a_cols(w3[hw][ks], p.w3, H, m, p.n_head, [&](int e) {
-                        const int idx = ks * KC + e;
+                        const int idx = ks * KC3 + e;
                         return wave * FPW + (idx >> 2) * 16 + 4 * q + (idx & 3);
                     });
                     if constexpr (W3_LDS)
@@ -194,18 +207,19 @@ struct Mlp {
 
     // Accumulators of this wave's MT output tiles for row tile `nt`: the
     // per-feature start `ini` plus W times the row tile's inputs.
-    template <int KS>
-    __device__ __forceinline__ static void mma_rows(f32x4 (&acc)[MT], const Frag (&w)[MT][KS],
+    template <class MM, int KS>
+    __device__ __forceinline__ static void mma_rows(f32x4 (&acc)[MT],
+                                                    const typename MM::frag (&w)[MT][KS],
                                                     const float4 (&ini)[MT], const char* in,
                                                     int p_in, int nt, int lane) {
-        const int lr = lane & 15, kq = (lane >> 4) * KC;
+        const int lr = lane & 15, kq = (lane >> 4) * MM::KC;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{ini[mt].x, ini[mt].y, ini[mt].z, ini[mt].w};
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            const Frag b = M::lds(in + (nt * 16 + lr) * p_in + (ks * K + kq) * EB);
+            const typename MM::frag b = MM::lds(in + (nt * 16 + lr) * p_in + (ks * MM::K + kq) * EB);
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) acc[mt] = M::mma(w[mt][ks], b, acc[mt]);
+            for (int mt = 0; mt < MT; ++mt) acc[mt] = MM::mma(w[mt][ks], b, acc[mt]);
         }
     }
 
@@ -230,10 +244,16 @@ struct Mlp {
 
     // B fragment of head K-step ks from this wave's packed layer-2 outputs of
     // one row tile (the order load() gave the head weights).
-    __device__ __forceinline__ static Frag head_frag(const Packed (&pk)[MT], int ks) {
+    __device__ __forceinline__ static Frag3 head_frag(const Packed (&pk)[MT], int ks) {
         if constexpr (DT == DT_BF16) {
             const uint4 u = make_uint4(pk[2 * ks].x, pk[2 * ks].y, pk[2 * ks + 1].x, pk[2 * ks + 1].y);
-            return __builtin_bit_cast(Frag, u);
+            return __builtin_bit_cast(Frag3, u);
+        } else if constexpr (std::is_same<M3, MmaF8K128>::value) {
+            // 32 elements: the packed outputs of tiles 8 ks .. 8 ks + 7
+            Frag3 f;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) f[i] = (int)pk[8 * ks + i];
+            return f;
         } else if constexpr (DT == DT_FP8) {
             return (long)((uint64_t)pk[2 * ks] | ((uint64_t)pk[2 * ks + 1] << 32));
         } else {
@@ -267,9 +287,9 @@ struct Mlp {
         if constexpr (HEAD) {
 #pragma unroll
             for (int ks = 0; ks < KHS; ++ks) {
-                const Frag b = head_frag(pk, ks);
+                const Frag3 b = head_frag(pk, ks);
 #pragma unroll
-                for (int hw = 0; hw < NHW; ++hw) acc3[hw][nt] = M::mma(w3[hw][ks], b, acc3[hw][nt]);
+                for (int hw = 0; hw < NHW; ++hw) acc3[hw][nt] = M3::mma(w3[hw][ks], b, acc3[hw][nt]);
             }
         } else {
 #pragma unroll
@@ -290,8 +310,8 @@ struct Mlp {
     // whose layer-2 weights take more than 64 registers per lane -- each row
     // tile is multiplied, then activated). `tab` holds the layer's
     // accumulator starts and tanh factors.
-    template <int KS, bool HEAD, int LAYER>
-    __device__ __forceinline__ void dense_tanh(const Frag (&w)[MT][KS], const float* tab,
+    template <class MM, int KS, bool HEAD, int LAYER>
+    __device__ __forceinline__ void dense_tanh(const typename MM::frag (&w)[MT][KS], const float* tab,
                                                const char* in, int p_in, char* out, float inv_q,
                                                int wave, int lane, f32x4 (&acc3)[NHW][NT]) {
         float4 ini[MT], kx[MT];
@@ -311,17 +331,17 @@ struct Mlp {
             for (int nt = 0; nt < NT; ++nt) {
                 f32x4 acc[MT];
                 per_feature();   // re-read per row tile: fewer live registers
-                mma_rows<KS>(acc, w, ini, in, p_in, nt, lane);
+                mma_rows<MM, KS>(acc, w, ini, in, p_in, nt, lane);
                 tanh_rows<HEAD, LAYER>(acc, kx, out, inv_q, nt, wave, lane, acc3);
             }
             return;
         }
         per_feature();
         f32x4 acc[2][MT];
-        mma_rows<KS>(acc[0], w, ini, in, p_in, 0, lane);
+        mma_rows<MM, KS>(acc[0], w, ini, in, p_in, 0, lane);
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-            if (nt + 1 < NT) mma_rows<KS>(acc[(nt + 1) & 1], w, ini, in, p_in, nt + 1, lane);
+            if (nt + 1 < NT) mma_rows<MM, KS>(acc[(nt + 1) & 1], w, ini, in, p_in, nt + 1, lane);
             tanh_rows<HEAD, LAYER>(acc[nt & 1], kx, out, inv_q, nt, wave, lane, acc3);
             if (nt + 1 < NT) {
                 // all LDS reads of the next row tile first, a few vector
@@ -357,11 +377,11 @@ struct Mlp {
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int ks = 0; ks < K1S; ++ks) w1r[mt][ks] = w1_lds(smem + OFF_W1, wave, mt, ks, lane);
-            dense_tanh<K1S, false, 0>(w1r, tab, smem + OFF_IN, P_IN, smem + OFF_H1, inv_q1, wave, lane,
-                                   acc);
+            dense_tanh<M, K1S, false, 0>(w1r, tab, smem + OFF_IN, P_IN, smem + OFF_H1, inv_q1, wave,
+                                         lane, acc);
         } else {
-            dense_tanh<K1S, false, 0>(w1, tab, smem + OFF_IN, P_IN, smem + OFF_H1, inv_q1, wave, lane,
-                                   acc);
+            dense_tanh<M, K1S, false, 0>(w1, tab, smem + OFF_IN, P_IN, smem + OFF_H1, inv_q1, wave,
+                                         lane, acc);
         }
         __syncthreads();
         if constexpr (!HS) {
@@ -372,24 +392,25 @@ struct Mlp {
                     for (int ks = 0; ks < KHS; ++ks) w3[hw][ks] = w3_lds(smem + OFF_W3, wave, hw, ks, lane);
             }
             // split-K: the head consumes each wave's own h2 from its registers
-            dense_tanh<K2S, true, 1>(w2, tab + 2 * H, smem + OFF_H1, P_H, nullptr, inv_q2, wave, lane,
-                                  acc);
+            dense_tanh<M2, K2S, true, 1>(w2, tab + 2 * H, smem + OFF_H1, P_H, nullptr, inv_q2, wave,
+                                         lane, acc);
         } else {
-            dense_tanh<K2S, false, 1>(w2, tab + 2 * H, smem + OFF_H1, P_H, smem + OFF_H2, inv_q2, wave,
-                                   lane, acc);
+            dense_tanh<M2, K2S, false, 1>(w2, tab + 2 * H, smem + OFF_H1, P_H, smem + OFF_H2, inv_q2,
+                                          wave, lane, acc);
             __syncthreads();   // every wave reads all of h2
             const char* h2 = smem + OFF_H2 + head_row0(wave) * 16 * P_H;
+            const int kq3 = (lane >> 4) * KC3;
 #pragma unroll
             for (int ks = 0; ks < KHS; ++ks) {
-                Frag b[NTR];
+                Frag3 b[NTR];
 #pragma unroll
                 for (int i = 0; i < NTR; ++i)
-                    b[i] = M::lds(h2 + (i * 16 + lr) * P_H + (ks * K + kq) * EB);
+                    b[i] = M3::lds(h2 + (i * 16 + lr) * P_H + (ks * K3 + kq3) * EB);
 #pragma unroll
                 for (int hw = 0; hw < NHW; ++hw) {
                     if (head_tile(wave, hw) >= NHT) break;
 #pragma unroll
-                    for (int i = 0; i < NTR; ++i) acc[hw][i] = M::mma(w3[hw][ks], b[i], acc[hw][i]);
+                    for (int i = 0; i < NTR; ++i) acc[hw][i] = M3::mma(w3[hw][ks], b[i], acc[hw][i]);
                 }
             }
         }
