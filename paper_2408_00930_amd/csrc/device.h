@@ -350,6 +350,12 @@ template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v) {
     return __builtin_bit_cast(float, dpp_i<CTRL>(__builtin_bit_cast(int, v)));
 }
+// The same with a row mask: rows outside it get 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_f_rows(float v) {
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROWS, 0xF, false));
+}
 constexpr int kDppSwap1 = 0xB1;        // quad_perm [1,0,3,2]
 constexpr int kDppSwap2 = 0x4E;        // quad_perm [2,3,0,1]
 constexpr int kDppHalfMirror = 0x141;  // lane i <-> 7 - i within 8 lanes

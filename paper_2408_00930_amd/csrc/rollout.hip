@@ -81,6 +81,18 @@ k_policy_trace(EnvArgs env, PolicyArgs pol, char* act1, char* act2) {
     policy_tile<E, DT, H, NW, NT, HS, OCC, true>(env, pol, act1, act2);
 }
 
+template <class E, int H>
+__global__ void __launch_bounds__(64) k_plain_policy_rw(EnvArgs env, PolicyArgs pol) {
+    policy_row_rw<E, H, false>(env, pol, nullptr, nullptr);
+}
+
+template <class E, int H>
+__global__ void __launch_bounds__(64) k_policy_trace_rw(EnvArgs env, PolicyArgs pol, char* act1,
+                                                        char* act2) {
+    policy_row_rw<E, H, true>(env, pol, reinterpret_cast<float*>(act1),
+                              reinterpret_cast<float*>(act2));
+}
+
 // Plain sampling: G lanes per row, the same group code as the fused kernel.
 template <class E, int G>
 __global__ void __launch_bounds__(256) k_plain_sample(EnvArgs env, PolicyArgs pol, TrajArgs tr,
@@ -297,8 +309,18 @@ const void* step_entry() {
      reinterpret_cast<const void*>(&k_fused<E, E2, DT, H, NW, NT, HS, OCC>), nullptr,  \
      nullptr, nullptr, nullptr, 0},
 
+// The row-per-wave form of the FP32 64-wide policy (one wave, one row per
+// tile).
+#define WSX_RW_ENTRY(E, H)                                                             \
+    {{E::KIND, DT_F32, H, 1, 1, 1, 0},                                                \
+     reinterpret_cast<const void*>(&k_fused_rw<E, H>),                                \
+     reinterpret_cast<const void*>(&k_plain_policy_rw<E, H>),                         \
+     reinterpret_cast<const void*>(&k_policy_trace_rw<E, H>),                         \
+     reinterpret_cast<const void*>(&k_plain_sample<E, 1>), step_entry<E, 1>(), 1},
+
 static const VariantEntry kVariants[] = {WSX_VARIANTS(WSX_ENTRY)
-                                             WSX_PAIR_VARIANTS(WSX_PAIR_ENTRY)};
+                                             WSX_PAIR_VARIANTS(WSX_PAIR_ENTRY)
+                                                 WSX_RW_ENTRY(CartPole, 64)};
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 int n_variants() { return kNumVariants; }

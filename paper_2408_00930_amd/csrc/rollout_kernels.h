@@ -1218,6 +1218,223 @@ k_fused(Batch batch) {
     }
 }
 
+// ------------------------------------------- one wave per row (FP32) --
+// For a small FP32 policy (CartPole's 4-64-64-3) a 16-row MFMA tile that
+// holds a few replicas wastes most of its products, and each step pays three
+// workgroup barriers. This form gives a one-wave workgroup one row at a time:
+// lane j owns hidden feature j of both layers (its rows of W1 and W2 and its
+// column of the head in registers), the layers are FP32 FMAs, the hidden
+// activations pass between the wave's lanes through 256 bytes of LDS, and
+// the head is a butterfly sum over the lanes. Every lane then holds the same
+// head, so the per-row phase runs on all lanes with the same values and a
+// step needs no barrier.
+__device__ __forceinline__ float wave_sum(float v) {
+    v = group_sum<16>(v);   // every lane of 16-lane row k: its sum r_k
+    // row_bcast:15 adds lane 15's r0 into row 1 and lane 47's r2 into row 3,
+    // row_bcast:31 adds lane 31's r0 + r1 into row 3: lane 63 holds
+    // (r3 + r2) + (r1 + r0), read into a scalar register for every lane
+    v += dpp_f_rows<0x142, 0xA>(v);
+    v += dpp_f_rows<0x143, 0xC>(v);
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
+template <class E, int H>
+struct RowMlp {
+    static_assert(H == 64, "one lane per hidden feature");
+    using HO = HeadOf<E>;
+    static constexpr int OD = E::OD, NH = HO::NH;
+    float w1[OD], w2[H], w3[NH], b3[NH];
+    float b1, b2;
+
+    __device__ void load(const PolicyArgs& p, int lane) {
+        const float* W1 = static_cast<const float*>(p.w1);
+        const float* W2 = static_cast<const float*>(p.w2);
+        const float* W3 = static_cast<const float*>(p.w3);
+#pragma unroll
+        for (int k = 0; k < OD; ++k) w1[k] = W1[lane * p.d_in + k];
+#pragma unroll
+        for (int k = 0; k < H; ++k) w2[k] = W2[lane * H + k];
+#pragma unroll
+        for (int o = 0; o < NH; ++o) {
+            w3[o] = W3[o * H + lane];
+            b3[o] = p.b3[o];
+        }
+        b1 = p.b1[lane];
+        b2 = p.b2[lane];
+    }
+
+    // Head outputs for observation `o` (the same on every lane) and this
+    // lane's hidden activations; `lds` holds H floats private to the wave.
+    __device__ void forward(const float (&o)[OD], float* lds, int lane, float (&head)[NH],
+                            float& h1, float& h2) const {
+        float z1 = b1;
+#pragma unroll
+        for (int k = 0; k < OD; ++k) z1 = __builtin_fmaf(w1[k], o[k], z1);
+        h1 = tanh_scaled(z1, kTwoLog2e);
+        lds[lane] = h1;
+        wave_lds_sync();
+        float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};   // k mod 8
+#pragma unroll
+        for (int k4 = 0; k4 < H / 4; ++k4) {
+            const float4 v = reinterpret_cast<const float4*>(lds)[k4];
+            const int c = 4 * (k4 & 1);
+            acc[c + 0] = __builtin_fmaf(w2[4 * k4 + 0], v.x, acc[c + 0]);
+            acc[c + 1] = __builtin_fmaf(w2[4 * k4 + 1], v.y, acc[c + 1]);
+            acc[c + 2] = __builtin_fmaf(w2[4 * k4 + 2], v.z, acc[c + 2]);
+            acc[c + 3] = __builtin_fmaf(w2[4 * k4 + 3], v.w, acc[c + 3]);
+        }
+        const float z2 = b2 + (((acc[0] + acc[1]) + (acc[2] + acc[3])) +
+                               ((acc[4] + acc[5]) + (acc[6] + acc[7])));
+        h2 = tanh_scaled(z2, kTwoLog2e);
+#pragma unroll
+        for (int j = 0; j < NH; ++j) head[j] = b3[j] + wave_sum(w3[j] * h2);
+    }
+};
+
+// The row-per-wave form over the tiles (rows) of a launch's segments, with
+// the same reset pre-pass and returns post-pass as k_fused.
+template <class E, int H>
+__global__ void __launch_bounds__(64) k_fused_rw(Batch batch) {
+    using HO = HeadOf<E>;
+    using B = Block<E, 1>;
+    constexpr int C = B::C;
+    static_assert(E::LANES == 1, "one-lane environments");
+    __shared__ __attribute__((aligned(16))) char smem[64 * 32];   // h1, then the returns' buffer
+    __shared__ Segment seg;
+    float* h1s = reinterpret_cast<float*>(smem);
+    const int lane = threadIdx.x;
+    const float* staged = nullptr;
+    if (batch.any_reset) {
+        for (int tile = blockIdx.x; tile < batch.n_tiles; tile += gridDim.x) {
+            const int si = segment_index(batch, tile);
+            __syncthreads();
+            stage_segment(batch, si, &seg, lane, 64);
+            __syncthreads();
+            if (__builtin_amdgcn_readfirstlane(seg.reset)) reset_tile<E, 64>(seg, tile, smem, staged, lane);
+        }
+    }
+    RowMlp<E, H> mlp;
+    int loaded = -1;
+    for (int tile = blockIdx.x; tile < batch.n_tiles; tile += gridDim.x) {
+        const int si = segment_index(batch, tile);
+        __syncthreads();
+        stage_segment(batch, si, &seg, lane, 64);
+        __syncthreads();
+        const EnvArgs env = uniform(seg.env);
+        const TrajArgs tr = uniform(seg.tr);
+        const PolicyArgs& pol = seg.pol;
+        if (si != loaded) {
+            mlp.load(pol, lane);
+            loaded = si;
+        }
+        const int horizon = __builtin_amdgcn_readfirstlane(seg.steps);
+        const int passes = horizon + (__builtin_amdgcn_readfirstlane(seg.last) ? 1 : 0);
+        const RngKey key = rng_key(env);
+        const uint32_t t0 = step_base(env);
+        const Tile tl = tile_of(env, tile - __builtin_amdgcn_readfirstlane(seg.tile_begin));
+        if (tl.row0 >= tl.row1) continue;
+        const int row = tile_row(env, tl.row0);
+        const float log_std = (E::NACT == 0 && pol.log_std) ? pol.log_std[0] : 0.0f;
+        const float sigma = expf(log_std);
+        EnvCtx ctx{nullptr, nullptr, 1};
+        float s[E::SR];
+        load_state<E>(env, row, s);
+        float o[E::OD];
+        E::observe(s, o);
+        if (horizon > 0) {
+            float ok = 0.0f;
+#pragma unroll
+            for (int k = 0; k < E::OD; ++k) ok = lane == k ? o[k] : ok;
+            if (lane < E::OD) tr.obs[(size_t)row * E::OD + lane] = ok;
+        }
+        // the draws of the next 64 steps, one per lane, taken with readlane
+        Pre<E> ahead{0.0f, 0.0f};
+        for (int step = 0; step < passes; ++step) {
+            const uint32_t t = t0 + (uint32_t)step;
+            if (step % 64 == 0) ahead = prepare<E>(key, t + (uint32_t)lane, (uint32_t)row, log_std);
+            float head[HO::NH], h1, h2;
+            mlp.forward(o, h1s, lane, head, h1, h2);
+            const float hv = head[HO::NOUT];
+            if (step == horizon) {
+                if (lane == 0) tr.last_value[row] = hv;
+                break;
+            }
+            Pre<E> pre;
+            pre.u = __builtin_bit_cast(float, __builtin_amdgcn_readlane(
+                                                  __builtin_bit_cast(int, ahead.u), step % 64));
+            pre.logp = __builtin_bit_cast(float, __builtin_amdgcn_readlane(
+                                                     __builtin_bit_cast(int, ahead.logp), step % 64));
+            float hb[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) hb[c] = c < HO::NOUT ? head[c] : 0.0f;
+            float logp;
+            const Act<E> act = decide<E, 1, C>(hb, 0, pre, sigma, logp);
+            const size_t idx = (size_t)step * env.n_rows + row;
+            float reward;
+            bool done;
+            E::template step<1>(s, act.index, act.value, t, (uint32_t)row, key, ctx, 0, reward, done);
+            if (done) E::reset(s, key, t + 1, (uint32_t)row, ctx);
+            if (lane == 0) {
+                tr.value[idx] = hv;
+                tr.logp[idx] = logp;
+                store_action<E>(tr, idx, act);
+                tr.reward[idx] = reward;
+                tr.done[idx] = done ? 1 : 0;
+            }
+            E::observe(s, o);
+            if (step + 1 < horizon) {
+                float ok = 0.0f;
+#pragma unroll
+                for (int k = 0; k < E::OD; ++k) ok = lane == k ? o[k] : ok;
+                if (lane < E::OD) tr.obs[((size_t)(step + 1) * env.n_rows + row) * E::OD + lane] = ok;
+            }
+        }
+        if (lane == 0) save_state<E, 1>(env, row, s, 0);
+    }
+    if (batch.any_gae) {
+        for (int tile = blockIdx.x; tile < batch.n_tiles; tile += gridDim.x) {
+            const int si = segment_index(batch, tile);
+            __syncthreads();
+            stage_segment(batch, si, &seg, lane, 64);
+            __syncthreads();
+            const GaeArgs gae = uniform(seg.gae);
+            if (gae.ret == nullptr) continue;
+            const EnvArgs env = uniform(seg.env);
+            const TrajArgs tr = uniform(seg.tr);
+            const Tile tl = tile_of(env, tile - __builtin_amdgcn_readfirstlane(seg.tile_begin));
+            tile_gae<64, 16>(env, tr, gae, tl, __builtin_amdgcn_readfirstlane(seg.steps),
+                             reinterpret_cast<double*>(smem), (int)sizeof(smem), lane);
+        }
+    }
+}
+
+// The row-per-wave policy alone, one row per workgroup (the plain form's
+// policy step and the checker's trace): the same RowMlp code as k_fused_rw.
+template <class E, int H, bool TRACE>
+__device__ __forceinline__ void policy_row_rw(const EnvArgs& env, const PolicyArgs& pol, float* a1,
+                                              float* a2) {
+    using HO = HeadOf<E>;
+    __shared__ __attribute__((aligned(16))) float h1s[H];
+    const int lane = threadIdx.x;
+    const int64_t row = blockIdx.x;
+    if (row >= env.n_rows) return;
+    RowMlp<E, H> mlp;
+    mlp.load(pol, lane);
+    float o[E::OD];
+#pragma unroll
+    for (int k = 0; k < E::OD; ++k) o[k] = env.obs_scratch[(size_t)row * E::OD + k];
+    float head[HO::NH], h1, h2;
+    mlp.forward(o, h1s, lane, head, h1, h2);
+    if constexpr (TRACE) {
+        a1[(size_t)row * H + lane] = h1;
+        a2[(size_t)row * H + lane] = h2;
+    }
+    float hj = 0.0f;
+#pragma unroll
+    for (int j = 0; j < HO::NH; ++j) hj = lane == j ? head[j] : hj;
+    if (lane < HO::NH) env.head_scratch[(size_t)row * HO::NH + lane] = hj;
+}
+
 // -------------------------------------------------------------- reset --
 template <class E>
 __global__ void k_reset(EnvArgs env) {

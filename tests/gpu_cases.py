@@ -20,7 +20,7 @@ def say(*args):
 
 
 class Case:
-    def __init__(self, kind, n_envs, seed=0, tile_rows=0, offsets=None):
+    def __init__(self, kind, n_envs, seed=0, tile_rows=0, offsets=None, waves=0):
         from paper_2408_00930_amd import wsx
         self.kind = kind
         self.seed = seed
@@ -30,7 +30,7 @@ class Case:
         self.offsets = offsets
         self.params = inputs.reaction_params(seed) if kind == O.REACTION else None
         self.env = wsx.Env(kind, n_envs, seed=seed, agent_offsets=offsets, params=self.params,
-                           tile_rows=tile_rows)
+                           tile_rows=tile_rows, waves=waves)
         self.dpol = wsx.DevicePolicy(self.policy)
         self.rows = self.env.rows
         self.ohold = O.env_hold(kind, n_envs, offsets,
