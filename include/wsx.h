@@ -323,7 +323,7 @@ int wsx_ac_grad(const wsx_policy* policy, int32_t n_actions, const float* obs,
 /* wsx_ac_grad without a workspace argument and without any allocation, for
  * callers that cannot allocate device memory (code under HIP graph capture,
  * tight serving or training loops, harnesses that forbid hipMalloc). The
- * workspace is a file-scope device array of the library (about 25 MiB, one
+ * workspace is a file-scope device array of the library (about 23 MiB, one
  * per GPU, held until the process ends), which bounds `samples` to
  * WSX_AC_STATIC_MAX_SAMPLES; larger counts return WSX_EINVAL, other errors
  * as wsx_ac_grad. Same arguments and results as wsx_ac_grad (the same kernels
