@@ -751,7 +751,7 @@ int wsx_ac_grad_workspace_bytes(const wsx_policy* policy, int64_t samples, size_
     if (samples < 1) return fail(WSX_EINVAL, "samples must be >= 1");
     if (!bytes) return fail(WSX_EINVAL, "bytes is NULL");
     const int g = ac_grid(samples);
-    *bytes = ac_workspace_bytes(policy->dtype, policy->h1, samples, g, g);
+    *bytes = ac_workspace_bytes(policy->dtype, policy->h1, samples, g);
     return WSX_OK;
 }
 
@@ -780,7 +780,7 @@ int wsx_ac_grad(const wsx_policy* policy, int32_t n_actions, const float* obs,
     if (n_actions == 0 && !grads->log_std)
         return fail(WSX_EINVAL, "Gaussian policy: grads->log_std is NULL");
     const int g = ac_grid(samples);
-    const size_t need = ac_workspace_bytes(policy->dtype, policy->h1, samples, g, g);
+    const size_t need = ac_workspace_bytes(policy->dtype, policy->h1, samples, g);
     if (!workspace || workspace_bytes < need)
         return fail(WSX_EINVAL, "workspace of %zu bytes < %zu needed", workspace_bytes, need);
     AcLaunch l{};
@@ -796,8 +796,7 @@ int wsx_ac_grad(const wsx_policy* policy, int32_t n_actions, const float* obs,
     l.args.inv_n = (float)(1.0 / (double)samples);
     l.dtype = policy->dtype;
     l.workspace = workspace;
-    l.grid1 = g;
-    l.grid2 = g;
+    l.grid = g;
     l.out = AcOut{grads->w1, grads->b1, grads->w2, grads->b2, grads->w3, grads->b3,
                   n_actions == 0 ? grads->log_std : nullptr};
     const hipError_t e = launch_ac_grad(l, static_cast<hipStream_t>(stream));
@@ -817,7 +816,7 @@ int wsx_ac_grad_static(const wsx_policy* policy, int32_t n_actions, const float*
     if (const int rc = check_ac_policy(policy)) return rc;
     if (samples >= 1) {
         const int g = ac_grid(samples);
-        if (ac_workspace_bytes(policy->dtype, policy->h1, samples, g, g) > ac_static_capacity())
+        if (ac_workspace_bytes(policy->dtype, policy->h1, samples, g) > ac_static_capacity())
             return fail(WSX_EUNSUPPORTED, "the static workspace does not hold this policy shape");
     }
     hipError_t err;

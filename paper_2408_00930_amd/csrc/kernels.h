@@ -137,7 +137,7 @@ struct AcLaunch {
     AcArgs args;
     int dtype;
     void* workspace;
-    int grid1, grid2;        // workgroups of the per-tile kernels and of dW2
+    int grid;                // workgroups of the two per-tile kernels
     AcOut out;
 };
 // Adam on several tensors in one launch (the same step and hyper-parameters).
@@ -161,7 +161,7 @@ constexpr int64_t kAcStaticSamples = 2048;
 size_t ac_static_capacity();
 void* ac_static_workspace(hipError_t* err);
 int64_t ac_chunk_samples(int64_t n);   // samples per chunk of a call over n
-size_t ac_workspace_bytes(int dtype, int hidden, int64_t n, int grid1, int grid2);
+size_t ac_workspace_bytes(int dtype, int hidden, int64_t n, int grid);
 hipError_t launch_ac_grad(const AcLaunch& l, hipStream_t s);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
                        float b1, float b2, float eps, float c1, float c2, void* store,

@@ -14,16 +14,16 @@
 // before they meet the weights and the layer inputs; bias gradients sum the
 // unrounded values.
 //
-// Four kernels:
+// Three kernels:
 //  k_ac_fwd   per 32-sample tile: forward (layer 1, layer 2, head), head
 //             gradient, dz2 = (dhead W3) (1 - t2^2); accumulates dW3, db3,
 //             db2 and the log-std gradient; writes the dz2 rows to the
-//             workspace (the only per-sample staging).
-//  k_ac_bwd1  per tile: layer 1 again, dz1 = (dz2 W2) (1 - t1^2); accumulates
-//             dW1 and db1.
-//  k_ac_dw2   per tile: layer 1 again, dW2 = sum_i dz2_i h1_i^T with h1 from
-//             the accumulators and dz2 transposed into LDS, split over the
-//             samples (split-K).
+//             workspace (the only per-sample staging, written once, read
+//             once).
+//  k_ac_bwd   per tile: layer 1 again, dz1 = (dz2 W2) (1 - t1^2) with W2's
+//             columns in LDS, dW1 and db1, and dW2 = sum_i dz2_i h1_i^T
+//             with h1 from the accumulators and dz2 read down the columns of
+//             its rows in LDS, split over the samples (split-K).
 //  k_ac_sum   per-workgroup partial sums -> the gradients, one launch.
 // The products run with samples as the MFMA rows (the weight fragments the
 // roll-out loads as A operands serve unchanged as B operands), so the
@@ -94,6 +94,20 @@ __device__ __forceinline__ bf16x8 lds_k_perm(const char* T, int pitch, int c, in
     const uint2 lo = *reinterpret_cast<const uint2*>(T + c * pitch + (4 * q) * 2);
     const uint2 hi = *reinterpret_cast<const uint2*>(T + c * pitch + (16 + 4 * q) * 2);
     return __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
+}
+
+// The same fragment from a row-major LDS tile T[sample][column]: column c,
+// the same samples, eight 16-bit reads down the column.
+__device__ __forceinline__ bf16x8 lds_col_perm(const char* T, int pitch, int c, int q) {
+    uint16_t v[8];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        v[i] = *reinterpret_cast<const uint16_t*>(T + (4 * q + i) * pitch + c * 2);
+        v[4 + i] = *reinterpret_cast<const uint16_t*>(T + (16 + 4 * q + i) * pitch + c * 2);
+    }
+    bf16x8 f;
+    __builtin_memcpy(&f, v, 16);
+    return f;
 }
 
 __device__ __forceinline__ float act_tanh(float z) { return tanh_scaled(z, kTwoLog2e); }
@@ -406,25 +420,38 @@ k_ac_fwd(AcArgs a) {
     }
 }
 
+// The backward pass of a tile after the forward kernel, from the tile's dz2
+// rows (read once) and its observations: layer 1 again (h1 of this wave's
+// features: unrounded for tanh', rounded as the forward rounded it for dW2),
+// dh1 = dz2 W2 with W2's columns at this wave's features as B fragments,
+// dz1 = dh1 (1 - t1^2), dW1 += dz1^T x0 and db1, and dW2 += dz2^T h1 with h1
+// from the accumulators as B fragments (K = the tile's samples in
+// accumulator order) and each dz2 column's A fragment read down the tile's
+// rows in the same sample order. The dW2 partial sums (all of dW2's rows at
+// this wave's columns) stay in registers for the whole launch, so W2's
+// columns live in LDS instead ([wave][mt][ks][lane] fragments, written once
+// per workgroup). The next tile's observations and dz2 rows are loaded into
+// registers while the current one runs; two barriers per tile.
 template <int DT, int H, int KIN, int NHP>
 __global__ void __launch_bounds__((AcShape<DT, H, KIN, NHP>::NTHR))
-k_ac_bwd1(AcArgs a) {
+k_ac_bwd(AcArgs a) {
     using S = AcShape<DT, H, KIN, NHP>;
     using M = typename S::M;
     using Frag = typename S::Frag;
-    constexpr int R = S::R, MT = S::MT, K = S::K, KC = S::KC, EB = S::EB;
-    // by tile parity: a tile's inputs go to the buffers its predecessor's
-    // predecessor read, so one barrier per tile remains
-    __shared__ __attribute__((aligned(16))) char x0b[2][R * S::P_IN];
-    __shared__ __attribute__((aligned(16))) char x0Tb[2][S::KT * 16 * S::P_T];
-    __shared__ __attribute__((aligned(16))) char dzs[2][R * S::P_H];
+    constexpr int R = S::R, MT = S::MT, K = S::K, KC = S::KC, EB = S::EB, NJT = H / 16;
+    constexpr int NW = S::NTHR / 64;
+    __shared__ __attribute__((aligned(16))) Frag w2tl[NW * MT * S::K2S * 64];
+    __shared__ __attribute__((aligned(16))) char x0[R * S::P_IN];
+    __shared__ __attribute__((aligned(16))) char x0T[S::KT * 16 * S::P_T];
+    __shared__ __attribute__((aligned(16))) char dzs[R * S::P_H];
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lr = lane & 15, q = lane >> 4;
     const int kq = q * KC;
     const PolicyArgs& p = a.pol;
-    // layer-1 rows of this wave's features, and the columns of W2 at these
-    // features (B of dh1 = dz2 W2: K runs over layer-2 features)
-    Frag w1[MT][S::K1S], w2t[MT][S::K2S];
+    auto w2t = [&](int mt, int ks) -> Frag& {
+        return w2tl[((wave * MT + mt) * S::K2S + ks) * 64 + lane];
+    };
+    Frag w1[MT][S::K1S];
     float b1v[MT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
@@ -432,25 +459,24 @@ k_ac_bwd1(AcArgs a) {
 #pragma unroll
         for (int ks = 0; ks < S::K1S; ++ks) load_a(w1[mt][ks], p.w1, p.d_in, f, H, ks * K + kq, p.d_in);
 #pragma unroll
-        for (int ks = 0; ks < S::K2S; ++ks) load_col(w2t[mt][ks], p.w2, H, f, ks * K + kq, H);
+        for (int ks = 0; ks < S::K2S; ++ks) load_col(w2t(mt, ks), p.w2, H, f, ks * K + kq, H);
         b1v[mt] = p.b1[f];
     }
-    f32x4 dw1[MT][S::KT];
+    f32x4 dw1[MT][S::KT], acc[NJT][MT];
     float db1a[MT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
         db1a[mt] = 0.0f;
 #pragma unroll
         for (int it = 0; it < S::KT; ++it) dw1[mt][it] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int jt = 0; jt < NJT; ++jt) acc[jt][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
     // transposed-input rows >= KIN stay zero
-    for (int e = tid; e < (S::KT * 16 - KIN) * R; e += S::NTHR) {
-        put<DT>(x0Tb[0] + (KIN + e / R) * S::P_T + (e % R) * EB, 0.0f);
-        put<DT>(x0Tb[1] + (KIN + e / R) * S::P_T + (e % R) * EB, 0.0f);
-    }
+    for (int e = tid; e < (S::KT * 16 - KIN) * R; e += S::NTHR)
+        put<DT>(x0T + (KIN + e / R) * S::P_T + (e % R) * EB, 0.0f);
 
     const int64_t n_tiles = (a.n + R - 1) / R;
-    // the next tile's observations and dz2 rows are loaded while this tile runs
     constexpr int CH = H * EB / 16;
     constexpr int DPER = (R * CH + S::NTHR - 1) / S::NTHR;
     uint4 dzv[DPER];
@@ -469,40 +495,49 @@ k_ac_bwd1(AcArgs a) {
     ObsPrefetch<S> obs;
     obs.load(a, blockIdx.x, tid);
     load_dz(blockIdx.x);
-    int pb = 0;
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x, pb ^= 1) {
-        char* x0 = x0b[pb];
-        char* x0T = x0Tb[pb];
-        char* dz = dzs[pb];
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        lds_barrier();   // the previous tile's reads of the buffers are done
         obs.template store<DT>(x0, x0T, tid);
 #pragma unroll
         for (int u = 0; u < DPER; ++u) {
             const int e = tid + u * S::NTHR;
-            if (e < R * CH) *reinterpret_cast<uint4*>(dz + (e / CH) * S::P_H + (e % CH) * 16) = dzv[u];
+            if (e < R * CH) *reinterpret_cast<uint4*>(dzs + (e / CH) * S::P_H + (e % CH) * 16) = dzv[u];
         }
         obs.load(a, tile + gridDim.x, tid);
         load_dz(tile + gridDim.x);
         lds_barrier();
+        f32x4 t[MT][2];   // h1 of this wave's features, unrounded
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-            f32x4 dz1[2];
+            f32x4 g[2];
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt) {
-                f32x4 acc = {b1v[mt], b1v[mt], b1v[mt], b1v[mt]};
+                f32x4 z = {b1v[mt], b1v[mt], b1v[mt], b1v[mt]};
 #pragma unroll
                 for (int ks = 0; ks < S::K1S; ++ks)
-                    acc = M::mma(M::lds(x0 + (nt * 16 + lr) * S::P_IN + (ks * K + kq) * EB), w1[mt][ks], acc);
-                f32x4 g = {0.f, 0.f, 0.f, 0.f};
+                    z = M::mma(M::lds(x0 + (nt * 16 + lr) * S::P_IN + (ks * K + kq) * EB), w1[mt][ks], z);
 #pragma unroll
-                for (int ks = 0; ks < S::K2S; ++ks)
-                    g = M::mma(M::lds(dz + (nt * 16 + lr) * S::P_H + (ks * K + kq) * EB), w2t[mt][ks], g);
+                for (int i = 0; i < 4; ++i) t[mt][nt][i] = act_tanh(z[i]);
+                g[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+            for (int ks = 0; ks < S::K2S; ++ks) {
+                const Frag B_ = w2t(mt, ks);
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+                    g[nt] = M::mma(M::lds(dzs + (nt * 16 + lr) * S::P_H + (ks * K + kq) * EB), B_, g[nt]);
+                // a few K-steps' operands in flight, not all (registers)
+                if (ks % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+            }
+            f32x4 dz1[2];
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const float t = act_tanh(acc[i]);
-                    dz1[nt][i] = g[i] * (1.0f - t * t);
+                    const float th = t[mt][nt][i];
+                    dz1[nt][i] = g[nt][i] * (1.0f - th * th);
                     db1a[mt] += dz1[nt][i];
                 }
-            }
             // dW1 += dz1^T x0 (K = the tile's samples in accumulator order)
 #pragma unroll
             for (int it = 0; it < S::KT; ++it) {
@@ -521,6 +556,32 @@ k_ac_bwd1(AcArgs a) {
                 }
             }
         }
+        // dW2 += dz2^T h1
+        if constexpr (DT == DT_BF16) {
+            Frag Bh[MT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) Bh[mt] = pack_acc_k(t[mt][0], t[mt][1]);
+#pragma unroll
+            for (int jt = 0; jt < NJT; ++jt) {
+                const Frag A_ = lds_col_perm(dzs, S::P_H, jt * 16 + lr, q);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) acc[jt][mt] = M::mma(A_, Bh[mt], acc[jt][mt]);
+                if (jt % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+#pragma unroll
+            for (int jt = 0; jt < NJT; ++jt)
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const float A_ = *reinterpret_cast<const float*>(
+                            dzs + (16 * nt + 4 * q + i) * S::P_H + (jt * 16 + lr) * EB);
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt)
+                            acc[jt][mt] = M::mma(A_, t[mt][nt][i], acc[jt][mt]);
+                    }
+        }
     }
     float* out = a.part_bwd + (size_t)blockIdx.x * S::BWD_FLOATS;
 #pragma unroll
@@ -537,134 +598,14 @@ k_ac_bwd1(AcArgs a) {
         v += __shfl_xor(v, 32);
         if (q == 0) part_out(&out[H * KIN + f0 + lr], v, a.accumulate);
     }
-}
-
-// dW2[j][k] = sum_i dz2[i][j] h1[i][k] over this workgroup's tiles. Each wave
-// recomputes layer 1 for its own features k (the forward's code, so h1 is
-// the forward's, rounded as the forward rounded it) and takes h1 straight
-// from the accumulators as the B fragments (K = the tile's samples in
-// accumulator order). The dz2 rows are transposed into LDS ([feature]
-// [sample]), from which the A fragments of every feature j are read in the
-// same sample order. A tile's observations and dz2 rows are loaded one tile
-// ahead and stored into the LDS buffers of the tile's parity, so one barrier
-// per tile remains.
-template <int DT, int H, int KIN, int NHP>
-__global__ void __launch_bounds__((AcShape<DT, H, KIN, NHP>::NTHR))
-k_ac_dw2(AcArgs a) {
-    using S = AcShape<DT, H, KIN, NHP>;
-    using M = typename S::M;
-    using Frag = typename S::Frag;
-    constexpr int R = S::R, MT = S::MT, K = S::K, KC = S::KC, EB = S::EB, NJT = H / 16;
-    __shared__ __attribute__((aligned(16))) char x0b[2][R * S::P_IN];
-    __shared__ __attribute__((aligned(16))) char dzTb[2][H * S::P_T];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lr = lane & 15, q = lane >> 4;
-    const int kq = q * KC;
-    const PolicyArgs& p = a.pol;
-    Frag w1[MT][S::K1S];
-    float b1v[MT];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-        const int f = wave * S::FPW + mt * 16 + lr;
-#pragma unroll
-        for (int ks = 0; ks < S::K1S; ++ks) load_a(w1[mt][ks], p.w1, p.d_in, f, H, ks * K + kq, p.d_in);
-        b1v[mt] = p.b1[f];
-    }
-    f32x4 acc[NJT][MT];
-#pragma unroll
-    for (int jt = 0; jt < NJT; ++jt)
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) acc[jt][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    const int64_t n_tiles = (a.n + R - 1) / R;
-    // dz2 chunks of 16 bytes (KC = 16 / EB features of one sample), sample
-    // fastest over the threads, so the transposed LDS stores of a wave fall
-    // on distinct banks
-    constexpr int CH = H * EB / 16, FPC = 16 / EB;
-    constexpr int DPER = (R * CH + S::NTHR - 1) / S::NTHR;
-    uint4 dzv[DPER];
-    auto load_dz = [&](int64_t tile) {
-#pragma unroll
-        for (int u = 0; u < DPER; ++u) {
-            const int e = tid + u * S::NTHR;
-            const int r = e % R, c = e / R;
-            const int64_t n = tile * R + r;
-            dzv[u] = make_uint4(0u, 0u, 0u, 0u);
-            if (e < R * CH && n < a.n)
-                dzv[u] = *reinterpret_cast<const uint4*>(a.dz2_rows + (size_t)n * (H * EB) +
-                                                         (size_t)c * 16);
-        }
-    };
-    ObsPrefetch<S> obs;
-    obs.load(a, blockIdx.x, tid);
-    load_dz(blockIdx.x);
-    int pb = 0;
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x, pb ^= 1) {
-        char* x0 = x0b[pb];
-        char* dzT = dzTb[pb];
-        obs.template store<DT>(x0, nullptr, tid);
-#pragma unroll
-        for (int u = 0; u < DPER; ++u) {
-            const int e = tid + u * S::NTHR;
-            if (e >= R * CH) break;
-            const int r = e % R, c = e / R;
-            const uint32_t wd[4] = {dzv[u].x, dzv[u].y, dzv[u].z, dzv[u].w};
-#pragma unroll
-            for (int k = 0; k < FPC; ++k) {
-                char* dst = dzT + (c * FPC + k) * S::P_T + r * EB;
-                if constexpr (EB == 2)
-                    *reinterpret_cast<uint16_t*>(dst) = (uint16_t)(wd[k >> 1] >> (16 * (k & 1)));
-                else
-                    *reinterpret_cast<uint32_t*>(dst) = wd[k];
-            }
-        }
-        obs.load(a, tile + gridDim.x, tid);
-        load_dz(tile + gridDim.x);
-        lds_barrier();
-        f32x4 t[MT][2];   // h1 of this wave's features, unrounded
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-            for (int nt = 0; nt < 2; ++nt) {
-                f32x4 z = {b1v[mt], b1v[mt], b1v[mt], b1v[mt]};
-#pragma unroll
-                for (int ks = 0; ks < S::K1S; ++ks)
-                    z = M::mma(M::lds(x0 + (nt * 16 + lr) * S::P_IN + (ks * K + kq) * EB), w1[mt][ks], z);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) t[mt][nt][i] = act_tanh(z[i]);
-            }
-        if constexpr (DT == DT_BF16) {
-            Frag B_[MT];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) B_[mt] = pack_acc_k(t[mt][0], t[mt][1]);
-#pragma unroll
-            for (int jt = 0; jt < NJT; ++jt) {
-                const Frag A_ = lds_k_perm(dzT, S::P_T, jt * 16 + lr, q);
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt) acc[jt][mt] = M::mma(A_, B_[mt], acc[jt][mt]);
-            }
-        } else {
-#pragma unroll
-            for (int jt = 0; jt < NJT; ++jt)
-#pragma unroll
-                for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const float A_ = *reinterpret_cast<const float*>(
-                            dzT + (jt * 16 + lr) * S::P_T + (16 * nt + 4 * q + i) * EB);
-#pragma unroll
-                        for (int mt = 0; mt < MT; ++mt)
-                            acc[jt][mt] = M::mma(A_, t[mt][nt][i], acc[jt][mt]);
-                    }
-        }
-    }
-    float* out = a.part_w2 + (size_t)blockIdx.x * H * H;
+    float* w2o = a.part_w2 + (size_t)blockIdx.x * H * H;
 #pragma unroll
     for (int jt = 0; jt < NJT; ++jt)
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                part_out(&out[(size_t)(jt * 16 + 4 * q + i) * H + wave * S::FPW + mt * 16 + lr],
+                part_out(&w2o[(size_t)(jt * 16 + 4 * q + i) * H + wave * S::FPW + mt * 16 + lr],
                          acc[jt][mt][i], a.accumulate);
 }
 
@@ -765,14 +706,13 @@ __global__ void __launch_bounds__(256) k_adam_many(AdamTable t, float lr, float 
 template <int DT, int H, int KIN, int NHP>
 struct AcVariant {
     using S = AcShape<DT, H, KIN, NHP>;
-    // the three per-tile kernels over one chunk of samples
-    static void chunk(const AcArgs& a, int grid1, int grid2, hipStream_t s) {
-        hipLaunchKernelGGL((k_ac_fwd<DT, H, KIN, NHP>), dim3(grid1), dim3(S::NTHR), 0, s, a);
-        hipLaunchKernelGGL((k_ac_bwd1<DT, H, KIN, NHP>), dim3(grid1), dim3(S::NTHR), 0, s, a);
-        hipLaunchKernelGGL((k_ac_dw2<DT, H, KIN, NHP>), dim3(grid2), dim3(S::NTHR), 0, s, a);
+    // the two per-tile kernels over one chunk of samples
+    static void chunk(const AcArgs& a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_ac_fwd<DT, H, KIN, NHP>), dim3(grid), dim3(S::NTHR), 0, s, a);
+        hipLaunchKernelGGL((k_ac_bwd<DT, H, KIN, NHP>), dim3(grid), dim3(S::NTHR), 0, s, a);
     }
     // the partial sums of every workgroup -> the gradients
-    static hipError_t sum(const AcArgs& a, int grid1, int grid2, const AcOut& o, hipStream_t s) {
+    static hipError_t sum(const AcArgs& a, int grid, const AcOut& o, hipStream_t s) {
         const PolicyArgs& p = a.pol;
         const int F = S::FWD_FLOATS, B = S::BWD_FLOATS;
         SumTable t{};
@@ -783,18 +723,18 @@ struct AcVariant {
             t.seg[ns++] = SumSeg{part, out, stride, off, nparts, rows, cols, cols_in};
             most = std::max<int64_t>(most, (int64_t)rows * cols);
         };
-        seg(a.part_fwd, F, grid1, 0, p.n_head, H, H, o.w3);
-        seg(a.part_fwd, F, grid1, (int64_t)NHP * H, 1, H, H, o.b2);
-        seg(a.part_fwd, F, grid1, (int64_t)NHP * H + H, 1, p.n_head, p.n_head, o.b3);
-        if (o.log_std) seg(a.part_fwd, F, grid1, (int64_t)NHP * H + H + NHP, 1, 1, 1, o.log_std);
-        seg(a.part_bwd, B, grid1, 0, H, p.d_in, KIN, o.w1);
-        seg(a.part_bwd, B, grid1, (int64_t)H * KIN, 1, H, H, o.b1);
-        seg(a.part_w2, (int64_t)H * H, grid2, 0, H, H, H, o.w2);
+        seg(a.part_fwd, F, grid, 0, p.n_head, H, H, o.w3);
+        seg(a.part_fwd, F, grid, (int64_t)NHP * H, 1, H, H, o.b2);
+        seg(a.part_fwd, F, grid, (int64_t)NHP * H + H, 1, p.n_head, p.n_head, o.b3);
+        if (o.log_std) seg(a.part_fwd, F, grid, (int64_t)NHP * H + H + NHP, 1, 1, 1, o.log_std);
+        seg(a.part_bwd, B, grid, 0, H, p.d_in, KIN, o.w1);
+        seg(a.part_bwd, B, grid, (int64_t)H * KIN, 1, H, H, o.b1);
+        seg(a.part_w2, (int64_t)H * H, grid, 0, H, H, H, o.w2);
         hipLaunchKernelGGL(k_ac_sum, dim3((unsigned)((most + 31) / 32), ns), dim3(256), 0, s, t);
         return hipGetLastError();
     }
-    static size_t part_floats(int grid1, int grid2) {
-        return (size_t)grid1 * (S::FWD_FLOATS + S::BWD_FLOATS) + (size_t)grid2 * H * H;
+    static size_t part_floats(int grid) {
+        return (size_t)grid * (S::FWD_FLOATS + S::BWD_FLOATS + H * H);
     }
 };
 
@@ -872,16 +812,16 @@ void* ac_static_workspace(hipError_t* err) {
     return g_scratch_ptr[dev];
 }
 
-size_t ac_workspace_bytes(int dtype, int hidden, int64_t n, int grid1, int grid2) {
+size_t ac_workspace_bytes(int dtype, int hidden, int64_t n, int grid) {
     n = ac_chunk_samples(n);
     const size_t eb = dtype == DT_BF16 ? 2 : 4;
     const size_t rows = (size_t)n * hidden * eb;
     // partial sums of the widest head compiled for this format and width
     size_t part = 0;
     if (dtype == DT_F32 && hidden == 64)
-        part = AcVariant<DT_F32, 64, 4, 16>::part_floats(grid1, grid2);
+        part = AcVariant<DT_F32, 64, 4, 16>::part_floats(grid);
     else if (dtype == DT_BF16 && hidden == 256)
-        part = AcVariant<DT_BF16, 256, 32, 64>::part_floats(grid1, grid2);
+        part = AcVariant<DT_BF16, 256, 32, 64>::part_floats(grid);
     return 256 + ac_round_up(rows) + part * sizeof(float);
 }
 
@@ -898,8 +838,8 @@ hipError_t launch_ac_grad(const AcLaunch& l, hipStream_t s) {
         a.dz2_rows = w;
         w += ac_round_up(rows);
         a.part_fwd = reinterpret_cast<float*>(w);
-        a.part_bwd = a.part_fwd + (size_t)l.grid1 * S::FWD_FLOATS;
-        a.part_w2 = a.part_bwd + (size_t)l.grid1 * S::BWD_FLOATS;
+        a.part_bwd = a.part_fwd + (size_t)l.grid * S::FWD_FLOATS;
+        a.part_w2 = a.part_bwd + (size_t)l.grid * S::BWD_FLOATS;
         // chunks of samples in stream order; inv_n stays 1 / (all samples)
         for (int64_t c0 = 0; c0 < l.args.n; c0 += chunk) {
             AcArgs c = a;
@@ -909,9 +849,9 @@ hipError_t launch_ac_grad(const AcLaunch& l, hipStream_t s) {
             c.ret = l.args.ret + c0;
             c.adv = l.args.adv + c0;
             c.accumulate = c0 > 0;
-            V::chunk(c, l.grid1, l.grid2, s);
+            V::chunk(c, l.grid, s);
         }
-        return V::sum(a, l.grid1, l.grid2, l.out, s);
+        return V::sum(a, l.grid, l.out, s);
     });
 }
 
