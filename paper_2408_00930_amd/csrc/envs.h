@@ -47,10 +47,14 @@ struct CartPole {
         const float x = s[0], xd = s[1], th = s[2], thd = s[3];
         float sn, cs;
         sin_cos(th, sn, cs);
-        const float push = (force + m_pole * half_len * thd * thd * sn) / m_total;
-        const float thdd =
-            (gravity * sn - cs * push) / (half_len * (4.0f / 3.0f - m_pole * cs * cs / m_total));
-        const float xdd = push - m_pole * half_len * thdd * cs / m_total;
+        // divisions as products with reciprocals (the constant one folded,
+        // the other v_rcp_f32): the per-row phase is a latency chain, and an
+        // IEEE division is ten dependent instructions
+        const float inv_total = 1.0f / m_total;
+        const float push = (force + m_pole * half_len * thd * thd * sn) * inv_total;
+        const float thdd = (gravity * sn - cs * push) *
+                           __builtin_amdgcn_rcpf(half_len * (4.0f / 3.0f - m_pole * cs * cs * inv_total));
+        const float xdd = push - m_pole * half_len * thdd * cs * inv_total;
         s[0] = x + dt * xd;
         s[1] = xd + dt * xdd;
         s[2] = th + dt * thd;
@@ -145,7 +149,7 @@ struct Acrobot {
         const float grav1 = 1.5f * g * s1 + grav2;
         const float rhs1 = -(cor1 + grav1);
         const float rhs2 = tau - cor2 - grav2;
-        const float inv_det = 1.0f / (m11 * m22 - m12 * m12);
+        const float inv_det = __builtin_amdgcn_rcpf(m11 * m22 - m12 * m12);   // det >= 2.56
         dq[0] = w1;
         dq[1] = w2;
         dq[2] = (m22 * rhs1 - m12 * rhs2) * inv_det;

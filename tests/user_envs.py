@@ -58,10 +58,11 @@ struct UserEnv {
         const float x = s[0], xd = s[1], th = s[2], thd = s[3];
         float sn, cs;
         sin_cos(th, sn, cs);
-        const float push = (force + m_pole * half_len * thd * thd * sn) / m_total;
-        const float thdd =
-            (gravity * sn - cs * push) / (half_len * (4.0f / 3.0f - m_pole * cs * cs / m_total));
-        const float xdd = push - m_pole * half_len * thdd * cs / m_total;
+        const float inv_total = 1.0f / m_total;
+        const float push = (force + m_pole * half_len * thd * thd * sn) * inv_total;
+        const float thdd = (gravity * sn - cs * push) *
+                           __builtin_amdgcn_rcpf(half_len * (4.0f / 3.0f - m_pole * cs * cs * inv_total));
+        const float xdd = push - m_pole * half_len * thdd * cs * inv_total;
         s[0] = x + dt * xd;
         s[1] = xd + dt * xdd;
         s[2] = th + dt * thd;
