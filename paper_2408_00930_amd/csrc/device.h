@@ -336,6 +336,19 @@ __device__ __forceinline__ void store1(char* p, float v, float inv_s) {
     }
 }
 
+// ------------------------------------------------ workgroup placement --
+// The dispatcher deals workgroups out to the eight XCDs in turn (workgroup b
+// to XCD b mod 8), and each XCD has its own L2. This renumbers the grid so
+// that every XCD's workgroups take one contiguous range of indices
+// (a bijection on [0, gridDim.x)): neighbouring tiles, whose records share
+// cache lines in the [step][row] arrays, then meet in one L2, which merges
+// their partial lines before they go to HBM.
+__device__ __forceinline__ int xcd_block() {
+    const int b = blockIdx.x, g = gridDim.x;
+    const int x = b & 7, q = g >> 3, r = g & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 // ------------------------------------------------------- lane groups --
 // A row of a tile is served by G consecutive lanes (G a power of two <= 16,
 // groups aligned within a 16-lane row of the wave). The reductions use DPP

@@ -1154,11 +1154,12 @@ k_fused(Batch batch) {
         reinterpret_cast<uint32_t*>(smem + L::OFF_IN)[i] = 0u;
 
     __shared__ Segment seg;          // the current tile's segment
+    const int first = xcd_block();   // this workgroup's tiles: first + k * gridDim.x
     if (batch.any_reset) {
         // reset the rows of this workgroup's tiles before any weights occupy
         // registers; the tiles below read the state back (the workgroup's own
         // stores, visible after a barrier)
-        for (int tile = blockIdx.x; tile < batch.n_tiles; tile += gridDim.x) {
+        for (int tile = first; tile < batch.n_tiles; tile += gridDim.x) {
             const int si = segment_index(batch, tile);
             __syncthreads();
             stage_segment(batch, si, &seg, tid, NTHR);
@@ -1174,7 +1175,7 @@ k_fused(Batch batch) {
             }
         }
     }
-    for (int tile = blockIdx.x; tile < batch.n_tiles; tile += gridDim.x) {
+    for (int tile = first; tile < batch.n_tiles; tile += gridDim.x) {
         const int si = segment_index(batch, tile);   // uniform over the workgroup
         __syncthreads();   // the previous tile's last reads of `seg` and the table are done
         stage_segment(batch, si, &seg, tid, NTHR);
@@ -1198,7 +1199,7 @@ k_fused(Batch batch) {
         // them (the weights are no longer needed, so this pass takes no
         // registers from the roll-out), with the whole LDS as its buffer
         static_assert(L::BYTES >= 32 * R, "one segment per row fits");
-        for (int tile = blockIdx.x; tile < batch.n_tiles; tile += gridDim.x) {
+        for (int tile = first; tile < batch.n_tiles; tile += gridDim.x) {
             const int si = segment_index(batch, tile);
             __syncthreads();   // the previous pass over `seg` and the buffer is done
             stage_segment(batch, si, &seg, tid, NTHR);
@@ -1304,8 +1305,9 @@ __global__ void __launch_bounds__(64) k_fused_rw(Batch batch) {
     float* h1s = reinterpret_cast<float*>(smem);
     const int lane = threadIdx.x;
     const float* staged = nullptr;
+    const int first = xcd_block();   // this workgroup's rows: first + k * gridDim.x
     if (batch.any_reset) {
-        for (int tile = blockIdx.x; tile < batch.n_tiles; tile += gridDim.x) {
+        for (int tile = first; tile < batch.n_tiles; tile += gridDim.x) {
             const int si = segment_index(batch, tile);
             __syncthreads();
             stage_segment(batch, si, &seg, lane, 64);
@@ -1315,7 +1317,7 @@ __global__ void __launch_bounds__(64) k_fused_rw(Batch batch) {
     }
     RowMlp<E, H> mlp;
     int loaded = -1;
-    for (int tile = blockIdx.x; tile < batch.n_tiles; tile += gridDim.x) {
+    for (int tile = first; tile < batch.n_tiles; tile += gridDim.x) {
         const int si = segment_index(batch, tile);
         __syncthreads();
         stage_segment(batch, si, &seg, lane, 64);
@@ -1392,7 +1394,7 @@ __global__ void __launch_bounds__(64) k_fused_rw(Batch batch) {
         if (lane == 0) save_state<E, 1>(env, row, s, 0);
     }
     if (batch.any_gae) {
-        for (int tile = blockIdx.x; tile < batch.n_tiles; tile += gridDim.x) {
+        for (int tile = first; tile < batch.n_tiles; tile += gridDim.x) {
             const int si = segment_index(batch, tile);
             __syncthreads();
             stage_segment(batch, si, &seg, lane, 64);
