@@ -28,6 +28,18 @@
 
 namespace wsx {
 
+// Entry sub + j G of a row's observation held on every lane of the row's G
+// lanes, picked by selects (a branch per entry would split the step into
+// many small blocks).
+template <int OD, int G>
+__device__ __forceinline__ float obs_entry(const float (&o)[OD], int j, int sub) {
+    float v = 0.0f;
+#pragma unroll
+    for (int m = 0; m < G && j * G + m < OD; ++m) v = sub == m ? o[j * G + m] : v;
+    return v;
+}
+
+
 static_assert(Reaction::NCACHE == kReactionCache, "one reaction cache size");
 
 // ------------------------------------------------------ per-kind shapes --
@@ -483,8 +495,10 @@ struct Mlp {
     __device__ static void put_obs(char* smem, int r, const float (&o)[OD], float inv_q0, int sub) {
         char* p = smem + OFF_IN + r * P_IN;
 #pragma unroll
-        for (int k = 0; k < OD; ++k)
-            if (k % G == sub) store1<DT>(p + k * EB, o[k], inv_q0);
+        for (int j = 0; j < (OD + G - 1) / G; ++j) {
+            const float v = obs_entry<OD, G>(o, j, sub);
+            if (j * G + G <= OD || sub + j * G < OD) store1<DT>(p + (sub + j * G) * EB, v, inv_q0);
+        }
     }
     // The same from a lane's slice: entries k = sub + j G of the row.
     template <int OD, int G>
@@ -598,6 +612,37 @@ __device__ __forceinline__ Act<E> choose(const float (&hb)[C], int sub, const Rn
     return decide<E, G, C>(hb, sub, prepare<E>(key, t, row, log_std), expf(log_std), logp);
 }
 
+// ------------------------------------------------- global-memory views --
+// The fused kernels read their segment's pointers from LDS, so the compiler
+// cannot tell that they point to global memory and would use flat
+// instructions, which count against the LDS counter too: every later LDS wait
+// and barrier would wait for the step's record stores to reach memory. The
+// view carries the record pointers as global (address space 1) ones.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+
+struct GTraj {
+    gptr<float> obs;
+    gptr<void> action;
+    gptr<float> reward;
+    gptr<uint8_t> done;
+    gptr<float> value, logp, last_value;
+};
+
+__device__ __forceinline__ GTraj global_view(const TrajArgs& t) {
+    return GTraj{(gptr<float>)t.obs,    (gptr<void>)t.action, (gptr<float>)t.reward,
+                 (gptr<uint8_t>)t.done, (gptr<float>)t.value, (gptr<float>)t.logp,
+                 (gptr<float>)t.last_value};
+}
+
+template <class E>
+__device__ __forceinline__ void store_action(const GTraj& tr, size_t idx, const Act<E>& a) {
+    if constexpr (E::NACT > 0)
+        ((gptr<uint8_t>)tr.action)[idx] = (uint8_t)a.index;
+    else
+        ((gptr<float>)tr.action)[idx] = a.value;
+}
+
 template <class E>
 __device__ __forceinline__ void store_action(const TrajArgs& tr, size_t idx, const Act<E>& a) {
     if constexpr (E::NACT > 0)
@@ -632,11 +677,15 @@ __device__ __forceinline__ void save_state(const EnvArgs& env, int64_t row, cons
         if (i % G == sub) env.state[(size_t)i * env.n_rows + row] = s[i];
 }
 
-template <int OD, int G>
-__device__ __forceinline__ void store_obs(float* dst, const float (&o)[OD], int sub) {
+// Lane `sub` of the row's G lanes stores entries k = sub + j G (obs_entry
+// picks them by selects).
+template <int OD, int G, class P>
+__device__ __forceinline__ void store_obs(P dst, const float (&o)[OD], int sub) {
 #pragma unroll
-    for (int k = 0; k < OD; ++k)
-        if (k % G == sub) dst[k] = o[k];
+    for (int j = 0; j < (OD + G - 1) / G; ++j) {
+        const float v = obs_entry<OD, G>(o, j, sub);
+        if (j * G + G <= OD || sub + j * G < OD) dst[sub + j * G] = v;
+    }
 }
 
 // State and observation slices: lane `sub` of a row's group of G holds the
@@ -654,8 +703,8 @@ __device__ __forceinline__ void save_slice(const EnvArgs& env, int64_t row,
 #pragma unroll
     for (int j = 0; j < E::SD / G; ++j) env.state[(size_t)(sub + j * G) * env.n_rows + row] = s[j];
 }
-template <int OD, int G>
-__device__ __forceinline__ void store_obs_slice(float* dst, const float (&o)[OD / G], int sub) {
+template <int OD, int G, class P>
+__device__ __forceinline__ void store_obs_slice(P dst, const float (&o)[OD / G], int sub) {
 #pragma unroll
     for (int j = 0; j < OD / G; ++j) dst[sub + j * G] = o[j];
 }
@@ -777,7 +826,7 @@ __device__ __forceinline__ void stage_segment(const Batch& b, int i, Segment* ds
 // block. The records are the workgroup's own stores, visible after the
 // barrier that precedes the call; `buf` is reused by the caller afterwards.
 template <int NTHR, int GB>
-__device__ void tile_gae(const EnvArgs& env, const TrajArgs& tr, const GaeArgs& g, const Tile& tl,
+__device__ void tile_gae(const EnvArgs& env, const GTraj& tr, const GaeArgs& g, const Tile& tl,
                          int horizon, double* buf, int buf_bytes, int tid) {
     const int n = tl.row1 - tl.row0;
     if (n <= 0 || horizon <= 0) return;
@@ -852,11 +901,11 @@ __device__ void tile_gae(const EnvArgs& env, const TrajArgs& tr, const GaeArgs& 
                     v_next = v;
                     const size_t i = (size_t)t * rows + row;
                     if (g.out_f64) {
-                        static_cast<double*>(g.ret)[i] = G;
-                        static_cast<double*>(g.adv)[i] = A;
+                        ((gptr<double>)g.ret)[i] = G;
+                        ((gptr<double>)g.adv)[i] = A;
                     } else {
-                        static_cast<float*>(g.ret)[i] = (float)G;
-                        static_cast<float*>(g.adv)[i] = (float)A;
+                        ((gptr<float>)g.ret)[i] = (float)G;
+                        ((gptr<float>)g.adv)[i] = (float)A;
                     }
                 }
             }
@@ -916,7 +965,7 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
     // the segment's fields the steps use, read once from LDS into scalar
     // registers (they are uniform over the workgroup)
     const EnvArgs env = uniform(sg.env);
-    const TrajArgs tr = uniform(sg.tr);
+    const GTraj tr = global_view(uniform(sg.tr));
     const int horizon = __builtin_amdgcn_readfirstlane(sg.steps);
     const RngKey key = rng_key(env);
     const uint32_t t0 = step_base(env);
@@ -1067,7 +1116,7 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
             }
         }
         if (valid && step < horizon) {
-            float* dst = tr.obs + ((size_t)(step + 1) * env.n_rows + row) * E::OD;
+            const gptr<float> dst = tr.obs + ((size_t)(step + 1) * env.n_rows + row) * E::OD;
             if constexpr (kSlice) {
                 L::template put_obs_slice<E::OD, G>(smem, rr, s, inv_q0, sub);
                 if (step + 1 < horizon) store_obs_slice<E::OD, G>(dst, s, sub);
@@ -1207,7 +1256,7 @@ k_fused(Batch batch) {
             const GaeArgs gae = uniform(seg.gae);
             if (gae.ret == nullptr) continue;
             const EnvArgs env = uniform(seg.env);
-            const TrajArgs tr = uniform(seg.tr);
+            const GTraj tr = global_view(uniform(seg.tr));
             const Tile tl = tile_of(env, tile - __builtin_amdgcn_readfirstlane(seg.tile_begin));
             // blocks of 36 steps hold a 200-step horizon's segments over
             // six row groups; kernels that keep fewer registers free for
@@ -1323,7 +1372,7 @@ __global__ void __launch_bounds__(64) k_fused_rw(Batch batch) {
         stage_segment(batch, si, &seg, lane, 64);
         __syncthreads();
         const EnvArgs env = uniform(seg.env);
-        const TrajArgs tr = uniform(seg.tr);
+        const GTraj tr = global_view(uniform(seg.tr));
         const PolicyArgs& pol = seg.pol;
         if (si != loaded) {
             mlp.load(pol, lane);
@@ -1402,7 +1451,7 @@ __global__ void __launch_bounds__(64) k_fused_rw(Batch batch) {
             const GaeArgs gae = uniform(seg.gae);
             if (gae.ret == nullptr) continue;
             const EnvArgs env = uniform(seg.env);
-            const TrajArgs tr = uniform(seg.tr);
+            const GTraj tr = global_view(uniform(seg.tr));
             const Tile tl = tile_of(env, tile - __builtin_amdgcn_readfirstlane(seg.tile_begin));
             tile_gae<64, 16>(env, tr, gae, tl, __builtin_amdgcn_readfirstlane(seg.steps),
                              reinterpret_cast<double*>(smem), (int)sizeof(smem), lane);
