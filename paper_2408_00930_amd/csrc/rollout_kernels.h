@@ -480,8 +480,11 @@ struct Mlp {
         for (int w = 0; w < NPART; ++w) {
             const float* pr = part + (w * R + r) * P_PART;
 #pragma unroll
-            for (int c = 0; c < C; ++c)
-                if (j0 + c < NH - 1) acc[c] += pr[j0 + c];
+            for (int c = 0; c < C; ++c) {   // entries past the logits read the value and add 0
+                const int j = j0 + c < NH - 1 ? j0 + c : NH - 1;
+                const float v = pr[j];
+                acc[c] += j0 + c < NH - 1 ? v : 0.0f;
+            }
             accv += pr[NH - 1];
         }
 #pragma unroll
@@ -535,8 +538,9 @@ __device__ __forceinline__ int sample_categorical(const float (&lg)[C], int sub,
     float e[C];
     float s = 0.0f;
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-        e[c] = j0 + c < K ? expf(lg[c] - mx) : 0.0f;
+    for (int c = 0; c < C; ++c) {   // exp of every entry, then a select: no branch
+        const float ex = expf(lg[c] - mx);
+        e[c] = j0 + c < K ? ex : 0.0f;
         s += e[c];
     }
     const float z = group_sum<G>(s);
