@@ -342,18 +342,30 @@ struct Reaction {
     // the same total.
     template <int G>
     __device__ static float energy(const float* x, const float* p, const EnvCtx& c, int sub) {
+        float xs[(NDIM + G - 1) / G];
+#pragma unroll
+        for (int m = 0; m < (NDIM + G - 1) / G; ++m) {
+            const int i = sub + m * G;
+            float xi = 0.0f;
+#pragma unroll
+            for (int j = 0; j < NDIM; ++j) xi = j == i ? x[j] : xi;
+            xs[m] = xi;
+        }
+        return energy_slice<G>(xs, p, c, sub);
+    }
+    // The same from the lane's own coordinates xs[m] = x[sub + m G]. Terms
+    // past the last coordinate add zero (the running sum is never -0, so the
+    // total is unchanged) instead of branching.
+    template <int G>
+    __device__ static float energy_slice(const float* xs, const float* p, const EnvCtx& c, int sub) {
         const float* nhw = p + NDIM * NDIM + NG * NDIM;
         const float* amp = nhw + NG;
         float part = 0.0f;
 #pragma unroll
         for (int m = 0; m < (NDIM + G - 1) / G; ++m) {
             const int i = sub + m * G;
-            if (i < NDIM) {
-                float xi = 0.0f;
-#pragma unroll
-                for (int j = 0; j < NDIM; ++j) xi = j == i ? x[j] : xi;
-                part += 0.5f * xi * (float)c.cache[i * c.cache_stride];
-            }
+            const float t = 0.5f * xs[m] * (float)c.cache[(i < NDIM ? i : NDIM - 1) * c.cache_stride];
+            part += i < NDIM ? t : 0.0f;
         }
 #pragma unroll
         for (int m = 0; m < NG / G; ++m) {
@@ -395,6 +407,29 @@ struct Reaction {
                                 const EnvCtx& c, int sub, float& reward, bool& done) {
         step_noise<G>(s, a, noise_normal(key, t + 1, row), c, sub, reward);
         done = false;
+    }
+    // The step on a row whose G lanes each hold only their own coordinates
+    // xs[m] = x[sub + m G] (and every lane the energy `en`): the moved
+    // coordinate comes from the lane that holds it (`base` is the group's
+    // first lane in the wave), and the arithmetic is that of step_noise.
+    template <int G>
+    __device__ static void step_slice(float* xs, float& en, int a, float z, const EnvCtx& c,
+                                      int sub, int base, float& reward) {
+        constexpr int NX = (NDIM + G - 1) / G;
+        const int coord = a >> 1;
+        const float delta = (a & 1) ? -0.05f : 0.05f;
+        const int owner = coord % G, jm = coord / G;
+        float held = xs[0];
+#pragma unroll
+        for (int m = 1; m < NX; ++m) held = jm == m ? xs[m] : held;
+        const float x_old = __shfl(held, base + owner);
+        const float x_new = x_old + delta;
+#pragma unroll
+        for (int m = 0; m < NX; ++m) xs[m] = (sub == owner && jm == m) ? x_new : xs[m];
+        cache_move<G>(coord, x_old, x_new, c.lds_params, c, sub);
+        const float e_new = energy_slice<G>(xs, c.lds_params, c, sub) + 0.05f * z;
+        reward = -(e_new - en);
+        en = e_new;
     }
     // The step with its noise normal z already drawn (noise_normal(key, t + 1,
     // row)); never terminates.

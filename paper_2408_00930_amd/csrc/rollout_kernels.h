@@ -505,11 +505,11 @@ struct Mlp {
     }
     // The same from a lane's slice: entries k = sub + j G of the row.
     template <int OD, int G>
-    __device__ static void put_obs_slice(char* smem, int r, const float (&o)[OD / G], float inv_q0,
-                                         int sub) {
+    __device__ static void put_obs_slice(char* smem, int r, const float* o, float inv_q0, int sub) {
         char* p = smem + OFF_IN + r * P_IN;
 #pragma unroll
-        for (int j = 0; j < OD / G; ++j) store1<DT>(p + (sub + j * G) * EB, o[j], inv_q0);
+        for (int j = 0; j < (OD + G - 1) / G; ++j)
+            if (OD % G == 0 || sub + j * G < OD) store1<DT>(p + (sub + j * G) * EB, o[j], inv_q0);
     }
 };
 
@@ -708,9 +708,34 @@ __device__ __forceinline__ void save_slice(const EnvArgs& env, int64_t row,
     for (int j = 0; j < E::SD / G; ++j) env.state[(size_t)(sub + j * G) * env.n_rows + row] = s[j];
 }
 template <int OD, int G, class P>
-__device__ __forceinline__ void store_obs_slice(P dst, const float (&o)[OD / G], int sub) {
+__device__ __forceinline__ void store_obs_slice(P dst, const float* o, int sub) {
 #pragma unroll
-    for (int j = 0; j < OD / G; ++j) dst[sub + j * G] = o[j];
+    for (int j = 0; j < (OD + G - 1) / G; ++j)
+        if (OD % G == 0 || sub + j * G < OD) dst[sub + j * G] = o[j];
+}
+
+// The reaction walk's slice of a row on lane `sub`: coordinates x[sub + m G]
+// (zero past the last), then the energy (on every lane).
+template <int G>
+__device__ __forceinline__ void load_rx_slice(const EnvArgs& env, int64_t row, float* s, int sub) {
+    constexpr int NX = (Reaction::NDIM + G - 1) / G;
+#pragma unroll
+    for (int m = 0; m < NX; ++m) {
+        const int i = sub + m * G;
+        s[m] = i < Reaction::NDIM ? env.state[(size_t)i * env.n_rows + row] : 0.0f;
+    }
+    s[NX] = env.state[(size_t)Reaction::NDIM * env.n_rows + row];
+}
+template <int G>
+__device__ __forceinline__ void save_rx_slice(const EnvArgs& env, int64_t row, const float* s,
+                                              int sub) {
+    constexpr int NX = (Reaction::NDIM + G - 1) / G;
+#pragma unroll
+    for (int m = 0; m < NX; ++m) {
+        const int i = sub + m * G;
+        if (i < Reaction::NDIM) env.state[(size_t)i * env.n_rows + row] = s[m];
+    }
+    if (sub == Reaction::NDIM % G) env.state[(size_t)Reaction::NDIM * env.n_rows + row] = s[NX];
 }
 
 // Stage the reaction potential in LDS: A, centres, -1/(2 w^2), amplitudes.
@@ -988,15 +1013,20 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
     const int drow = tl.row0 + dr;
     const bool dvalid = kDrawLanes && dr >= 0 && dr < R && drow < tl.row1;
     // the market's lanes hold slices of the row's state (its observation is
-    // the state itself); the other kinds hold the whole state on every lane
+    // the state itself); the reaction walk's lanes hold slices of its
+    // coordinates (its observation) and the energy; the other kinds hold the
+    // whole state on every lane
     constexpr bool kSlice = E::KIND == Market::KIND;
+    constexpr bool kRx = E::KIND == Reaction::KIND && kAhead;
     static_assert(!kSlice || (E::SD % G == 0 && E::OD == E::SD), "state slices");
-    constexpr int NS = kSlice ? E::SD / G : E::SR;
+    constexpr int NXS = (E::OD + G - 1) / G;   // observation entries per lane
+    constexpr int NS = kSlice ? E::SD / G : kRx ? NXS + 1 : E::SR;
     float s[NS];
 #pragma unroll
     for (int i = 0; i < NS; ++i) s[i] = 0.0f;
     if (valid) {
         if constexpr (kSlice) load_slice<E, G>(env, row, s, sub);
+        else if constexpr (kRx) load_rx_slice<G>(env, row, s, sub);
         else load_state<E>(env, row, s);
     }
     if constexpr (E::KIND == Reaction::KIND) {
@@ -1014,7 +1044,7 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
         for (int i = tid; i < 4 * R; i += NTHR) sums[i] = 0;
     }
     if (mine) {
-        if constexpr (kSlice) {
+        if constexpr (kSlice || kRx) {
             L::template put_obs_slice<E::OD, G>(smem, rr, s, inv_q0, sub);
             if (valid && horizon > 0) store_obs_slice<E::OD, G>(tr.obs + (size_t)row * E::OD, s, sub);
         } else {
@@ -1106,8 +1136,9 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
                     nxt = prepare<E>(key, t + 1, (uint32_t)row, log_std);
                 float reward;
                 bool done = false;
-                if constexpr (E::KIND == Reaction::KIND && kAhead)
-                    Reaction::step_noise<G>(s, act.index, noise_z, ctx, sub, reward);
+                if constexpr (kRx)
+                    Reaction::step_slice<G>(s, s[NXS], act.index, noise_z, ctx, sub, ahead_base,
+                                            reward);
                 else
                     E::template step<G>(s, act.index, act.value, t, (uint32_t)row, key, ctx, sub,
                                         reward, done);
@@ -1121,7 +1152,7 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
         }
         if (valid && step < horizon) {
             const gptr<float> dst = tr.obs + ((size_t)(step + 1) * env.n_rows + row) * E::OD;
-            if constexpr (kSlice) {
+            if constexpr (kSlice || kRx) {
                 L::template put_obs_slice<E::OD, G>(smem, rr, s, inv_q0, sub);
                 if (step + 1 < horizon) store_obs_slice<E::OD, G>(dst, s, sub);
             } else {
@@ -1135,6 +1166,7 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
     }
     if (valid) {
         if constexpr (kSlice) save_slice<E, G>(env, row, s, sub);
+        else if constexpr (kRx) save_rx_slice<G>(env, row, s, sub);
         else save_state<E, G>(env, row, s, sub);
     }
     if constexpr (E::KIND == Reaction::KIND) {
