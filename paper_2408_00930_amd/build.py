@@ -34,9 +34,16 @@ def hipcc() -> str:
     return path
 
 
+# The roll-out kernels keep their weights in registers; with the matrix-core
+# accumulators in VGPRs (not AGPRs) the tanh epilogue reads them without a
+# v_accvgpr_read per value (one vector instruction in six of the epilogue).
+SOURCE_FLAGS = {"rollout.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [hipcc()] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = ([hipcc()] + FLAGS + SOURCE_FLAGS.get(src, []) +
+           ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj])
     res = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in res.stderr.splitlines() if "packed-fp32-ops" not in l)
     if res.returncode != 0:
