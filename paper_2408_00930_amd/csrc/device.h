@@ -137,7 +137,9 @@ __device__ __forceinline__ uint32_t pack_fp8x4(float a, float b, float c, float 
     b = __builtin_amdgcn_fmed3f(b, -448.0f, 448.0f);
     c = __builtin_amdgcn_fmed3f(c, -448.0f, 448.0f);
     d = __builtin_amdgcn_fmed3f(d, -448.0f, 448.0f);
-    int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+    // the first conversion's other half is overwritten by the second: its
+    // old value may be anything (here a's bits, so no register is zeroed)
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, __builtin_bit_cast(int, a), false);
     w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
     return (uint32_t)w;
 }
@@ -357,8 +359,8 @@ __device__ __forceinline__ int xcd_block() {
 // same partial results on every lane, so every lane of a group ends with the
 // same value.
 template <int CTRL>
-__device__ __forceinline__ int dpp_i(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+__device__ __forceinline__ int dpp_i(int v) {   // every control used reads a lane of the row
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
 }
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v) {
@@ -386,12 +388,16 @@ __device__ __forceinline__ float group_sum(float v) {
     return v;
 }
 
+// The maximum by compare and select: fmaxf would first canonicalise the
+// permuted value (one more instruction per level). Lanes may end with zeros
+// of different signs, which no caller can tell apart (x - 0 and x + 0 agree).
 template <int G>
 __device__ __forceinline__ float group_max(float v) {
-    if constexpr (G >= 2) v = fmaxf(v, dpp_f<kDppSwap1>(v));
-    if constexpr (G >= 4) v = fmaxf(v, dpp_f<kDppSwap2>(v));
-    if constexpr (G >= 8) v = fmaxf(v, dpp_f<kDppHalfMirror>(v));
-    if constexpr (G >= 16) v = fmaxf(v, dpp_f<kDppMirror>(v));
+    float o;
+    if constexpr (G >= 2) { o = dpp_f<kDppSwap1>(v); v = o > v ? o : v; }
+    if constexpr (G >= 4) { o = dpp_f<kDppSwap2>(v); v = o > v ? o : v; }
+    if constexpr (G >= 8) { o = dpp_f<kDppHalfMirror>(v); v = o > v ? o : v; }
+    if constexpr (G >= 16) { o = dpp_f<kDppMirror>(v); v = o > v ? o : v; }
     return v;
 }
 

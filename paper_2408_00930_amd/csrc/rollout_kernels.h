@@ -544,13 +544,13 @@ __device__ __forceinline__ int sample_categorical(const float (&lg)[C], int sub,
         s += e[c];
     }
     const float z = group_sum<G>(s);
-    const float inv_z = 1.0f / z;
+    const float uz = u * z;   // u < C_k tested as u z < (unnormalised) C_k: no division
     float acc = group_prefix<G>(s, sub);
     int cand = K;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         acc += e[c];
-        if (cand == K && j0 + c < K && u < acc * inv_z) cand = j0 + c;
+        if (cand == K && j0 + c < K && uz < acc) cand = j0 + c;
     }
     int a = group_min<G>(cand);
     if (a >= K) a = K - 1;
