@@ -408,14 +408,44 @@ struct Reaction {
         step_noise<G>(s, a, noise_normal(key, t + 1, row), c, sub, reward);
         done = false;
     }
+    // What a lane's step reads that does not depend on the move: its cache
+    // entries (y_i, i = sub + m G; d_k, k = sub + m G) and its Gaussians'
+    // -1/(2 w^2) and amplitudes, loaded ahead so that the move waits only for
+    // the two coordinate-dependent parameter reads.
+    template <int G>
+    struct Lane {
+        static constexpr int NX = (NDIM + G - 1) / G, NK = NG / G;
+        double y[NX], d[NK];
+        float nhw[NK], amp[NK];
+    };
+    template <int G>
+    __device__ static void lane_load(Lane<G>& l, const EnvCtx& c, int sub) {
+        const float* nhw = c.lds_params + NDIM * NDIM + NG * NDIM;
+        const float* amp = nhw + NG;
+#pragma unroll
+        for (int m = 0; m < Lane<G>::NX; ++m) {
+            const int i = sub + m * G;
+            l.y[m] = c.cache[(i < NDIM ? i : NDIM - 1) * c.cache_stride];
+        }
+#pragma unroll
+        for (int m = 0; m < Lane<G>::NK; ++m) {
+            const int k = sub + m * G;
+            l.d[m] = c.cache[(NDIM + k) * c.cache_stride];
+            l.nhw[m] = nhw[k];
+            l.amp[m] = amp[k];
+        }
+    }
     // The step on a row whose G lanes each hold only their own coordinates
     // xs[m] = x[sub + m G] (and every lane the energy `en`): the moved
     // coordinate comes from the lane that holds it (`base` is the group's
-    // first lane in the wave), and the arithmetic is that of step_noise.
+    // first lane in the wave); the cache update and the energy are those of
+    // cache_move and energy_slice, from the lane's preloaded entries.
     template <int G>
-    __device__ static void step_slice(float* xs, float& en, int a, float z, const EnvCtx& c,
-                                      int sub, int base, float& reward) {
-        constexpr int NX = (NDIM + G - 1) / G;
+    __device__ static void step_slice(float* xs, float& en, Lane<G>& l, int a, float z,
+                                      const EnvCtx& c, int sub, int base, float& reward) {
+        constexpr int NX = Lane<G>::NX, NK = Lane<G>::NK;
+        const float* A = c.lds_params;
+        const float* cen = c.lds_params + NDIM * NDIM;
         const int coord = a >> 1;
         const float delta = (a & 1) ? -0.05f : 0.05f;
         const int owner = coord % G, jm = coord / G;
@@ -426,8 +456,32 @@ struct Reaction {
         const float x_new = x_old + delta;
 #pragma unroll
         for (int m = 0; m < NX; ++m) xs[m] = (sub == owner && jm == m) ? x_new : xs[m];
-        cache_move<G>(coord, x_old, x_new, c.lds_params, c, sub);
-        const float e_new = energy_slice<G>(xs, c.lds_params, c, sub) + 0.05f * z;
+        const double dl = (double)x_new - (double)x_old;   // exact
+#pragma unroll
+        for (int m = 0; m < NX; ++m) {
+            const int i = sub + m * G;
+            if (i < NDIM) {
+                l.y[m] = __builtin_fma(dl, (double)A[i * NDIM + coord], l.y[m]);
+                c.cache[i * c.cache_stride] = l.y[m];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < NK; ++m) {
+            const int k = sub + m * G;
+            const double two_off = 2.0 * ((double)x_old - (double)cen[k * NDIM + coord]) + dl;
+            l.d[m] = __builtin_fma(dl, two_off, l.d[m]);
+            c.cache[(NDIM + k) * c.cache_stride] = l.d[m];
+        }
+        float part = 0.0f;
+#pragma unroll
+        for (int m = 0; m < NX; ++m) {
+            const int i = sub + m * G;
+            const float t = 0.5f * xs[m] * (float)l.y[m];
+            part += i < NDIM ? t : 0.0f;
+        }
+#pragma unroll
+        for (int m = 0; m < NK; ++m) part += l.amp[m] * expf((float)l.d[m] * l.nhw[m]);
+        const float e_new = group_sum<G>(part) + 0.05f * z;
         reward = -(e_new - en);
         en = e_new;
     }

@@ -1085,6 +1085,9 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
             if constexpr (E::KIND == Reaction::KIND) noise_z = __shfl(ahead_z, src);
         }
         Act<E> act{0, 0.0f};
+        // reaction: the lane's cache entries and constants, read ahead of the draw
+        [[maybe_unused]] typename std::conditional<kRx, Reaction::Lane<G>, int>::type rxl{};
+        if constexpr (kRx) Reaction::lane_load<G>(rxl, ctx, sub);
         if (valid) {
             float hb[C], hv;
             L::template head_block<HO::NH, C>(smem, b3b, b3v, rr, j0, hb, hv);
@@ -1137,8 +1140,8 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
                 float reward;
                 bool done = false;
                 if constexpr (kRx)
-                    Reaction::step_slice<G>(s, s[NXS], act.index, noise_z, ctx, sub, ahead_base,
-                                            reward);
+                    Reaction::step_slice<G>(s, s[NXS], rxl, act.index, noise_z, ctx, sub,
+                                            ahead_base, reward);
                 else
                     E::template step<G>(s, act.index, act.value, t, (uint32_t)row, key, ctx, sub,
                                         reward, done);
