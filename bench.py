@@ -554,10 +554,12 @@ def measure(workload, args, wsx, inputs, torch, plain_steps, cpu_envs, single_th
                 params=inputs.reaction_params(0) if kind == wsx.REACTION else None))
         t0 = time.perf_counter()
         if batched:
-            tuned["batch"] = wsx.autotune_batch(spec, spec[0]["horizon"], reps=2)
+            # median of five timed roll-outs per candidate: with two, a hot
+            # clock after the previous workload has flipped kernels 6 % apart
+            tuned["batch"] = wsx.autotune_batch(spec, spec[0]["horizon"], reps=5)
         else:
             for key, d in zip(keys, spec):
-                tuned[key] = wsx.autotune(d["kind"], d["n_envs"], d["policy"], d["horizon"], reps=2,
+                tuned[key] = wsx.autotune(d["kind"], d["n_envs"], d["policy"], d["horizon"], reps=5,
                                           seed=0, agent_offsets=d["agent_offsets"],
                                           params=d["params"])
         print(f"[bench] {workload} autotune: {tuned} in {time.perf_counter() - t0:.1f} s",

@@ -7,7 +7,9 @@ bench.py times them (the autotuner's kernel shape, the same launch form):
   agents in 128-row tiles, more tiles than workgroups, so the persistent tile
   loop runs), horizon 250, the autotuned eight-wave kernel with the split-M
   head;
-- the reaction walk: 4,096 replicas, horizon 1,000, FP8 policy;
+- the reaction walk: 4,096 replicas, horizon 1,000, FP8 policy, with both
+  kernels the autotuner chooses between (four waves with all the weights,
+  eight waves at two per SIMD);
 - CartPole: 1,000 replicas, horizon 500, free-running against the oracle.
 
 Each runs as the benchmark runs it: reset, roll-out and returns/GAE in one
@@ -214,9 +216,16 @@ def test_market_full_size_matches_oracle_on_sampled_steps():
     print("PRECISION " + json.dumps(prec), flush=True)
 
 
-def test_reaction_full_size_matches_oracle_on_sampled_steps():
-    """4,096 reaction walkers, horizon 1,000, FP8 policy, the autotuned shape;
-    every walker at the sampled steps, late steps included."""
+# the two reaction kernels the autotuner picks between for this workload (one
+# wave per SIMD with all the weights; two waves per SIMD with half each)
+RX_SHAPES = [(16, 4, 1), (16, 8, 2)]
+
+
+@pytest.mark.parametrize("rx_shape", RX_SHAPES, ids=[",".join(map(str, s)) for s in RX_SHAPES])
+def test_reaction_full_size_matches_oracle_on_sampled_steps(rx_shape):
+    """4,096 reaction walkers, horizon 1,000, FP8 policy, each kernel shape the
+    benchmark's autotuner chooses between; every walker at the sampled steps,
+    late steps included."""
     import torch
     from paper_2408_00930_amd import wsx
     cfg = inputs.CONFIGS["reaction_4k"]
@@ -225,11 +234,12 @@ def test_reaction_full_size_matches_oracle_on_sampled_steps():
     pol = inputs.policy_for(O.REACTION, cfg["dtype"], cfg["hidden"], seed=0)
     dp = wsx.DevicePolicy(pol)
     params = inputs.reaction_params(0)
-    say("full size reaction: autotune")
-    best = wsx.autotune(O.REACTION, n, dp, T, reps=1, seed=0, params=params)
-    env = wsx.Env(O.REACTION, n, seed=0, params=params)
+    say("full size reaction: shape", rx_shape)
+    env = wsx.Env(O.REACTION, n, seed=0, params=params,
+                  **dict(zip(("tile_rows", "waves", "occupancy"), rx_shape)))
     shape = wsx.env_shape(env)
-    print("shape", best, shape, flush=True)
+    assert tuple(shape[:3]) == rx_shape, shape
+    print("shape", shape, flush=True)
     prec = {"kind": O.REACTION, "rows": n, "steps_checked": list(STEPS), "shape": list(shape)}
     (tr,), ((ret, adv),) = _one_launch([env], [dp], [O.REACTION], T, EPOCH, [prec])
     g = _steps(tr, STEPS + tuple(t + 1 for t in STEPS))
