@@ -275,7 +275,7 @@ struct Market {
 // ------------------------------------------------------------ Reaction --
 // 20-D walk on E(x) = x^T A x / 2 + sum_k a_k exp(-|x - c_k|^2 / (2 w_k^2))
 // plus 0.05 N(0,1) noise per evaluation. The LDS parameter block is A (400),
-// centres (64 x 20), -1/(2 w^2) (64), amplitudes (64).
+// centres (64 x 20), widths (64; staged in LDS as -log2(e)/(2 w^2)), amplitudes (64).
 struct Reaction {
     static constexpr int KIND = 5, SD = 21, SR = 21, OD = 20, NACT = 40, NDIM = 20, NG = 64, LANES = 16;
     __device__ static void complete(float*) {}
@@ -370,7 +370,7 @@ struct Reaction {
 #pragma unroll
         for (int m = 0; m < NG / G; ++m) {
             const int k = sub + m * G;
-            part += amp[k] * expf((float)c.cache[(NDIM + k) * c.cache_stride] * nhw[k]);
+            part += amp[k] * __builtin_amdgcn_exp2f((float)c.cache[(NDIM + k) * c.cache_stride] * nhw[k]);
         }
         return group_sum<G>(part);
     }
@@ -410,7 +410,7 @@ struct Reaction {
     }
     // What a lane's step reads that does not depend on the move: its cache
     // entries (y_i, i = sub + m G; d_k, k = sub + m G) and its Gaussians'
-    // -1/(2 w^2) and amplitudes, loaded ahead so that the move waits only for
+    // -log2(e)/(2 w^2) and amplitudes, loaded ahead so that the move waits only for
     // the two coordinate-dependent parameter reads.
     template <int G>
     struct Lane {
@@ -480,7 +480,7 @@ struct Reaction {
             part += i < NDIM ? t : 0.0f;
         }
 #pragma unroll
-        for (int m = 0; m < NK; ++m) part += l.amp[m] * expf((float)l.d[m] * l.nhw[m]);
+        for (int m = 0; m < NK; ++m) part += l.amp[m] * __builtin_amdgcn_exp2f((float)l.d[m] * l.nhw[m]);
         const float e_new = group_sum<G>(part) + 0.05f * z;
         reward = -(e_new - en);
         en = e_new;

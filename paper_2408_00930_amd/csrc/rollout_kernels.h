@@ -738,12 +738,13 @@ __device__ __forceinline__ void save_rx_slice(const EnvArgs& env, int64_t row, c
     if (sub == Reaction::NDIM % G) env.state[(size_t)Reaction::NDIM * env.n_rows + row] = s[NX];
 }
 
-// Stage the reaction potential in LDS: A, centres, -1/(2 w^2), amplitudes.
+// Stage the reaction potential in LDS: A, centres, -log2(e)/(2 w^2) (so a
+// well's term is amp * 2^(d * that), one v_exp_f32), amplitudes.
 __device__ __forceinline__ void stage_params(float* dst, const float* src, int tid, int nthreads) {
     constexpr int NA = Reaction::NDIM * Reaction::NDIM + Reaction::NG * Reaction::NDIM;
     for (int i = tid; i < Reaction::PARAM_FLOATS; i += nthreads) {
         float v = src[i];
-        if (i >= NA && i < NA + Reaction::NG) v = -0.5f / (v * v);
+        if (i >= NA && i < NA + Reaction::NG) v = -0.72134752044448170f / (v * v);   // log2(e) / 2
         dst[i] = v;
     }
 }
