@@ -221,12 +221,14 @@ class EnvSet:
                                 self.ret, self.adv)
 
 
-def batch_step(sets, i, wsx, torch, timed, k_events, one_launch=True):
-    """All sets in ONE fused launch on the first set's stream. one_launch: the
-    reset, the roll-out and the returns/GAE of every set in that launch
-    (wsx_rollout_batch_ext); else the separate calls (reset per set, the
-    batched roll-out, returns per set), the launch alone timed as the kernel."""
-    st = sets[0].stream
+def batch_step(sets, i, wsx, torch, timed, k_events, one_launch=True, stream=None):
+    """All sets in ONE fused launch on `stream` (default: the first set's
+    stream). one_launch: the reset, the roll-out and the returns/GAE of every
+    set in that launch (wsx_rollout_batch_ext); else the separate calls (reset
+    per set, the batched roll-out, returns per set), the launch alone timed as
+    the kernel. k_events None: the caller's events time the launch."""
+    st = stream if stream is not None else sets[0].stream
+    timed = timed and k_events is not None
     with torch.cuda.stream(st):
         if not one_launch:
             for s in sets:
@@ -317,11 +319,14 @@ def run_form(sets, mode, steps, warmup, wsx, torch, first_epoch, batched=False, 
     main = torch.cuda.current_stream()
     k_events = []
 
+    # A batched step is one launch (or, without one_launch, the launch with
+    # its reset and returns kernels) on the main stream, as a training loop
+    # would enqueue it: a second stream adds two cross-stream waits per step
+    # (~25 us). With one_launch the step's own events time the launch.
     def one(i, timed):
         if batched:
-            sets[0].stream.wait_stream(main)
-            batch_step(sets, i, wsx, torch, timed, k_events, one_launch)
-            main.wait_stream(sets[0].stream)
+            batch_step(sets, i, wsx, torch, timed, None if one_launch else k_events,
+                       one_launch, stream=main)
             return
         for s in sets:
             s.stream.wait_stream(main)
@@ -347,7 +352,7 @@ def run_form(sets, mode, steps, warmup, wsx, torch, first_epoch, batched=False, 
     elapsed = time.perf_counter() - t0
     lat = sorted(a.elapsed_time(b) for a, b in step_ev)
     if batched:
-        kern = {"batch": [a.elapsed_time(b) for a, b in k_events]}
+        kern = {"batch": [a.elapsed_time(b) for a, b in (step_ev if one_launch else k_events)]}
     else:
         kern = {s.key: [a.elapsed_time(b) for a, b in zip(s.k_start, s.k_end)] for s in sets}
     return elapsed, lat, kern
