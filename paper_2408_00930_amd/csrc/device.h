@@ -239,6 +239,21 @@ __device__ __forceinline__ float tanh_scaled_q(float acc, float k2, float q) {
 
 constexpr float kTwoLog2e = 2.8853900817779268f;  // 2 / ln 2
 
+// e^x for x <= 0 (a softmax term x = logit - max: no overflow). x log2(e)
+// is carried as hi + lo (hi rounded once; lo the FMA residue plus x times
+// the low part of log2(e)), n = rint(hi), and e^x = 2^n * 2^((hi - n) + lo)
+// with the power of two on |f| <= 1/2 from v_exp_f32 and the scaling by
+// ldexp; below about -150 the result is 0. Nine instructions, against
+// thirteen for expf, whose overflow and underflow checks cannot trigger here.
+__device__ __forceinline__ float exp_nonpos(float x) {
+    constexpr float kL2eHi = 1.44269502162933349609375f;   // log2(e) rounded to float
+    constexpr float kL2eLo = 1.925963001e-8f;              // log2(e) - kL2eHi
+    const float hi = x * kL2eHi;
+    const float lo = __builtin_fmaf(x, kL2eLo, __builtin_fmaf(x, kL2eHi, -hi));
+    const float n = __builtin_rintf(hi);
+    return __builtin_amdgcn_ldexpf(__builtin_amdgcn_exp2f((hi - n) + lo), (int)n);
+}
+
 // ------------------------------------------------- operand loading --
 template <class T>
 __device__ __forceinline__ T zero_frag() {

@@ -539,7 +539,10 @@ __device__ __forceinline__ int sample_categorical(const float (&lg)[C], int sub,
     float s = 0.0f;
 #pragma unroll
     for (int c = 0; c < C; ++c) {   // exp of every entry, then a select: no branch
-        const float ex = expf(lg[c] - mx);
+        // exp_nonpos measured faster for rows of one and four lanes (CartPole
+        // 0.438 -> 0.424 ms, market 9.88 -> 9.78 ms) but slower for the
+        // reaction's 16-lane rows (3.12 -> 3.24 ms, same box), which keep expf
+        const float ex = G <= 4 ? exp_nonpos(lg[c] - mx) : expf(lg[c] - mx);
         e[c] = j0 + c < K ? ex : 0.0f;
         s += e[c];
     }
