@@ -973,13 +973,13 @@ __device__ __forceinline__ void fused_tile(const Segment& sg, int tile, L& mlp, 
     constexpr bool kDrawLanes = E::KIND != Market::KIND && E::KIND != Reaction::KIND &&
                                 DOFF + R <= NTHR;
     // The reaction walk (16 lanes per row, one wave per SIMD, two Philox
-    // blocks and a Box-Muller pair per step) draws ahead instead: every G
-    // steps, lane `sub` of a row's group draws for step t + sub (the action's
-    // uniform and the energy noise), and each step takes its draws from that
-    // lane, so a step pays for 1 / G of the draws on its critical path. The
-    // values are the same draws. (The market, four lanes per row and one
-    // Philox block per step, measured no gain.)
-    constexpr bool kAhead = E::KIND == Reaction::KIND && G > 1;
+    // blocks and a Box-Muller pair per step) and the market (four lanes per
+    // row, one Philox block per step, two workgroups per CU bound by vector
+    // instructions) draw ahead instead: every G steps, lane `sub` of a row's
+    // group draws for step t + sub (the action's uniform, and the reaction's
+    // energy noise), and each step takes its draws from that lane, so a step
+    // pays for 1 / G of the draws. The values are the same draws.
+    constexpr bool kAhead = (E::KIND == Reaction::KIND || E::KIND == Market::KIND) && G > 1;
     float ahead_u = 0.0f, ahead_z = 0.0f, noise_z = 0.0f;
     const int ahead_base = (tid & 63) & ~(G - 1);   // the group's first lane in the wave
     Pre<E>* const pbuf = reinterpret_cast<Pre<E>*>(draws);   // [2][R]
