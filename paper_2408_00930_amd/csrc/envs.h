@@ -220,21 +220,34 @@ struct Market {
         demand_half = j > 2 ? j - 2 : 0;
         supply_18th = 2 * k + 9 * (j < 2 ? 2 - j : 0);
     }
-    __device__ static void settle(float* s, int a, int demand_half_sum, int supply_18th_sum,
-                                  float& reward) {
+    // The terms of a settled step: labour, trade, consumption, reward and the
+    // log price, from the action and the env-wide integer sums. Reciprocals
+    // stand in for the four divisions (k / 9, S / 18, the price ratio and
+    // bought / price), each within an ulp or two: this is a per-row
+    // dependent chain and a full-precision division is about ten
+    // instructions of it.
+    __device__ static void terms(int a, int demand_half_sum, int supply_18th_sum, float& labour,
+                                 float& trade, float& cons, float& reward, float& lp) {
         const int k = a % 10, j = a / 10;
-        const float labour = (float)k / 9.0f;
-        const float trade = (float)(j - 2) * 0.5f;
+        labour = (float)k * (1.0f / 9.0f);
+        trade = (float)(j - 2) * 0.5f;
         const float eps = 1e-3f;
         const float demand = (float)demand_half_sum * 0.5f;
-        const float supply = (float)supply_18th_sum / 18.0f;
-        const float price = (demand + eps) / (supply + eps);
+        const float supply = (float)supply_18th_sum * (1.0f / 18.0f);
+        const float num = demand + eps, den = supply + eps;
+        const float price = num * __builtin_amdgcn_rcpf(den);
         const float sold = trade < 0.0f ? -trade : 0.0f;
         const float bought = trade > 0.0f ? trade : 0.0f;
-        const float cons = fmaxf(0.0f, labour - sold + bought / price);
+        cons = fmaxf(0.0f, labour - sold + bought * (den * __builtin_amdgcn_rcpf(num)));
         reward = log1pf(cons) - 0.1f * labour * labour;
+        lp = logf(price);
+    }
+    __device__ static void settle(float* s, int a, int demand_half_sum, int supply_18th_sum,
+                                  float& reward) {
+        float labour, trade, cons, lp;
+        terms(a, demand_half_sum, supply_18th_sum, labour, trade, cons, reward, lp);
         s[0] = 0.9f * s[0] + 0.1f * (cons - 0.5f);
-        s[1] = logf(price);
+        s[1] = lp;
         s[2] = labour;
         s[3] = trade;
         s[4] = cons;
@@ -246,18 +259,8 @@ struct Market {
     template <int G>
     __device__ static void settle_slice(float (&s)[32 / G], int sub, int a, int demand_half_sum,
                                         int supply_18th_sum, float& reward) {
-        const int k = a % 10, j = a / 10;
-        const float labour = (float)k / 9.0f;
-        const float trade = (float)(j - 2) * 0.5f;
-        const float eps = 1e-3f;
-        const float demand = (float)demand_half_sum * 0.5f;
-        const float supply = (float)supply_18th_sum / 18.0f;
-        const float price = (demand + eps) / (supply + eps);
-        const float sold = trade < 0.0f ? -trade : 0.0f;
-        const float bought = trade > 0.0f ? trade : 0.0f;
-        const float cons = fmaxf(0.0f, labour - sold + bought / price);
-        reward = log1pf(cons) - 0.1f * labour * labour;
-        const float lp = logf(price);
+        float labour, trade, cons, lp;
+        terms(a, demand_half_sum, supply_18th_sum, labour, trade, cons, reward, lp);
 #pragma unroll
         for (int q = 0; q < 32 / G; ++q) {
             const int i = sub + q * G;
