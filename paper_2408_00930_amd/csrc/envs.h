@@ -161,22 +161,27 @@ struct Acrobot {
         const float tau = fminf(fmaxf(torque, -1.0f), 1.0f);
         const float h = 0.2f;
         float k1[4], k2[4], k3[4], k4[4], y[4];
-        float a1, b1, a2, b2;   // sin / cos of a stage's angles
+        // sin / cos of a stage's angles (|angle| below about 10: the wrapped
+        // angle plus h times a stage rate of up to ~9 pi) from the hardware
+        // instructions, whose error there (below about 8e-7) moves the step's
+        // result by ~1e-6 of its scale; the state's own sin / cos (the
+        // observation) stay exact to about an ulp (complete)
+        float a1, b1, a2, b2;
         deriv(s, tau, s[4], s[5], s[6], s[7], k1);
 #pragma unroll
         for (int i = 0; i < 4; ++i) y[i] = s[i] + 0.5f * h * k1[i];
-        sin_cos(y[0], a1, b1);
-        sin_cos(y[1], a2, b2);
+        sin_cos_hw(y[0], a1, b1);
+        sin_cos_hw(y[1], a2, b2);
         deriv(y, tau, a1, b1, a2, b2, k2);
 #pragma unroll
         for (int i = 0; i < 4; ++i) y[i] = s[i] + 0.5f * h * k2[i];
-        sin_cos(y[0], a1, b1);
-        sin_cos(y[1], a2, b2);
+        sin_cos_hw(y[0], a1, b1);
+        sin_cos_hw(y[1], a2, b2);
         deriv(y, tau, a1, b1, a2, b2, k3);
 #pragma unroll
         for (int i = 0; i < 4; ++i) y[i] = s[i] + h * k3[i];
-        sin_cos(y[0], a1, b1);
-        sin_cos(y[1], a2, b2);
+        sin_cos_hw(y[0], a1, b1);
+        sin_cos_hw(y[1], a2, b2);
         deriv(y, tau, a1, b1, a2, b2, k4);
 #pragma unroll
         for (int i = 0; i < 4; ++i) y[i] = s[i] + (h / 6.0f) * (k1[i] + 2.0f * k2[i] + 2.0f * k3[i] + k4[i]);
