@@ -108,6 +108,14 @@ __device__ __forceinline__ void sin_cos_hw(float x, float& sn, float& cs) {
     cs = __builtin_amdgcn_cosf(r);
 }
 
+// ln x from the hardware's v_log_f32 (log2) times ln 2: two instructions
+// against about fifteen for logf. Within a few 1e-7 absolute for the
+// arguments it is used on (normal floats between 1e-5 and 1e5: a softmax
+// normaliser, the market's price and 1 + consumption).
+__device__ __forceinline__ float log_hw(float x) {
+    return __builtin_amdgcn_logf(x) * 0.69314718055994531f;
+}
+
 // sin(pi y) and cos(pi y): y - k/2 is exact for the nearest half-integer k/2.
 __device__ __forceinline__ void sin_cos_pi(float y, float& sn, float& cs) {
     const float k = rintf(2.0f * y);

@@ -228,9 +228,9 @@ struct Market {
     // The terms of a settled step: labour, trade, consumption, reward and the
     // log price, from the action and the env-wide integer sums. Reciprocals
     // stand in for the four divisions (k / 9, S / 18, the price ratio and
-    // bought / price), each within an ulp or two: this is a per-row
-    // dependent chain and a full-precision division is about ten
-    // instructions of it.
+    // bought / price), each within an ulp or two, and the hardware log for
+    // logf / log1pf (a few 1e-7 absolute): this is a per-row dependent chain
+    // and a full-precision division or log is ten to fifteen instructions.
     __device__ static void terms(int a, int demand_half_sum, int supply_18th_sum, float& labour,
                                  float& trade, float& cons, float& reward, float& lp) {
         const int k = a % 10, j = a / 10;
@@ -244,8 +244,8 @@ struct Market {
         const float sold = trade < 0.0f ? -trade : 0.0f;
         const float bought = trade > 0.0f ? trade : 0.0f;
         cons = fmaxf(0.0f, labour - sold + bought * (den * __builtin_amdgcn_rcpf(num)));
-        reward = log1pf(cons) - 0.1f * labour * labour;
-        lp = logf(price);
+        reward = log_hw(1.0f + cons) - 0.1f * labour * labour;
+        lp = log_hw(price);
     }
     __device__ static void settle(float* s, int a, int demand_half_sum, int supply_18th_sum,
                                   float& reward) {

@@ -562,7 +562,7 @@ __device__ __forceinline__ int sample_categorical(const float (&lg)[C], int sub,
     for (int c = 0; c < C; ++c)
         if (j0 + c == a) la = lg[c];
     la = group_sum<G>(la);   // only the owner contributes
-    logp = (la - mx) - logf(z);
+    logp = (la - mx) - log_hw(z);   // z >= 1 (its largest term is 1)
     return a;
 }
 
